@@ -1,0 +1,175 @@
+"""CPU FP64 oracle of the multiple-tau correlator (test infrastructure only).
+
+The oracle is the plain, slow, obviously-correct reference the GPU library is
+checked against: Algorithm 1 (update) and Algorithm 2 (readout) of the paper's
+Appendix D, applied per channel in double precision, plus the trapezoid
+Green-Kubo integral (Eqs. for viscosity and thermal conductivity, Section
+2.3) and the direct k-space density sum (Eq. k-density, Section "Currents").
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+and the GPU library never calls it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = [os.path.join(_HERE, "corr_oracle.c")]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-Wextra", "-o", _LIB_PATH] + _SRC + ["-lm"]
+        subprocess.check_call(cmd)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        L.oracle_create.restype = vp
+        L.oracle_create.argtypes = [i64, i32, i32, i32, i32]
+        L.oracle_destroy.argtypes = [vp]
+        L.oracle_push.argtypes = [vp, vp, vp]
+        L.oracle_push.restype = i32
+        L.oracle_n_push.argtypes = [vp]
+        L.oracle_n_push.restype = i64
+        L.oracle_max_out.argtypes = [vp]
+        L.oracle_max_out.restype = i32
+        L.oracle_readout.argtypes = [vp, i64, i64, vp, vp, vp, vp]
+        L.oracle_readout.restype = i32
+        L.oracle_raw.argtypes = [vp, i64, vp, vp, vp]
+        L.oracle_raw.restype = i32
+        L.oracle_trapezoid.argtypes = [i32, vp, vp, dbl, vp]
+        L.oracle_trapezoid.restype = dbl
+        L.oracle_rhok.argtypes = [vp, i64, vp, i32, dbl, vp, vp]
+        L.oracle_rhok.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleCorrelator:
+    """n_ch independent FP64 multiple-tau correlators (b levels, p points, m)."""
+
+    def __init__(self, n_ch: int, levels: int, points: int, m: int = 2, complex_: bool = False):
+        self._h = lib().oracle_create(int(n_ch), int(levels), int(points), int(m), int(complex_))
+        if not self._h:
+            raise ValueError("invalid oracle correlator parameters")
+        self.n_ch, self.levels, self.points, self.m = int(n_ch), int(levels), int(points), int(m)
+        self.complex = bool(complex_)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().oracle_destroy(h)
+            self._h = None
+
+    def push(self, x) -> None:
+        x = np.asarray(x)
+        if self.complex:
+            xc = x.astype(np.complex128)
+            re = np.ascontiguousarray(xc.real)
+            im = np.ascontiguousarray(xc.imag)
+        else:
+            if np.iscomplexobj(x):
+                raise TypeError("complex samples pushed into a real correlator")
+            re = np.ascontiguousarray(x, dtype=np.float64)
+            im = None
+        if re.shape != (self.n_ch,):
+            raise ValueError(f"expected {self.n_ch} samples, got {re.shape}")
+        if lib().oracle_push(self._h, _ptr(re), _ptr(im)) != 0:
+            raise RuntimeError("oracle_push failed")
+
+    def push_series(self, xs) -> None:
+        """xs: [S][n_ch] -- push S steps in order."""
+        for row in xs:
+            self.push(row)
+
+    @property
+    def n_push(self) -> int:
+        return int(lib().oracle_n_push(self._h))
+
+    def readout(self, ch_begin: int = 0, ch_end: int | None = None):
+        """Group mean over channels [ch_begin, ch_end): (t_steps, C, count)."""
+        if ch_end is None:
+            ch_end = self.n_ch
+        nmax = int(lib().oracle_max_out(self._h))
+        t = np.zeros(nmax)
+        cre = np.zeros(nmax)
+        cim = np.zeros(nmax)
+        cnt = np.zeros(nmax, dtype=np.int64)
+        n = lib().oracle_readout(self._h, int(ch_begin), int(ch_end), _ptr(t), _ptr(cre),
+                                 _ptr(cim), _ptr(cnt))
+        if n < 0:
+            raise RuntimeError(f"oracle_readout failed ({n})")
+        c = cre[:n] + 1j * cim[:n] if self.complex else cre[:n]
+        return t[:n], c, cnt[:n]
+
+    def raw(self, ch: int):
+        """Per-(level, lag) sums and counts of one channel, shape [b][p]."""
+        n = self.levels * self.points
+        sre = np.zeros(n)
+        sim = np.zeros(n)
+        cnt = np.zeros(n, dtype=np.int64)
+        if lib().oracle_raw(self._h, int(ch), _ptr(sre), _ptr(sim), _ptr(cnt)) != 0:
+            raise RuntimeError("oracle_raw failed")
+        s = sre + 1j * sim if self.complex else sre
+        return s.reshape(self.levels, self.points), cnt.reshape(self.levels, self.points)
+
+
+def trapezoid(t, c, t_cut: float | None = None):
+    """Running trapezoid integral from t[0] and its value at t_cut (R14)."""
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    run = np.zeros_like(t)
+    if t_cut is None:
+        t_cut = float(t[-1]) if len(t) else 0.0
+    at = lib().oracle_trapezoid(len(t), _ptr(t), _ptr(c), float(t_cut), _ptr(run))
+    return run, float(at)
+
+
+def rhok(pos_f32: np.ndarray, kvec: np.ndarray, box: float) -> np.ndarray:
+    """n(k) = sum_j exp(i k.r_j) from FP32 positions [3][N], in FP64."""
+    pos = np.ascontiguousarray(pos_f32, dtype=np.float32)
+    assert pos.ndim == 2 and pos.shape[0] == 3
+    kv = np.ascontiguousarray(kvec, dtype=np.int32)
+    nk = kv.shape[0]
+    re = np.zeros(nk)
+    im = np.zeros(nk)
+    lib().oracle_rhok(_ptr(pos), int(pos.shape[1]), _ptr(kv), int(nk), float(box), _ptr(re),
+                      _ptr(im))
+    return re + 1j * im
+
+
+def green_kubo_viscosity(t, c_shear_mean, volume, kB, temperature, t_cut=None):
+    """Eq. (viscosity): V/(kB T) * integral of the mean off-diagonal stress ACF."""
+    run, at = trapezoid(t, c_shear_mean, t_cut)
+    f = volume / (kB * temperature)
+    return run * f, at * f
+
+
+def green_kubo_conductivity(t, c_flux_mean, volume, kB, temperature, t_cut=None):
+    """Eq. (thermal conductivity): V/(3 kB T^2) * integral of q(t).q(0); the dot
+    product of three components equals 3x their mean autocorrelation."""
+    run, at = trapezoid(t, c_flux_mean, t_cut)
+    f = volume / (3.0 * kB * temperature * temperature) * 3.0
+    return run * f, at * f
