@@ -1,0 +1,208 @@
+/*
+ * corr.h -- C ABI of the MI355X (gfx950) on-the-fly multiple-tau correlator.
+ *
+ * The library implements the per-step update of the multiple-tau correlator
+ * of the DL_POLY 5 paper (Section 2.2; Appendix D, Algorithm 1), its readout
+ * (Algorithm 2) and the Green-Kubo integrals for shear viscosity and thermal
+ * conductivity (Section 2.3, Eqs. for viscosity and thermal conductivity),
+ * for many independent channels at once on one GPU.  Channels are organised
+ * in groups; every channel of a group shares the correlator parameters
+ * (b blocks/levels, p points per level, averaging factor m, update interval
+ * u) and the sample / accumulator precision.  A group can instead be fed
+ * with atom positions, in which case the library evaluates the k-space
+ * density n(k) = sum_j exp(i k.r_j) (Section "Currents", Eq. k-density) for
+ * each of its k-vectors on every push and correlates those.
+ *
+ * Conventions shared by every entry point:
+ *  - every call returns int: CORR_OK (0) or a negative corr_status; no
+ *    exception or longjmp crosses the ABI;
+ *  - "device" pointers are HIP device allocations on the context's device,
+ *    "host" pointers are ordinary host memory;
+ *  - a context is bound to one device and one HIP stream (hipStream_t passed
+ *    as void*, NULL = the null stream); all device work is issued on that
+ *    stream in call order; a context is not thread-safe;
+ *  - the context owns every device allocation it makes and frees it in
+ *    corr_destroy;
+ *  - on an error the message is available from corr_last_error(ctx) (or
+ *    corr_last_error(NULL) for errors of corr_create).
+ */
+#ifndef CORR_H
+#define CORR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct corr_ctx corr_ctx;
+
+enum corr_status {
+    CORR_OK = 0,
+    CORR_E_INVALID = -1,     /* bad argument or descriptor                      */
+    CORR_E_OOM = -2,         /* device allocation failed                         */
+    CORR_E_DEVICE = -3,      /* a HIP call failed (message names it)             */
+    CORR_E_STATE = -4,       /* call not valid in the context's current state    */
+    CORR_E_UNSUPPORTED = -5  /* valid descriptor this build does not implement   */
+};
+
+/* Sample precision (complex types are interleaved re, im). */
+enum corr_dtype { CORR_F32 = 1, CORR_F64 = 2, CORR_CF32 = 3, CORR_CF64 = 4 };
+
+/* Per-lag accumulator: FP64; compensated (Kahan) FP32 value + compensation
+ * planes; or plain FP32 (uncompensated, for precision comparisons only).
+ * KAHAN_F32 and F32 require a single-precision sample dtype. */
+enum corr_accum { CORR_ACC_F64 = 1, CORR_ACC_KAHAN_F32 = 2, CORR_ACC_F32 = 3 };
+
+/* Where a group's samples come from on each push. */
+enum corr_source {
+    CORR_SRC_SAMPLES = 0, /* caller provides n_channels samples per push        */
+    CORR_SRC_RHOK = 1     /* caller provides positions; channels = k-vectors     */
+};
+
+/* corr_create flags. */
+enum corr_flags {
+    CORR_FLAG_GRAPH = 1u,     /* capture one push of all groups in a HIP graph    */
+    CORR_FLAG_PER_GROUP = 2u, /* one kernel launch per group and push (the plain
+                                 form) instead of one batched launch            */
+    CORR_FLAG_TIMING = 4u     /* bracket the push kernel launch(es) of every push
+                                 with HIP events (see corr_kernel_time)         */
+};
+
+typedef struct corr_group_desc {
+    int64_t n_channels;     /* channels; for CORR_SRC_RHOK the number of k-vectors */
+    int32_t levels;         /* b >= 1 blocks                                       */
+    int32_t points;         /* p >= 2 values per block                             */
+    int32_t m;              /* averaging factor, 2 <= m < p                        */
+    int32_t dtype;          /* enum corr_dtype (CORR_SRC_RHOK: CF32 or CF64)       */
+    int32_t accum;          /* enum corr_accum                                     */
+    int32_t source;         /* enum corr_source                                    */
+    int32_t update_every;   /* u >= 1: scales reported lag times only (Sec. 2.2)  */
+    int32_t reserved;
+    double dt;              /* simulation time step; lag time = L m^k u dt        */
+    /* CORR_SRC_RHOK only (ignored otherwise): */
+    const int32_t *kvec;    /* host [n_channels][3] integer n, k = 2 pi n / box;
+                               copied during corr_create                          */
+    int64_t n_atoms;        /* positions per push, layout float [3][n_atoms]      */
+    double box;             /* cubic box edge L                                   */
+} corr_group_desc;
+
+/* Launch shape of the push kernel.  Channels are stored in tiles of
+ * tile_channels consecutive channels (the state layout depends on it, so it
+ * is fixed at create); each thread handles chans_per_thread consecutive
+ * channels of a tile; the batched kernel runs grid_blocks blocks that stride
+ * over all tiles of all groups (0 = one block per tile).  Zeros everywhere
+ * select the library defaults (or the autotuner's cached choice). */
+typedef struct corr_tuning {
+    int32_t tile_channels;    /* 64..4096, multiple of 64 * chans_per_thread        */
+    int32_t chans_per_thread; /* 1, 2 or 4                                          */
+    int32_t lag_chunk;        /* lags loaded per batch: 4, 8 or 16                  */
+    int32_t grid_blocks;      /* 0 = one block per tile                              */
+} corr_tuning;
+
+/*
+ * Create a context for n_groups channel groups on HIP device `device`, whose
+ * work is issued on `stream`.  Validates every descriptor (CORR_E_INVALID on
+ * b < 1, p < 2, m < 2, m >= p, n_channels < 1, u < 1, an unknown dtype /
+ * accumulator / source, a compensated or FP32 accumulator with a double
+ * dtype, a k-density group without k-vectors, positions or a positive box),
+ * allocates and zeroes all state (CORR_E_OOM on failure) and, with
+ * CORR_FLAG_GRAPH, captures the push graph.  `tuning` may be NULL.
+ * On success *out receives the context.
+ */
+int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device, void *stream,
+                uint32_t flags, const corr_tuning *tuning, corr_ctx **out);
+
+/* Device buffer the library reads a group's samples from when corr_push is
+ * given NULL for that group: n_channels elements of the group dtype, or for
+ * CORR_SRC_RHOK float positions [3][n_atoms].  The pointer is stable for the
+ * life of the context (required by graph mode). */
+int corr_input_buffer(corr_ctx *ctx, int32_t group, void **dev_ptr, size_t *bytes);
+
+/* Replace a group's input buffer by caller-owned device memory of at least
+ * the bytes corr_input_buffer reports (dev_ptr NULL restores the library's own
+ * buffer).  The caller keeps it valid until it is unbound or the context is
+ * destroyed.  In graph mode the push graph is captured again, so later
+ * replays read the new buffer.  Synchronises the context's stream. */
+int corr_bind_input(corr_ctx *ctx, int32_t group, void *dev_ptr, size_t bytes);
+
+/*
+ * One correlator update (Algorithm 1 applied with block index 1) of every
+ * channel of every group.  samples: NULL (use every group's input buffer) or
+ * a host array of n_groups device pointers, each NULL (use that group's input
+ * buffer) or the group's samples for this step (layout as for
+ * corr_input_buffer).  The pointers are only read by work issued on the
+ * context's stream; they must stay valid until that work has run.  In graph
+ * mode, a push whose pointers are all NULL (or equal to the input buffers)
+ * replays the captured graph; any other pointer launches the same kernels
+ * directly.
+ */
+int corr_push(corr_ctx *ctx, const void *const *samples);
+
+/* Number of pushes so far and the maximum number of readout points of a
+ * group, p + (b - 1)(p - floor(p/m)) (Algorithm 2). */
+int corr_query(const corr_ctx *ctx, int32_t group, int64_t *n_pushes, int32_t *n_out_max);
+
+typedef struct corr_readout_opts {
+    int64_t ch_begin, ch_end; /* channels averaged; [0, 0) = all channels          */
+    double t_cut;             /* Green-Kubo cut-off time; <= 0 = last emitted lag   */
+    int32_t gk_kind;          /* 0: raw integral of C; 1: shear viscosity
+                                 V/(kB T) * integral (channels = the shear
+                                 components); 2: thermal conductivity
+                                 V/(3 kB T^2) * integral of q(t).q(0), the dot
+                                 product taken as 3x the channel mean            */
+    int32_t reserved;
+    double volume, kB, temperature; /* used by gk_kind 1 and 2                     */
+    int64_t slice_begin, slice_end; /* channels returned in c_per_channel          */
+} corr_readout_opts;
+
+/*
+ * Readout (Algorithm 2) of one group, non-destructive: more pushes may
+ * follow.  Synchronises the context's stream.  For every (level k, lag L)
+ * with a non-zero count, in level-major lag-minor order, writes
+ *   t[i]     = L m^k u dt,
+ *   c[i]     = mean over the selected channels of sum/count (complex dtypes:
+ *              c is [n_out][2] re, im; k-density groups are scaled by
+ *              1/n_atoms, i.e. F(k,t) of Section "Currents"),
+ *   count[i] = pushes that contributed, max(0, floor(S / m^k) - L),
+ *   gk_running[i] = trapezoid integral of Re c from t[0] to t[i] times the
+ *              gk_kind prefactor, and *gk_at_cut the same at opts->t_cut,
+ * and, if c_per_channel is not NULL, the per-channel values for channels
+ * [slice_begin, slice_end) as [slice][n_out] (complex: [slice][n_out][2]).
+ * Output arrays are host memory of at least n_out_max entries (corr_query);
+ * any of t, count, gk_running, gk_at_cut may be NULL.  opts may be NULL.
+ */
+int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, int32_t *n_out,
+                  double *t, double *c, int64_t *count, double *gk_running, double *gk_at_cut,
+                  double *c_per_channel);
+
+/* Wait for all work issued by the context. */
+int corr_sync(corr_ctx *ctx);
+
+/* Free every device allocation of the context (synchronises first). */
+int corr_destroy(corr_ctx *ctx);
+
+/* Message of the last failed call on ctx (NULL: of the last failed
+ * corr_create on this thread).  Never NULL; owned by the library. */
+const char *corr_last_error(const corr_ctx *ctx);
+
+/* Device bytes of correlator state held by a group (ring and accumulator
+ * planes, padded to whole tiles). */
+int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
+
+/* With CORR_FLAG_TIMING: synchronise and return the summed device time of
+ * the push kernel launches (HIP events recorded on the context's stream
+ * around the correlator-update kernel(s) only, excluding the k-density
+ * producer and the step counter) and the number of timed pushes since the
+ * last reset.  In graph mode the events bracket the whole graph replay.
+ * reset != 0 clears both after reading.  CORR_E_STATE without the flag. */
+int corr_kernel_time(corr_ctx *ctx, double *ms_total, int64_t *n_pushes, int32_t reset);
+
+/* Launch shape in use. */
+int corr_get_tuning(const corr_ctx *ctx, corr_tuning *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CORR_H */

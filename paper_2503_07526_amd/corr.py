@@ -1,0 +1,275 @@
+"""ctypes binding of the correlator's C ABI (include/corr.h).
+
+Argument marshalling only: every step of the per-step update, the k-space
+density and the readout reduction runs in the library's HIP kernels.  PyTorch
+supplies device memory (sample tensors) and streams.  If the library has not
+been built the import fails; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime first, so one runtime serves both)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcorr_gfx950.so")
+
+CORR_OK, CORR_E_INVALID, CORR_E_OOM, CORR_E_DEVICE, CORR_E_STATE, CORR_E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5
+DTYPES = {"f32": 1, "f64": 2, "cf32": 3, "cf64": 4}
+ACCUMS = {"f64": 1, "kahan": 2, "f32": 3}
+SOURCES = {"samples": 0, "rhok": 1}
+FLAG_GRAPH, FLAG_PER_GROUP, FLAG_TIMING = 1, 2, 4
+_TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64, "cf32": torch.complex64,
+                "cf64": torch.complex128}
+
+
+class CorrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"corr error {code}: {msg}")
+        self.code = code
+
+
+class _GroupDesc(ctypes.Structure):
+    _fields_ = [("n_channels", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("points", ctypes.c_int32), ("m", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("accum", ctypes.c_int32), ("source", ctypes.c_int32),
+                ("update_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("kvec", ctypes.POINTER(ctypes.c_int32)),
+                ("n_atoms", ctypes.c_int64), ("box", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_channels", ctypes.c_int32), ("chans_per_thread", ctypes.c_int32),
+                ("lag_chunk", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class _ReadoutOpts(ctypes.Structure):
+    _fields_ = [("ch_begin", ctypes.c_int64), ("ch_end", ctypes.c_int64),
+                ("t_cut", ctypes.c_double), ("gk_kind", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("volume", ctypes.c_double),
+                ("kB", ctypes.c_double), ("temperature", ctypes.c_double),
+                ("slice_begin", ctypes.c_int64), ("slice_end", ctypes.c_int64)]
+
+
+EXPORTS = ["corr_create", "corr_input_buffer", "corr_bind_input", "corr_push", "corr_query",
+           "corr_finalize", "corr_sync", "corr_destroy", "corr_last_error", "corr_state_bytes",
+           "corr_get_tuning", "corr_kernel_time"]
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.corr_create.argtypes = [ctypes.POINTER(_GroupDesc), i32, i32, vp, ctypes.c_uint32,
+                                  ctypes.POINTER(Tuning), ctypes.POINTER(vp)]
+        L.corr_input_buffer.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(sz)]
+        L.corr_bind_input.argtypes = [vp, i32, vp, sz]
+        L.corr_push.argtypes = [vp, ctypes.POINTER(vp)]
+        L.corr_query.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+        L.corr_finalize.argtypes = [vp, i32, ctypes.POINTER(_ReadoutOpts), ctypes.POINTER(i32),
+                                    vp, vp, vp, vp, vp, vp]
+        L.corr_sync.argtypes = [vp]
+        L.corr_destroy.argtypes = [vp]
+        L.corr_last_error.argtypes = [vp]
+        L.corr_last_error.restype = ctypes.c_char_p
+        L.corr_state_bytes.argtypes = [vp, i32, ctypes.POINTER(i64)]
+        L.corr_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.corr_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                       i32]
+        for name in EXPORTS:
+            if name != "corr_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+@dataclass
+class GroupDesc:
+    """One channel group: b levels of p points, averaging m (Section 2.2)."""
+    n_channels: int
+    levels: int
+    points: int
+    m: int = 2
+    dtype: str = "f32"
+    accum: str = "f64"
+    source: str = "samples"
+    update_every: int = 1
+    dt: float = 1.0
+    kvec: np.ndarray | None = None
+    n_atoms: int = 0
+    box: float = 0.0
+    _kbuf: object = field(default=None, repr=False)
+
+    def to_c(self) -> _GroupDesc:
+        d = _GroupDesc()
+        d.n_channels, d.levels, d.points, d.m = self.n_channels, self.levels, self.points, self.m
+        d.dtype, d.accum, d.source = DTYPES[self.dtype], ACCUMS[self.accum], SOURCES[self.source]
+        d.update_every, d.dt = self.update_every, self.dt
+        if self.kvec is not None:
+            self._kbuf = np.ascontiguousarray(self.kvec, dtype=np.int32)
+            d.kvec = self._kbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.n_atoms, d.box = int(self.n_atoms), float(self.box)
+        return d
+
+    @property
+    def max_out(self) -> int:
+        return self.points + (self.levels - 1) * (self.points - self.points // self.m)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+class Correlator:
+    """A context of channel groups on one GPU (wraps corr_create ... corr_destroy)."""
+
+    def __init__(self, groups, device: int = 0, stream: torch.cuda.Stream | None = None,
+                 graph: bool = False, per_group: bool = False, tuning: dict | None = None,
+                 timing: bool = False):
+        L = lib()
+        self.groups = list(groups)
+        descs = (_GroupDesc * len(self.groups))(*[g.to_c() for g in self.groups])
+        self.device = int(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        flags = (FLAG_GRAPH if graph else 0) | (FLAG_PER_GROUP if per_group else 0) | \
+            (FLAG_TIMING if timing else 0)
+        tn = Tuning(**tuning) if tuning else None
+        h = ctypes.c_void_p()
+        rc = L.corr_create(descs, len(self.groups), self.device,
+                           ctypes.c_void_p(self.stream.cuda_stream), flags,
+                           ctypes.byref(tn) if tn is not None else None, ctypes.byref(h))
+        if rc != CORR_OK:
+            raise CorrError(rc, L.corr_last_error(None).decode())
+        self._h = h
+        self._bound = {}
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, rc):
+        if rc != CORR_OK:
+            raise CorrError(rc, lib().corr_last_error(self._h).decode())
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().corr_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------ API
+    def input_buffer(self, g: int):
+        p = ctypes.c_void_p()
+        n = ctypes.c_size_t()
+        self._check(lib().corr_input_buffer(self._h, g, ctypes.byref(p), ctypes.byref(n)))
+        return int(p.value or 0), int(n.value)
+
+    def bind_input(self, g: int, tensor: torch.Tensor | None):
+        """Make `tensor` (kept alive here) the buffer group g reads on NULL pushes."""
+        if tensor is None:
+            self._check(lib().corr_bind_input(self._h, g, None, 0))
+            self._bound.pop(g, None)
+            return
+        assert tensor.is_cuda and tensor.is_contiguous()
+        nbytes = tensor.numel() * tensor.element_size()
+        self._check(lib().corr_bind_input(self._h, g, ctypes.c_void_p(tensor.data_ptr()), nbytes))
+        self._bound[g] = tensor
+
+    def push(self, samples=None):
+        """samples: None (input buffers) or a list with one tensor (or None) per group."""
+        if samples is None:
+            self._check(lib().corr_push(self._h, None))
+            return
+        arr = (ctypes.c_void_p * len(self.groups))(*[_ptr(s) for s in samples])
+        self._check(lib().corr_push(self._h, arr))
+
+    def sync(self):
+        self._check(lib().corr_sync(self._h))
+
+    def n_pushes(self, g: int = 0) -> int:
+        n = ctypes.c_int64()
+        m = ctypes.c_int32()
+        self._check(lib().corr_query(self._h, g, ctypes.byref(n), ctypes.byref(m)))
+        return int(n.value)
+
+    def state_bytes(self, g: int) -> int:
+        n = ctypes.c_int64()
+        self._check(lib().corr_state_bytes(self._h, g, ctypes.byref(n)))
+        return int(n.value)
+
+    def kernel_time(self, reset: bool = False):
+        """(summed push-kernel milliseconds, timed pushes) from the library's HIP events."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(lib().corr_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+        return float(ms.value), int(n.value)
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        self._check(lib().corr_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def finalize(self, g: int, ch=None, t_cut: float = 0.0, gk_kind: int = 0, volume=0.0,
+                 kB=0.0, temperature=0.0, slice_=None):
+        """Readout (Algorithm 2) of group g.  Returns a dict with t, c, count,
+        gk_running, gk_at_cut and, if slice_=(b, e) is given, c_per_channel."""
+        gd = self.groups[g]
+        nmax = gd.max_out
+        cplx = gd.dtype in ("cf32", "cf64")
+        o = _ReadoutOpts()
+        if ch is not None:
+            o.ch_begin, o.ch_end = int(ch[0]), int(ch[1])
+        o.t_cut, o.gk_kind = float(t_cut), int(gk_kind)
+        o.volume, o.kB, o.temperature = float(volume), float(kB), float(temperature)
+        t = np.zeros(nmax)
+        c = np.zeros((nmax, 2) if cplx else nmax)
+        cnt = np.zeros(nmax, dtype=np.int64)
+        run = np.zeros(nmax)
+        at = ctypes.c_double()
+        n_out = ctypes.c_int32()
+        per = None
+        if slice_ is not None:
+            o.slice_begin, o.slice_end = int(slice_[0]), int(slice_[1])
+            ns = o.slice_end - o.slice_begin
+            per = np.zeros((ns, nmax, 2) if cplx else (ns, nmax))
+        P = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        self._check(lib().corr_finalize(self._h, g, ctypes.byref(o), ctypes.byref(n_out), P(t),
+                                        P(c), P(cnt), P(run), ctypes.byref(at), P(per)))
+        n = int(n_out.value)
+        res = {"t": t[:n], "count": cnt[:n], "gk_running": run[:n], "gk_at_cut": float(at.value)}
+        if cplx:
+            res["c"] = c[:n, 0] + 1j * c[:n, 1]
+        else:
+            res["c"] = c[:n]
+        if per is not None:
+            if cplx:
+                res["c_per_channel"] = per[:, :n, 0] + 1j * per[:, :n, 1]
+            else:
+                res["c_per_channel"] = per[:, :n]
+        return res

@@ -1,0 +1,117 @@
+// corr_internal.h -- layout and kernel-argument structures shared by the
+// host runtime and the HIP kernels of the correlator library.
+//
+// State layout (per group, in one device allocation): channels are grouped
+// in tiles of `tw` consecutive channels; tile t occupies `tile_bytes` bytes
+// at state + t * tile_bytes.  Inside a tile, level 0 comes first, then
+// levels 1..b-1, each laid out as
+//     ring  [p][tw]          sample type S (ring slot r of every channel)
+//     acc   [nl][tw]         accumulator plane(s), one row per lag
+// where nl = p for level 0 and p - floor(p/m) for the coarser levels (they
+// only ever accumulate lags floor(p/m)..p-1, Algorithm 1).  A compensated
+// accumulator has two planes, value rows then compensation rows.  Every row
+// is a multiple of 256 bytes, so wave-wide vector loads are whole cache
+// lines and all planes stay aligned.
+#ifndef CORR_INTERNAL_H
+#define CORR_INTERNAL_H
+
+#include <stdint.h>
+
+namespace corr {
+
+constexpr int kMaxGroups = 8;
+
+// (sample dtype, accumulator) combinations; the kernels are specialised on it.
+enum Kind : int32_t {
+    K_F32_F64 = 0,   // float samples, double sums
+    K_F32_KAHAN = 1, // float samples, compensated float sums
+    K_F32_F32 = 2,   // float samples, plain float sums
+    K_F64_F64 = 3,   // double samples, double sums
+    K_CF32_F64 = 4,  // complex float samples, complex double sums
+    K_CF32_KAHAN = 5,
+    K_CF32_F32 = 6,
+    K_CF64_F64 = 7,
+    K_COUNT = 8
+};
+
+struct GroupArgs {
+    const void *samples; // this push's samples (device), n_ch elements
+    char *state;         // tile 0 of the group
+    int64_t n_ch;        // channels
+    int64_t n_tiles;     // tiles (ceil(n_ch / tw))
+    int64_t tile_first;  // index of the group's first tile in the batched tile space
+    int64_t tile_bytes;  // bytes per tile
+    int64_t lvl0_bytes;  // bytes of level 0 inside a tile
+    int64_t lvlk_bytes;  // bytes of each level >= 1 inside a tile
+    int32_t kind;        // enum Kind
+    int32_t p, m, levels;
+    int32_t lag0;        // floor(p / m): first lag of levels >= 1
+    int32_t tw;          // channels per tile
+    int32_t s_bytes;     // bytes per sample
+    int32_t a_bytes;     // bytes per accumulator plane element
+};
+
+struct PushArgs {
+    GroupArgs g[kMaxGroups];
+    int32_t n_groups;
+    int32_t pad_;
+    int64_t total_tiles;
+    const int64_t *step; // device: pushes completed before this one
+};
+
+// Number of accumulator planes of a kind (2 for compensated sums).
+inline int acc_planes(int kind) { return (kind == K_F32_KAHAN || kind == K_CF32_KAHAN) ? 2 : 1; }
+inline bool kind_complex(int kind) { return kind >= K_CF32_F64; }
+inline int kind_sample_bytes(int kind)
+{
+    switch (kind) {
+    case K_F32_F64: case K_F32_KAHAN: case K_F32_F32: return 4;
+    case K_F64_F64: case K_CF32_F64: case K_CF32_KAHAN: case K_CF32_F32: return 8;
+    default: return 16;
+    }
+}
+inline int kind_acc_bytes(int kind)
+{
+    switch (kind) {
+    case K_F32_F64: case K_F64_F64: return 8;
+    case K_F32_KAHAN: case K_F32_F32: return 4;
+    case K_CF32_F64: case K_CF64_F64: return 16;
+    default: return 8; // complex float planes
+    }
+}
+
+// k-density producer arguments.
+struct RhokArgs {
+    const float *pos;      // [3][n_atoms]
+    int64_t n_atoms;
+    const int32_t *kq;     // [nk][3] integer k-vectors, sorted by (nz, ny, nx)
+    const int32_t *kperm;  // [nk]: output index of sorted k-vector q
+    int32_t nk;
+    int32_t n_chunks;      // k-chunks
+    double inv_box;        // 1 / L
+    double *partial;       // [n_atom_blocks][nk][2] FP64 partial sums
+    int32_t n_atom_blocks;
+    int32_t atoms_per_block;
+    void *out;             // [nk] complex samples (float2 or double2)
+    int32_t out_double;    // 1: double2 output
+    int32_t nmax;          // max |n component|
+};
+
+// Readout reduction arguments.
+struct ReduceArgs {
+    const char *state;
+    int64_t tile_bytes;
+    int32_t tw;
+    int32_t kind;
+    const int64_t *hi_off;  // [n_entries] byte offset inside a tile of the entry's row
+    const int64_t *lo_off;  // [n_entries] compensation row offset (compensated kinds)
+    int32_t n_entries;
+    int32_t blocks_per_entry;
+    int64_t ch_begin, ch_end;
+    double *partial;        // [n_entries][blocks_per_entry][2]
+    double *out;            // [n_entries][2]
+};
+
+} // namespace corr
+
+#endif

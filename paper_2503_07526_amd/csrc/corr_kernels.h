@@ -1,0 +1,23 @@
+// corr_kernels.h -- host-side launchers of the correlator's HIP kernels.
+#ifndef CORR_KERNELS_H
+#define CORR_KERNELS_H
+
+#include <hip/hip_runtime.h>
+
+#include "corr_internal.h"
+
+namespace corr {
+
+hipError_t launch_push_batched(const PushArgs &a, int cpt, int lch, int grid, int block,
+                               hipStream_t st);
+hipError_t launch_push_group(const GroupArgs &g, const int64_t *step, int cpt, int lch, int block,
+                             hipStream_t st);
+hipError_t launch_step_increment(int64_t *step, hipStream_t st);
+hipError_t launch_rhok(const RhokArgs &a, hipStream_t st);
+int rhok_tile_atoms(int nmax);
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
+hipError_t launch_gather(const ReduceArgs &a, hipStream_t st);
+
+} // namespace corr
+
+#endif

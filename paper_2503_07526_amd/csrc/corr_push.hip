@@ -1,0 +1,396 @@
+// corr_push.hip -- per-step correlator update on gfx950.
+//
+// One push is Algorithm 1 of the paper's Appendix D called with block index
+// 1 for every channel: write the newest sample into the level-0 ring,
+// accumulate x * conj(ring[lag L]) for L = 0..min(S, p)-1, and, every m^k
+// pushes, average the last m values of level k-1 into level k and
+// accumulate lags floor(p/m)..p-1 there.  All channels of a group receive the
+// same number of pushes, so the ring cursors, fill levels and counts of the
+// algorithm are the same for every channel and follow from the push index
+// alone: level k has received S_k = floor(S / m^k) values, its newest value
+// sits in slot (S_k - 1) mod p, and lag L of level k has count
+// max(0, S_k - L).  No per-channel integer state exists; the averaging
+// accumulator of Algorithm 1 is replaced by the last m ring values of the
+// level above (p > m, so they are always still in the ring).
+//
+// Threads own channels (one to four consecutive channels each); a block owns
+// a tile of the state laid out structure-of-arrays (corr_internal.h), so the
+// lanes of a wave read and write whole consecutive cache lines of every ring
+// and accumulator row.
+#include <hip/hip_runtime.h>
+
+#include "corr_kernels.h"
+
+namespace corr {
+
+// Whole-vector loads and stores of N consecutive elements (N * sizeof(T) is
+// 4..64 bytes and naturally aligned by the tile layout): moved as a vector of
+// dwords so that each lane issues 16-byte memory instructions.
+template <typename T, int N>
+__device__ __forceinline__ void vload(const T *p, T (&out)[N])
+{
+    constexpr int W = (int)(sizeof(T) * N / 4);
+    typedef uint32_t V __attribute__((ext_vector_type(W)));
+    const V v = *reinterpret_cast<const V *>(p);
+    __builtin_memcpy(&out[0], &v, sizeof(T) * N);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void vstore(T *p, const T (&in)[N])
+{
+    constexpr int W = (int)(sizeof(T) * N / 4);
+    typedef uint32_t V __attribute__((ext_vector_type(W)));
+    V v;
+    __builtin_memcpy(&v, &in[0], sizeof(T) * N);
+    *reinterpret_cast<V *>(p) = v;
+}
+
+// ---------------------------------------------------------------- kinds
+template <int K> struct KT;
+template <> struct KT<K_F32_F64>    { using S = float;   using A = double;  static constexpr int NP = 1; };
+template <> struct KT<K_F32_KAHAN>  { using S = float;   using A = float;   static constexpr int NP = 2; };
+template <> struct KT<K_F32_F32>    { using S = float;   using A = float;   static constexpr int NP = 1; };
+template <> struct KT<K_F64_F64>    { using S = double;  using A = double;  static constexpr int NP = 1; };
+template <> struct KT<K_CF32_F64>   { using S = float2;  using A = double2; static constexpr int NP = 1; };
+template <> struct KT<K_CF32_KAHAN> { using S = float2;  using A = float2;  static constexpr int NP = 2; };
+template <> struct KT<K_CF32_F32>   { using S = float2;  using A = float2;  static constexpr int NP = 1; };
+template <> struct KT<K_CF64_F64>   { using S = double2; using A = double2; static constexpr int NP = 1; };
+
+// Sample arithmetic used by the block average (sum in push order, then / m).
+__device__ __forceinline__ float sadd(float a, float b) { return a + b; }
+__device__ __forceinline__ double sadd(double a, double b) { return a + b; }
+__device__ __forceinline__ float2 sadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 sadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float sdiv(float a, int m) { return a / (float)m; }
+__device__ __forceinline__ double sdiv(double a, int m) { return a / (double)m; }
+__device__ __forceinline__ float2 sdiv(float2 a, int m) { return make_float2(a.x / (float)m, a.y / (float)m); }
+__device__ __forceinline__ double2 sdiv(double2 a, int m) { return make_double2(a.x / (double)m, a.y / (double)m); }
+template <typename S> __device__ __forceinline__ S szero();
+template <> __device__ __forceinline__ float szero<float>() { return 0.0f; }
+template <> __device__ __forceinline__ double szero<double>() { return 0.0; }
+template <> __device__ __forceinline__ float2 szero<float2>() { return make_float2(0.0f, 0.0f); }
+template <> __device__ __forceinline__ double2 szero<double2>() { return make_double2(0.0, 0.0); }
+
+// sum += x * conj(r) in the accumulator precision of kind K.  The compensated
+// form is Kahan summation with the product folded into the first step:
+// y = x*r - c (one rounding), t = h + y, c = (t - h) - y, h = t; the true sum is
+// h - c.
+template <int K> struct Acc;
+template <> struct Acc<K_F32_F64> {
+    static __device__ __forceinline__ void add(double &h, double &, float x, float r)
+    { h = __builtin_fma((double)x, (double)r, h); }
+};
+template <> struct Acc<K_F32_KAHAN> {
+    static __device__ __forceinline__ void add(float &h, float &c, float x, float r)
+    {
+        float y = __builtin_fmaf(x, r, -c);
+        float t = h + y;
+        c = (t - h) - y;
+        h = t;
+    }
+};
+template <> struct Acc<K_F32_F32> {
+    static __device__ __forceinline__ void add(float &h, float &, float x, float r)
+    { h = __builtin_fmaf(x, r, h); }
+};
+template <> struct Acc<K_F64_F64> {
+    static __device__ __forceinline__ void add(double &h, double &, double x, double r)
+    { h = __builtin_fma(x, r, h); }
+};
+template <> struct Acc<K_CF32_F64> {
+    static __device__ __forceinline__ void add(double2 &h, double2 &, float2 x, float2 r)
+    {
+        const double xr = x.x, xi = x.y, rr = r.x, ri = r.y;
+        h.x = __builtin_fma(xr, rr, __builtin_fma(xi, ri, h.x));
+        h.y = __builtin_fma(xi, rr, __builtin_fma(-xr, ri, h.y));
+    }
+};
+template <> struct Acc<K_CF32_KAHAN> {
+    static __device__ __forceinline__ void add(float2 &h, float2 &c, float2 x, float2 r)
+    {
+        float yr = __builtin_fmaf(x.x, r.x, __builtin_fmaf(x.y, r.y, -c.x));
+        float yi = __builtin_fmaf(x.y, r.x, __builtin_fmaf(-x.x, r.y, -c.y));
+        float tr = h.x + yr;
+        float ti = h.y + yi;
+        c.x = (tr - h.x) - yr;
+        c.y = (ti - h.y) - yi;
+        h.x = tr;
+        h.y = ti;
+    }
+};
+template <> struct Acc<K_CF32_F32> {
+    static __device__ __forceinline__ void add(float2 &h, float2 &, float2 x, float2 r)
+    {
+        h.x = __builtin_fmaf(x.x, r.x, __builtin_fmaf(x.y, r.y, h.x));
+        h.y = __builtin_fmaf(x.y, r.x, __builtin_fmaf(-x.x, r.y, h.y));
+    }
+};
+template <> struct Acc<K_CF64_F64> {
+    static __device__ __forceinline__ void add(double2 &h, double2 &, double2 x, double2 r)
+    {
+        h.x = __builtin_fma(x.x, r.x, __builtin_fma(x.y, r.y, h.x));
+        h.y = __builtin_fma(x.y, r.x, __builtin_fma(-x.x, r.y, h.y));
+    }
+};
+
+// NJ consecutive lags [L0, L0 + NJ) of one level, branch-free: all loads of
+// the chunk are issued before any arithmetic so that each lane has many
+// independent memory requests in flight.  Lag L reads ring slot
+// (slot - L) mod p; lag 0 (newest value times itself) takes x from registers.
+template <int K, int CPT, int NJ>
+__device__ __forceinline__ void lag_chunk(const typename KT<K>::S (&x)[CPT],
+                                          const typename KT<K>::S *ring, typename KT<K>::A *hi,
+                                          typename KT<K>::A *lo, int slot, int p, int L0,
+                                          int row_base, int tw, int lane_off)
+{
+    using S = typename KT<K>::S;
+    using A = typename KT<K>::A;
+    constexpr int NP = KT<K>::NP;
+    S r[NJ][CPT];
+    A h[NJ][CPT];
+    A c[NJ][CPT];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        int sl = slot - (L0 + j);
+        if (sl < 0) sl += p;
+        vload<S, CPT>(ring + (size_t)sl * tw + lane_off, r[j]);
+        const size_t ro = (size_t)(L0 + j - row_base) * tw + lane_off;
+        vload<A, CPT>(hi + ro, h[j]);
+        if constexpr (NP == 2) vload<A, CPT>(lo + ro, c[j]);
+    }
+    if (L0 == 0) {
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) r[0][i] = x[i];
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) Acc<K>::add(h[j][i], c[j][i], x[i], r[j][i]);
+        const size_t ro = (size_t)(L0 + j - row_base) * tw + lane_off;
+        vstore<A, CPT>(hi + ro, h[j]);
+        if constexpr (NP == 2) vstore<A, CPT>(lo + ro, c[j]);
+    }
+}
+
+// Lag loop of one level: lags [l_begin, l_end), accumulator row L - row_base.
+// Full chunks of LCH lags, then chunks of 4, then single lags.
+template <int K, int CPT, int LCH>
+__device__ __forceinline__ void lag_loop(const typename KT<K>::S (&x)[CPT],
+                                         const typename KT<K>::S *ring, typename KT<K>::A *hi,
+                                         typename KT<K>::A *lo, int slot, int p, int l_begin,
+                                         int l_end, int row_base, int tw, int lane_off)
+{
+    int L = l_begin;
+#pragma unroll 1
+    for (; L + LCH <= l_end; L += LCH)
+        lag_chunk<K, CPT, LCH>(x, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
+    if constexpr (LCH > 4) {
+#pragma unroll 1
+        for (; L + 4 <= l_end; L += 4)
+            lag_chunk<K, CPT, 4>(x, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
+    }
+#pragma unroll 1
+    for (; L < l_end; ++L)
+        lag_chunk<K, CPT, 1>(x, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
+}
+
+// One push of one tile of one group.  s = 1-based push index.
+template <int K, int CPT, int LCH>
+__device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int64_t s)
+{
+    using S = typename KT<K>::S;
+    using A = typename KT<K>::A;
+    const int tw = g.tw;
+    const int p = g.p;
+    const int m = g.m;
+    const int lane_off = (int)threadIdx.x * CPT;
+    const int64_t ch0 = tile * (int64_t)tw + lane_off;
+
+    // Samples of this push; channels past the end of the group read as 0 (the
+    // state of the padded tail is allocated and never read out).
+    S x[CPT];
+    const S *src = static_cast<const S *>(g.samples);
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) x[i] = (ch0 + i < g.n_ch) ? src[ch0 + i] : szero<S>();
+
+    char *tb = g.state + tile * g.tile_bytes;
+    const int64_t rowS = (int64_t)tw * (int64_t)sizeof(S);
+
+    // Level 0: ring write and lags 0..min(s, p)-1.
+    {
+        S *ring = reinterpret_cast<S *>(tb);
+        A *hi = reinterpret_cast<A *>(tb + (int64_t)p * rowS);
+        A *lo = hi + (size_t)p * tw;
+        const int slot = (int)((s - 1) % p);
+        vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, x);
+        const int nlag = (int)(s < p ? s : p);
+        lag_loop<K, CPT, LCH>(x, ring, hi, lo, slot, p, 0, nlag, 0, tw, lane_off);
+    }
+
+    // Cascade: level k receives a value when m^k divides s.
+    int kmax = 0;
+    {
+        int64_t q = s;
+        while (kmax < g.levels - 1 && q % m == 0) {
+            q /= m;
+            ++kmax;
+        }
+    }
+    S vprev[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) vprev[i] = x[i];
+    int64_t s_prev = s;
+    const char *lvl_prev = tb;
+    const int lag0 = g.lag0;
+    const int nlk = p - lag0;
+#pragma unroll 1
+    for (int k = 1; k <= kmax; ++k) {
+        // Mean of the last m values of level k-1, summed oldest first.
+        const S *ringp = reinterpret_cast<const S *>(lvl_prev);
+        const int slotp = (int)((s_prev - 1) % p);
+        S v[CPT];
+        {
+            int sl = slotp - (m - 1);
+            if (sl < 0) sl += p;
+            vload<S, CPT>(ringp + (size_t)sl * tw + lane_off, v);
+#pragma unroll 1
+            for (int j = m - 2; j >= 1; --j) {
+                int sj = slotp - j;
+                if (sj < 0) sj += p;
+                S t[CPT];
+                vload<S, CPT>(ringp + (size_t)sj * tw + lane_off, t);
+#pragma unroll
+                for (int i = 0; i < CPT; ++i) v[i] = sadd(v[i], t[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) v[i] = sdiv(sadd(v[i], vprev[i]), m);
+        }
+        char *lvl = tb + g.lvl0_bytes + (int64_t)(k - 1) * g.lvlk_bytes;
+        S *ring = reinterpret_cast<S *>(lvl);
+        A *hi = reinterpret_cast<A *>(lvl + (int64_t)p * rowS);
+        A *lo = hi + (size_t)nlk * tw;
+        const int64_t sk = s_prev / m;
+        const int slot = (int)((sk - 1) % p);
+        vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, v);
+        const int nl = (int)(sk < p ? sk : p);
+        if (nl > lag0) lag_loop<K, CPT, LCH>(v, ring, hi, lo, slot, p, lag0, nl, lag0, tw, lane_off);
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) vprev[i] = v[i];
+        s_prev = sk;
+        lvl_prev = lvl;
+    }
+}
+
+template <int CPT, int LCH>
+__device__ __forceinline__ void dispatch_tile(const GroupArgs &g, int64_t tile, int64_t s)
+{
+    switch (g.kind) {
+    case K_F32_F64: push_tile<K_F32_F64, CPT, LCH>(g, tile, s); break;
+    case K_F32_KAHAN: push_tile<K_F32_KAHAN, CPT, LCH>(g, tile, s); break;
+    case K_F32_F32: push_tile<K_F32_F32, CPT, LCH>(g, tile, s); break;
+    case K_F64_F64: push_tile<K_F64_F64, CPT, LCH>(g, tile, s); break;
+    case K_CF32_F64: push_tile<K_CF32_F64, CPT, LCH>(g, tile, s); break;
+    case K_CF32_KAHAN: push_tile<K_CF32_KAHAN, CPT, LCH>(g, tile, s); break;
+    case K_CF32_F32: push_tile<K_CF32_F32, CPT, LCH>(g, tile, s); break;
+    default: push_tile<K_CF64_F64, CPT, LCH>(g, tile, s); break;
+    }
+}
+
+// Batched form: every group of the context in one launch.  Blocks stride over
+// the concatenated tile space of all groups (a persistent grid when
+// gridDim.x is smaller than the number of tiles).
+template <int CPT, int LCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void push_batched_kernel(PushArgs a)
+{
+    const int64_t s = *a.step + 1;
+#pragma unroll 1
+    for (int64_t t = blockIdx.x; t < a.total_tiles; t += gridDim.x) {
+        int gi = 0;
+        while (gi + 1 < a.n_groups && t >= a.g[gi + 1].tile_first) ++gi;
+        // Copy the group's arguments with constant indices (keeps them in
+        // scalar registers instead of a private copy of the whole table).
+        GroupArgs g;
+        switch (gi) {
+        case 0: g = a.g[0]; break;
+        case 1: g = a.g[1]; break;
+        case 2: g = a.g[2]; break;
+        case 3: g = a.g[3]; break;
+        case 4: g = a.g[4]; break;
+        case 5: g = a.g[5]; break;
+        case 6: g = a.g[6]; break;
+        default: g = a.g[7]; break;
+        }
+        dispatch_tile<CPT, LCH>(g, t - g.tile_first, s);
+    }
+}
+
+// Plain form: one group per launch, one block per tile, kind fixed at compile time.
+template <int K, int CPT, int LCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void push_group_kernel(GroupArgs g, const int64_t *step)
+{
+    const int64_t s = *step + 1;
+    push_tile<K, CPT, LCH>(g, (int64_t)blockIdx.x, s);
+}
+
+__global__ void step_increment_kernel(int64_t *step)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step = *step + 1;
+}
+
+// ------------------------------------------------------------ host launchers
+template <int CPT, int LCH>
+static hipError_t launch_batched_t(const PushArgs &a, int grid, int block, hipStream_t st)
+{
+    hipLaunchKernelGGL((push_batched_kernel<CPT, LCH>), dim3(grid), dim3(block), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_push_batched(const PushArgs &a, int cpt, int lch, int grid, int block,
+                               hipStream_t st)
+{
+    if (cpt == 1 && lch == 16) return launch_batched_t<1, 16>(a, grid, block, st);
+    if (cpt == 1 && lch == 8) return launch_batched_t<1, 8>(a, grid, block, st);
+    if (cpt == 2 && lch == 8) return launch_batched_t<2, 8>(a, grid, block, st);
+    if (cpt == 2 && lch == 4) return launch_batched_t<2, 4>(a, grid, block, st);
+    if (cpt == 4 && lch == 4) return launch_batched_t<4, 4>(a, grid, block, st);
+    if (cpt == 4 && lch == 8) return launch_batched_t<4, 8>(a, grid, block, st);
+    return hipErrorInvalidValue;
+}
+
+template <int CPT, int LCH>
+static hipError_t launch_group_t(const GroupArgs &g, const int64_t *step, int block,
+                                 hipStream_t st)
+{
+    const dim3 grid((unsigned)g.n_tiles);
+    switch (g.kind) {
+    case K_F32_F64: hipLaunchKernelGGL((push_group_kernel<K_F32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
+    case K_F32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_F32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
+    case K_F32_F32: hipLaunchKernelGGL((push_group_kernel<K_F32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
+    case K_F64_F64: hipLaunchKernelGGL((push_group_kernel<K_F64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
+    case K_CF32_F64: hipLaunchKernelGGL((push_group_kernel<K_CF32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
+    case K_CF32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_CF32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
+    case K_CF32_F32: hipLaunchKernelGGL((push_group_kernel<K_CF32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
+    default: hipLaunchKernelGGL((push_group_kernel<K_CF64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_push_group(const GroupArgs &g, const int64_t *step, int cpt, int lch, int block,
+                             hipStream_t st)
+{
+    if (cpt == 1 && lch == 16) return launch_group_t<1, 16>(g, step, block, st);
+    if (cpt == 1 && lch == 8) return launch_group_t<1, 8>(g, step, block, st);
+    if (cpt == 2 && lch == 8) return launch_group_t<2, 8>(g, step, block, st);
+    if (cpt == 2 && lch == 4) return launch_group_t<2, 4>(g, step, block, st);
+    if (cpt == 4 && lch == 4) return launch_group_t<4, 4>(g, step, block, st);
+    if (cpt == 4 && lch == 8) return launch_group_t<4, 8>(g, step, block, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_increment(int64_t *step, hipStream_t st)
+{
+    hipLaunchKernelGGL(step_increment_kernel, dim3(1), dim3(64), 0, st, step);
+    return hipGetLastError();
+}
+
+} // namespace corr

@@ -1,0 +1,802 @@
+// corr_runtime.cpp -- host side of the correlator library: the C ABI of
+// include/corr.h, the state layout planner, push orchestration (batched or
+// per-group launches, optional HIP graph), and the readout (Algorithm 2 of
+// the paper's Appendix D) with the trapezoid Green-Kubo integrals (Section
+// 2.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/corr.h"
+#include "corr_kernels.h"
+
+using namespace corr;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Group {
+    corr_group_desc d{};
+    int kind = 0;
+    int p = 0, m = 0, b = 0, lag0 = 0, nlk = 0;
+    int s_bytes = 0, a_bytes = 0, np = 1;
+    int64_t n_ch = 0, n_tiles = 0, tile_bytes = 0, lvl0_bytes = 0, lvlk_bytes = 0;
+    char *state = nullptr;
+    void *input = nullptr;     // buffer read when a push passes NULL (own or bound)
+    void *own_input = nullptr; // the library's own input allocation
+    size_t input_bytes = 0;
+    // k-density producer
+    bool rhok = false;
+    void *rhok_out = nullptr;
+    int32_t *d_kq = nullptr;
+    int32_t *d_kperm = nullptr;
+    double *d_partial = nullptr;
+    RhokArgs rargs{};
+};
+
+} // namespace
+
+struct corr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0;
+    corr_tuning tuning{};
+    std::vector<Group> groups;
+    int64_t *d_step = nullptr;
+    int64_t n_push = 0;
+    PushArgs pargs{};
+    int64_t total_tiles = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    // push-kernel timing (CORR_FLAG_TIMING)
+    std::vector<hipEvent_t> ev_start, ev_end;
+    size_t ev_used = 0;
+    double timed_ms = 0.0;
+    int64_t timed_pushes = 0;
+    // readout scratch
+    void *d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+    std::string err;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int set_err(corr_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+int hip_err(corr_ctx *c, hipError_t e, const char *what)
+{
+    return set_err(c, e == hipErrorOutOfMemory ? CORR_E_OOM : CORR_E_DEVICE, "%s: %s (%d)", what,
+                   hipGetErrorString(e), (int)e);
+}
+
+#define HIP_TRY(ctx, expr)                                                                       \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return hip_err((ctx), e_, #expr);                                  \
+    } while (0)
+
+int kind_of(int dtype, int accum)
+{
+    switch (dtype) {
+    case CORR_F32:
+        return accum == CORR_ACC_F64 ? K_F32_F64 : accum == CORR_ACC_KAHAN_F32 ? K_F32_KAHAN
+                                                                                : K_F32_F32;
+    case CORR_F64: return K_F64_F64;
+    case CORR_CF32:
+        return accum == CORR_ACC_F64 ? K_CF32_F64 : accum == CORR_ACC_KAHAN_F32 ? K_CF32_KAHAN
+                                                                                 : K_CF32_F32;
+    default: return K_CF64_F64;
+    }
+}
+
+int validate(const corr_group_desc &g, int idx)
+{
+    auto bad = [&](const char *why) {
+        return set_err(nullptr, CORR_E_INVALID, "group %d: %s", idx, why);
+    };
+    if (g.n_channels < 1) return bad("n_channels must be >= 1");
+    if (g.levels < 1) return bad("levels (b) must be >= 1");
+    if (g.points < 2) return bad("points (p) must be >= 2");
+    if (g.m < 2) return bad("m must be >= 2");
+    if (g.m >= g.points) return bad("m must be < p");
+    if (g.update_every < 1) return bad("update_every must be >= 1");
+    if (g.dtype < CORR_F32 || g.dtype > CORR_CF64) return bad("unknown dtype");
+    if (g.accum < CORR_ACC_F64 || g.accum > CORR_ACC_F32) return bad("unknown accumulator");
+    if (g.source != CORR_SRC_SAMPLES && g.source != CORR_SRC_RHOK) return bad("unknown source");
+    if ((g.dtype == CORR_F64 || g.dtype == CORR_CF64) && g.accum != CORR_ACC_F64)
+        return bad("double samples need double accumulators");
+    if (g.source == CORR_SRC_RHOK) {
+        if (g.dtype != CORR_CF32 && g.dtype != CORR_CF64) return bad("k-density needs a complex dtype");
+        if (!g.kvec) return bad("k-density group without k-vectors");
+        if (g.n_atoms < 1) return bad("k-density group needs n_atoms >= 1");
+        if (!(g.box > 0.0)) return bad("k-density group needs box > 0");
+        for (int64_t q = 0; q < g.n_channels; ++q)
+            for (int d = 0; d < 3; ++d)
+                if (g.kvec[3 * q + d] > 64 || g.kvec[3 * q + d] < -64)
+                    return set_err(nullptr, CORR_E_UNSUPPORTED,
+                                   "group %d: k-vector components beyond +-64", idx);
+    }
+    if (g.points > 4096) return set_err(nullptr, CORR_E_UNSUPPORTED, "group %d: p > 4096", idx);
+    if (g.levels > 40) return set_err(nullptr, CORR_E_UNSUPPORTED, "group %d: b > 40", idx);
+    return CORR_OK;
+}
+
+int validate_tuning(const corr_tuning &t)
+{
+    const int cpt = t.chans_per_thread, lch = t.lag_chunk;
+    const bool pair_ok = (cpt == 1 && (lch == 16 || lch == 8)) || (cpt == 2 && (lch == 8 || lch == 4)) ||
+                         (cpt == 4 && (lch == 4 || lch == 8));
+    if (!pair_ok)
+        return set_err(nullptr, CORR_E_INVALID, "tuning: unsupported (chans_per_thread, lag_chunk) = (%d, %d)",
+                       cpt, lch);
+    if (t.tile_channels < 64 || t.tile_channels > 4096 || t.tile_channels % (64 * cpt) != 0 ||
+        t.tile_channels / cpt > 1024)
+        return set_err(nullptr, CORR_E_INVALID, "tuning: tile_channels %d invalid for %d channels/thread",
+                       t.tile_channels, cpt);
+    if (t.grid_blocks < 0) return set_err(nullptr, CORR_E_INVALID, "tuning: grid_blocks < 0");
+    return CORR_OK;
+}
+
+void free_group(Group &g)
+{
+    if (g.state) (void)hipFree(g.state);
+    if (g.own_input) (void)hipFree(g.own_input);
+    if (g.rhok_out) (void)hipFree(g.rhok_out);
+    if (g.d_kq) (void)hipFree(g.d_kq);
+    if (g.d_kperm) (void)hipFree(g.d_kperm);
+    if (g.d_partial) (void)hipFree(g.d_partial);
+    g = Group{};
+}
+
+void free_ctx(corr_ctx *c)
+{
+    if (!c) return;
+    DeviceGuard dg(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (auto &g : c->groups) free_group(g);
+    if (c->d_step) (void)hipFree(c->d_step);
+    if (c->d_scratch) (void)hipFree(c->d_scratch);
+    for (auto e : c->ev_start) (void)hipEventDestroy(e);
+    for (auto e : c->ev_end) (void)hipEventDestroy(e);
+    delete c;
+}
+
+constexpr size_t kEventPool = 1024;
+
+// Fold the elapsed times of all recorded event pairs into the total.
+int fold_events(corr_ctx *c)
+{
+    if (c->ev_used == 0) return CORR_OK;
+    HIP_TRY(c, hipEventSynchronize(c->ev_end[c->ev_used - 1]));
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_start[i], c->ev_end[i]));
+        c->timed_ms += (double)ms;
+    }
+    c->timed_pushes += (int64_t)c->ev_used;
+    c->ev_used = 0;
+    return CORR_OK;
+}
+
+// Next free event pair (folds the pool when it is full).
+int next_events(corr_ctx *c, hipEvent_t *a, hipEvent_t *b)
+{
+    if (c->ev_used == kEventPool) {
+        int rc = fold_events(c);
+        if (rc != CORR_OK) return rc;
+    }
+    if (c->ev_used == c->ev_start.size()) {
+        hipEvent_t e0, e1;
+        HIP_TRY(c, hipEventCreate(&e0));
+        HIP_TRY(c, hipEventCreate(&e1));
+        c->ev_start.push_back(e0);
+        c->ev_end.push_back(e1);
+    }
+    *a = c->ev_start[c->ev_used];
+    *b = c->ev_end[c->ev_used];
+    c->ev_used += 1;
+    return CORR_OK;
+}
+
+// Issue one push of every group on stream `st` with the given per-group
+// sample pointers (already resolved, never NULL).
+int issue_push(corr_ctx *c, const void *const *src, hipStream_t st)
+{
+    PushArgs a = c->pargs;
+    for (size_t i = 0; i < c->groups.size(); ++i) {
+        Group &g = c->groups[i];
+        if (g.rhok) {
+            RhokArgs ra = g.rargs;
+            ra.pos = static_cast<const float *>(src[i]);
+            HIP_TRY(c, launch_rhok(ra, st));
+            a.g[i].samples = g.rhok_out;
+        } else {
+            a.g[i].samples = src[i];
+        }
+    }
+    const int cpt = c->tuning.chans_per_thread, lch = c->tuning.lag_chunk;
+    const int block = c->tuning.tile_channels / cpt;
+    // Events are only recorded on direct launches, never while capturing.
+    const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        int rc = next_events(c, &e0, &e1);
+        if (rc != CORR_OK) return rc;
+        HIP_TRY(c, hipEventRecord(e0, st));
+    }
+    if (c->flags & CORR_FLAG_PER_GROUP) {
+        for (int i = 0; i < a.n_groups; ++i)
+            HIP_TRY(c, launch_push_group(a.g[i], c->d_step, cpt, lch, block, st));
+    } else {
+        int64_t grid = c->tuning.grid_blocks > 0 ? c->tuning.grid_blocks : a.total_tiles;
+        grid = std::min<int64_t>(grid, a.total_tiles);
+        grid = std::min<int64_t>(grid, 0x7fffffff);
+        HIP_TRY(c, launch_push_batched(a, cpt, lch, (int)grid, block, st));
+    }
+    if (timed) HIP_TRY(c, hipEventRecord(e1, st));
+    HIP_TRY(c, launch_step_increment(c->d_step, st));
+    return CORR_OK;
+}
+
+// (Re)capture one push of every group, reading the current input buffers,
+// into c->gexec.
+int capture_graph(corr_ctx *c)
+{
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    std::vector<const void *> src(c->groups.size());
+    for (size_t i = 0; i < c->groups.size(); ++i) src[i] = c->groups[i].input;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = issue_push(c, src.data(), c->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc != CORR_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ec != hipSuccess) return hip_err(c, ec, "hipStreamEndCapture");
+    c->graph = graph;
+    HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    return CORR_OK;
+}
+
+int ensure_scratch(corr_ctx *c, size_t bytes)
+{
+    if (c->scratch_bytes >= bytes) return CORR_OK;
+    if (c->d_scratch) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        (void)hipFree(c->d_scratch);
+        c->d_scratch = nullptr;
+        c->scratch_bytes = 0;
+    }
+    HIP_TRY(c, hipMalloc(&c->d_scratch, bytes));
+    c->scratch_bytes = bytes;
+    return CORR_OK;
+}
+
+struct Entry {
+    int level, lag;
+    int64_t count;
+    int64_t hi_off, lo_off;
+};
+
+} // namespace
+
+extern "C" {
+
+const char *corr_last_error(const corr_ctx *ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device, void *stream,
+                uint32_t flags, const corr_tuning *tuning, corr_ctx **out)
+{
+    g_create_error.clear();
+    if (!out) return set_err(nullptr, CORR_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!groups || n_groups < 1) return set_err(nullptr, CORR_E_INVALID, "need at least one group");
+    if (n_groups > kMaxGroups)
+        return set_err(nullptr, CORR_E_UNSUPPORTED, "at most %d groups per context", kMaxGroups);
+    if (flags & ~(uint32_t)(CORR_FLAG_GRAPH | CORR_FLAG_PER_GROUP | CORR_FLAG_TIMING))
+        return set_err(nullptr, CORR_E_INVALID, "unknown flags 0x%x", flags);
+    for (int i = 0; i < n_groups; ++i) {
+        int rc = validate(groups[i], i);
+        if (rc != CORR_OK) return rc;
+    }
+    corr_tuning tn{512, 2, 8, 0};
+    if (tuning && (tuning->tile_channels || tuning->chans_per_thread || tuning->lag_chunk ||
+                   tuning->grid_blocks)) {
+        tn = *tuning;
+        if (!tn.chans_per_thread) tn.chans_per_thread = 2;
+        if (!tn.lag_chunk) tn.lag_chunk = tn.chans_per_thread == 1 ? 16 : tn.chans_per_thread == 2 ? 8 : 4;
+        if (!tn.tile_channels) tn.tile_channels = 256 * tn.chans_per_thread;
+    }
+    {
+        int rc = validate_tuning(tn);
+        if (rc != CORR_OK) return rc;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return set_err(nullptr, CORR_E_DEVICE, "device %d not available (%d devices)", device, ndev);
+
+    corr_ctx *c = new (std::nothrow) corr_ctx();
+    if (!c) return set_err(nullptr, CORR_E_OOM, "host allocation failed");
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->flags = flags;
+    c->tuning = tn;
+    DeviceGuard dg(device);
+
+    auto fail = [&](int rc) {
+        g_create_error = c->err;
+        free_ctx(c);
+        return rc;
+    };
+#define CREATE_HIP(expr)                                                                         \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail(hip_err(c, e_, #expr));                                \
+    } while (0)
+
+    const int tw = tn.tile_channels;
+    c->groups.resize((size_t)n_groups);
+    int64_t tile_first = 0;
+    for (int i = 0; i < n_groups; ++i) {
+        Group &g = c->groups[(size_t)i];
+        g.d = groups[i];
+        g.d.kvec = nullptr;
+        g.kind = kind_of(g.d.dtype, g.d.accum);
+        g.p = g.d.points;
+        g.m = g.d.m;
+        g.b = g.d.levels;
+        g.lag0 = g.p / g.m;
+        g.nlk = g.p - g.lag0;
+        g.s_bytes = kind_sample_bytes(g.kind);
+        g.a_bytes = kind_acc_bytes(g.kind);
+        g.np = acc_planes(g.kind);
+        g.n_ch = g.d.n_channels;
+        g.n_tiles = (g.n_ch + tw - 1) / tw;
+        const int64_t rowS = (int64_t)tw * g.s_bytes;
+        const int64_t rowA = (int64_t)tw * g.a_bytes;
+        g.lvl0_bytes = g.p * rowS + (int64_t)g.np * g.p * rowA;
+        g.lvlk_bytes = g.p * rowS + (int64_t)g.np * g.nlk * rowA;
+        g.tile_bytes = g.lvl0_bytes + (int64_t)(g.b - 1) * g.lvlk_bytes;
+        const size_t state_bytes = (size_t)g.n_tiles * (size_t)g.tile_bytes;
+        CREATE_HIP(hipMalloc(&g.state, state_bytes));
+        CREATE_HIP(hipMemsetAsync(g.state, 0, state_bytes, c->stream));
+
+        g.rhok = g.d.source == CORR_SRC_RHOK;
+        if (g.rhok) {
+            g.input_bytes = (size_t)3 * (size_t)g.d.n_atoms * sizeof(float);
+            const int nk = (int)g.n_ch;
+            // Sort k-vectors by (nz, ny, nx) so that neighbouring threads read
+            // neighbouring table entries; kperm maps back to the caller's order.
+            std::vector<int> order((size_t)nk);
+            for (int q = 0; q < nk; ++q) order[(size_t)q] = q;
+            const int32_t *kv = groups[i].kvec;
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+                for (int d = 2; d >= 0; --d)
+                    if (kv[3 * x + d] != kv[3 * y + d]) return kv[3 * x + d] < kv[3 * y + d];
+                return false;
+            });
+            std::vector<int32_t> kq((size_t)nk * 3), kperm((size_t)nk);
+            int nmax = 0;
+            for (int q = 0; q < nk; ++q) {
+                for (int d = 0; d < 3; ++d) {
+                    kq[(size_t)q * 3 + d] = kv[3 * order[(size_t)q] + d];
+                    nmax = std::max(nmax, std::abs(kv[3 * order[(size_t)q] + d]));
+                }
+                kperm[(size_t)q] = order[(size_t)q];
+            }
+            CREATE_HIP(hipMalloc(&g.d_kq, kq.size() * sizeof(int32_t)));
+            CREATE_HIP(hipMalloc(&g.d_kperm, kperm.size() * sizeof(int32_t)));
+            CREATE_HIP(hipMemcpy(g.d_kq, kq.data(), kq.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            CREATE_HIP(hipMemcpy(g.d_kperm, kperm.data(), kperm.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice));
+            const int n_chunks = (nk + 255) / 256;
+            // Enough atom blocks to give every compute unit several blocks.
+            int n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(1024 / n_chunks, (g.d.n_atoms + 255) / 256));
+            n_ab = std::max(n_ab, 1);
+            const int64_t apb = (g.d.n_atoms + n_ab - 1) / n_ab;
+            CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * nk * 2 * sizeof(double)));
+            CREATE_HIP(hipMalloc(&g.rhok_out, (size_t)nk * g.s_bytes));
+            CREATE_HIP(hipMemsetAsync(g.rhok_out, 0, (size_t)nk * g.s_bytes, c->stream));
+            RhokArgs &r = g.rargs;
+            r.pos = nullptr;
+            r.n_atoms = g.d.n_atoms;
+            r.kq = g.d_kq;
+            r.kperm = g.d_kperm;
+            r.nk = nk;
+            r.n_chunks = n_chunks;
+            r.inv_box = 1.0 / g.d.box;
+            r.partial = g.d_partial;
+            r.n_atom_blocks = n_ab;
+            r.atoms_per_block = (int32_t)apb;
+            r.out = g.rhok_out;
+            r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
+            r.nmax = nmax;
+        } else {
+            g.input_bytes = (size_t)g.n_ch * g.s_bytes;
+        }
+        CREATE_HIP(hipMalloc(&g.own_input, g.input_bytes));
+        CREATE_HIP(hipMemsetAsync(g.own_input, 0, g.input_bytes, c->stream));
+        g.input = g.own_input;
+
+        GroupArgs &ga = c->pargs.g[i];
+        ga.samples = nullptr;
+        ga.state = g.state;
+        ga.n_ch = g.n_ch;
+        ga.n_tiles = g.n_tiles;
+        ga.tile_first = tile_first;
+        ga.tile_bytes = g.tile_bytes;
+        ga.lvl0_bytes = g.lvl0_bytes;
+        ga.lvlk_bytes = g.lvlk_bytes;
+        ga.kind = g.kind;
+        ga.p = g.p;
+        ga.m = g.m;
+        ga.levels = g.b;
+        ga.lag0 = g.lag0;
+        ga.tw = tw;
+        ga.s_bytes = g.s_bytes;
+        ga.a_bytes = g.a_bytes;
+        tile_first += g.n_tiles;
+    }
+    c->pargs.n_groups = n_groups;
+    c->pargs.total_tiles = tile_first;
+    c->total_tiles = tile_first;
+    CREATE_HIP(hipMalloc(&c->d_step, sizeof(int64_t)));
+    CREATE_HIP(hipMemsetAsync(c->d_step, 0, sizeof(int64_t), c->stream));
+    c->pargs.step = c->d_step;
+    CREATE_HIP(hipStreamSynchronize(c->stream));
+
+    if (flags & CORR_FLAG_GRAPH) {
+        CREATE_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        int rc = capture_graph(c);
+        if (rc != CORR_OK) return fail(rc);
+    }
+#undef CREATE_HIP
+    *out = c;
+    return CORR_OK;
+}
+
+int corr_input_buffer(corr_ctx *ctx, int32_t group, void **dev_ptr, size_t *bytes)
+{
+    if (!ctx) return CORR_E_INVALID;
+    if (group < 0 || group >= (int)ctx->groups.size())
+        return set_err(ctx, CORR_E_INVALID, "group %d out of range", group);
+    if (dev_ptr) *dev_ptr = ctx->groups[(size_t)group].input;
+    if (bytes) *bytes = ctx->groups[(size_t)group].input_bytes;
+    return CORR_OK;
+}
+
+int corr_bind_input(corr_ctx *ctx, int32_t group, void *dev_ptr, size_t bytes)
+{
+    if (!ctx) return CORR_E_INVALID;
+    if (group < 0 || group >= (int)ctx->groups.size())
+        return set_err(ctx, CORR_E_INVALID, "group %d out of range", group);
+    Group &g = ctx->groups[(size_t)group];
+    if (dev_ptr && bytes < g.input_bytes)
+        return set_err(ctx, CORR_E_INVALID, "bound buffer has %zu bytes, group needs %zu", bytes,
+                       g.input_bytes);
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    g.input = dev_ptr ? dev_ptr : g.own_input;
+    if (ctx->flags & CORR_FLAG_GRAPH) return capture_graph(ctx);
+    return CORR_OK;
+}
+
+int corr_push(corr_ctx *ctx, const void *const *samples)
+{
+    if (!ctx) return CORR_E_INVALID;
+    DeviceGuard dg(ctx->device);
+    const size_t ng = ctx->groups.size();
+    std::vector<const void *> src(ng);
+    bool all_default = true;
+    for (size_t i = 0; i < ng; ++i) {
+        const void *p = samples ? samples[i] : nullptr;
+        if (!p) p = ctx->groups[i].input;
+        if (p != ctx->groups[i].input) all_default = false;
+        src[i] = p;
+    }
+    if (ctx->gexec && all_default) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (ctx->flags & CORR_FLAG_TIMING) {
+            int rc = next_events(ctx, &e0, &e1);
+            if (rc != CORR_OK) return rc;
+            HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+        }
+        HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+        if (e1) HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+    } else {
+        int rc = issue_push(ctx, src.data(), ctx->stream);
+        if (rc != CORR_OK) return rc;
+    }
+    ctx->n_push += 1;
+    return CORR_OK;
+}
+
+int corr_query(const corr_ctx *ctx, int32_t group, int64_t *n_pushes, int32_t *n_out_max)
+{
+    if (!ctx) return CORR_E_INVALID;
+    if (group < 0 || group >= (int)ctx->groups.size()) return CORR_E_INVALID;
+    const Group &g = ctx->groups[(size_t)group];
+    if (n_pushes) *n_pushes = ctx->n_push;
+    if (n_out_max) *n_out_max = g.p + (g.b - 1) * g.nlk;
+    return CORR_OK;
+}
+
+int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes)
+{
+    if (!ctx || !bytes) return CORR_E_INVALID;
+    if (group < 0 || group >= (int)ctx->groups.size()) return CORR_E_INVALID;
+    const Group &g = ctx->groups[(size_t)group];
+    *bytes = g.n_tiles * g.tile_bytes;
+    return CORR_OK;
+}
+
+int corr_kernel_time(corr_ctx *ctx, double *ms_total, int64_t *n_pushes, int32_t reset)
+{
+    if (!ctx) return CORR_E_INVALID;
+    if (!(ctx->flags & CORR_FLAG_TIMING))
+        return set_err(ctx, CORR_E_STATE, "context created without CORR_FLAG_TIMING");
+    DeviceGuard dg(ctx->device);
+    int rc = fold_events(ctx);
+    if (rc != CORR_OK) return rc;
+    if (ms_total) *ms_total = ctx->timed_ms;
+    if (n_pushes) *n_pushes = ctx->timed_pushes;
+    if (reset) {
+        ctx->timed_ms = 0.0;
+        ctx->timed_pushes = 0;
+    }
+    return CORR_OK;
+}
+
+int corr_get_tuning(const corr_ctx *ctx, corr_tuning *out)
+{
+    if (!ctx || !out) return CORR_E_INVALID;
+    *out = ctx->tuning;
+    return CORR_OK;
+}
+
+int corr_sync(corr_ctx *ctx)
+{
+    if (!ctx) return CORR_E_INVALID;
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return CORR_OK;
+}
+
+int corr_destroy(corr_ctx *ctx)
+{
+    if (!ctx) return CORR_E_INVALID;
+    free_ctx(ctx);
+    return CORR_OK;
+}
+
+int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, int32_t *n_out,
+                  double *t, double *c, int64_t *count, double *gk_running, double *gk_at_cut,
+                  double *c_per_channel)
+{
+    if (!ctx) return CORR_E_INVALID;
+    if (group < 0 || group >= (int)ctx->groups.size())
+        return set_err(ctx, CORR_E_INVALID, "group %d out of range", group);
+    if (!n_out || !c) return set_err(ctx, CORR_E_INVALID, "n_out and c are required");
+    DeviceGuard dg(ctx->device);
+    const Group &g = ctx->groups[(size_t)group];
+    corr_readout_opts o{};
+    if (opts) o = *opts;
+    int64_t cb = o.ch_begin, ce = o.ch_end;
+    if (cb == 0 && ce == 0) ce = g.n_ch;
+    if (cb < 0 || ce > g.n_ch || cb >= ce)
+        return set_err(ctx, CORR_E_INVALID, "channel range [%lld, %lld) invalid", (long long)cb,
+                       (long long)ce);
+    const bool want_slice = c_per_channel != nullptr;
+    int64_t sb = o.slice_begin, se = o.slice_end;
+    if (want_slice && (sb < 0 || se > g.n_ch || sb >= se))
+        return set_err(ctx, CORR_E_INVALID, "slice [%lld, %lld) invalid", (long long)sb,
+                       (long long)se);
+    if (o.gk_kind < 0 || o.gk_kind > 2) return set_err(ctx, CORR_E_INVALID, "gk_kind must be 0, 1 or 2");
+    if (o.gk_kind != 0 && !(o.volume > 0 && o.kB > 0 && o.temperature > 0))
+        return set_err(ctx, CORR_E_INVALID, "Green-Kubo prefactor needs volume, kB, temperature > 0");
+
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t S = ctx->n_push;
+    const int tw = ctx->tuning.tile_channels;
+    const int64_t rowS = (int64_t)tw * g.s_bytes;
+    const int64_t rowA = (int64_t)tw * g.a_bytes;
+
+    // Entries with non-zero count, Algorithm 2 order.
+    std::vector<Entry> ent;
+    {
+        int64_t Sk = S;
+        for (int k = 0; k < g.b && Sk > 0; ++k) {
+            const int l0 = k == 0 ? 0 : g.lag0;
+            const int nl = k == 0 ? g.p : g.nlk;
+            const int64_t lvl = k == 0 ? 0 : g.lvl0_bytes + (int64_t)(k - 1) * g.lvlk_bytes;
+            for (int L = l0; L < g.p; ++L) {
+                const int64_t cnt = Sk - L;
+                if (cnt <= 0) continue;
+                Entry e;
+                e.level = k;
+                e.lag = L;
+                e.count = cnt;
+                e.hi_off = lvl + (int64_t)g.p * rowS + (int64_t)(L - l0) * rowA;
+                e.lo_off = e.hi_off + (int64_t)nl * rowA;
+                ent.push_back(e);
+            }
+            Sk /= g.m;
+        }
+    }
+    const int ne = (int)ent.size();
+    *n_out = ne;
+    if (ne == 0) {
+        if (gk_at_cut) *gk_at_cut = 0.0;
+        return CORR_OK;
+    }
+    const int64_t nsel = ce - cb;
+    const int bpe = (int)std::max<int64_t>(1, std::min<int64_t>(256, (nsel + 4095) / 4096));
+    const int64_t n_slice = want_slice ? (se - sb) : 0;
+    // scratch: offsets (2 * ne int64), partial (ne * bpe * 2 doubles), sums (ne * 2 doubles),
+    // slice (n_slice * ne * 2 doubles)
+    const size_t off_bytes = (size_t)2 * ne * sizeof(int64_t);
+    const size_t part_bytes = (size_t)ne * bpe * 2 * sizeof(double);
+    const size_t sum_bytes = (size_t)ne * 2 * sizeof(double);
+    const size_t slice_bytes = (size_t)n_slice * ne * 2 * sizeof(double);
+    const size_t total = off_bytes + part_bytes + sum_bytes + std::max(slice_bytes, (size_t)16);
+    {
+        int rc = ensure_scratch(ctx, total);
+        if (rc != CORR_OK) return rc;
+    }
+    char *sc = static_cast<char *>(ctx->d_scratch);
+    int64_t *d_off = reinterpret_cast<int64_t *>(sc);
+    double *d_part = reinterpret_cast<double *>(sc + off_bytes);
+    double *d_sum = reinterpret_cast<double *>(sc + off_bytes + part_bytes);
+    double *d_slice = reinterpret_cast<double *>(sc + off_bytes + part_bytes + sum_bytes);
+    std::vector<int64_t> offs((size_t)2 * ne);
+    for (int i = 0; i < ne; ++i) {
+        offs[(size_t)i] = ent[(size_t)i].hi_off;
+        offs[(size_t)ne + i] = ent[(size_t)i].lo_off;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(d_off, offs.data(), off_bytes, hipMemcpyHostToDevice, ctx->stream));
+    ReduceArgs ra{};
+    ra.state = g.state;
+    ra.tile_bytes = g.tile_bytes;
+    ra.tw = tw;
+    ra.kind = g.kind;
+    ra.hi_off = d_off;
+    ra.lo_off = d_off + ne;
+    ra.n_entries = ne;
+    ra.blocks_per_entry = bpe;
+    ra.ch_begin = cb;
+    ra.ch_end = ce;
+    ra.partial = d_part;
+    ra.out = d_sum;
+    HIP_TRY(ctx, launch_reduce(ra, ctx->stream));
+    std::vector<double> sums((size_t)ne * 2);
+    HIP_TRY(ctx, hipMemcpyAsync(sums.data(), d_sum, sum_bytes, hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<double> slice;
+    if (want_slice) {
+        ReduceArgs rs = ra;
+        rs.ch_begin = sb;
+        rs.ch_end = se;
+        rs.out = d_slice;
+        HIP_TRY(ctx, launch_gather(rs, ctx->stream));
+        slice.resize((size_t)n_slice * ne * 2);
+        HIP_TRY(ctx, hipMemcpyAsync(slice.data(), d_slice, slice_bytes, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+
+    const bool cplx = kind_complex(g.kind);
+    const double norm = g.rhok ? 1.0 / (double)g.d.n_atoms : 1.0; // F(k,t) = <n n*> / N
+    const double tunit = (double)g.d.update_every * g.d.dt;
+    std::vector<double> tt((size_t)ne), cre((size_t)ne);
+    for (int i = 0; i < ne; ++i) {
+        const Entry &e = ent[(size_t)i];
+        double mk = 1.0;
+        for (int j = 0; j < e.level; ++j) mk *= (double)g.m;
+        tt[(size_t)i] = (double)e.lag * mk * tunit;
+        const double den = (double)e.count * (double)nsel;
+        const double vr = sums[(size_t)2 * i] / den * norm;
+        const double vi = sums[(size_t)2 * i + 1] / den * norm;
+        cre[(size_t)i] = vr;
+        if (t) t[i] = tt[(size_t)i];
+        if (count) count[i] = e.count;
+        if (cplx) {
+            c[2 * i] = vr;
+            c[2 * i + 1] = vi;
+        } else {
+            c[i] = vr;
+        }
+    }
+    if (want_slice) {
+        for (int64_t s = 0; s < n_slice; ++s)
+            for (int i = 0; i < ne; ++i) {
+                const double den = (double)ent[(size_t)i].count;
+                const double vr = slice[((size_t)s * ne + i) * 2] / den * norm;
+                const double vi = slice[((size_t)s * ne + i) * 2 + 1] / den * norm;
+                if (cplx) {
+                    c_per_channel[((size_t)s * ne + i) * 2] = vr;
+                    c_per_channel[((size_t)s * ne + i) * 2 + 1] = vi;
+                } else {
+                    c_per_channel[(size_t)s * ne + i] = vr;
+                }
+            }
+    }
+    // Green-Kubo: trapezoid of Re C over the emitted lag grid from t = 0 (the
+    // grid is increasing when m divides p; otherwise it is taken in sorted order).
+    double pref = 1.0;
+    if (o.gk_kind == 1) pref = o.volume / (o.kB * o.temperature);
+    if (o.gk_kind == 2) pref = o.volume / (3.0 * o.kB * o.temperature * o.temperature) * 3.0;
+    std::vector<int> ord((size_t)ne);
+    for (int i = 0; i < ne; ++i) ord[(size_t)i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return tt[(size_t)a] < tt[(size_t)b]; });
+    const double tcut = o.t_cut > 0 ? o.t_cut : tt[(size_t)ord.back()];
+    double acc = 0.0, at_cut = 0.0;
+    bool cut_done = tcut <= tt[(size_t)ord[0]];
+    if (gk_running) gk_running[ord[0]] = 0.0;
+    for (int j = 1; j < ne; ++j) {
+        const int i0 = ord[(size_t)j - 1], i1 = ord[(size_t)j];
+        const double t0 = tt[(size_t)i0], t1 = tt[(size_t)i1];
+        const double c0 = cre[(size_t)i0], c1 = cre[(size_t)i1];
+        if (!cut_done && tcut < t1) {
+            const double f = (tcut - t0) / (t1 - t0);
+            const double cc = c0 + f * (c1 - c0);
+            at_cut = acc + 0.5 * (tcut - t0) * (c0 + cc);
+            cut_done = true;
+        }
+        acc += 0.5 * (t1 - t0) * (c0 + c1);
+        if (gk_running) gk_running[i1] = acc * pref;
+    }
+    if (!cut_done) at_cut = acc;
+    if (gk_at_cut) *gk_at_cut = at_cut * pref;
+    return CORR_OK;
+}
+
+} // extern "C"

@@ -27,7 +27,7 @@ GPU_LIB = os.path.join(_HERE, "libsynth_gpu.so")
 GAMMA = 0x9E3779B97F4A7C15
 MASK64 = (1 << 64) - 1
 
-HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-mcode-object-version=5", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-ffp-contract=off"]
 

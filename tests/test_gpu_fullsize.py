@@ -1,0 +1,114 @@
+"""Parity at the benchmark's full sizes and launch configuration, on sampled
+channels the oracle recomputes one by one from the regenerated input series,
+plus properties that hold at any size (exact counts and lag grid)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_helpers import TOL, say
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def _check_channels(corr, g, spec, channels_ranges, S, b, p, m, tol, label):
+    for (lo, hi) in channels_ranges:
+        res = corr.finalize(g, slice_=(lo, hi))
+        chans = np.arange(lo, hi)
+        x, _ = spec.series(0, S, channels=chans)
+        o = oracle.OracleCorrelator(len(chans), b, p, m)
+        for row in x:
+            o.push(row.astype(np.float64))
+        for i in range(len(chans)):
+            t, c, n = o.readout(i, i + 1)
+            assert np.array_equal(res["t"], t) and np.array_equal(res["count"], n)
+            err = np.max(np.abs(res["c_per_channel"][i] - c)) / abs(c[0])
+            assert err <= tol, f"{label}: channel {lo + i}: {err:.3e} > {tol}"
+    return res
+
+
+def test_plain_3e6_channels_1e4_steps():
+    """Plain form at scale: 3x10^6 FP32 velocity channels (10^6 atoms, tau per
+    atom uniform in [20, 200]), FP64 sums, 12 levels x 16 points, m = 2,
+    10^4 pushes, one group and one kernel per push."""
+    from paper_2503_07526_amd import Correlator, GroupDesc
+    n, S, b, p, m = 3_000_000, 10_000, 12, 16, 2
+    say(f"[full size plain] n={n} S={S}")
+    spec = synth.OUSpec.make(seed=1, stream=1, n=n, comps=3, tau=20, tau_hi=200)
+    gen = synth.GpuOU(spec)
+    chunk = 250
+    buf = torch.empty((chunk, n), dtype=torch.float32, device="cuda")
+    with Correlator([GroupDesc(n, b, p, m, dtype="f32", accum="f64")], per_group=True) as c:
+        for s0 in range(0, S, chunk):
+            gen.fill(buf, chunk)
+            for j in range(chunk):
+                c.push([buf[j]])
+        torch.cuda.synchronize()
+        say("  pushes done")
+        res = _check_channels(c, 0, spec, [(0, 4), (1_234_567, 1_234_571), (n - 4, n)], S, b, p,
+                              m, TOL[("f32", "f64")], "plain")
+        # whole-group properties: lag grid and closed-form counts
+        assert len(res["t"]) == p + (b - 1) * (p - p // m)
+        for t, cnt in zip(res["t"], res["count"]):
+            k = 0
+            while t >= p * m ** k and k < b - 1:
+                k += 1
+            L = int(t) // m ** k
+            assert cnt == S // m ** k - L
+        full = c.finalize(0)
+        assert abs(full["c"][0] - 1.0) < 0.01   # unit-variance OU: C(0) ~ 1
+
+
+def test_batched_config_full_size_short_run():
+    """The batched workload at full size (3x10^7 compensated-FP32 velocity
+    channels, k-space density of 2048 k-vectors from 10^6 atoms, 9 FP64 global
+    channels) for 64 pushes; sampled velocity channels and k-vectors against
+    the oracle."""
+    from paper_2503_07526_amd import Correlator, GroupDesc
+    S = 64
+    nv, N, box = 30_000_000, 1_000_000, 100.0
+    kv = synth.kvectors(2048)
+    say(f"[full size batched] nv={nv} N={N} S={S}")
+    vspec = synth.OUSpec.make(seed=3, stream=1, n=nv, comps=3, tau=20, tau_hi=200)
+    gspec = synth.OUSpec.make(seed=3, stream=2, n=9, tau=100, dtype=np.float64)
+    pspec = synth.PositionSpec(seed=3, stream=3, n_atoms=N, box=box, sigma_d=0.1, tau_d=50)
+    groups = [GroupDesc(nv, 10, 16, 2, dtype="f32", accum="kahan"),
+              GroupDesc(2048, 16, 32, 2, dtype="cf32", accum="kahan", source="rhok", kvec=kv,
+                        n_atoms=N, box=box),
+              GroupDesc(9, 20, 16, 2, dtype="f64", accum="f64")]
+    gv, gg, gp = synth.GpuOU(vspec), synth.GpuOU(gspec), synth.GpuPositions(pspec)
+    bv = torch.empty((S, nv), dtype=torch.float32, device="cuda")
+    bg = torch.empty((S, 9), dtype=torch.float64, device="cuda")
+    bp = torch.empty((S, 3, N), dtype=torch.float32, device="cuda")
+    gv.fill(bv, S)
+    gg.fill(bg, S)
+    gp.fill(bp, S)
+    with Correlator(groups) as c:
+        for s in range(S):
+            c.push([bv[s], bp[s], bg[s]])
+        torch.cuda.synchronize()
+        say("  pushes done")
+        _check_channels(c, 0, vspec, [(0, 3), (nv - 3, nv)], S, 10, 16, 2,
+                        TOL[("f32", "kahan")], "velocity")
+        del bv
+        # k-space density: oracle n(k) of 4 k-vectors per step from the same positions
+        res = c.finalize(1, slice_=(0, 4))
+        xp, _ = pspec.series(0, S)
+        o = oracle.OracleCorrelator(4, 16, 32, 2, complex_=True)
+        for s in range(S):
+            o.push(oracle.rhok(xp[s], kv[:4], box))
+        for i in range(4):
+            t, cc, n = o.readout(i, i + 1)
+            assert np.array_equal(res["t"], t) and np.array_equal(res["count"], n)
+            err = np.max(np.abs(res["c_per_channel"][i] - cc / N)) / abs(cc[0] / N)
+            assert err <= TOL[("cf32", "kahan")], f"rho(k) k={i}: {err:.3e}"
+        rg = c.finalize(2)
+        xg = bg.cpu().numpy()
+        og = oracle.OracleCorrelator(9, 20, 16, 2)
+        for row in xg:
+            og.push(row)
+        t, cg, n = og.readout()
+        assert np.array_equal(rg["t"], t) and np.array_equal(rg["count"], n)
+        assert np.max(np.abs(rg["c"] - cg)) / abs(cg[0]) <= TOL[("f64", "f64")]

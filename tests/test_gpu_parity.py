@@ -1,0 +1,220 @@
+"""GPU parity: the HIP correlator (through the C ABI) against the CPU FP64
+oracle on the same seeded inputs.  Counts and lag times must match exactly;
+C(t) within the tolerance of its precision class (tests/gpu_helpers.TOL),
+measured as max |dC| / |C(0)| over the group mean and over sampled channels.
+Sizes span several 512-channel tiles with a ragged tail."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_helpers import TOL, gate, oracle_run, ou_inputs, say
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def corrmod():
+    import paper_2503_07526_amd as m
+    m.lib()  # fails loudly if the HIP library is missing
+    return m
+
+
+def _push_all(corr, xs):
+    dev = torch.device("cuda:0")
+    ts = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in xs]
+    for s in range(xs[0].shape[0]):
+        corr.push([t[s] for t in ts])
+    torch.cuda.synchronize()
+
+
+KINDS = [("f32", "f64"), ("f32", "kahan"), ("f32", "f32"), ("f64", "f64"),
+         ("cf32", "f64"), ("cf32", "kahan"), ("cf32", "f32"), ("cf64", "f64")]
+
+
+@pytest.mark.parametrize("dtype,accum", KINDS)
+def test_parity_each_kind(corrmod, dtype, accum):
+    n, S, b, p, m = 1300, 1200, 7, 16, 2
+    say(f"[parity kind] dtype={dtype} accum={accum} n={n} S={S} b={b} p={p}")
+    x = ou_inputs(7, 11, n, S, dtype)
+    o = oracle_run(x, b, p, m)
+    with corrmod.Correlator([corrmod.GroupDesc(n, b, p, m, dtype=dtype, accum=accum)]) as c:
+        _push_all(c, [x])
+        sl = (n - 5, n)
+        res = c.finalize(0, slice_=sl)
+        err = gate(res, o, TOL[(dtype, accum)], slice_=sl, label=f"{dtype}/{accum}")
+        res0 = c.finalize(0, slice_=(0, 4))
+        gate(res0, o, TOL[(dtype, accum)], slice_=(0, 4), label=f"{dtype}/{accum} head")
+    say(f"  max |dC|/|C(0)| = {err:.2e}")
+
+
+@pytest.mark.parametrize("n,S,b,p,m", [
+    (1, 50, 4, 16, 2),        # one channel
+    (513, 5, 4, 16, 2),       # fewer pushes than points
+    (700, 0, 4, 16, 2),       # no push at all
+    (700, 777, 5, 7, 3),      # m does not divide p
+    (700, 400, 3, 4, 2),      # small p
+    (700, 300, 6, 3, 2),      # p = 3, lag0 = 1
+    (600, 700, 4, 9, 4),      # m = 4
+    (1100, 600, 6, 32, 2),    # p = 32 (two lag chunks)
+    (520, 1000, 1, 16, 2),    # single level
+    (1030, 2048, 12, 16, 2),  # pushes = 2^11: deepest level just reached
+])
+def test_parity_shapes(corrmod, n, S, b, p, m):
+    say(f"[parity shape] n={n} S={S} b={b} p={p} m={m}")
+    x = ou_inputs(3, 5, n, max(S, 1), "f64")[:S]
+    o = oracle.OracleCorrelator(n, b, p, m)
+    for row in x:
+        o.push(row)
+    with corrmod.Correlator([corrmod.GroupDesc(n, b, p, m, dtype="f64", accum="f64")]) as c:
+        if S:
+            _push_all(c, [x])
+        res = c.finalize(0, slice_=(0, min(n, 3)))
+        assert c.n_pushes() == S
+        if S == 0:
+            assert len(res["t"]) == 0
+            return
+        gate(res, o, 1e-12, slice_=(0, min(n, 3)), label="shape")
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(tile_channels=256, chans_per_thread=1, lag_chunk=16, grid_blocks=0),
+    dict(tile_channels=256, chans_per_thread=1, lag_chunk=8, grid_blocks=0),
+    dict(tile_channels=512, chans_per_thread=2, lag_chunk=8, grid_blocks=0),
+    dict(tile_channels=256, chans_per_thread=2, lag_chunk=4, grid_blocks=3),
+    dict(tile_channels=1024, chans_per_thread=4, lag_chunk=4, grid_blocks=0),
+    dict(tile_channels=256, chans_per_thread=4, lag_chunk=8, grid_blocks=5),
+])
+def test_tile_invariance_bitwise(corrmod, tuning):
+    """Every launch shape gives bit-identical results (one thread owns each
+    channel; the readout reduction order does not depend on the tiling)."""
+    n, S = 2100, 600
+    say(f"[tile invariance] {tuning}")
+    xs = [ou_inputs(1, 2, n, S, "f32"), ou_inputs(1, 3, 300, S, "cf32")]
+    groups = [corrmod.GroupDesc(n, 6, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(300, 5, 32, 2, dtype="cf32", accum="f64")]
+    ref = []
+    with corrmod.Correlator(groups) as c:
+        _push_all(c, xs)
+        ref = [c.finalize(g, slice_=(0, 7)) for g in range(2)]
+    with corrmod.Correlator(groups, tuning=tuning) as c:
+        _push_all(c, xs)
+        got = [c.finalize(g, slice_=(0, 7)) for g in range(2)]
+    for r, g in zip(ref, got):
+        assert np.array_equal(r["c"], g["c"])
+        assert np.array_equal(r["c_per_channel"], g["c_per_channel"])
+
+
+def test_snapshot_is_non_destructive(corrmod):
+    n, S = 900, 500
+    say("[snapshot] finalize mid-run then continue")
+    x = ou_inputs(9, 9, n, S, "f32")
+    with corrmod.Correlator([corrmod.GroupDesc(n, 6, 16, 2, accum="kahan")]) as a, \
+            corrmod.Correlator([corrmod.GroupDesc(n, 6, 16, 2, accum="kahan")]) as b:
+        _push_all(a, [x[:123]])
+        mid = a.finalize(0)
+        _push_all(a, [x[123:]])
+        _push_all(b, [x])
+        ra, rb = a.finalize(0), b.finalize(0)
+        assert np.array_equal(ra["c"], rb["c"]) and np.array_equal(ra["count"], rb["count"])
+        o = oracle_run(x[:123], 6, 16, 2)
+        gate(mid, o, TOL[("f32", "kahan")], label="mid-run")
+
+
+def test_rhok_magnitude_and_phase(corrmod):
+    """One push: C(0) of k = |n(k)|^2 / N.  Two pushes with every atom moved by
+    d: C(lag 1) = exp(i k.d) |n(k)|^2 / N (later times conj(earlier))."""
+    kv = synth.kvectors(300)
+    N, box = 5000, 100.0
+    say(f"[rho(k)] N={N} nk={len(kv)}")
+    ps = synth.PositionSpec(4, 4, N, box)
+    r0 = ps.r0.copy()
+    d = np.array([0.37, -1.25, 2.5], dtype=np.float32)
+    r1 = (r0 + d[:, None]).astype(np.float32)
+    g = corrmod.GroupDesc(len(kv), 3, 8, 2, dtype="cf32", accum="f64", source="rhok", kvec=kv,
+                          n_atoms=N, box=box)
+    with corrmod.Correlator([g]) as c:
+        _push_all(c, [r0[None]])
+        res = c.finalize(0, slice_=(0, len(kv)))
+        rho0 = oracle.rhok(r0, kv, box)
+        expect = np.abs(rho0) ** 2 / N
+        got = res["c_per_channel"][:, 0]
+        assert np.max(np.abs(got - expect)) / np.max(expect) < 2e-6
+        _push_all(c, [r1[None]])
+        res = c.finalize(0, slice_=(0, len(kv)))
+        rho1 = oracle.rhok(r1, kv, box)
+        expect1 = rho1 * np.conj(rho0) / N
+        got1 = res["c_per_channel"][:, 1]
+        assert np.max(np.abs(got1 - expect1)) / np.max(np.abs(expect1)) < 2e-6
+
+
+def test_batched_mixed_groups_and_modes(corrmod):
+    """Three uneven groups in one context (compensated FP32 velocities, the
+    k-space density, FP64 global channels): parity with the oracle, and
+    bit-identical state from the batched launch, the per-group launches and the
+    HIP graph replay."""
+    S, nv, N, box = 400, 2500, 3000, 100.0
+    kv = synth.kvectors(200)
+    say(f"[batched] S={S} nv={nv} N={N} nk={len(kv)}")
+    xv = ou_inputs(5, 1, nv, S, "f32")
+    xg = ou_inputs(5, 2, 9, S, "f64", tau=50, tau_hi=None)
+    pos = synth.PositionSpec(5, 3, N, box)
+    xp, _ = pos.series(0, S)
+    groups = [corrmod.GroupDesc(nv, 7, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(len(kv), 6, 32, 2, dtype="cf32", accum="kahan", source="rhok",
+                                kvec=kv, n_atoms=N, box=box),
+              corrmod.GroupDesc(9, 9, 16, 2, dtype="f64", accum="f64")]
+    ov = oracle_run(xv, 7, 16, 2)
+    og = oracle_run(xg, 9, 16, 2)
+    orh = oracle.OracleCorrelator(len(kv), 6, 32, 2, complex_=True)
+    for s in range(S):
+        orh.push(oracle.rhok(xp[s], kv, box))
+    results = {}
+    for mode in ("batched", "per_group", "graph"):
+        say(f"  mode {mode}")
+        with corrmod.Correlator(groups, graph=(mode == "graph"),
+                                per_group=(mode == "per_group")) as c:
+            dev = torch.device("cuda:0")
+            tv = torch.from_numpy(xv).to(dev)
+            tg = torch.from_numpy(xg).to(dev)
+            tp = torch.from_numpy(xp).to(dev)
+            if mode == "graph":
+                bv = torch.empty_like(tv[0]); bp = torch.empty_like(tp[0]); bg = torch.empty_like(tg[0])
+                c.bind_input(0, bv); c.bind_input(1, bp); c.bind_input(2, bg)
+                for s in range(S):
+                    bv.copy_(tv[s]); bp.copy_(tp[s]); bg.copy_(tg[s])
+                    c.push()
+            else:
+                for s in range(S):
+                    c.push([tv[s], tp[s], tg[s]])
+            results[mode] = [c.finalize(g, slice_=(0, 5)) for g in range(3)]
+    for mode in ("per_group", "graph"):
+        for g in range(3):
+            assert np.array_equal(results[mode][g]["c"], results["batched"][g]["c"]), (mode, g)
+            assert np.array_equal(results[mode][g]["c_per_channel"],
+                                  results["batched"][g]["c_per_channel"]), (mode, g)
+    r = results["batched"]
+    e1 = gate(r[0], ov, TOL[("f32", "kahan")], slice_=(0, 5), label="velocity")
+    e2 = gate(r[1], orh, TOL[("cf32", "kahan")], scale=1.0 / N, slice_=(0, 5), label="rho(k)")
+    e3 = gate(r[2], og, TOL[("f64", "f64")], slice_=(0, 5), label="global")
+    say(f"  errors: velocity {e1:.2e} rho(k) {e2:.2e} global {e3:.2e}")
+
+
+def test_green_kubo_readout(corrmod):
+    """gk_running / gk_at_cut follow the trapezoid integral of the oracle's C
+    with the viscosity and conductivity prefactors (Section 2.3)."""
+    S = 3000
+    x = ou_inputs(2, 8, 9, S, "f64", tau=50, tau_hi=None)
+    o = oracle_run(x, 10, 16, 2)
+    V, kB, T = 1000.0, 1.380649e-23 * 1e23, 300.0
+    with corrmod.Correlator([corrmod.GroupDesc(9, 10, 16, 2, dtype="f64", dt=0.001)]) as c:
+        _push_all(c, [x])
+        for kind, ch, fn in ((1, (3, 6), oracle.green_kubo_viscosity),
+                             (2, (6, 9), oracle.green_kubo_conductivity)):
+            res = c.finalize(0, ch=ch, gk_kind=kind, volume=V, kB=kB, temperature=T, t_cut=0.5)
+            t, cm, _ = o.readout(*ch)
+            run, at = fn(t * 0.001, cm, V, kB, T, t_cut=0.5)
+            assert np.allclose(res["gk_running"], run, rtol=1e-12, atol=1e-12 * abs(run).max())
+            assert abs(res["gk_at_cut"] - at) <= 1e-12 * abs(at)
