@@ -95,7 +95,8 @@ typedef struct corr_group_desc {
  * over all tiles of all groups (0 = one block per tile).  Zeros everywhere
  * select the library defaults (or the autotuner's cached choice). */
 typedef struct corr_tuning {
-    int32_t tile_channels;    /* 64..4096, multiple of 64 * chans_per_thread        */
+    int32_t tile_channels;    /* multiple of 64 * chans_per_thread, at most
+                                 256 * chans_per_thread (256 threads per block) */
     int32_t chans_per_thread; /* 1, 2 or 4                                          */
     int32_t lag_chunk;        /* lags loaded per batch: 4, 8 or 16                  */
     int32_t grid_blocks;      /* 0 = one block per tile                              */

@@ -268,8 +268,11 @@ class Correlator:
         else:
             res["c"] = c[:n]
         if per is not None:
+            # the library writes [slice][n_out] (complex: [slice][n_out][2]) contiguously
+            ns = per.shape[0]
             if cplx:
-                res["c_per_channel"] = per[:, :n, 0] + 1j * per[:, :n, 1]
+                flat = per.reshape(-1)[: ns * n * 2].reshape(ns, n, 2)
+                res["c_per_channel"] = flat[:, :, 0] + 1j * flat[:, :, 1]
             else:
-                res["c_per_channel"] = per[:, :n]
+                res["c_per_channel"] = per.reshape(-1)[: ns * n].reshape(ns, n)
         return res

@@ -55,6 +55,13 @@ struct corr_ctx {
     PushArgs pargs{};
     int64_t total_tiles = 0;
     hipStream_t cap_stream = nullptr;
+    // k-density groups run on a side stream (producer, then their own push
+    // launch) forked from and joined to the main stream on every push, so the
+    // ALU-bound producer overlaps the HBM-bound push of the other groups.
+    std::vector<int> main_set, side_set; // context group indices
+    PushArgs pa_main{}, pa_side{};
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     // push-kernel timing (CORR_FLAG_TIMING)
@@ -156,6 +163,9 @@ int validate(const corr_group_desc &g, int idx)
     return CORR_OK;
 }
 
+// Push kernels are compiled for at most this many threads per block.
+constexpr int kMaxBlock = 256;
+
 int validate_tuning(const corr_tuning &t)
 {
     const int cpt = t.chans_per_thread, lch = t.lag_chunk;
@@ -165,7 +175,7 @@ int validate_tuning(const corr_tuning &t)
         return set_err(nullptr, CORR_E_INVALID, "tuning: unsupported (chans_per_thread, lag_chunk) = (%d, %d)",
                        cpt, lch);
     if (t.tile_channels < 64 || t.tile_channels > 4096 || t.tile_channels % (64 * cpt) != 0 ||
-        t.tile_channels / cpt > 1024)
+        t.tile_channels / cpt > kMaxBlock)
         return set_err(nullptr, CORR_E_INVALID, "tuning: tile_channels %d invalid for %d channels/thread",
                        t.tile_channels, cpt);
     if (t.grid_blocks < 0) return set_err(nullptr, CORR_E_INVALID, "tuning: grid_blocks < 0");
@@ -191,6 +201,9 @@ void free_ctx(corr_ctx *c)
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (auto &g : c->groups) free_group(g);
     if (c->d_step) (void)hipFree(c->d_step);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
@@ -236,32 +249,15 @@ int next_events(corr_ctx *c, hipEvent_t *a, hipEvent_t *b)
     return CORR_OK;
 }
 
-// Issue one push of every group on stream `st` with the given per-group
-// sample pointers (already resolved, never NULL).
-int issue_push(corr_ctx *c, const void *const *src, hipStream_t st)
+// Push kernel launch(es) for the groups of one set (batched: one launch;
+// per-group form: one launch per group).
+int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
+               const std::vector<const void *> &resolved, hipStream_t st)
 {
-    PushArgs a = c->pargs;
-    for (size_t i = 0; i < c->groups.size(); ++i) {
-        Group &g = c->groups[i];
-        if (g.rhok) {
-            RhokArgs ra = g.rargs;
-            ra.pos = static_cast<const float *>(src[i]);
-            HIP_TRY(c, launch_rhok(ra, st));
-            a.g[i].samples = g.rhok_out;
-        } else {
-            a.g[i].samples = src[i];
-        }
-    }
+    PushArgs a = base;
+    for (size_t j = 0; j < idx.size(); ++j) a.g[j].samples = resolved[(size_t)idx[j]];
     const int cpt = c->tuning.chans_per_thread, lch = c->tuning.lag_chunk;
     const int block = c->tuning.tile_channels / cpt;
-    // Events are only recorded on direct launches, never while capturing.
-    const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed) {
-        int rc = next_events(c, &e0, &e1);
-        if (rc != CORR_OK) return rc;
-        HIP_TRY(c, hipEventRecord(e0, st));
-    }
     if (c->flags & CORR_FLAG_PER_GROUP) {
         for (int i = 0; i < a.n_groups; ++i)
             HIP_TRY(c, launch_push_group(a.g[i], c->d_step, cpt, lch, block, st));
@@ -271,7 +267,51 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st)
         grid = std::min<int64_t>(grid, 0x7fffffff);
         HIP_TRY(c, launch_push_batched(a, cpt, lch, (int)grid, block, st));
     }
+    return CORR_OK;
+}
+
+// Issue one push of every group on stream `st` with the given per-group
+// sample pointers (already resolved, never NULL).
+int issue_push(corr_ctx *c, const void *const *src, hipStream_t st)
+{
+    const size_t ng = c->groups.size();
+    std::vector<const void *> resolved(ng);
+    for (size_t i = 0; i < ng; ++i) resolved[i] = c->groups[i].rhok ? c->groups[i].rhok_out : src[i];
+    // Events are only recorded on direct launches, never while capturing.
+    const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream;
+    const bool fork = !c->side_set.empty() && !c->main_set.empty();
+    if (fork) {
+        HIP_TRY(c, hipEventRecord(c->ev_fork, st));
+        HIP_TRY(c, hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+    }
+    hipStream_t pst = fork ? c->side_stream : st;
+    for (int i : c->side_set) {
+        RhokArgs ra = c->groups[(size_t)i].rargs;
+        ra.pos = static_cast<const float *>(src[i]);
+        HIP_TRY(c, launch_rhok(ra, pst));
+    }
+    if (fork) {
+        int rc = launch_set(c, c->pa_side, c->side_set, resolved, pst);
+        if (rc != CORR_OK) return rc;
+        HIP_TRY(c, hipEventRecord(c->ev_join, pst));
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        int rc = next_events(c, &e0, &e1);
+        if (rc != CORR_OK) return rc;
+        HIP_TRY(c, hipEventRecord(e0, st));
+    }
+    if (fork) {
+        int rc = launch_set(c, c->pa_main, c->main_set, resolved, st);
+        if (rc != CORR_OK) return rc;
+    } else {
+        std::vector<int> all(ng);
+        for (size_t i = 0; i < ng; ++i) all[i] = (int)i;
+        int rc = launch_set(c, c->pargs, all, resolved, st);
+        if (rc != CORR_OK) return rc;
+    }
     if (timed) HIP_TRY(c, hipEventRecord(e1, st));
+    if (fork) HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
     HIP_TRY(c, launch_step_increment(c->d_step, st));
     return CORR_OK;
 }
@@ -349,7 +389,9 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         int rc = validate(groups[i], i);
         if (rc != CORR_OK) return rc;
     }
-    corr_tuning tn{512, 2, 8, 0};
+    // Default launch shape: 512-channel tiles, 2 channels per thread (256-thread
+    // blocks), 8 lags per load batch, a persistent grid of 8 blocks per CU.
+    corr_tuning tn{512, 2, 8, 2048};
     if (tuning && (tuning->tile_channels || tuning->chans_per_thread || tuning->lag_chunk ||
                    tuning->grid_blocks)) {
         tn = *tuning;
@@ -490,9 +532,31 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     c->pargs.n_groups = n_groups;
     c->pargs.total_tiles = tile_first;
     c->total_tiles = tile_first;
+    for (int i = 0; i < n_groups; ++i)
+        (c->groups[(size_t)i].rhok ? c->side_set : c->main_set).push_back(i);
+    if (!c->side_set.empty() && !c->main_set.empty()) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const std::vector<int> &idx = pass == 0 ? c->main_set : c->side_set;
+            PushArgs &pa = pass == 0 ? c->pa_main : c->pa_side;
+            pa = c->pargs;
+            int64_t tf = 0;
+            for (size_t j = 0; j < idx.size(); ++j) {
+                pa.g[j] = c->pargs.g[(size_t)idx[j]];
+                pa.g[j].tile_first = tf;
+                tf += pa.g[j].n_tiles;
+            }
+            pa.n_groups = (int32_t)idx.size();
+            pa.total_tiles = tf;
+        }
+        CREATE_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+        CREATE_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        CREATE_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
     CREATE_HIP(hipMalloc(&c->d_step, sizeof(int64_t)));
     CREATE_HIP(hipMemsetAsync(c->d_step, 0, sizeof(int64_t), c->stream));
     c->pargs.step = c->d_step;
+    c->pa_main.step = c->d_step;
+    c->pa_side.step = c->d_step;
     CREATE_HIP(hipStreamSynchronize(c->stream));
 
     if (flags & CORR_FLAG_GRAPH) {

@@ -83,6 +83,8 @@ def test_rhok_descriptor_needs_positions_and_box(corrmod):
     dict(tile_channels=100, chans_per_thread=1, lag_chunk=16, grid_blocks=0),
     dict(tile_channels=256, chans_per_thread=3, lag_chunk=8, grid_blocks=0),
     dict(tile_channels=4096, chans_per_thread=1, lag_chunk=16, grid_blocks=0),
+    dict(tile_channels=512, chans_per_thread=1, lag_chunk=16, grid_blocks=0),
+    dict(tile_channels=2048, chans_per_thread=4, lag_chunk=4, grid_blocks=0),
 ])
 def test_invalid_tuning_rejected(corrmod, tuning):
     rc, msg = _create(corrmod, corrmod.GroupDesc(64, 4, 16), tuning)

@@ -50,7 +50,9 @@ def test_plain_3e6_channels_1e4_steps():
         res = _check_channels(c, 0, spec, [(0, 4), (1_234_567, 1_234_571), (n - 4, n)], S, b, p,
                               m, TOL[("f32", "f64")], "plain")
         # whole-group properties: lag grid and closed-form counts
-        assert len(res["t"]) == p + (b - 1) * (p - p // m)
+        expect_n = sum(1 for k in range(b) for L in range(0 if k == 0 else p // m, p)
+                       if S // m ** k - L > 0)
+        assert len(res["t"]) == expect_n
         for t, cnt in zip(res["t"], res["count"]):
             k = 0
             while t >= p * m ** k and k < b - 1:
