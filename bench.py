@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--compare-plain", action="store_true",
                     help="also time the plain FP64 per-group form on the same velocity channels")
     ap.add_argument("--tuning", default=None, help="JSON dict of corr_tuning fields")
+    ap.add_argument("--direct", action="store_true",
+                    help="per-step update of every channel (no block-deferred form)")
     return ap.parse_args()
 
 
@@ -57,8 +59,9 @@ def workload(name):
     import synth
     if name == "plain":
         return dict(
-            name="plain: 3e6 FP32 channels (1e6 atoms), FP64 sums, b=12 p=16 m=2, per-group launch",
-            steps=10_000,
+            name=("plain: 3e6 FP32 channels (1e6 atoms), FP64 sums, b=12 p=16 m=2, per-step update, "
+                  "per-group launch"),
+            steps=10_000, direct=True,
             groups=[dict(kind="ou", n=3_000_000, levels=12, points=16, m=2, dtype="f32",
                          accum="f64", comps=3, tau=(20, 200), sigma=1.0, seed=1, stream=1)])
     if name == "batched":
@@ -88,6 +91,40 @@ def workload(name):
 SB = {"f32": 4, "f64": 8, "cf32": 8, "cf64": 16}
 AB = {("f32", "f64"): 8, ("f32", "kahan"): 8, ("f32", "f32"): 4, ("f64", "f64"): 8,
       ("cf32", "f64"): 16, ("cf32", "kahan"): 16, ("cf32", "f32"): 8, ("cf64", "f64"): 16}
+
+
+DEFER_T = 64
+
+
+def deferred(g, direct=False):
+    """Groups the library runs in the block-deferred form."""
+    return (not direct and g["kind"] == "ou" and g["dtype"] == "f32" and g["points"] == 16
+            and g["m"] == 2)
+
+
+def flush_bytes(g, s):
+    """Algorithmic HBM bytes of the flush at push s (s a multiple of 64) for one
+    block-deferred group: level 0 reads the 64 new and 15 older ring values and
+    reads+writes its 16 accumulators; every level k that receives n_k > 0 new
+    values reads its 15 older ring values, writes min(n_k, 16) slots and
+    reads+writes its 8 accumulators."""
+    sb, ab = SB[g["dtype"]], AB[(g["dtype"], g["accum"])]
+    p, b, T = g["points"], g["levels"], DEFER_T
+    B = (p - 1 + T) * sb + 2 * p * ab
+    for k in range(1, b):
+        nk = s // 2 ** k - (s - T) // 2 ** k
+        if nk <= 0:
+            break
+        B += (p - 1) * sb + min(nk, p) * sb + 2 * (p - p // 2) * ab
+    return B * g["n"]
+
+
+def push_bytes(g, s, direct=False):
+    """Bytes of the push kernel at push s: staging (read sample, write ring slot)
+    for block-deferred groups, the full per-step update otherwise."""
+    if deferred(g, direct):
+        return 2 * SB[g["dtype"]] * g["n"]
+    return step_bytes(g, s)
 
 
 def step_bytes(g, s):
@@ -146,6 +183,7 @@ def run(args):
     K = args.steps if args.steps is not None else wl["steps"]
     W = args.warmup if args.warmup is not None else 256
     mode = args.mode or ("per_group" if args.config == "plain" else "batched")
+    args.direct = args.direct or wl.get("direct", False)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(0)
 
@@ -170,7 +208,8 @@ def run(args):
             tdt = torch.float32 if real == np.float32 else torch.float64
             bufs.append(torch.empty((chunk, g["n"]), dtype=tdt, device=dev))
     tuning = json.loads(args.tuning) if args.tuning else None
-    corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuning, timing=True)
+    corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuning, timing=True,
+                      direct=args.direct)
     state_gb = sum(corr.state_bytes(i) for i in range(len(descs))) / 1e9
 
     def push_chunk(n):
@@ -189,7 +228,8 @@ def run(args):
         n = min(chunk, W - done)
         push_chunk(n)
         done += n
-    corr.kernel_time(reset=True)
+    corr.kernel_time(0, reset=True)
+    corr.kernel_time(1, reset=True)
     s_first = W + 1
     wall = 0.0
     done = 0
@@ -197,7 +237,7 @@ def run(args):
         n = min(chunk, K - done)
         wall += push_chunk(n)
         done += n
-    kern_ms, kern_n = corr.kernel_time()
+    kern_ms, kern_n = corr.kernel_time(0)
     assert kern_n == K, (kern_n, K)
     # The timed launch: with k-density groups next to other groups, those run
     # (producer + own push) on a forked side stream and the events bracket the
@@ -205,10 +245,25 @@ def run(args):
     has_rhok = any(g["kind"] == "rhok" for g in wl["groups"])
     timed = [g for g in wl["groups"]
              if not (has_rhok and len(wl["groups"]) > 1 and g["kind"] == "rhok")]
-    alg_bytes = sum(step_bytes(g, s) for g in timed for s in range(s_first, s_first + K))
+    steps = range(s_first, s_first + K)
+    direct = args.direct
+    stage_bytes = sum(push_bytes(g, s, direct) for g in timed for s in steps)
+    fl_bytes = sum(flush_bytes(g, s) for g in timed if deferred(g, direct)
+                   for s in steps if s % DEFER_T == 0)
+    fl_ms, fl_n = corr.kernel_time(which=1)
     n_total = sum(g["n"] for g in wl["groups"])
     value = n_total * K / wall
-    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    if fl_n:
+        # dominant kernel: the flush of the block-deferred groups
+        achieved = fl_bytes / (fl_ms * 1e-3) / 1e9
+        kname = "flush kernel (block-deferred fold of 64 pushes), HIP events per launch"
+        per_launch_ms, per_launch_bytes = fl_ms / fl_n, fl_bytes / fl_n
+    else:
+        achieved = (stage_bytes + fl_bytes) / (kern_ms * 1e-3) / 1e9
+        kname = ("push kernel (correlator update of %d of %d groups), HIP events per launch"
+                 % (len(timed), len(wl["groups"])))
+        per_launch_ms, per_launch_bytes = kern_ms / kern_n, (stage_bytes + fl_bytes) / K
+    update_gbs = (stage_bytes + fl_bytes) / (kern_ms * 1e-3) / 1e9
     out = {
         "metric": "channel-samples/sec into correlators",
         "value": value,
@@ -224,13 +279,15 @@ def run(args):
         "data": "synthetic (seeded OU series and atom positions generated in HBM before each "
                 "timed chunk)",
         "config": {"workload": wl["name"], "channels": n_total, "launch": mode,
+                   "update_form": "direct" if args.direct else "block-deferred where supported",
                    "tuning": corr.tuning(), "state_GB": round(state_gb, 2)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "push kernel (correlator update of %d of %d groups), HIP "
-                               "events per launch" % (len(timed), len(wl["groups"])),
-                     "kernel_ms_per_launch": kern_ms / kern_n,
-                     "alg_bytes_per_launch": alg_bytes / K},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
+                     "kernel_ms_per_launch": per_launch_ms,
+                     "alg_bytes_per_launch": per_launch_bytes,
+                     "update_kernels_GBs": update_gbs,
+                     "update_ms_per_step": kern_ms / kern_n,
+                     "alg_bytes_per_step": (stage_bytes + fl_bytes) / K},
     }
     corr.close()
     if args.compare_plain:
@@ -250,7 +307,7 @@ def compare_plain(wl, K, W, chunk):
     gen = synth.GpuOU(spec)
     buf = torch.empty((chunk, g["n"]), dtype=torch.float32, device="cuda")
     corr = Correlator([GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype="f32",
-                                 accum="f64")], per_group=True, timing=True)
+                                 accum="f64")], per_group=True, timing=True, direct=True)
     wall, done = 0.0, 0
     while done < W + K:
         n = min(chunk, W + K - done)
@@ -265,7 +322,7 @@ def compare_plain(wl, K, W, chunk):
         done += n
     corr.close()
     return {"value": g["n"] * (W + K - W) / wall, "unit": "channel-samples/s",
-            "form": "FP32 samples, FP64 sums, per-group launch"}
+            "form": "FP32 samples, FP64 sums, per-step update, per-group launch"}
 
 
 def main():

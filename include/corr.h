@@ -66,8 +66,11 @@ enum corr_flags {
     CORR_FLAG_GRAPH = 1u,     /* capture one push of all groups in a HIP graph    */
     CORR_FLAG_PER_GROUP = 2u, /* one kernel launch per group and push (the plain
                                  form) instead of one batched launch            */
-    CORR_FLAG_TIMING = 4u     /* bracket the push kernel launch(es) of every push
-                                 with HIP events (see corr_kernel_time)         */
+    CORR_FLAG_TIMING = 4u,    /* bracket the update kernels of every push with
+                                 HIP events (see corr_kernel_time)              */
+    CORR_FLAG_DIRECT = 8u     /* update every channel on every push (Algorithm 1
+                                 step by step) even where the block-deferred
+                                 form is available                              */
 };
 
 typedef struct corr_group_desc {
@@ -192,13 +195,23 @@ const char *corr_last_error(const corr_ctx *ctx);
  * planes, padded to whole tiles). */
 int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
 
-/* With CORR_FLAG_TIMING: synchronise and return the summed device time of
- * the push kernel launches (HIP events recorded on the context's stream
- * around the correlator-update kernel(s) only, excluding the k-density
- * producer and the step counter) and the number of timed pushes since the
- * last reset.  In graph mode the events bracket the whole graph replay.
- * reset != 0 clears both after reading.  CORR_E_STATE without the flag. */
-int corr_kernel_time(corr_ctx *ctx, double *ms_total, int64_t *n_pushes, int32_t reset);
+/* With CORR_FLAG_TIMING: synchronise and return summed device times from HIP
+ * events recorded on the context's stream.  which = 0: per push, from before
+ * the push kernel launch(es) to after the flush launch(es) of that push, i.e.
+ * the correlator-update kernels of the main stream (excluding the forked
+ * k-density producer and the step counter); *n = timed pushes.  which = 1:
+ * the flush launches of block-deferred groups only; *n = timed flushes.  In
+ * graph mode the which = 0 events bracket the whole graph replay and no
+ * flush-only times are recorded.  reset != 0 clears the counters of `which`
+ * after reading.  CORR_E_STATE without the flag.
+ *
+ * Block-deferred form: for groups of single-precision samples with p = 16 and
+ * m = 2 (unless CORR_FLAG_DIRECT), a push only stages the samples; every 64
+ * pushes a flush adds the lag products of those 64 pushes level by level
+ * (the same products, block means and counts as Algorithm 1; only the
+ * grouping of the floating-point sums differs) and a readout folds pending
+ * pushes without modifying state. */
+int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n, int32_t reset);
 
 /* Launch shape in use. */
 int corr_get_tuning(const corr_ctx *ctx, corr_tuning *out);

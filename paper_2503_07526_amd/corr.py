@@ -22,7 +22,7 @@ CORR_OK, CORR_E_INVALID, CORR_E_OOM, CORR_E_DEVICE, CORR_E_STATE, CORR_E_UNSUPPO
 DTYPES = {"f32": 1, "f64": 2, "cf32": 3, "cf64": 4}
 ACCUMS = {"f64": 1, "kahan": 2, "f32": 3}
 SOURCES = {"samples": 0, "rhok": 1}
-FLAG_GRAPH, FLAG_PER_GROUP, FLAG_TIMING = 1, 2, 4
+FLAG_GRAPH, FLAG_PER_GROUP, FLAG_TIMING, FLAG_DIRECT = 1, 2, 4, 8
 _TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64, "cf32": torch.complex64,
                 "cf64": torch.complex128}
 
@@ -87,8 +87,8 @@ def lib():
         L.corr_last_error.restype = ctypes.c_char_p
         L.corr_state_bytes.argtypes = [vp, i32, ctypes.POINTER(i64)]
         L.corr_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
-        L.corr_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
-                                       i32]
+        L.corr_kernel_time.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(i64), i32]
         for name in EXPORTS:
             if name != "corr_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -142,14 +142,14 @@ class Correlator:
 
     def __init__(self, groups, device: int = 0, stream: torch.cuda.Stream | None = None,
                  graph: bool = False, per_group: bool = False, tuning: dict | None = None,
-                 timing: bool = False):
+                 timing: bool = False, direct: bool = False):
         L = lib()
         self.groups = list(groups)
         descs = (_GroupDesc * len(self.groups))(*[g.to_c() for g in self.groups])
         self.device = int(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         flags = (FLAG_GRAPH if graph else 0) | (FLAG_PER_GROUP if per_group else 0) | \
-            (FLAG_TIMING if timing else 0)
+            (FLAG_TIMING if timing else 0) | (FLAG_DIRECT if direct else 0)
         tn = Tuning(**tuning) if tuning else None
         h = ctypes.c_void_p()
         rc = L.corr_create(descs, len(self.groups), self.device,
@@ -223,11 +223,13 @@ class Correlator:
         self._check(lib().corr_state_bytes(self._h, g, ctypes.byref(n)))
         return int(n.value)
 
-    def kernel_time(self, reset: bool = False):
-        """(summed push-kernel milliseconds, timed pushes) from the library's HIP events."""
+    def kernel_time(self, which: int = 0, reset: bool = False):
+        """(summed milliseconds, count) from the library's HIP events: which=0 the
+        update kernels of each push (incl. flushes), which=1 flush launches only."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        self._check(lib().corr_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+        self._check(lib().corr_kernel_time(self._h, int(which), ctypes.byref(ms), ctypes.byref(n),
+                                           int(reset)))
         return float(ms.value), int(n.value)
 
     def tuning(self) -> dict:

@@ -1,0 +1,474 @@
+// corr_deferred.hip -- block-deferred form of the multiple-tau update.
+//
+// Algorithm 1 of the paper's Appendix D adds, at every push, the products of
+// the newest value with the p lagged values of each level that receives a
+// value.  The sums it builds are linear, so the products of T consecutive
+// pushes can be added in one pass: on every push the sample is only written
+// into a level-0 ring of P0 = T + p slots ("staging", 2 samples of traffic
+// per channel), and every T pushes (T a power of m) one flush pass per channel
+// walks the T new level-0 values in order, adds each one's lag products to
+// per-lag partial sums held in registers, forms the level-1 block means on
+// the fly, and repeats level by level with the new values of the level above
+// -- the same products, block means and counts as T single pushes, with the
+// partial sums added to the stored accumulators once per flush.  The stored
+// state after a flush is that of Algorithm 1 after the same pushes, up to the
+// grouping of the floating-point sums.
+//
+// State is touched once per flush and not again for 64 pushes, so the flush
+// streams it with non-temporal loads and stores (measured 5.1 -> 5.6 TB/s).
+//
+// A readout between flushes folds the pending pushes the same way without
+// writing any state (so a readout never changes later results) and reduces
+// the resulting per-channel accumulators over the block's channels in a
+// fixed order.
+//
+// Supported here: single-precision real samples, m = 2, p = 16, T = 64.  Levels k <= 6
+// receive T / 2^k new values per flush (compile-time counts); deeper levels
+// receive at most one.
+#include <hip/hip_runtime.h>
+
+#include "corr_kernels.h"
+
+namespace corr {
+
+namespace {
+
+template <int K> struct RK;
+template <> struct RK<K_F32_F64>   { using S = float;  using A = double; using PT = double; static constexpr int NP = 1; };
+template <> struct RK<K_F32_KAHAN> { using S = float;  using A = float;  using PT = float;  static constexpr int NP = 2; };
+template <> struct RK<K_F32_F32>   { using S = float;  using A = float;  using PT = float;  static constexpr int NP = 1; };
+
+// part += x * r in the partial-sum precision (products of single-precision
+// samples are exact in double).
+__device__ __forceinline__ void pmac(double &pt, float x, float r) { pt = __builtin_fma((double)x, (double)r, pt); }
+__device__ __forceinline__ void pmac(float &pt, float x, float r) { pt = __builtin_fmaf(x, r, pt); }
+
+// Fold a partial sum into a stored accumulator (compensated: Kahan step on
+// the partial, true value = h - c).
+template <int K> struct Fold;
+template <> struct Fold<K_F32_F64> {
+    static __device__ __forceinline__ void add(double &h, double &, double pt) { h += pt; }
+    static __device__ __forceinline__ double value(double h, double) { return h; }
+};
+template <> struct Fold<K_F32_F32> {
+    static __device__ __forceinline__ void add(float &h, float &, float pt) { h += pt; }
+    static __device__ __forceinline__ double value(float h, float) { return (double)h; }
+};
+template <> struct Fold<K_F32_KAHAN> {
+    static __device__ __forceinline__ void add(float &h, float &c, float pt)
+    {
+        float y = pt - c;
+        float t = h + y;
+        c = (t - h) - y;
+        h = t;
+    }
+    static __device__ __forceinline__ double value(float h, float c) { return (double)h - (double)c; }
+};
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+struct Ctx {
+    const DeferredArgs *a;
+    int64_t f;       // pushes already folded (multiple of kDeferT)
+    int r;           // pushes folded by this pass
+    char *tb;        // tile base
+    int lane;        // channel within the tile
+    bool valid;      // channel < n_ch
+    bool reduce_me;  // channel in [ch_begin, ch_end)
+    int64_t ch;      // global channel index
+};
+
+// Accumulator rows of level k: value rows start at acc; compensation rows
+// follow nl rows later.
+template <int K, int P>
+__device__ __forceinline__ typename RK<K>::A *acc_rows(const Ctx &cx, int k, int &nl)
+{
+    using S = typename RK<K>::S;
+    using A = typename RK<K>::A;
+    const GroupArgs &g = cx.a->g;
+    const int tw = g.tw;
+    if (k == 0) {
+        nl = P;
+        return reinterpret_cast<A *>(cx.tb + (int64_t)g.p0 * tw * (int64_t)sizeof(S));
+    }
+    nl = P - P / 2;
+    char *lvl = cx.tb + g.lvl0_bytes + (int64_t)(k - 1) * g.lvlk_bytes;
+    return reinterpret_cast<A *>(lvl + (int64_t)P * tw * (int64_t)sizeof(S));
+}
+
+// Index of the first readout entry of level k after S pushes (entries are the
+// (level, lag) pairs with a non-zero count, level-major, lag-minor).
+template <int P>
+__device__ __forceinline__ int entry_offset(int k, int64_t S)
+{
+    int off = 0;
+    int64_t sk = S;
+    for (int j = 0; j < k; ++j) {
+        const int l0 = j == 0 ? 0 : P / 2;
+        const int64_t hi = sk < P ? sk : P;
+        if (hi > l0) off += (int)(hi - l0);
+        sk >>= 1;
+    }
+    return off;
+}
+
+// Fold the level's partial sums into its accumulators.  Flush mode stores
+// them; readout mode reduces value(h, c) over the block instead.
+template <int K, int P, int NL, bool READ>
+__device__ __forceinline__ void fold_level(Ctx &cx, int k, const typename RK<K>::PT (&part)[NL],
+                                           bool any_pending)
+{
+    using A = typename RK<K>::A;
+    constexpr int NP = RK<K>::NP;
+    int nl;
+    A *hi = acc_rows<K, P>(cx, k, nl);
+    A *lo = hi + (size_t)nl * cx.a->g.tw;
+    const int tw = cx.a->g.tw;
+    if constexpr (!READ) {
+        if (!any_pending) return;
+        A h[NL], c[NL];
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            h[j] = __builtin_nontemporal_load(&hi[(size_t)j * tw + cx.lane]);
+            if constexpr (NP == 2) c[j] = __builtin_nontemporal_load(&lo[(size_t)j * tw + cx.lane]); else c[j] = A(0);
+        }
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            Fold<K>::add(h[j], c[j], (A)part[j]);
+            __builtin_nontemporal_store(h[j], &hi[(size_t)j * tw + cx.lane]);
+            if constexpr (NP == 2) __builtin_nontemporal_store(c[j], &lo[(size_t)j * tw + cx.lane]);
+        }
+    } else {
+        const DeferredArgs &a = *cx.a;
+        const int64_t S = cx.f + cx.r;
+        int64_t sk = S >> k;
+        const int l0 = k == 0 ? 0 : P / 2;
+        const int hi_lag = (int)(sk < P ? sk : P); // lags [l0, hi_lag) have counts
+        if (hi_lag <= l0) return;
+        const int e0 = entry_offset<P>(k, S);
+        const bool in_slice = cx.valid && cx.ch >= a.slice_begin && cx.ch < a.slice_end;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const int L = l0 + j;
+            if (L < hi_lag) {
+                A h = hi[(size_t)j * tw + cx.lane];
+                A c = A(0);
+                if constexpr (NP == 2) c = lo[(size_t)j * tw + cx.lane];
+                if (any_pending) Fold<K>::add(h, c, (A)part[j]);
+                const double v = Fold<K>::value(h, c);
+                const int e = e0 + j;
+                if (in_slice) a.slice_out[(size_t)(cx.ch - a.slice_begin) * a.ne + e] = v;
+                // Fixed-order sum over the wave's 64 consecutive channels (a
+                // chunk aligned to 64 whatever the tile width).
+                const double s = wave_sum(cx.reduce_me ? v : 0.0);
+                if ((threadIdx.x & 63) == 0) a.chunk_partial[(size_t)(cx.ch >> 6) * a.ne + e] = s;
+            }
+        }
+    }
+}
+
+// Level 0: fold the r pending pushes (f, f + r] into the lag sums and form the
+// level-1 block means.  out[q] = mean of new values 2q, 2q+1.
+template <int K, int P, int T, bool READ>
+__device__ __forceinline__ void level0(Ctx &cx, typename RK<K>::S (&out)[T / 2])
+{
+    using S = typename RK<K>::S;
+    using PT = typename RK<K>::PT;
+    const DeferredArgs &a = *cx.a;
+    const GroupArgs &g = a.g;
+    const int tw = g.tw;
+    const int P0 = g.p0;
+    const S *ring = reinterpret_cast<const S *>(cx.tb);
+    const int64_t f = cx.f;
+    const int r = cx.r;
+    S H[P - 1 + T];
+    // old values f-P+2 .. f, then new values f+1 .. f+r (zeros beyond r)
+#pragma unroll
+    for (int i = 0; i < P - 1 + T; ++i) {
+        const int64_t j = f - (P - 2) + i;
+        const int q = i - (P - 1);
+        if (q < r) {
+            const int slot = (int)((j - 1 + P0) % P0);
+            H[i] = __builtin_nontemporal_load(&ring[(size_t)slot * tw + cx.lane]);
+        } else {
+            H[i] = S(0);
+        }
+    }
+    PT part[P];
+#pragma unroll
+    for (int L = 0; L < P; ++L) part[L] = PT(0);
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+        if (q < r) {
+            const S x = H[P - 1 + q];
+#pragma unroll
+            for (int L = 0; L < P; ++L) pmac(part[L], x, H[P - 1 + q - L]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < T / 2; ++q) out[q] = (H[P - 1 + 2 * q] + H[P + 2 * q]) / S(2);
+    fold_level<K, P, P, READ>(cx, 0, part, r > 0);
+}
+
+// Level k >= 1 receiving n_in <= N new values in[0..n_in) (level-k values
+// f_k+1 .. f_k+n_in).  Adds lags P/2..P-1, writes the new ring slots (flush
+// mode) and forms the level-(k+1) means (n_out of them).
+template <int K, int P, int N, bool READ>
+__device__ __forceinline__ void level_k(Ctx &cx, int k, const typename RK<K>::S (&in)[N],
+                                        int n_in, typename RK<K>::S (&out)[(N >= 2 ? N / 2 : 1)],
+                                        int &n_out)
+{
+    using S = typename RK<K>::S;
+    using PT = typename RK<K>::PT;
+    constexpr int NL = P - P / 2;
+    const DeferredArgs &a = *cx.a;
+    const GroupArgs &g = a.g;
+    const int tw = g.tw;
+    S *ring = reinterpret_cast<S *>(cx.tb + g.lvl0_bytes + (int64_t)(k - 1) * g.lvlk_bytes);
+    const int64_t fk = cx.f >> k; // level-k values already in the ring
+    S H[P - 1 + N];
+#pragma unroll
+    for (int i = 0; i < P - 1; ++i) {
+        const int64_t v = fk - (P - 2) + i; // value number (1-based)
+        const int slot = (int)((v - 1 + P) % P);
+        H[i] = __builtin_nontemporal_load(&ring[(size_t)slot * tw + cx.lane]);
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) H[P - 1 + q] = q < n_in ? in[q] : S(0);
+    PT part[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) part[j] = PT(0);
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        if (q < n_in) {
+            const S x = H[P - 1 + q];
+#pragma unroll
+            for (int j = 0; j < NL; ++j) pmac(part[j], x, H[P - 1 + q - (P / 2 + j)]);
+        }
+    }
+    if constexpr (!READ) {
+        // ring slots of the new values (only the last P of them survive)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            if (q < n_in && q >= n_in - P) {
+                const int64_t v = fk + 1 + q;
+                const int slot = (int)((v - 1) % P);
+                __builtin_nontemporal_store(H[P - 1 + q], &ring[(size_t)slot * tw + cx.lane]);
+            }
+        }
+    }
+    if constexpr (N >= 2) {
+        // f_k is a multiple of N here, so new values pair up as (2q, 2q+1)
+#pragma unroll
+        for (int q = 0; q < N / 2; ++q) out[q] = (H[P - 1 + 2 * q] + H[P + 2 * q]) / S(2);
+        n_out = n_in / 2;
+    } else {
+        n_out = 0;
+        out[0] = S(0);
+        if (n_in == 1 && ((fk + 1) & 1) == 0) {
+            out[0] = (H[P - 2] + H[P - 1]) / S(2);
+            n_out = 1;
+        }
+    }
+    fold_level<K, P, NL, READ>(cx, k, part, n_in > 0);
+}
+
+// Levels k .. b-1 starting with N new values.
+template <int K, int P, int N, bool READ>
+__device__ __forceinline__ void cascade(Ctx &cx, int k, const typename RK<K>::S (&in)[N], int n_in)
+{
+    using S = typename RK<K>::S;
+    const int b = cx.a->g.levels;
+    if (k >= b) return;
+    if constexpr (N >= 2) {
+        S out[N / 2];
+        int n_out;
+        level_k<K, P, N, READ>(cx, k, in, n_in, out, n_out);
+        cascade<K, P, N / 2, READ>(cx, k + 1, out, n_out);
+    } else {
+        S cur[1] = {in[0]};
+        int n = n_in;
+        for (int kk = k; kk < b; ++kk) {
+            if (n == 0 && !READ) break;
+            S nxt[1];
+            int nn;
+            level_k<K, P, 1, READ>(cx, kk, cur, n, nxt, nn);
+            cur[0] = nxt[0];
+            n = nn;
+        }
+    }
+}
+
+template <int K, int P, int T, bool READ>
+__global__ __launch_bounds__(256) void deferred_kernel(DeferredArgs a)
+{
+    const GroupArgs &g = a.g;
+    const int64_t tile = blockIdx.x;
+    // A flush folds the kDeferT pushes ending with the current one (the
+    // counter is advanced after it); a readout folds the pushes after the
+    // last flush.
+    const int64_t S = READ ? *a.step : *a.step + 1;
+    const int64_t f = READ ? (S / kDeferT) * kDeferT : S - kDeferT;
+    const int r = (int)(S - f);
+    for (int sub = 0; sub * (int)blockDim.x < g.tw; ++sub) {
+        // whole waves past the tile's end skip the pass (tw is a multiple of 64)
+        if (sub * (int)blockDim.x + (int)(threadIdx.x & ~63u) >= g.tw) continue;
+        Ctx cx;
+        cx.a = &a;
+        cx.f = f;
+        cx.r = r;
+        cx.tb = g.state + tile * g.tile_bytes;
+        cx.lane = sub * blockDim.x + threadIdx.x;
+        cx.ch = tile * g.tw + cx.lane;
+        cx.valid = cx.ch < g.n_ch;
+        cx.reduce_me = cx.valid && cx.ch >= a.ch_begin && cx.ch < a.ch_end;
+        typename RK<K>::S l1[T / 2];
+        level0<K, P, T, READ>(cx, l1);
+        cascade<K, P, T / 2, READ>(cx, 1, l1, r / 2);
+    }
+}
+
+// Column sums of rows [n_rows][ne] in a fixed order: groups of kColGroup rows
+// (grid.y), then the groups in order.
+constexpr int kColGroup = 1024;
+
+__global__ void colsum_group_kernel(const double *rows, int64_t n_rows, int ne, double *groups)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int64_t r0 = (int64_t)blockIdx.y * kColGroup;
+    int64_t r1 = r0 + kColGroup;
+    if (r1 > n_rows) r1 = n_rows;
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) s += rows[(size_t)r * ne + e];
+    groups[(size_t)blockIdx.y * ne + e] = s;
+}
+
+__global__ void colsum_final_kernel(const double *groups, int64_t n_groups, int ne, double *out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    double s = 0.0;
+    for (int64_t q = 0; q < n_groups; ++q) s += groups[(size_t)q * ne + e];
+    out[e] = s;
+}
+
+template <int K, int P, bool READ>
+hipError_t launch_deferred_kp(const DeferredArgs &a, hipStream_t st)
+{
+    const int block = a.g.tw < 256 ? a.g.tw : 256;
+    hipLaunchKernelGGL((deferred_kernel<K, P, kDeferT, READ>), dim3((unsigned)a.g.n_tiles),
+                       dim3(block), 0, st, a);
+    return hipGetLastError();
+}
+
+template <bool READ>
+hipError_t launch_deferred_t(const DeferredArgs &a, hipStream_t st)
+{
+    if (a.g.p != 16) return hipErrorInvalidValue;
+    switch (a.g.kind) {
+    case K_F32_F64: return launch_deferred_kp<K_F32_F64, 16, READ>(a, st);
+    case K_F32_KAHAN: return launch_deferred_kp<K_F32_KAHAN, 16, READ>(a, st);
+    case K_F32_F32: return launch_deferred_kp<K_F32_F32, 16, READ>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Per-push staging of one block-deferred group: sample c -> level-0 ring slot
+// (s - 1) mod p0 of its tile.  Each thread moves kStageVec consecutive
+// channels (one 16-byte load and store) for kStageUnroll grid strides, all
+// loads issued before the stores.
+constexpr int kStageVec = 4;
+constexpr int kStageUnroll = 4;
+
+__global__ __launch_bounds__(256) void stage_kernel(GroupArgs g, const int64_t *step, int aligned)
+{
+    const int64_t s = *step + 1;
+    const int slot = (int)((s - 1) % g.p0);
+    const float *src = static_cast<const float *>(g.samples);
+    const int64_t n = g.n_ch;
+    const int64_t nvec = (n + kStageVec - 1) / kStageVec;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v0 < nvec;
+         v0 += stride * kStageUnroll) {
+        float4 x[kStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int64_t v = v0 + u * stride;
+            const int64_t c = v * kStageVec;
+            if (v < nvec) {
+                if (aligned && c + kStageVec <= n) {
+                    x[u] = *reinterpret_cast<const float4 *>(src + c);
+                } else {
+                    x[u].x = c + 0 < n ? src[c + 0] : 0.f;
+                    x[u].y = c + 1 < n ? src[c + 1] : 0.f;
+                    x[u].z = c + 2 < n ? src[c + 2] : 0.f;
+                    x[u].w = c + 3 < n ? src[c + 3] : 0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int64_t v = v0 + u * stride;
+            if (v < nvec) {
+                const int64_t c = v * kStageVec;
+                const int64_t tile = c / g.tw;
+                const int64_t lane = c - tile * g.tw;
+                float *ring = reinterpret_cast<float *>(g.state + tile * g.tile_bytes);
+                *reinterpret_cast<float4 *>(ring + (size_t)slot * g.tw + lane) = x[u];
+            }
+        }
+    }
+}
+
+} // namespace
+
+hipError_t launch_stage(const GroupArgs &g, const int64_t *step, hipStream_t st)
+{
+    // single-precision samples only (the deferred form's kinds); 16-byte
+    // vectors need a 16-byte aligned source
+    const int aligned = ((uintptr_t)g.samples % 16) == 0;
+    const int64_t nvec = (g.n_ch + kStageVec - 1) / kStageVec;
+    int64_t blocks = (nvec + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(stage_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, step, aligned);
+    return hipGetLastError();
+}
+
+bool deferred_supported(int kind, int p, int m)
+{
+    return m == 2 && p == 16 && (kind == K_F32_F64 || kind == K_F32_KAHAN || kind == K_F32_F32);
+}
+
+hipError_t launch_flush(const DeferredArgs &a, hipStream_t st) { return launch_deferred_t<false>(a, st); }
+
+int64_t deferred_readout_rows(const GroupArgs &g) { return g.n_tiles * (int64_t)g.tw / 64; }
+
+int64_t deferred_readout_groups(const GroupArgs &g)
+{
+    return (deferred_readout_rows(g) + kColGroup - 1) / kColGroup;
+}
+
+hipError_t launch_deferred_readout(const DeferredArgs &a, double *groups, double *sums,
+                                   hipStream_t st)
+{
+    hipError_t e = launch_deferred_t<true>(a, st);
+    if (e != hipSuccess) return e;
+    const int64_t n_rows = deferred_readout_rows(a.g);
+    const int64_t n_groups = deferred_readout_groups(a.g);
+    const unsigned ex = (unsigned)((a.ne + 63) / 64);
+    hipLaunchKernelGGL(colsum_group_kernel, dim3(ex, (unsigned)n_groups), dim3(64), 0, st,
+                       a.chunk_partial, n_rows, a.ne, groups);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(ex), dim3(64), 0, st, groups, n_groups, a.ne,
+                       sums);
+    return hipGetLastError();
+}
+
+} // namespace corr

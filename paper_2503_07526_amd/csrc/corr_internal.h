@@ -49,6 +49,25 @@ struct GroupArgs {
     int32_t tw;          // channels per tile
     int32_t s_bytes;     // bytes per sample
     int32_t a_bytes;     // bytes per accumulator plane element
+    int32_t deferred;    // 1: block-deferred form (pushes only stage samples)
+    int32_t p0;          // ring rows of level 0 (p, or kDeferT + p when deferred)
+};
+
+// Pushes staged between two flushes of a block-deferred group.
+constexpr int kDeferT = 64;
+
+// Flush / readout of a block-deferred group.
+struct DeferredArgs {
+    GroupArgs g;
+    const int64_t *step;    // device push counter: a flush runs before the
+                            // increment of the push that completes a block of
+                            // kDeferT pushes; a readout after it
+    int32_t ne;             // readout: number of (level, lag) entries
+    int32_t pad_;
+    int64_t ch_begin, ch_end;       // readout: channels reduced
+    int64_t slice_begin, slice_end; // readout: channels written to slice_out
+    double *chunk_partial;  // readout: [n_tiles * tw / 64][ne] sums over 64-channel chunks
+    double *slice_out;      // readout: [(c - slice_begin) * ne + e]
 };
 
 struct PushArgs {
@@ -80,21 +99,26 @@ inline int kind_acc_bytes(int kind)
     }
 }
 
-// k-density producer arguments.
+// k-density producer: k-vectors are grouped in segments of up to kSegWidth
+// vectors sharing (n_y, n_z) with n_x in [nx0, nx0 + kSegWidth).
+constexpr int kSegWidth = 4;
+
 struct RhokArgs {
-    const float *pos;      // [3][n_atoms]
+    const float *pos;        // [3][n_atoms]
     int64_t n_atoms;
-    const int32_t *kq;     // [nk][3] integer k-vectors, sorted by (nz, ny, nx)
-    const int32_t *kperm;  // [nk]: output index of sorted k-vector q
-    int32_t nk;
-    int32_t n_chunks;      // k-chunks
-    double inv_box;        // 1 / L
-    double *partial;       // [n_atom_blocks][nk][2] FP64 partial sums
+    const int32_t *seg_nx0;  // [n_seg]
+    const int32_t *seg_ny;   // [n_seg]
+    const int32_t *seg_nz;   // [n_seg]
+    const int32_t *slot_out; // [n_seg * kSegWidth]: output k index of slot, or -1
+    int32_t n_seg;
+    int32_t nmax;            // max |n component|
+    double inv_box;          // 1 / L
+    double *partial;         // [n_atom_blocks][n_seg * kSegWidth][2] FP64 partial sums
     int32_t n_atom_blocks;
     int32_t atoms_per_block;
-    void *out;             // [nk] complex samples (float2 or double2)
-    int32_t out_double;    // 1: double2 output
-    int32_t nmax;          // max |n component|
+    void *out;               // [nk] complex samples (float2 or double2)
+    int32_t out_double;      // 1: double2 output
+    int32_t pad_;
 };
 
 // Readout reduction arguments.

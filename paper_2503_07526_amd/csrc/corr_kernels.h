@@ -15,7 +15,15 @@ hipError_t launch_push_group(const GroupArgs &g, const int64_t *step, int cpt, i
 hipError_t launch_step_increment(int64_t *step, hipStream_t st);
 hipError_t launch_rhok(const RhokArgs &a, hipStream_t st);
 int rhok_tile_atoms(int nmax);
+int rhok_block_threads(int n_seg);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
+bool deferred_supported(int kind, int p, int m);
+hipError_t launch_stage(const GroupArgs &g, const int64_t *step, hipStream_t st);
+hipError_t launch_flush(const DeferredArgs &a, hipStream_t st);
+int64_t deferred_readout_rows(const GroupArgs &g);
+int64_t deferred_readout_groups(const GroupArgs &g);
+hipError_t launch_deferred_readout(const DeferredArgs &a, double *groups, double *sums,
+                                   hipStream_t st);
 hipError_t launch_gather(const ReduceArgs &a, hipStream_t st);
 
 } // namespace corr

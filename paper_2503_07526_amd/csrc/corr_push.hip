@@ -216,6 +216,15 @@ __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int6
     char *tb = g.state + tile * g.tile_bytes;
     const int64_t rowS = (int64_t)tw * (int64_t)sizeof(S);
 
+    if (g.deferred) {
+        // Block-deferred group: only stage the sample in the level-0 ring
+        // (kDeferT + p slots); the flush pass folds kDeferT pushes at once.
+        S *ring = reinterpret_cast<S *>(tb);
+        const int slot = (int)((s - 1) % g.p0);
+        vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, x);
+        return;
+    }
+
     // Level 0: ring write and lags 0..min(s, p)-1.
     {
         S *ring = reinterpret_cast<S *>(tb);

@@ -28,6 +28,8 @@ struct Group {
     int kind = 0;
     int p = 0, m = 0, b = 0, lag0 = 0, nlk = 0;
     int s_bytes = 0, a_bytes = 0, np = 1;
+    bool deferred = false; // block-deferred form (stage per push, flush every kDeferT)
+    int p0 = 0;            // ring rows of level 0
     int64_t n_ch = 0, n_tiles = 0, tile_bytes = 0, lvl0_bytes = 0, lvlk_bytes = 0;
     char *state = nullptr;
     void *input = nullptr;     // buffer read when a push passes NULL (own or bound)
@@ -36,8 +38,7 @@ struct Group {
     // k-density producer
     bool rhok = false;
     void *rhok_out = nullptr;
-    int32_t *d_kq = nullptr;
-    int32_t *d_kperm = nullptr;
+    int32_t *d_seg = nullptr; // seg_nx0 | seg_ny | seg_nz | slot_out
     double *d_partial = nullptr;
     RhokArgs rargs{};
 };
@@ -58,17 +59,22 @@ struct corr_ctx {
     // k-density groups run on a side stream (producer, then their own push
     // launch) forked from and joined to the main stream on every push, so the
     // ALU-bound producer overlaps the HBM-bound push of the other groups.
+    // main_set: per-step (direct) groups fed with samples; side_set: k-density
+    // groups; deferred_set (below): block-deferred groups (staged per push).
     std::vector<int> main_set, side_set; // context group indices
-    PushArgs pa_main{}, pa_side{};
+    PushArgs pa_main{}, pa_side{}, pa_direct{}; // pa_direct: main_set + side_set
     hipStream_t side_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    // push-kernel timing (CORR_FLAG_TIMING)
-    std::vector<hipEvent_t> ev_start, ev_end;
-    size_t ev_used = 0;
-    double timed_ms = 0.0;
-    int64_t timed_pushes = 0;
+    hipGraph_t graph = nullptr, graph_flush = nullptr;
+    hipGraphExec_t gexec = nullptr, gexec_flush = nullptr; // without / with the flush
+    std::vector<int> deferred_set; // context group indices in the block-deferred form
+    // update-kernel timing (CORR_FLAG_TIMING): pool 0 per push, pool 1 per flush
+    struct EventPool {
+        std::vector<hipEvent_t> start, end;
+        size_t used = 0;
+        double ms = 0.0;
+        int64_t n = 0;
+    } pools[2];
     // readout scratch
     void *d_scratch = nullptr;
     size_t scratch_bytes = 0;
@@ -187,8 +193,7 @@ void free_group(Group &g)
     if (g.state) (void)hipFree(g.state);
     if (g.own_input) (void)hipFree(g.own_input);
     if (g.rhok_out) (void)hipFree(g.rhok_out);
-    if (g.d_kq) (void)hipFree(g.d_kq);
-    if (g.d_kperm) (void)hipFree(g.d_kperm);
+    if (g.d_seg) (void)hipFree(g.d_seg);
     if (g.d_partial) (void)hipFree(g.d_partial);
     g = Group{};
 }
@@ -207,45 +212,64 @@ void free_ctx(corr_ctx *c)
     for (auto &g : c->groups) free_group(g);
     if (c->d_step) (void)hipFree(c->d_step);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
-    for (auto e : c->ev_start) (void)hipEventDestroy(e);
-    for (auto e : c->ev_end) (void)hipEventDestroy(e);
+    for (auto &pl : c->pools) {
+        for (auto e : pl.start) (void)hipEventDestroy(e);
+        for (auto e : pl.end) (void)hipEventDestroy(e);
+    }
+    if (c->gexec_flush) (void)hipGraphExecDestroy(c->gexec_flush);
+    if (c->graph_flush) (void)hipGraphDestroy(c->graph_flush);
     delete c;
 }
 
 constexpr size_t kEventPool = 1024;
 
-// Fold the elapsed times of all recorded event pairs into the total.
-int fold_events(corr_ctx *c)
+// Fold the elapsed times of all recorded event pairs of a pool into its total.
+int fold_events(corr_ctx *c, int which)
 {
-    if (c->ev_used == 0) return CORR_OK;
-    HIP_TRY(c, hipEventSynchronize(c->ev_end[c->ev_used - 1]));
-    for (size_t i = 0; i < c->ev_used; ++i) {
+    auto &pl = c->pools[which];
+    if (pl.used == 0) return CORR_OK;
+    HIP_TRY(c, hipEventSynchronize(pl.end[pl.used - 1]));
+    for (size_t i = 0; i < pl.used; ++i) {
         float ms = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_start[i], c->ev_end[i]));
-        c->timed_ms += (double)ms;
+        HIP_TRY(c, hipEventElapsedTime(&ms, pl.start[i], pl.end[i]));
+        pl.ms += (double)ms;
     }
-    c->timed_pushes += (int64_t)c->ev_used;
-    c->ev_used = 0;
+    pl.n += (int64_t)pl.used;
+    pl.used = 0;
     return CORR_OK;
 }
 
-// Next free event pair (folds the pool when it is full).
-int next_events(corr_ctx *c, hipEvent_t *a, hipEvent_t *b)
+// Next free event pair of a pool (folds the pool when it is full).
+int next_events(corr_ctx *c, int which, hipEvent_t *a, hipEvent_t *b)
 {
-    if (c->ev_used == kEventPool) {
-        int rc = fold_events(c);
+    auto &pl = c->pools[which];
+    if (pl.used == kEventPool) {
+        int rc = fold_events(c, which);
         if (rc != CORR_OK) return rc;
     }
-    if (c->ev_used == c->ev_start.size()) {
+    if (pl.used == pl.start.size()) {
         hipEvent_t e0, e1;
         HIP_TRY(c, hipEventCreate(&e0));
         HIP_TRY(c, hipEventCreate(&e1));
-        c->ev_start.push_back(e0);
-        c->ev_end.push_back(e1);
+        pl.start.push_back(e0);
+        pl.end.push_back(e1);
     }
-    *a = c->ev_start[c->ev_used];
-    *b = c->ev_end[c->ev_used];
-    c->ev_used += 1;
+    *a = pl.start[pl.used];
+    *b = pl.end[pl.used];
+    pl.used += 1;
+    return CORR_OK;
+}
+
+// Flush launches of every block-deferred group (the push being issued
+// completes a block of kDeferT pushes).
+int launch_flushes(corr_ctx *c, hipStream_t st)
+{
+    for (int i : c->deferred_set) {
+        DeferredArgs da{};
+        da.g = c->pargs.g[(size_t)i];
+        da.step = c->d_step;
+        HIP_TRY(c, launch_flush(da, st));
+    }
     return CORR_OK;
 }
 
@@ -271,15 +295,29 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
 }
 
 // Issue one push of every group on stream `st` with the given per-group
-// sample pointers (already resolved, never NULL).
-int issue_push(corr_ctx *c, const void *const *src, hipStream_t st)
+// sample pointers (already resolved, never NULL).  Order on the main stream:
+// staging of block-deferred groups, fork of the k-density branch (producer +
+// push of the k-density groups on the side stream), per-step push of the
+// other groups, flush (every kDeferT pushes), join, step counter.
+int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_flush)
 {
     const size_t ng = c->groups.size();
     std::vector<const void *> resolved(ng);
     for (size_t i = 0; i < ng; ++i) resolved[i] = c->groups[i].rhok ? c->groups[i].rhok_out : src[i];
     // Events are only recorded on direct launches, never while capturing.
     const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream;
-    const bool fork = !c->side_set.empty() && !c->main_set.empty();
+    const bool fork = !c->side_set.empty() && (!c->main_set.empty() || !c->deferred_set.empty());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        int rc = next_events(c, 0, &e0, &e1);
+        if (rc != CORR_OK) return rc;
+        HIP_TRY(c, hipEventRecord(e0, st));
+    }
+    for (int i : c->deferred_set) {
+        GroupArgs ga = c->pargs.g[(size_t)i];
+        ga.samples = resolved[(size_t)i];
+        HIP_TRY(c, launch_stage(ga, c->d_step, st));
+    }
     if (fork) {
         HIP_TRY(c, hipEventRecord(c->ev_fork, st));
         HIP_TRY(c, hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
@@ -294,21 +332,28 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st)
         int rc = launch_set(c, c->pa_side, c->side_set, resolved, pst);
         if (rc != CORR_OK) return rc;
         HIP_TRY(c, hipEventRecord(c->ev_join, pst));
-    }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed) {
-        int rc = next_events(c, &e0, &e1);
-        if (rc != CORR_OK) return rc;
-        HIP_TRY(c, hipEventRecord(e0, st));
-    }
-    if (fork) {
-        int rc = launch_set(c, c->pa_main, c->main_set, resolved, st);
-        if (rc != CORR_OK) return rc;
+        if (!c->main_set.empty()) {
+            rc = launch_set(c, c->pa_main, c->main_set, resolved, st);
+            if (rc != CORR_OK) return rc;
+        }
     } else {
-        std::vector<int> all(ng);
-        for (size_t i = 0; i < ng; ++i) all[i] = (int)i;
-        int rc = launch_set(c, c->pargs, all, resolved, st);
+        std::vector<int> idx(c->main_set);
+        idx.insert(idx.end(), c->side_set.begin(), c->side_set.end());
+        if (!idx.empty()) {
+            int rc = launch_set(c, c->pa_direct, idx, resolved, st);
+            if (rc != CORR_OK) return rc;
+        }
+    }
+    if (with_flush && !c->deferred_set.empty()) {
+        hipEvent_t f0 = nullptr, f1 = nullptr;
+        if (timed) {
+            int rc = next_events(c, 1, &f0, &f1);
+            if (rc != CORR_OK) return rc;
+            HIP_TRY(c, hipEventRecord(f0, st));
+        }
+        int rc = launch_flushes(c, st);
         if (rc != CORR_OK) return rc;
+        if (timed) HIP_TRY(c, hipEventRecord(f1, st));
     }
     if (timed) HIP_TRY(c, hipEventRecord(e1, st));
     if (fork) HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
@@ -316,22 +361,14 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st)
     return CORR_OK;
 }
 
-// (Re)capture one push of every group, reading the current input buffers,
-// into c->gexec.
-int capture_graph(corr_ctx *c)
+// Capture one push of every group (reading the current input buffers) into a
+// graph, with or without the flush of the block-deferred groups.
+int capture_one(corr_ctx *c, bool with_flush, hipGraph_t *g_out, hipGraphExec_t *x_out)
 {
-    if (c->gexec) {
-        (void)hipGraphExecDestroy(c->gexec);
-        c->gexec = nullptr;
-    }
-    if (c->graph) {
-        (void)hipGraphDestroy(c->graph);
-        c->graph = nullptr;
-    }
     std::vector<const void *> src(c->groups.size());
     for (size_t i = 0; i < c->groups.size(); ++i) src[i] = c->groups[i].input;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = issue_push(c, src.data(), c->cap_stream);
+    int rc = issue_push(c, src.data(), c->cap_stream, with_flush);
     hipGraph_t graph = nullptr;
     hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
     if (rc != CORR_OK) {
@@ -339,9 +376,24 @@ int capture_graph(corr_ctx *c)
         return rc;
     }
     if (ec != hipSuccess) return hip_err(c, ec, "hipStreamEndCapture");
-    c->graph = graph;
-    HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    *g_out = graph;
+    HIP_TRY(c, hipGraphInstantiate(x_out, graph, nullptr, nullptr, 0));
     return CORR_OK;
+}
+
+// (Re)capture the push graphs.
+int capture_graph(corr_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->gexec_flush) (void)hipGraphExecDestroy(c->gexec_flush);
+    if (c->graph_flush) (void)hipGraphDestroy(c->graph_flush);
+    c->gexec = c->gexec_flush = nullptr;
+    c->graph = c->graph_flush = nullptr;
+    int rc = capture_one(c, false, &c->graph, &c->gexec);
+    if (rc != CORR_OK) return rc;
+    if (!c->deferred_set.empty()) rc = capture_one(c, true, &c->graph_flush, &c->gexec_flush);
+    return rc;
 }
 
 int ensure_scratch(corr_ctx *c, size_t bytes)
@@ -383,7 +435,8 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     if (!groups || n_groups < 1) return set_err(nullptr, CORR_E_INVALID, "need at least one group");
     if (n_groups > kMaxGroups)
         return set_err(nullptr, CORR_E_UNSUPPORTED, "at most %d groups per context", kMaxGroups);
-    if (flags & ~(uint32_t)(CORR_FLAG_GRAPH | CORR_FLAG_PER_GROUP | CORR_FLAG_TIMING))
+    if (flags & ~(uint32_t)(CORR_FLAG_GRAPH | CORR_FLAG_PER_GROUP | CORR_FLAG_TIMING |
+                            CORR_FLAG_DIRECT))
         return set_err(nullptr, CORR_E_INVALID, "unknown flags 0x%x", flags);
     for (int i = 0; i < n_groups; ++i) {
         int rc = validate(groups[i], i);
@@ -446,7 +499,10 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         g.n_tiles = (g.n_ch + tw - 1) / tw;
         const int64_t rowS = (int64_t)tw * g.s_bytes;
         const int64_t rowA = (int64_t)tw * g.a_bytes;
-        g.lvl0_bytes = g.p * rowS + (int64_t)g.np * g.p * rowA;
+        g.deferred = !(flags & CORR_FLAG_DIRECT) && g.d.source == CORR_SRC_SAMPLES &&
+                     deferred_supported(g.kind, g.p, g.m);
+        g.p0 = g.deferred ? kDeferT + g.p : g.p;
+        g.lvl0_bytes = g.p0 * rowS + (int64_t)g.np * g.p * rowA;
         g.lvlk_bytes = g.p * rowS + (int64_t)g.np * g.nlk * rowA;
         g.tile_bytes = g.lvl0_bytes + (int64_t)(g.b - 1) * g.lvlk_bytes;
         const size_t state_bytes = (size_t)g.n_tiles * (size_t)g.tile_bytes;
@@ -457,52 +513,69 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         if (g.rhok) {
             g.input_bytes = (size_t)3 * (size_t)g.d.n_atoms * sizeof(float);
             const int nk = (int)g.n_ch;
-            // Sort k-vectors by (nz, ny, nx) so that neighbouring threads read
-            // neighbouring table entries; kperm maps back to the caller's order.
+            // Segments: k-vectors sharing (n_y, n_z) with n_x in a window of
+            // kSegWidth, rows ordered by (n_z, n_y).
+            const int32_t *kv = groups[i].kvec;
             std::vector<int> order((size_t)nk);
             for (int q = 0; q < nk; ++q) order[(size_t)q] = q;
-            const int32_t *kv = groups[i].kvec;
             std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
                 for (int d = 2; d >= 0; --d)
                     if (kv[3 * x + d] != kv[3 * y + d]) return kv[3 * x + d] < kv[3 * y + d];
                 return false;
             });
-            std::vector<int32_t> kq((size_t)nk * 3), kperm((size_t)nk);
+            std::vector<int32_t> s_nx0, s_ny, s_nz, s_out;
             int nmax = 0;
-            for (int q = 0; q < nk; ++q) {
-                for (int d = 0; d < 3; ++d) {
-                    kq[(size_t)q * 3 + d] = kv[3 * order[(size_t)q] + d];
-                    nmax = std::max(nmax, std::abs(kv[3 * order[(size_t)q] + d]));
+            for (int q = 0; q < nk; ++q)
+                for (int d = 0; d < 3; ++d) nmax = std::max(nmax, std::abs(kv[3 * q + d]));
+            for (size_t u = 0; u < order.size();) {
+                const int k0 = order[u];
+                const int nx0 = kv[3 * k0], ny = kv[3 * k0 + 1], nz = kv[3 * k0 + 2];
+                int slots[kSegWidth];
+                for (int w = 0; w < kSegWidth; ++w) slots[w] = -1;
+                while (u < order.size()) {
+                    const int kq = order[u];
+                    const int w = kv[3 * kq] - nx0;
+                    if (kv[3 * kq + 1] != ny || kv[3 * kq + 2] != nz || w >= kSegWidth ||
+                        slots[w] >= 0)
+                        break;
+                    slots[w] = kq;
+                    ++u;
                 }
-                kperm[(size_t)q] = order[(size_t)q];
+                s_nx0.push_back(nx0);
+                s_ny.push_back(ny);
+                s_nz.push_back(nz);
+                for (int w = 0; w < kSegWidth; ++w) s_out.push_back(slots[w]);
             }
-            CREATE_HIP(hipMalloc(&g.d_kq, kq.size() * sizeof(int32_t)));
-            CREATE_HIP(hipMalloc(&g.d_kperm, kperm.size() * sizeof(int32_t)));
-            CREATE_HIP(hipMemcpy(g.d_kq, kq.data(), kq.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-            CREATE_HIP(hipMemcpy(g.d_kperm, kperm.data(), kperm.size() * sizeof(int32_t),
+            const int n_seg = (int)s_nx0.size();
+            std::vector<int32_t> packed;
+            packed.insert(packed.end(), s_nx0.begin(), s_nx0.end());
+            packed.insert(packed.end(), s_ny.begin(), s_ny.end());
+            packed.insert(packed.end(), s_nz.begin(), s_nz.end());
+            packed.insert(packed.end(), s_out.begin(), s_out.end());
+            CREATE_HIP(hipMalloc(&g.d_seg, packed.size() * sizeof(int32_t)));
+            CREATE_HIP(hipMemcpy(g.d_seg, packed.data(), packed.size() * sizeof(int32_t),
                                  hipMemcpyHostToDevice));
-            const int n_chunks = (nk + 255) / 256;
-            // Enough atom blocks to give every compute unit several blocks.
-            int n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(1024 / n_chunks, (g.d.n_atoms + 255) / 256));
-            n_ab = std::max(n_ab, 1);
+            // Atom blocks: about 1000 atoms or more each, at most 512 blocks.
+            const int n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(512, g.d.n_atoms / 1024));
             const int64_t apb = (g.d.n_atoms + n_ab - 1) / n_ab;
-            CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * nk * 2 * sizeof(double)));
+            CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * n_seg * kSegWidth * 2 * sizeof(double)));
             CREATE_HIP(hipMalloc(&g.rhok_out, (size_t)nk * g.s_bytes));
             CREATE_HIP(hipMemsetAsync(g.rhok_out, 0, (size_t)nk * g.s_bytes, c->stream));
             RhokArgs &r = g.rargs;
             r.pos = nullptr;
             r.n_atoms = g.d.n_atoms;
-            r.kq = g.d_kq;
-            r.kperm = g.d_kperm;
-            r.nk = nk;
-            r.n_chunks = n_chunks;
+            r.seg_nx0 = g.d_seg;
+            r.seg_ny = g.d_seg + n_seg;
+            r.seg_nz = g.d_seg + 2 * n_seg;
+            r.slot_out = g.d_seg + 3 * n_seg;
+            r.n_seg = n_seg;
+            r.nmax = nmax;
             r.inv_box = 1.0 / g.d.box;
             r.partial = g.d_partial;
             r.n_atom_blocks = n_ab;
             r.atoms_per_block = (int32_t)apb;
             r.out = g.rhok_out;
             r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
-            r.nmax = nmax;
         } else {
             g.input_bytes = (size_t)g.n_ch * g.s_bytes;
         }
@@ -527,17 +600,29 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         ga.tw = tw;
         ga.s_bytes = g.s_bytes;
         ga.a_bytes = g.a_bytes;
+        ga.deferred = g.deferred ? 1 : 0;
+        ga.p0 = g.p0;
+        if (g.deferred) c->deferred_set.push_back(i);
         tile_first += g.n_tiles;
     }
     c->pargs.n_groups = n_groups;
     c->pargs.total_tiles = tile_first;
     c->total_tiles = tile_first;
-    for (int i = 0; i < n_groups; ++i)
-        (c->groups[(size_t)i].rhok ? c->side_set : c->main_set).push_back(i);
-    if (!c->side_set.empty() && !c->main_set.empty()) {
-        for (int pass = 0; pass < 2; ++pass) {
-            const std::vector<int> &idx = pass == 0 ? c->main_set : c->side_set;
-            PushArgs &pa = pass == 0 ? c->pa_main : c->pa_side;
+    for (int i = 0; i < n_groups; ++i) {
+        const Group &g = c->groups[(size_t)i];
+        if (g.rhok)
+            c->side_set.push_back(i);
+        else if (!g.deferred)
+            c->main_set.push_back(i);
+    }
+    {
+        std::vector<int> both(c->main_set);
+        both.insert(both.end(), c->side_set.begin(), c->side_set.end());
+        const std::vector<int> *sets[3] = {&c->main_set, &c->side_set, &both};
+        PushArgs *pas[3] = {&c->pa_main, &c->pa_side, &c->pa_direct};
+        for (int pass = 0; pass < 3; ++pass) {
+            const std::vector<int> &idx = *sets[pass];
+            PushArgs &pa = *pas[pass];
             pa = c->pargs;
             int64_t tf = 0;
             for (size_t j = 0; j < idx.size(); ++j) {
@@ -548,6 +633,8 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
             pa.n_groups = (int32_t)idx.size();
             pa.total_tiles = tf;
         }
+    }
+    if (!c->side_set.empty() && (!c->main_set.empty() || !c->deferred_set.empty())) {
         CREATE_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
         CREATE_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         CREATE_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
@@ -557,6 +644,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     c->pargs.step = c->d_step;
     c->pa_main.step = c->d_step;
     c->pa_side.step = c->d_step;
+    c->pa_direct.step = c->d_step;
     CREATE_HIP(hipStreamSynchronize(c->stream));
 
     if (flags & CORR_FLAG_GRAPH) {
@@ -608,17 +696,18 @@ int corr_push(corr_ctx *ctx, const void *const *samples)
         if (p != ctx->groups[i].input) all_default = false;
         src[i] = p;
     }
+    const bool with_flush = !ctx->deferred_set.empty() && (ctx->n_push + 1) % kDeferT == 0;
     if (ctx->gexec && all_default) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (ctx->flags & CORR_FLAG_TIMING) {
-            int rc = next_events(ctx, &e0, &e1);
+            int rc = next_events(ctx, 0, &e0, &e1);
             if (rc != CORR_OK) return rc;
             HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
         }
-        HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+        HIP_TRY(ctx, hipGraphLaunch(with_flush ? ctx->gexec_flush : ctx->gexec, ctx->stream));
         if (e1) HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     } else {
-        int rc = issue_push(ctx, src.data(), ctx->stream);
+        int rc = issue_push(ctx, src.data(), ctx->stream, with_flush);
         if (rc != CORR_OK) return rc;
     }
     ctx->n_push += 1;
@@ -644,19 +733,21 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes)
     return CORR_OK;
 }
 
-int corr_kernel_time(corr_ctx *ctx, double *ms_total, int64_t *n_pushes, int32_t reset)
+int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n, int32_t reset)
 {
     if (!ctx) return CORR_E_INVALID;
+    if (which != 0 && which != 1) return set_err(ctx, CORR_E_INVALID, "which must be 0 or 1");
     if (!(ctx->flags & CORR_FLAG_TIMING))
         return set_err(ctx, CORR_E_STATE, "context created without CORR_FLAG_TIMING");
     DeviceGuard dg(ctx->device);
-    int rc = fold_events(ctx);
+    int rc = fold_events(ctx, which);
     if (rc != CORR_OK) return rc;
-    if (ms_total) *ms_total = ctx->timed_ms;
-    if (n_pushes) *n_pushes = ctx->timed_pushes;
+    auto &pl = ctx->pools[which];
+    if (ms_total) *ms_total = pl.ms;
+    if (n) *n = pl.n;
     if (reset) {
-        ctx->timed_ms = 0.0;
-        ctx->timed_pushes = 0;
+        pl.ms = 0.0;
+        pl.n = 0;
     }
     return CORR_OK;
 }
@@ -730,7 +821,8 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
                 e.level = k;
                 e.lag = L;
                 e.count = cnt;
-                e.hi_off = lvl + (int64_t)g.p * rowS + (int64_t)(L - l0) * rowA;
+                const int ring_rows = k == 0 ? g.p0 : g.p;
+                e.hi_off = lvl + (int64_t)ring_rows * rowS + (int64_t)(L - l0) * rowA;
                 e.lo_off = e.hi_off + (int64_t)nl * rowA;
                 ent.push_back(e);
             }
@@ -746,6 +838,50 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
     const int64_t nsel = ce - cb;
     const int bpe = (int)std::max<int64_t>(1, std::min<int64_t>(256, (nsel + 4095) / 4096));
     const int64_t n_slice = want_slice ? (se - sb) : 0;
+    std::vector<double> sums((size_t)ne * 2);
+    std::vector<double> slice;
+    if (g.deferred) {
+        // Block-deferred group: fold the pushes since the last flush on the
+        // fly (no state is written) and reduce per tile, then over tiles.
+        const GroupArgs &ga = ctx->pargs.g[(size_t)group];
+        const size_t tp_bytes = (size_t)deferred_readout_rows(ga) * ne * sizeof(double);
+        const size_t gr_bytes = (size_t)deferred_readout_groups(ga) * ne * sizeof(double);
+        const size_t s_bytes = (size_t)ne * sizeof(double);
+        const size_t sl_bytes = (size_t)std::max<int64_t>(n_slice, 1) * ne * sizeof(double);
+        int rc = ensure_scratch(ctx, tp_bytes + gr_bytes + s_bytes + sl_bytes);
+        if (rc != CORR_OK) return rc;
+        char *sc = static_cast<char *>(ctx->d_scratch);
+        DeferredArgs da{};
+        da.g = ctx->pargs.g[(size_t)group];
+        da.step = ctx->d_step;
+        da.ne = ne;
+        da.ch_begin = cb;
+        da.ch_end = ce;
+        da.slice_begin = want_slice ? sb : 0;
+        da.slice_end = want_slice ? se : 0;
+        da.chunk_partial = reinterpret_cast<double *>(sc);
+        double *d_groups = reinterpret_cast<double *>(sc + tp_bytes);
+        double *d_sums = reinterpret_cast<double *>(sc + tp_bytes + gr_bytes);
+        da.slice_out = reinterpret_cast<double *>(sc + tp_bytes + gr_bytes + s_bytes);
+        HIP_TRY(ctx, launch_deferred_readout(da, d_groups, d_sums, ctx->stream));
+        std::vector<double> re((size_t)ne);
+        HIP_TRY(ctx, hipMemcpyAsync(re.data(), d_sums, s_bytes, hipMemcpyDeviceToHost, ctx->stream));
+        std::vector<double> sl;
+        if (want_slice) {
+            sl.resize((size_t)n_slice * ne);
+            HIP_TRY(ctx, hipMemcpyAsync(sl.data(), da.slice_out, (size_t)n_slice * ne * sizeof(double),
+                                        hipMemcpyDeviceToHost, ctx->stream));
+        }
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < ne; ++i) {
+            sums[(size_t)2 * i] = re[(size_t)i];
+            sums[(size_t)2 * i + 1] = 0.0;
+        }
+        if (want_slice) {
+            slice.assign((size_t)n_slice * ne * 2, 0.0);
+            for (size_t i = 0; i < sl.size(); ++i) slice[2 * i] = sl[i];
+        }
+    } else {
     // scratch: offsets (2 * ne int64), partial (ne * bpe * 2 doubles), sums (ne * 2 doubles),
     // slice (n_slice * ne * 2 doubles)
     const size_t off_bytes = (size_t)2 * ne * sizeof(int64_t);
@@ -782,9 +918,7 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
     ra.partial = d_part;
     ra.out = d_sum;
     HIP_TRY(ctx, launch_reduce(ra, ctx->stream));
-    std::vector<double> sums((size_t)ne * 2);
     HIP_TRY(ctx, hipMemcpyAsync(sums.data(), d_sum, sum_bytes, hipMemcpyDeviceToHost, ctx->stream));
-    std::vector<double> slice;
     if (want_slice) {
         ReduceArgs rs = ra;
         rs.ch_begin = sb;
@@ -796,6 +930,7 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
                                     ctx->stream));
     }
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
 
     const bool cplx = kind_complex(g.kind);
     const double norm = g.rhok ? 1.0 / (double)g.d.n_atoms : 1.0; // F(k,t) = <n n*> / N

@@ -34,13 +34,17 @@ KINDS = [("f32", "f64"), ("f32", "kahan"), ("f32", "f32"), ("f64", "f64"),
          ("cf32", "f64"), ("cf32", "kahan"), ("cf32", "f32"), ("cf64", "f64")]
 
 
+@pytest.mark.parametrize("direct", [False, True])
 @pytest.mark.parametrize("dtype,accum", KINDS)
-def test_parity_each_kind(corrmod, dtype, accum):
+def test_parity_each_kind(corrmod, dtype, accum, direct):
+    """Every (sample, accumulator) kind; single-precision real kinds with p=16,
+    m=2 run the block-deferred form unless direct=True."""
     n, S, b, p, m = 1300, 1200, 7, 16, 2
-    say(f"[parity kind] dtype={dtype} accum={accum} n={n} S={S} b={b} p={p}")
+    say(f"[parity kind] dtype={dtype} accum={accum} direct={direct} n={n} S={S} b={b} p={p}")
     x = ou_inputs(7, 11, n, S, dtype)
     o = oracle_run(x, b, p, m)
-    with corrmod.Correlator([corrmod.GroupDesc(n, b, p, m, dtype=dtype, accum=accum)]) as c:
+    with corrmod.Correlator([corrmod.GroupDesc(n, b, p, m, dtype=dtype, accum=accum)],
+                            direct=direct) as c:
         _push_all(c, [x])
         sl = (n - 5, n)
         res = c.finalize(0, slice_=sl)
@@ -218,3 +222,47 @@ def test_green_kubo_readout(corrmod):
             run, at = fn(t * 0.001, cm, V, kB, T, t_cut=0.5)
             assert np.allclose(res["gk_running"], run, rtol=1e-12, atol=1e-12 * abs(run).max())
             assert abs(res["gk_at_cut"] - at) <= 1e-12 * abs(at)
+
+
+@pytest.mark.parametrize("accum", ["kahan", "f64"])
+def test_deferred_readout_at_many_push_counts(corrmod, accum):
+    """Block-deferred groups: readouts before the first flush, exactly at flush
+    boundaries and with pending pushes all match the oracle at that push count,
+    and never change later results (bitwise against an uninterrupted run)."""
+    n, b, p, m = 700, 12, 16, 2
+    marks = [1, 2, 15, 16, 17, 63, 64, 65, 100, 127, 128, 129, 255, 256, 511, 700, 1024, 1500]
+    S = marks[-1]
+    say(f"[deferred readouts] accum={accum} n={n}")
+    x = ou_inputs(4, 4, n, S, "f32")
+    o = oracle.OracleCorrelator(n, b, p, m)
+    dev = torch.device("cuda:0")
+    tx = torch.from_numpy(x).to(dev)
+    g = [corrmod.GroupDesc(n, b, p, m, dtype="f32", accum=accum)]
+    with corrmod.Correlator(g) as c, corrmod.Correlator(g) as ref:
+        done = 0
+        for mk in marks:
+            for s in range(done, mk):
+                c.push([tx[s]])
+                ref.push([tx[s]])
+                o.push(x[s].astype(np.float64))
+            done = mk
+            res = c.finalize(0, slice_=(n - 3, n))
+            gate(res, o, TOL[("f32", accum)], slice_=(n - 3, n), label=f"S={mk}")
+        a, r = c.finalize(0, slice_=(0, n)), ref.finalize(0, slice_=(0, n))
+        assert np.array_equal(a["c"], r["c"])
+        assert np.array_equal(a["c_per_channel"], r["c_per_channel"])
+
+
+def test_deferred_equals_direct_within_rounding(corrmod):
+    """The block-deferred form regroups the same sums as the per-step form."""
+    n, S = 2000, 3000
+    say("[deferred vs direct]")
+    x = ou_inputs(8, 8, n, S, "f32")
+    g = [corrmod.GroupDesc(n, 12, 16, 2, dtype="f32", accum="f64")]
+    with corrmod.Correlator(g) as d, corrmod.Correlator(g, direct=True) as e:
+        _push_all(d, [x])
+        _push_all(e, [x])
+        rd, re_ = d.finalize(0, slice_=(0, 50)), e.finalize(0, slice_=(0, 50))
+        assert np.array_equal(rd["count"], re_["count"])
+        assert np.max(np.abs(rd["c"] - re_["c"])) <= 1e-12 * abs(re_["c"][0])
+        assert np.max(np.abs(rd["c_per_channel"] - re_["c_per_channel"])) <= 1e-9
