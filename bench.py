@@ -41,7 +41,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--config", default="batched", choices=["plain", "batched", "large"])
+    ap.add_argument("--config", default="batched",
+                    choices=["plain", "batched", "large", "precision"])
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the launch-shape autotuner (library defaults)")
+    ap.add_argument("--precision-steps", type=int, default=1_000_000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy 8 times (reference for "
+                         "the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--chunk", type=int, default=128, help="pushes per generated input chunk")
     ap.add_argument("--mode", default=None, choices=["batched", "per_group"],
                     help="launch form (default: per_group for plain, batched otherwise)")
@@ -155,7 +162,7 @@ def cpu_baseline(wl):
     import oracle
     import synth
     g = max(wl["groups"], key=lambda x: x["n"])
-    n_ch, S = 4000, 2500
+    n_ch, S = 16000, 8000
     real = np.float32 if g["dtype"] == "f32" else np.float64
     spec = synth.OUSpec.make(g["seed"], g["stream"], n_ch, comps=g.get("comps", 1),
                              tau=g["tau"][0], tau_hi=g["tau"][1], dtype=real)
@@ -177,7 +184,7 @@ def run(args):
     import torch
 
     import synth
-    from paper_2503_07526_amd import Correlator, GroupDesc
+    from paper_2503_07526_amd import Correlator, GroupDesc, autotune
 
     wl = workload(args.config)
     K = args.steps if args.steps is not None else wl["steps"]
@@ -208,6 +215,11 @@ def run(args):
             tdt = torch.float32 if real == np.float32 else torch.float64
             bufs.append(torch.empty((chunk, g["n"]), dtype=tdt, device=dev))
     tuning = json.loads(args.tuning) if args.tuning else None
+    tune_s = 0.0
+    if tuning is None and not args.no_autotune:
+        t0 = time.perf_counter()
+        tuning = autotune(descs, per_group=(mode == "per_group"), direct=args.direct)
+        tune_s = time.perf_counter() - t0
     corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuning, timing=True,
                       direct=args.direct)
     state_gb = sum(corr.state_bytes(i) for i in range(len(descs))) / 1e9
@@ -289,10 +301,141 @@ def run(args):
                      "update_ms_per_step": kern_ms / kern_n,
                      "alg_bytes_per_step": (stage_bytes + fl_bytes) / K},
     }
+    out["config"]["autotune_s"] = round(tune_s, 2)
+    out["error_vs_fp64"] = spot_check(corr, wl, W + K)
     corr.close()
     if args.compare_plain:
         out["plain_form"] = compare_plain(wl, K, W, chunk)
     return out, wl
+
+
+def spot_check(corr, wl, S):
+    """Readout of a few channels of the largest group after the timed run,
+    against the FP64 oracle fed with the same series regenerated on the CPU:
+    max |C_gpu - C_oracle| / |C_oracle(0)| per channel, counts exact."""
+    import oracle
+    import synth
+    gi = max(range(len(wl["groups"])), key=lambda i: wl["groups"][i]["n"])
+    g = wl["groups"][gi]
+    real = np.float32 if g["dtype"] == "f32" else np.float64
+    spec = synth.OUSpec.make(g["seed"], g["stream"], g["n"], comps=g["comps"], tau=g["tau"][0],
+                             tau_hi=g["tau"][1], sigma=g["sigma"], dtype=real)
+    worst, chans, counts_ok = 0.0, [], True
+    for lo in (0, g["n"] // 2, g["n"] - 2):
+        res = corr.finalize(gi, slice_=(lo, lo + 2))
+        x, _ = spec.series(0, S, channels=np.arange(lo, lo + 2))
+        o = oracle.OracleCorrelator(2, g["levels"], g["points"], g["m"])
+        for row in x:
+            o.push(row.astype(np.float64))
+        for i in range(2):
+            t, c, n = o.readout(i, i + 1)
+            counts_ok &= bool(np.array_equal(res["count"], n) and np.array_equal(res["t"], t))
+            worst = max(worst, float(np.max(np.abs(res["c_per_channel"][i] - c)) / abs(c[0])))
+            chans.append(lo + i)
+    return {"max_abs_dC_over_C0": worst, "counts_and_lags_exact": counts_ok, "channels": chans,
+            "pushes": S, "accumulator": g["accum"]}
+
+
+def ou_expected(a, var, t_steps, p, m):
+    """E[C] of a stationary AR(1) series (autocorrelation a^l) block-averaged
+    over M = m^k samples at the multiple-tau lag grid (level k, lag L)."""
+    out = []
+    for t in t_steps:
+        k = 0
+        while t >= p * m ** k:
+            k += 1
+        M = m ** k
+        L = int(round(t)) // M
+        if k == 0:
+            out.append(var * a ** L)
+        else:
+            g = (1 - a ** M) / (1 - a)
+            out.append(var * a ** (M * L - (M - 1)) * g * g / (M * M))
+    return np.array(out)
+
+
+def precision(args):
+    """Compensated FP32 vs FP64 (vs plain FP32) sums on the precision workload:
+    10^5 velocity channels (tau=100) + 9 FP64 global channels (tau=100), 20
+    levels x 16 points, m=2, sigma 1 and 10^3, against the FP64 oracle on
+    sampled channels and against the closed-form OU expectation / sigma^2 tau
+    Green-Kubo integral for the group mean."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2503_07526_amd import Correlator, GroupDesc
+    S = args.precision_steps
+    nv, b, p, m, tau = 100_000, 20, 16, 2, 100.0
+    chunk = 512
+    sample = np.r_[0:16, nv - 16:nv]
+    runs = []
+    for sigma in (1.0, 1000.0):
+        vspec = synth.OUSpec.make(2, 1, nv, comps=3, tau=tau, sigma=sigma)
+        gspec = synth.OUSpec.make(2, 2, 9, tau=tau, sigma=sigma, dtype=np.float64)
+        # oracle on the sampled velocity channels and all global channels
+        xs, _ = vspec.series(0, S, channels=sample)
+        xg, _ = gspec.series(0, S)
+        ov = oracle.OracleCorrelator(len(sample), b, p, m)
+        og = oracle.OracleCorrelator(9, b, p, m)
+        for r1, r2 in zip(xs, xg):
+            ov.push(r1.astype(np.float64))
+            og.push(r2)
+        var = float(synth.stationary_variance(vspec.a[0], vspec.b[0]))
+        a64 = float(vspec.a[0])
+        for accum in ("kahan", "f64", "f32"):
+            t0 = time.perf_counter()
+            gv, gg = synth.GpuOU(vspec), synth.GpuOU(gspec)
+            bv = torch.empty((chunk, nv), dtype=torch.float32, device="cuda")
+            bg = torch.empty((chunk, 9), dtype=torch.float64, device="cuda")
+            corr = Correlator([GroupDesc(nv, b, p, m, dtype="f32", accum=accum),
+                               GroupDesc(9, b, p, m, dtype="f64", accum="f64")])
+            done = 0
+            while done < S:
+                n = min(chunk, S - done)
+                gv.fill(bv, n)
+                gg.fill(bg, n)
+                for j in range(n):
+                    corr.push([bv[j], bg[j]])
+                done += n
+            torch.cuda.synchronize()
+            res_s = [corr.finalize(0, slice_=(0, 16)), corr.finalize(0, slice_=(nv - 16, nv))]
+            per = np.vstack([r["c_per_channel"] for r in res_s])
+            err_v = 0.0
+            for i in range(len(sample)):
+                t, c, n_ = ov.readout(i, i + 1)
+                err_v = max(err_v, float(np.max(np.abs(per[i] - c)) / abs(c[0])))
+            rg = corr.finalize(1, slice_=(0, 9))
+            err_g = 0.0
+            for i in range(9):
+                t, c, n_ = og.readout(i, i + 1)
+                err_g = max(err_g, float(np.max(np.abs(rg["c_per_channel"][i] - c)) / abs(c[0])))
+            full = corr.finalize(0)
+            t_s = full["t"]
+            expect = ou_expected(a64, var, t_s, p, m)
+            gk_grid = oracle.trapezoid(t_s, expect)[1]
+            tau_eff = -1.0 / np.log(a64)
+            corr.close()
+            del bv, bg
+            torch.cuda.empty_cache()
+            runs.append({"sigma": sigma, "accumulator": accum,
+                         "velocity_max_abs_dC_over_C0_vs_fp64_oracle": err_v,
+                         "global_fp64_max_abs_dC_over_C0_vs_fp64_oracle": err_g,
+                         "group_gk": full["gk_at_cut"],
+                         "gk_grid_expected": gk_grid,
+                         "gk_closed_form_sigma2_tau": var * tau_eff,
+                         "c0_group_mean": float(full["c"][0]), "c0_expected": var,
+                         "seconds": round(time.perf_counter() - t0, 1)})
+            print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
+    worst = max(r["velocity_max_abs_dC_over_C0_vs_fp64_oracle"] for r in runs
+                if r["accumulator"] == "kahan")
+    return {"metric": "max |C_gpu - C_fp64oracle| / |C(0)|, compensated FP32 sums",
+            "value": worst, "unit": "relative", "higher_is_better": False,
+            "steps": S, "n_gpus": 1, "data": "synthetic OU series",
+            "config": {"workload": "precision: 1e5 FP32 channels + 9 FP64 channels, tau=100, "
+                                   "b=20 p=16 m=2, sigma 1 and 1e3",
+                       "sampled_velocity_channels": len(sample)},
+            "runs": runs}
 
 
 def compare_plain(wl, K, W, chunk):
@@ -331,6 +474,19 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding "
                                    "is a design note only (--gpus 1)", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(8):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_copy": src.numel() * 4,
+                          "bytes_written_per_copy": dst.numel() * 4, "copies": 8}), flush=True)
+        return
+    if args.config == "precision":
+        print(json.dumps(precision(args)), flush=True)
+        return
     out, wl = run(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -216,6 +216,22 @@ int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n,
 /* Launch shape in use. */
 int corr_get_tuning(const corr_ctx *ctx, corr_tuning *out);
 
+/*
+ * Autotuner: choose the launch shape for these groups on `device` by timing
+ * trial contexts (same descriptors with at most max_trial_channels channels
+ * per group, zero samples; all trial memory is freed before returning) over
+ * whole flush periods for every candidate shape, and return the fastest in
+ * *out.  The choice is cached in a text file of JSON lines (cache_path, or
+ * NULL for $CORR_TUNE_CACHE, else $HOME/.cache/corr_gfx950_tune.jsonl, else
+ * no cache) keyed by the device architecture, the flags and the group
+ * descriptors; a cached entry is returned without timing unless force != 0.
+ * corr_create with a NULL or all-zero tuning uses the cached entry for its
+ * key when one exists.  Synchronises the device.
+ */
+int corr_autotune(const corr_group_desc *groups, int32_t n_groups, int32_t device, void *stream,
+                  uint32_t flags, const char *cache_path, int64_t max_trial_channels,
+                  int32_t force, corr_tuning *out);
+
 #ifdef __cplusplus
 }
 #endif

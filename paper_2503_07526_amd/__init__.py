@@ -7,4 +7,4 @@ hand-written HIP kernels behind the C ABI of ``include/corr.h``.  This package
 is the thin Python binding (``corr.Correlator``) and the build script.
 """
 from .corr import (CorrError, Correlator, GroupDesc, Tuning, EXPORTS, LIB_PATH,  # noqa: F401
-                   lib)
+                   autotune, lib)

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcorr_gfx950.so")
 HIPCC = "/opt/rocm/bin/hipcc"
 
-SOURCES = ["corr_push.hip", "corr_deferred.hip", "corr_rhok.hip", "corr_reduce.hip", "corr_runtime.cpp"]
+SOURCES = ["corr_push.hip", "corr_deferred.hip", "corr_rhok.hip", "corr_reduce.hip",
+           "corr_runtime.cpp", "corr_autotune.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-mcode-object-version=5", "-fPIC",

@@ -60,7 +60,7 @@ class _ReadoutOpts(ctypes.Structure):
 
 EXPORTS = ["corr_create", "corr_input_buffer", "corr_bind_input", "corr_push", "corr_query",
            "corr_finalize", "corr_sync", "corr_destroy", "corr_last_error", "corr_state_bytes",
-           "corr_get_tuning", "corr_kernel_time"]
+           "corr_get_tuning", "corr_kernel_time", "corr_autotune"]
 
 _lib = None
 
@@ -89,6 +89,8 @@ def lib():
         L.corr_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.corr_kernel_time.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i64), i32]
+        L.corr_autotune.argtypes = [ctypes.POINTER(_GroupDesc), i32, i32, vp, ctypes.c_uint32,
+                                    ctypes.c_char_p, i64, i32, ctypes.POINTER(Tuning)]
         for name in EXPORTS:
             if name != "corr_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -127,6 +129,24 @@ class GroupDesc:
     @property
     def max_out(self) -> int:
         return self.points + (self.levels - 1) * (self.points - self.points // self.m)
+
+
+def autotune(groups, device: int = 0, stream=None, graph=False, per_group=False, direct=False,
+             cache_path: str | None = None, max_trial_channels: int = 0, force: bool = False):
+    """Run (or read from the cache) the launch-shape autotuner; returns the tuning dict."""
+    L = lib()
+    groups = list(groups)
+    descs = (_GroupDesc * len(groups))(*[g.to_c() for g in groups])
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    flags = (FLAG_GRAPH if graph else 0) | (FLAG_PER_GROUP if per_group else 0) | \
+        (FLAG_DIRECT if direct else 0)
+    t = Tuning()
+    rc = L.corr_autotune(descs, len(groups), int(device), ctypes.c_void_p(st.cuda_stream), flags,
+                         cache_path.encode() if cache_path else None, int(max_trial_channels),
+                         int(force), ctypes.byref(t))
+    if rc != CORR_OK:
+        raise CorrError(rc, "autotune failed")
+    return t.as_dict()
 
 
 def _ptr(t):

@@ -1,0 +1,162 @@
+// corr_autotune.cpp -- launch-shape autotuner with a persistent cache.
+//
+// The launch shape (tile width, channels per thread, lag batch, persistent
+// grid size) changes neither results nor state semantics, only speed, and the
+// best choice depends on the mix of groups.  corr_autotune times trial
+// contexts over whole flush periods for a fixed list of candidates and caches
+// the winner per (device architecture, flags, group descriptors) in a text
+// file of JSON lines; corr_create consults the cache when the caller passes no
+// tuning.
+#include <hip/hip_runtime.h>
+
+#include <sys/stat.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/corr.h"
+#include "corr_tune.h"
+
+namespace corr {
+
+std::string tune_cache_path(const char *explicit_path)
+{
+    if (explicit_path && *explicit_path) return explicit_path;
+    if (const char *e = std::getenv("CORR_TUNE_CACHE")) return e;
+    if (const char *h = std::getenv("HOME")) {
+        std::string dir = std::string(h) + "/.cache";
+        ::mkdir(dir.c_str(), 0755); // may already exist
+        return dir + "/corr_gfx950_tune.jsonl";
+    }
+    return std::string();
+}
+
+std::string tune_key(const corr_group_desc *g, int n, uint32_t flags, int device)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    std::ostringstream os;
+    os << "arch=" << arch << ";flags=" << (flags & ~(uint32_t)CORR_FLAG_TIMING);
+    for (int i = 0; i < n; ++i) {
+        os << ";g" << i << "=" << g[i].n_channels << "," << g[i].levels << "," << g[i].points << ","
+           << g[i].m << "," << g[i].dtype << "," << g[i].accum << "," << g[i].source;
+        if (g[i].source == CORR_SRC_RHOK) os << "," << g[i].n_atoms;
+    }
+    return os.str();
+}
+
+static bool parse_int(const std::string &line, const char *field, int *out)
+{
+    const std::string pat = std::string("\"") + field + "\":";
+    const size_t p = line.find(pat);
+    if (p == std::string::npos) return false;
+    *out = std::atoi(line.c_str() + p + pat.size());
+    return true;
+}
+
+bool tune_cache_lookup(const std::string &path, const std::string &key, corr_tuning *out)
+{
+    if (path.empty()) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    const std::string want = "\"key\":\"" + key + "\"";
+    std::string line;
+    bool found = false;
+    corr_tuning t{};
+    while (std::getline(f, line)) {
+        if (line.find(want) == std::string::npos) continue;
+        corr_tuning c{};
+        if (parse_int(line, "tile_channels", &c.tile_channels) &&
+            parse_int(line, "chans_per_thread", &c.chans_per_thread) &&
+            parse_int(line, "lag_chunk", &c.lag_chunk) &&
+            parse_int(line, "grid_blocks", &c.grid_blocks)) {
+            t = c; // the last entry for a key wins
+            found = true;
+        }
+    }
+    if (found) *out = t;
+    return found;
+}
+
+static void tune_cache_store(const std::string &path, const std::string &key, const corr_tuning &t,
+                             double ms_per_push)
+{
+    if (path.empty()) return;
+    std::ofstream f(path, std::ios::app);
+    if (!f) return;
+    f << "{\"key\":\"" << key << "\",\"tile_channels\":" << t.tile_channels
+      << ",\"chans_per_thread\":" << t.chans_per_thread << ",\"lag_chunk\":" << t.lag_chunk
+      << ",\"grid_blocks\":" << t.grid_blocks << ",\"ms_per_push\":" << ms_per_push << "}\n";
+}
+
+} // namespace corr
+
+using namespace corr;
+
+extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, int32_t device,
+                             void *stream, uint32_t flags, const char *cache_path,
+                             int64_t max_trial_channels, int32_t force, corr_tuning *out)
+{
+    if (!groups || n_groups < 1 || !out) return CORR_E_INVALID;
+    const std::string path = tune_cache_path(cache_path);
+    const std::string key = tune_key(groups, n_groups, flags, device);
+    if (!force && tune_cache_lookup(path, key, out)) return CORR_OK;
+
+    if (max_trial_channels <= 0) max_trial_channels = 8 << 20;
+    std::vector<corr_group_desc> trial(groups, groups + n_groups);
+    for (auto &g : trial) {
+        if (g.source == CORR_SRC_RHOK)
+            g.n_atoms = std::min<int64_t>(g.n_atoms, 1 << 18);
+        else
+            g.n_channels = std::min<int64_t>(g.n_channels, max_trial_channels);
+    }
+    static const corr_tuning cands[] = {
+        {256, 1, 8, 2048}, {256, 1, 16, 0},  {512, 2, 8, 2048}, {512, 2, 8, 0},
+        {512, 2, 4, 2048}, {256, 2, 8, 2048}, {1024, 4, 4, 2048}, {1024, 4, 4, 0},
+        {512, 4, 4, 2048},
+    };
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return CORR_E_DEVICE;
+    }
+    const int period = 64; // whole flush periods of the block-deferred form
+    double best = 1e300;
+    corr_tuning best_t{};
+    for (const corr_tuning &cand : cands) {
+        corr_ctx *ctx = nullptr;
+        const uint32_t tflags = flags & ~(uint32_t)CORR_FLAG_TIMING;
+        if (corr_create(trial.data(), n_groups, device, stream, tflags, &cand, &ctx) != CORR_OK)
+            continue; // e.g. out of memory for this layout
+        bool ok = true;
+        for (int s = 0; s < period && ok; ++s) ok = corr_push(ctx, nullptr) == CORR_OK;
+        ok = ok && hipEventRecord(e0, st) == hipSuccess;
+        for (int s = 0; s < 2 * period && ok; ++s) ok = corr_push(ctx, nullptr) == CORR_OK;
+        ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.f;
+        if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        corr_destroy(ctx);
+        if (ok && ms < best) {
+            best = ms;
+            best_t = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best == 1e300) return CORR_E_DEVICE;
+    *out = best_t;
+    tune_cache_store(path, key, best_t, best / (2 * period));
+    return CORR_OK;
+}

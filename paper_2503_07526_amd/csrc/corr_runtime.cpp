@@ -16,6 +16,7 @@
 
 #include "../../include/corr.h"
 #include "corr_kernels.h"
+#include "corr_tune.h"
 
 using namespace corr;
 
@@ -445,8 +446,18 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     // Default launch shape: 512-channel tiles, 2 channels per thread (256-thread
     // blocks), 8 lags per load batch, a persistent grid of 8 blocks per CU.
     corr_tuning tn{512, 2, 8, 2048};
-    if (tuning && (tuning->tile_channels || tuning->chans_per_thread || tuning->lag_chunk ||
-                   tuning->grid_blocks)) {
+    const bool given = tuning && (tuning->tile_channels || tuning->chans_per_thread ||
+                                  tuning->lag_chunk || tuning->grid_blocks);
+    if (!given) {
+        // the autotuner's cached choice for these groups, if any
+        corr_tuning cached{};
+        if (tune_cache_lookup(tune_cache_path(nullptr), tune_key(groups, n_groups, flags, device),
+                              &cached) &&
+            validate_tuning(cached) == CORR_OK)
+            tn = cached;
+        g_create_error.clear();
+    }
+    if (given) {
         tn = *tuning;
         if (!tn.chans_per_thread) tn.chans_per_thread = 2;
         if (!tn.lag_chunk) tn.lag_chunk = tn.chans_per_thread == 1 ? 16 : tn.chans_per_thread == 2 ? 8 : 4;

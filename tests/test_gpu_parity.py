@@ -266,3 +266,29 @@ def test_deferred_equals_direct_within_rounding(corrmod):
         assert np.array_equal(rd["count"], re_["count"])
         assert np.max(np.abs(rd["c"] - re_["c"])) <= 1e-12 * abs(re_["c"][0])
         assert np.max(np.abs(rd["c_per_channel"] - re_["c_per_channel"])) <= 1e-9
+
+
+def test_autotune_picks_and_caches(corrmod, tmp_path):
+    """The autotuner returns a valid launch shape, writes it to the cache, reads
+    it back without timing, and a context created with it matches the oracle."""
+    import time as _t
+    cache = str(tmp_path / "tune.jsonl")
+    groups = [corrmod.GroupDesc(5000, 6, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(9, 8, 16, 2, dtype="f64", accum="f64")]
+    say("[autotune]")
+    t0 = _t.perf_counter()
+    tn = corrmod.autotune(groups, cache_path=cache, max_trial_channels=1 << 14)
+    first = _t.perf_counter() - t0
+    assert tn["tile_channels"] % (64 * tn["chans_per_thread"]) == 0
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"key":"arch=gfx950' in lines[0]
+    t0 = _t.perf_counter()
+    tn2 = corrmod.autotune(groups, cache_path=cache, max_trial_channels=1 << 14)
+    assert tn2 == tn and _t.perf_counter() - t0 < first
+    x = ou_inputs(6, 6, 5000, 300, "f32")
+    o = oracle_run(x, 6, 16, 2)
+    with corrmod.Correlator(groups[:1], tuning=tn) as c:
+        assert c.tuning() == tn
+        _push_all(c, [x])
+        gate(c.finalize(0, slice_=(0, 3)), o, TOL[("f32", "kahan")], slice_=(0, 3),
+             label="autotuned")
