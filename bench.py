@@ -126,6 +126,26 @@ def flush_bytes(g, s):
     return B * g["n"]
 
 
+def group_channels(g, tw, j):
+    """Channels of tile group j (64 groups of contiguous tiles) of a block-deferred group."""
+    n_tiles = -(-g["n"] // tw)
+    tpg = -(-n_tiles // DEFER_T)
+    t0, t1 = j * tpg, min((j + 1) * tpg, n_tiles)
+    if t0 >= t1:
+        return 0
+    return max(0, min(t1 * tw, g["n"]) - t0 * tw)
+
+
+def staggered_flush_bytes(g, s, tw):
+    """Bytes of the flush issued with push s: tile group s mod 64 folds block
+    s // 64 (pushes (64 (q-1), 64 q])."""
+    j, q = s % DEFER_T, s // DEFER_T
+    if q < 1:
+        return 0
+    per_channel = flush_bytes(dict(g, n=1), q * DEFER_T)
+    return per_channel * group_channels(g, tw, j)
+
+
 def push_bytes(g, s, direct=False):
     """Bytes of the push kernel at push s: staging (read sample, write ring slot)
     for block-deferred groups, the full per-step update otherwise."""
@@ -260,15 +280,17 @@ def run(args):
     steps = range(s_first, s_first + K)
     direct = args.direct
     stage_bytes = sum(push_bytes(g, s, direct) for g in timed for s in steps)
-    fl_bytes = sum(flush_bytes(g, s) for g in timed if deferred(g, direct)
-                   for s in steps if s % DEFER_T == 0)
+    tw = corr.tuning()["tile_channels"]
+    fl_bytes = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
+                   for s in steps)
     fl_ms, fl_n = corr.kernel_time(which=1)
     n_total = sum(g["n"] for g in wl["groups"])
     value = n_total * K / wall
     if fl_n:
         # dominant kernel: the flush of the block-deferred groups
         achieved = fl_bytes / (fl_ms * 1e-3) / 1e9
-        kname = "flush kernel (block-deferred fold of 64 pushes), HIP events per launch"
+        kname = ("flush kernel (block-deferred fold of 64 pushes for 1/64 of the channels per "
+                 "push), HIP events per launch")
         per_launch_ms, per_launch_bytes = fl_ms / fl_n, fl_bytes / fl_n
     else:
         achieved = (stage_bytes + fl_bytes) / (kern_ms * 1e-3) / 1e9

@@ -200,17 +200,20 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
  * the push kernel launch(es) to after the flush launch(es) of that push, i.e.
  * the correlator-update kernels of the main stream (excluding the forked
  * k-density producer and the step counter); *n = timed pushes.  which = 1:
- * the flush launches of block-deferred groups only; *n = timed flushes.  In
+ * the flush launches of block-deferred groups only (one per push); *n =
+ * timed flushes.  In
  * graph mode the which = 0 events bracket the whole graph replay and no
  * flush-only times are recorded.  reset != 0 clears the counters of `which`
  * after reading.  CORR_E_STATE without the flag.
  *
  * Block-deferred form: for groups of single-precision samples with p = 16 and
- * m = 2 (unless CORR_FLAG_DIRECT), a push only stages the samples; every 64
- * pushes a flush adds the lag products of those 64 pushes level by level
- * (the same products, block means and counts as Algorithm 1; only the
- * grouping of the floating-point sums differs) and a readout folds pending
- * pushes without modifying state. */
+ * m = 2 (unless CORR_FLAG_DIRECT), a push stages the samples and flushes one
+ * of 64 channel subsets: subset j adds the lag products of block q (pushes
+ * 64(q-1)+1 .. 64q) level by level at push 64q + j -- the same products,
+ * block means and counts as Algorithm 1, only the grouping of the
+ * floating-point sums differs.  A readout first folds complete blocks a
+ * subset has not folded yet (exactly what its scheduled flush would do), then
+ * folds the pushes after the last block without modifying state. */
 int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n, int32_t reset);
 
 /* Launch shape in use. */

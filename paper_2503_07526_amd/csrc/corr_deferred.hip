@@ -308,13 +308,36 @@ template <int K, int P, int T, bool READ>
 __global__ __launch_bounds__(256) void deferred_kernel(DeferredArgs a)
 {
     const GroupArgs &g = a.g;
-    const int64_t tile = blockIdx.x;
-    // A flush folds the kDeferT pushes ending with the current one (the
-    // counter is advanced after it); a readout folds the pushes after the
-    // last flush.
-    const int64_t S = READ ? *a.step : *a.step + 1;
-    const int64_t f = READ ? (S / kDeferT) * kDeferT : S - kDeferT;
-    const int r = (int)(S - f);
+    int64_t f;
+    int r;
+    int64_t tile;
+    if constexpr (READ) {
+        // Readout (all tile groups caught up): fold the pushes after the
+        // last complete block without writing state.
+        const int64_t S = *a.step;
+        f = (S / kDeferT) * kDeferT;
+        r = (int)(S - f);
+        tile = blockIdx.x;
+    } else {
+        // Flush of tile group j, block q: scheduled at push kDeferT q + j
+        // (fixed_group < 0; the counter is advanced after this push) or
+        // requested explicitly.  Skipped when that block is already folded.
+        int j;
+        int64_t q;
+        if (a.fixed_group >= 0) {
+            j = a.fixed_group;
+            q = a.fixed_block;
+        } else {
+            const int64_t S = *a.step + 1;
+            j = (int)(S % kDeferT);
+            q = S / kDeferT;
+        }
+        if (q < 1 || a.flushed[j] >= q) return;
+        tile = (int64_t)j * a.tiles_per_group + blockIdx.x;
+        if (tile >= g.n_tiles || blockIdx.x >= a.tiles_per_group) return;
+        f = (q - 1) * kDeferT;
+        r = kDeferT;
+    }
     for (int sub = 0; sub * (int)blockDim.x < g.tw; ++sub) {
         // whole waves past the tile's end skip the pass (tw is a multiple of 64)
         if (sub * (int)blockDim.x + (int)(threadIdx.x & ~63u) >= g.tw) continue;
@@ -358,12 +381,31 @@ __global__ void colsum_final_kernel(const double *groups, int64_t n_groups, int 
     out[e] = s;
 }
 
+// Record that tile group j folded block q (runs after the flush kernel).
+__global__ void flush_commit_kernel(DeferredArgs a)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int j;
+    int64_t q;
+    if (a.fixed_group >= 0) {
+        j = a.fixed_group;
+        q = a.fixed_block;
+    } else {
+        const int64_t S = *a.step + 1;
+        j = (int)(S % kDeferT);
+        q = S / kDeferT;
+    }
+    if (q >= 1 && a.flushed[j] < q) a.flushed[j] = q;
+}
+
 template <int K, int P, bool READ>
 hipError_t launch_deferred_kp(const DeferredArgs &a, hipStream_t st)
 {
     const int block = a.g.tw < 256 ? a.g.tw : 256;
-    hipLaunchKernelGGL((deferred_kernel<K, P, kDeferT, READ>), dim3((unsigned)a.g.n_tiles),
-                       dim3(block), 0, st, a);
+    const int64_t grid = READ ? a.g.n_tiles : a.tiles_per_group;
+    if (grid < 1) return hipSuccess;
+    hipLaunchKernelGGL((deferred_kernel<K, P, kDeferT, READ>), dim3((unsigned)grid), dim3(block),
+                       0, st, a);
     return hipGetLastError();
 }
 
@@ -445,7 +487,13 @@ bool deferred_supported(int kind, int p, int m)
     return m == 2 && p == 16 && (kind == K_F32_F64 || kind == K_F32_KAHAN || kind == K_F32_F32);
 }
 
-hipError_t launch_flush(const DeferredArgs &a, hipStream_t st) { return launch_deferred_t<false>(a, st); }
+hipError_t launch_flush(const DeferredArgs &a, hipStream_t st)
+{
+    hipError_t e = launch_deferred_t<false>(a, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(flush_commit_kernel, dim3(1), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
 
 int64_t deferred_readout_rows(const GroupArgs &g) { return g.n_tiles * (int64_t)g.tw / 64; }
 

@@ -55,15 +55,21 @@ struct GroupArgs {
 
 // Pushes staged between two flushes of a block-deferred group.
 constexpr int kDeferT = 64;
+// Tile groups of a block-deferred group: tile group j folds block q (pushes
+// (kDeferT (q-1), kDeferT q]) at push kDeferT q + j, so every push flushes one
+// group; the level-0 ring keeps 2 kDeferT + p slots.
+constexpr int kFlushGroups = kDeferT;
 
 // Flush / readout of a block-deferred group.
 struct DeferredArgs {
     GroupArgs g;
-    const int64_t *step;    // device push counter: a flush runs before the
-                            // increment of the push that completes a block of
-                            // kDeferT pushes; a readout after it
+    const int64_t *step;    // device push counter (a scheduled flush runs before
+                            // the increment of its push, a readout after it)
+    int64_t *flushed;       // [kFlushGroups] last block folded per tile group
+    int64_t tiles_per_group;
+    int32_t fixed_group;    // >= 0: fold block fixed_block of this tile group
     int32_t ne;             // readout: number of (level, lag) entries
-    int32_t pad_;
+    int64_t fixed_block;
     int64_t ch_begin, ch_end;       // readout: channels reduced
     int64_t slice_begin, slice_end; // readout: channels written to slice_out
     double *chunk_partial;  // readout: [n_tiles * tw / 64][ne] sums over 64-channel chunks

@@ -29,8 +29,11 @@ struct Group {
     int kind = 0;
     int p = 0, m = 0, b = 0, lag0 = 0, nlk = 0;
     int s_bytes = 0, a_bytes = 0, np = 1;
-    bool deferred = false; // block-deferred form (stage per push, flush every kDeferT)
+    bool deferred = false; // block-deferred form (stage per push, staggered flushes)
     int p0 = 0;            // ring rows of level 0
+    int64_t *d_flushed = nullptr;                // [kFlushGroups] blocks folded per tile group
+    std::vector<int64_t> flushed;                // host mirror of d_flushed
+    int64_t tiles_per_group = 0;
     int64_t n_ch = 0, n_tiles = 0, tile_bytes = 0, lvl0_bytes = 0, lvlk_bytes = 0;
     char *state = nullptr;
     void *input = nullptr;     // buffer read when a push passes NULL (own or bound)
@@ -66,8 +69,8 @@ struct corr_ctx {
     PushArgs pa_main{}, pa_side{}, pa_direct{}; // pa_direct: main_set + side_set
     hipStream_t side_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipGraph_t graph = nullptr, graph_flush = nullptr;
-    hipGraphExec_t gexec = nullptr, gexec_flush = nullptr; // without / with the flush
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     std::vector<int> deferred_set; // context group indices in the block-deferred form
     // update-kernel timing (CORR_FLAG_TIMING): pool 0 per push, pool 1 per flush
     struct EventPool {
@@ -196,6 +199,7 @@ void free_group(Group &g)
     if (g.rhok_out) (void)hipFree(g.rhok_out);
     if (g.d_seg) (void)hipFree(g.d_seg);
     if (g.d_partial) (void)hipFree(g.d_partial);
+    if (g.d_flushed) (void)hipFree(g.d_flushed);
     g = Group{};
 }
 
@@ -217,8 +221,6 @@ void free_ctx(corr_ctx *c)
         for (auto e : pl.start) (void)hipEventDestroy(e);
         for (auto e : pl.end) (void)hipEventDestroy(e);
     }
-    if (c->gexec_flush) (void)hipGraphExecDestroy(c->gexec_flush);
-    if (c->graph_flush) (void)hipGraphDestroy(c->graph_flush);
     delete c;
 }
 
@@ -261,15 +263,51 @@ int next_events(corr_ctx *c, int which, hipEvent_t *a, hipEvent_t *b)
     return CORR_OK;
 }
 
-// Flush launches of every block-deferred group (the push being issued
-// completes a block of kDeferT pushes).
+DeferredArgs deferred_args(const corr_ctx *c, int i)
+{
+    const Group &g = c->groups[(size_t)i];
+    DeferredArgs da{};
+    da.g = c->pargs.g[(size_t)i];
+    da.step = c->d_step;
+    da.flushed = g.d_flushed;
+    da.tiles_per_group = g.tiles_per_group;
+    da.fixed_group = -1;
+    return da;
+}
+
+// Scheduled flush of every block-deferred group for the push being issued
+// (tile group S mod kDeferT folds block S / kDeferT if not done yet).
 int launch_flushes(corr_ctx *c, hipStream_t st)
 {
+    for (int i : c->deferred_set) HIP_TRY(c, launch_flush(deferred_args(c, i), st));
+    return CORR_OK;
+}
+
+// Host mirror of the scheduled flush of push S (after it was issued).
+void mirror_flushes(corr_ctx *c, int64_t S)
+{
+    const int j = (int)(S % kDeferT);
+    const int64_t q = S / kDeferT;
     for (int i : c->deferred_set) {
-        DeferredArgs da{};
-        da.g = c->pargs.g[(size_t)i];
-        da.step = c->d_step;
-        HIP_TRY(c, launch_flush(da, st));
+        Group &g = c->groups[(size_t)i];
+        if (q >= 1 && g.flushed[(size_t)j] < q) g.flushed[(size_t)j] = q;
+    }
+}
+
+// Before a readout: fold every complete block a tile group has not folded yet
+// (at most one per group: a block is scheduled within kDeferT - 1 pushes).
+int catch_up_flushes(corr_ctx *c, int gi)
+{
+    Group &g = c->groups[(size_t)gi];
+    const int64_t qn = c->n_push / kDeferT;
+    for (int j = 0; j < kFlushGroups; ++j) {
+        while (g.flushed[(size_t)j] < qn) {
+            DeferredArgs da = deferred_args(c, gi);
+            da.fixed_group = j;
+            da.fixed_block = g.flushed[(size_t)j] + 1;
+            HIP_TRY(c, launch_flush(da, c->stream));
+            g.flushed[(size_t)j] += 1;
+        }
     }
     return CORR_OK;
 }
@@ -387,14 +425,9 @@ int capture_graph(corr_ctx *c)
 {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
-    if (c->gexec_flush) (void)hipGraphExecDestroy(c->gexec_flush);
-    if (c->graph_flush) (void)hipGraphDestroy(c->graph_flush);
-    c->gexec = c->gexec_flush = nullptr;
-    c->graph = c->graph_flush = nullptr;
-    int rc = capture_one(c, false, &c->graph, &c->gexec);
-    if (rc != CORR_OK) return rc;
-    if (!c->deferred_set.empty()) rc = capture_one(c, true, &c->graph_flush, &c->gexec_flush);
-    return rc;
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    return capture_one(c, !c->deferred_set.empty(), &c->graph, &c->gexec);
 }
 
 int ensure_scratch(corr_ctx *c, size_t bytes)
@@ -512,13 +545,19 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         const int64_t rowA = (int64_t)tw * g.a_bytes;
         g.deferred = !(flags & CORR_FLAG_DIRECT) && g.d.source == CORR_SRC_SAMPLES &&
                      deferred_supported(g.kind, g.p, g.m);
-        g.p0 = g.deferred ? kDeferT + g.p : g.p;
+        g.p0 = g.deferred ? 2 * kDeferT + g.p : g.p;
         g.lvl0_bytes = g.p0 * rowS + (int64_t)g.np * g.p * rowA;
         g.lvlk_bytes = g.p * rowS + (int64_t)g.np * g.nlk * rowA;
         g.tile_bytes = g.lvl0_bytes + (int64_t)(g.b - 1) * g.lvlk_bytes;
         const size_t state_bytes = (size_t)g.n_tiles * (size_t)g.tile_bytes;
         CREATE_HIP(hipMalloc(&g.state, state_bytes));
         CREATE_HIP(hipMemsetAsync(g.state, 0, state_bytes, c->stream));
+        if (g.deferred) {
+            g.tiles_per_group = (g.n_tiles + kFlushGroups - 1) / kFlushGroups;
+            g.flushed.assign(kFlushGroups, 0);
+            CREATE_HIP(hipMalloc(&g.d_flushed, kFlushGroups * sizeof(int64_t)));
+            CREATE_HIP(hipMemsetAsync(g.d_flushed, 0, kFlushGroups * sizeof(int64_t), c->stream));
+        }
 
         g.rhok = g.d.source == CORR_SRC_RHOK;
         if (g.rhok) {
@@ -707,7 +746,7 @@ int corr_push(corr_ctx *ctx, const void *const *samples)
         if (p != ctx->groups[i].input) all_default = false;
         src[i] = p;
     }
-    const bool with_flush = !ctx->deferred_set.empty() && (ctx->n_push + 1) % kDeferT == 0;
+    const bool with_flush = !ctx->deferred_set.empty();
     if (ctx->gexec && all_default) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (ctx->flags & CORR_FLAG_TIMING) {
@@ -715,13 +754,14 @@ int corr_push(corr_ctx *ctx, const void *const *samples)
             if (rc != CORR_OK) return rc;
             HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
         }
-        HIP_TRY(ctx, hipGraphLaunch(with_flush ? ctx->gexec_flush : ctx->gexec, ctx->stream));
+        HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
         if (e1) HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     } else {
         int rc = issue_push(ctx, src.data(), ctx->stream, with_flush);
         if (rc != CORR_OK) return rc;
     }
     ctx->n_push += 1;
+    mirror_flushes(ctx, ctx->n_push);
     return CORR_OK;
 }
 
@@ -852,8 +892,13 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
     std::vector<double> sums((size_t)ne * 2);
     std::vector<double> slice;
     if (g.deferred) {
-        // Block-deferred group: fold the pushes since the last flush on the
-        // fly (no state is written) and reduce per tile, then over tiles.
+        // Block-deferred group: fold pending complete blocks (the scheduled
+        // flush would produce the same state), then fold the pushes after the
+        // last block on the fly (no state is written) and reduce.
+        {
+            int rc = catch_up_flushes(ctx, group);
+            if (rc != CORR_OK) return rc;
+        }
         const GroupArgs &ga = ctx->pargs.g[(size_t)group];
         const size_t tp_bytes = (size_t)deferred_readout_rows(ga) * ne * sizeof(double);
         const size_t gr_bytes = (size_t)deferred_readout_groups(ga) * ne * sizeof(double);
