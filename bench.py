@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--tuning", default=None, help="JSON dict of corr_tuning fields")
     ap.add_argument("--direct", action="store_true",
                     help="per-step update of every channel (no block-deferred form)")
+    ap.add_argument("--rhok-valu", action="store_true",
+                    help="k-density producer on the vector units instead of the matrix cores")
     return ap.parse_args()
 
 
@@ -238,10 +240,11 @@ def run(args):
     tune_s = 0.0
     if tuning is None and not args.no_autotune:
         t0 = time.perf_counter()
-        tuning = autotune(descs, per_group=(mode == "per_group"), direct=args.direct)
+        tuning = autotune(descs, per_group=(mode == "per_group"), direct=args.direct,
+                          rhok_valu=args.rhok_valu)
         tune_s = time.perf_counter() - t0
     corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuning, timing=True,
-                      direct=args.direct)
+                      direct=args.direct, rhok_valu=args.rhok_valu)
     state_gb = sum(corr.state_bytes(i) for i in range(len(descs))) / 1e9
 
     def push_chunk(n):
@@ -314,6 +317,7 @@ def run(args):
                 "timed chunk)",
         "config": {"workload": wl["name"], "channels": n_total, "launch": mode,
                    "update_form": "direct" if args.direct else "block-deferred where supported",
+                   "rhok_producer": "vector units" if args.rhok_valu else "matrix cores",
                    "tuning": corr.tuning(), "state_GB": round(state_gb, 2)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,

@@ -68,9 +68,16 @@ enum corr_flags {
                                  form) instead of one batched launch            */
     CORR_FLAG_TIMING = 4u,    /* bracket the update kernels of every push with
                                  HIP events (see corr_kernel_time)              */
-    CORR_FLAG_DIRECT = 8u     /* update every channel on every push (Algorithm 1
+    CORR_FLAG_DIRECT = 8u,    /* update every channel on every push (Algorithm 1
                                  step by step) even where the block-deferred
                                  form is available                              */
+    CORR_FLAG_RHOK_VALU = 16u /* evaluate n(k) on the vector units for every
+                                 k-density group; by default a group whose
+                                 k-set has |n component| <= 15 and at most 32
+                                 distinct n_z is evaluated as a matrix product
+                                 on the matrix cores (fp16 hi/lo operand split,
+                                 about 22 significant bits per product, fp32
+                                 tile sums added in fp64)                       */
 };
 
 typedef struct corr_group_desc {

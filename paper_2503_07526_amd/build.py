@@ -10,14 +10,15 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcorr_gfx950.so")
 HIPCC = "/opt/rocm/bin/hipcc"
 
-SOURCES = ["corr_push.hip", "corr_deferred.hip", "corr_rhok.hip", "corr_reduce.hip",
-           "corr_runtime.cpp", "corr_autotune.cpp"]
+SOURCES = ["corr_push.hip", "corr_deferred.hip", "corr_rhok.hip", "corr_rhok_mfma.hip",
+           "corr_reduce.hip", "corr_runtime.cpp", "corr_autotune.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-mcode-object-version=5", "-fPIC",
@@ -28,18 +29,23 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(obj_dir, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"]
-        cmd = [HIPCC] + FLAGS + lang + ["-c", path, "-o", obj]
+        cmds.append([HIPCC] + FLAGS + ["-x", "hip", "-c", path, "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        list(pool.map(compile_one, cmds))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

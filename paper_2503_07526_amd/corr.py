@@ -22,7 +22,7 @@ CORR_OK, CORR_E_INVALID, CORR_E_OOM, CORR_E_DEVICE, CORR_E_STATE, CORR_E_UNSUPPO
 DTYPES = {"f32": 1, "f64": 2, "cf32": 3, "cf64": 4}
 ACCUMS = {"f64": 1, "kahan": 2, "f32": 3}
 SOURCES = {"samples": 0, "rhok": 1}
-FLAG_GRAPH, FLAG_PER_GROUP, FLAG_TIMING, FLAG_DIRECT = 1, 2, 4, 8
+FLAG_GRAPH, FLAG_PER_GROUP, FLAG_TIMING, FLAG_DIRECT, FLAG_RHOK_VALU = 1, 2, 4, 8, 16
 _TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64, "cf32": torch.complex64,
                 "cf64": torch.complex128}
 
@@ -132,14 +132,15 @@ class GroupDesc:
 
 
 def autotune(groups, device: int = 0, stream=None, graph=False, per_group=False, direct=False,
-             cache_path: str | None = None, max_trial_channels: int = 0, force: bool = False):
+             cache_path: str | None = None, max_trial_channels: int = 0, force: bool = False,
+             rhok_valu: bool = False):
     """Run (or read from the cache) the launch-shape autotuner; returns the tuning dict."""
     L = lib()
     groups = list(groups)
     descs = (_GroupDesc * len(groups))(*[g.to_c() for g in groups])
     st = stream if stream is not None else torch.cuda.current_stream(device)
     flags = (FLAG_GRAPH if graph else 0) | (FLAG_PER_GROUP if per_group else 0) | \
-        (FLAG_DIRECT if direct else 0)
+        (FLAG_DIRECT if direct else 0) | (FLAG_RHOK_VALU if rhok_valu else 0)
     t = Tuning()
     rc = L.corr_autotune(descs, len(groups), int(device), ctypes.c_void_p(st.cuda_stream), flags,
                          cache_path.encode() if cache_path else None, int(max_trial_channels),
@@ -162,14 +163,15 @@ class Correlator:
 
     def __init__(self, groups, device: int = 0, stream: torch.cuda.Stream | None = None,
                  graph: bool = False, per_group: bool = False, tuning: dict | None = None,
-                 timing: bool = False, direct: bool = False):
+                 timing: bool = False, direct: bool = False, rhok_valu: bool = False):
         L = lib()
         self.groups = list(groups)
         descs = (_GroupDesc * len(self.groups))(*[g.to_c() for g in self.groups])
         self.device = int(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         flags = (FLAG_GRAPH if graph else 0) | (FLAG_PER_GROUP if per_group else 0) | \
-            (FLAG_TIMING if timing else 0) | (FLAG_DIRECT if direct else 0)
+            (FLAG_TIMING if timing else 0) | (FLAG_DIRECT if direct else 0) | \
+            (FLAG_RHOK_VALU if rhok_valu else 0)
         tn = Tuning(**tuning) if tuning else None
         h = ctypes.c_void_p()
         rc = L.corr_create(descs, len(self.groups), self.device,

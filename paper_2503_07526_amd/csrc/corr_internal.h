@@ -127,6 +127,29 @@ struct RhokArgs {
     int32_t pad_;
 };
 
+// k-density producer on the matrix cores: n(k) from real products over the
+// atoms of P(n_x, n_y) = X^{n_x} Y^{n_y} (rows: the distinct (n_x, n_y) pairs
+// of the k-set, padded to whole 16-row tiles) and Z^{|n_z|} (16 columns,
+// |n_z| = 0 .. 15); the sign of n_z selects how the sums combine.
+struct RhokMfmaArgs {
+    const float *pos;        // [3][n_atoms]
+    int64_t n_atoms;
+    const int32_t *pair_nx;  // [n_mtiles * 16], padding pairs (0, 0)
+    const int32_t *pair_ny;  // [n_mtiles * 16]
+    const int32_t *slot_k;   // [n_mtiles * 16][16 |n_z|][2 sign (n_z < 0)]: k index
+                             // stored for the slot, or -1
+    const int32_t *k_src;    // [nk]: partial row that holds k's sum
+    int32_t n_mtiles;
+    int32_t nmax;            // max |n component|, at most 15
+    double inv_box;          // 1 / L
+    double *partial;         // [nk][n_atom_blocks][2] FP64 partial sums
+    int32_t n_atom_blocks;
+    int32_t atoms_per_block;
+    void *out;               // [nk] complex samples (float2 or double2)
+    int32_t out_double;      // 1: double2 output
+    int32_t nk;
+};
+
 // Readout reduction arguments.
 struct ReduceArgs {
     const char *state;

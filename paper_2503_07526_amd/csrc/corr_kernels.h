@@ -16,6 +16,9 @@ hipError_t launch_step_increment(int64_t *step, hipStream_t st);
 hipError_t launch_rhok(const RhokArgs &a, hipStream_t st);
 int rhok_tile_atoms(int nmax);
 int rhok_block_threads(int n_seg);
+hipError_t launch_rhok_mfma(const RhokMfmaArgs &a, hipStream_t st);
+int rhok_mfma_cols();        // |n_z| columns of the matrix-core producer
+int rhok_mfma_max_nmax();    // largest |n component| it takes
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 bool deferred_supported(int kind, int p, int m);
 hipError_t launch_stage(const GroupArgs &g, const int64_t *step, hipStream_t st);

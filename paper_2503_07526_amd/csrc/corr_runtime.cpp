@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -45,6 +46,9 @@ struct Group {
     int32_t *d_seg = nullptr; // seg_nx0 | seg_ny | seg_nz | slot_out
     double *d_partial = nullptr;
     RhokArgs rargs{};
+    bool rhok_mfma = false;       // matrix-core producer (else rargs, vector units)
+    int32_t *d_mtab = nullptr;    // pair_nx | pair_ny | nz_list | slot_k | k_src
+    RhokMfmaArgs margs{};
 };
 
 } // namespace
@@ -199,6 +203,7 @@ void free_group(Group &g)
     if (g.rhok_out) (void)hipFree(g.rhok_out);
     if (g.d_seg) (void)hipFree(g.d_seg);
     if (g.d_partial) (void)hipFree(g.d_partial);
+    if (g.d_mtab) (void)hipFree(g.d_mtab);
     if (g.d_flushed) (void)hipFree(g.d_flushed);
     g = Group{};
 }
@@ -363,9 +368,16 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
     }
     hipStream_t pst = fork ? c->side_stream : st;
     for (int i : c->side_set) {
-        RhokArgs ra = c->groups[(size_t)i].rargs;
-        ra.pos = static_cast<const float *>(src[i]);
-        HIP_TRY(c, launch_rhok(ra, pst));
+        const Group &g = c->groups[(size_t)i];
+        if (g.rhok_mfma) {
+            RhokMfmaArgs ma = g.margs;
+            ma.pos = static_cast<const float *>(src[i]);
+            HIP_TRY(c, launch_rhok_mfma(ma, pst));
+        } else {
+            RhokArgs ra = g.rargs;
+            ra.pos = static_cast<const float *>(src[i]);
+            HIP_TRY(c, launch_rhok(ra, pst));
+        }
     }
     if (fork) {
         int rc = launch_set(c, c->pa_side, c->side_set, resolved, pst);
@@ -470,7 +482,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     if (n_groups > kMaxGroups)
         return set_err(nullptr, CORR_E_UNSUPPORTED, "at most %d groups per context", kMaxGroups);
     if (flags & ~(uint32_t)(CORR_FLAG_GRAPH | CORR_FLAG_PER_GROUP | CORR_FLAG_TIMING |
-                            CORR_FLAG_DIRECT))
+                            CORR_FLAG_DIRECT | CORR_FLAG_RHOK_VALU))
         return set_err(nullptr, CORR_E_INVALID, "unknown flags 0x%x", flags);
     for (int i = 0; i < n_groups; ++i) {
         int rc = validate(groups[i], i);
@@ -563,69 +575,122 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         if (g.rhok) {
             g.input_bytes = (size_t)3 * (size_t)g.d.n_atoms * sizeof(float);
             const int nk = (int)g.n_ch;
-            // Segments: k-vectors sharing (n_y, n_z) with n_x in a window of
-            // kSegWidth, rows ordered by (n_z, n_y).
             const int32_t *kv = groups[i].kvec;
-            std::vector<int> order((size_t)nk);
-            for (int q = 0; q < nk; ++q) order[(size_t)q] = q;
-            std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-                for (int d = 2; d >= 0; --d)
-                    if (kv[3 * x + d] != kv[3 * y + d]) return kv[3 * x + d] < kv[3 * y + d];
-                return false;
-            });
-            std::vector<int32_t> s_nx0, s_ny, s_nz, s_out;
             int nmax = 0;
             for (int q = 0; q < nk; ++q)
                 for (int d = 0; d < 3; ++d) nmax = std::max(nmax, std::abs(kv[3 * q + d]));
-            for (size_t u = 0; u < order.size();) {
-                const int k0 = order[u];
-                const int nx0 = kv[3 * k0], ny = kv[3 * k0 + 1], nz = kv[3 * k0 + 2];
-                int slots[kSegWidth];
-                for (int w = 0; w < kSegWidth; ++w) slots[w] = -1;
-                while (u < order.size()) {
-                    const int kq = order[u];
-                    const int w = kv[3 * kq] - nx0;
-                    if (kv[3 * kq + 1] != ny || kv[3 * kq + 2] != nz || w >= kSegWidth ||
-                        slots[w] >= 0)
-                        break;
-                    slots[w] = kq;
-                    ++u;
-                }
-                s_nx0.push_back(nx0);
-                s_ny.push_back(ny);
-                s_nz.push_back(nz);
-                for (int w = 0; w < kSegWidth; ++w) s_out.push_back(slots[w]);
-            }
-            const int n_seg = (int)s_nx0.size();
-            std::vector<int32_t> packed;
-            packed.insert(packed.end(), s_nx0.begin(), s_nx0.end());
-            packed.insert(packed.end(), s_ny.begin(), s_ny.end());
-            packed.insert(packed.end(), s_nz.begin(), s_nz.end());
-            packed.insert(packed.end(), s_out.begin(), s_out.end());
-            CREATE_HIP(hipMalloc(&g.d_seg, packed.size() * sizeof(int32_t)));
-            CREATE_HIP(hipMemcpy(g.d_seg, packed.data(), packed.size() * sizeof(int32_t),
-                                 hipMemcpyHostToDevice));
             // Atom blocks: about 1000 atoms or more each, at most 512 blocks.
             const int n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(512, g.d.n_atoms / 1024));
             const int64_t apb = (g.d.n_atoms + n_ab - 1) / n_ab;
-            CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * n_seg * kSegWidth * 2 * sizeof(double)));
             CREATE_HIP(hipMalloc(&g.rhok_out, (size_t)nk * g.s_bytes));
             CREATE_HIP(hipMemsetAsync(g.rhok_out, 0, (size_t)nk * g.s_bytes, c->stream));
-            RhokArgs &r = g.rargs;
-            r.pos = nullptr;
-            r.n_atoms = g.d.n_atoms;
-            r.seg_nx0 = g.d_seg;
-            r.seg_ny = g.d_seg + n_seg;
-            r.seg_nz = g.d_seg + 2 * n_seg;
-            r.slot_out = g.d_seg + 3 * n_seg;
-            r.n_seg = n_seg;
-            r.nmax = nmax;
-            r.inv_box = 1.0 / g.d.box;
-            r.partial = g.d_partial;
-            r.n_atom_blocks = n_ab;
-            r.atoms_per_block = (int32_t)apb;
-            r.out = g.rhok_out;
-            r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
+            // Matrix-core form: rows = distinct (n_x, n_y), columns = |n_z|.
+            g.rhok_mfma = !(flags & CORR_FLAG_RHOK_VALU) && nmax <= rhok_mfma_max_nmax();
+            if (g.rhok_mfma) {
+                std::map<std::pair<int, int>, int> pair_ix;
+                for (int q = 0; q < nk; ++q)
+                    pair_ix.emplace(std::make_pair(kv[3 * q], kv[3 * q + 1]), 0);
+                const int n_pairs = (int)pair_ix.size();
+                const int n_mtiles = (n_pairs + 15) / 16;
+                const int ncol = rhok_mfma_cols();
+                std::vector<int32_t> pnx((size_t)n_mtiles * 16, 0), pny((size_t)n_mtiles * 16, 0);
+                int u = 0;
+                for (auto &e : pair_ix) {
+                    e.second = u;
+                    pnx[(size_t)u] = e.first.first;
+                    pny[(size_t)u] = e.first.second;
+                    ++u;
+                }
+                std::vector<int32_t> slot_k((size_t)n_mtiles * 16 * ncol * 2, -1), k_src((size_t)nk);
+                for (int q = 0; q < nk; ++q) {
+                    const int pm = pair_ix[std::make_pair(kv[3 * q], kv[3 * q + 1])];
+                    const int nz = kv[3 * q + 2];
+                    const size_t slot = ((size_t)pm * ncol + std::abs(nz)) * 2 + (nz < 0 ? 1 : 0);
+                    if (slot_k[slot] < 0) slot_k[slot] = q; // first listing of a k-vector
+                    k_src[(size_t)q] = slot_k[slot];
+                }
+                std::vector<int32_t> packed;
+                packed.insert(packed.end(), pnx.begin(), pnx.end());
+                packed.insert(packed.end(), pny.begin(), pny.end());
+                packed.insert(packed.end(), slot_k.begin(), slot_k.end());
+                packed.insert(packed.end(), k_src.begin(), k_src.end());
+                CREATE_HIP(hipMalloc(&g.d_mtab, packed.size() * sizeof(int32_t)));
+                CREATE_HIP(hipMemcpy(g.d_mtab, packed.data(), packed.size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice));
+                CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * nk * 2 * sizeof(double)));
+                RhokMfmaArgs &r = g.margs;
+                r.pos = nullptr;
+                r.n_atoms = g.d.n_atoms;
+                r.pair_nx = g.d_mtab;
+                r.pair_ny = r.pair_nx + pnx.size();
+                r.slot_k = r.pair_ny + pny.size();
+                r.k_src = r.slot_k + slot_k.size();
+                r.n_mtiles = n_mtiles;
+                r.nmax = nmax;
+                r.inv_box = 1.0 / g.d.box;
+                r.partial = g.d_partial;
+                r.n_atom_blocks = n_ab;
+                r.atoms_per_block = (int32_t)apb;
+                r.out = g.rhok_out;
+                r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
+                r.nk = nk;
+            } else {
+                // Segments: k-vectors sharing (n_y, n_z) with n_x in a window of
+                // kSegWidth, rows ordered by (n_z, n_y).
+                std::vector<int> order((size_t)nk);
+                for (int q = 0; q < nk; ++q) order[(size_t)q] = q;
+                std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+                    for (int d = 2; d >= 0; --d)
+                        if (kv[3 * x + d] != kv[3 * y + d]) return kv[3 * x + d] < kv[3 * y + d];
+                    return false;
+                });
+                std::vector<int32_t> s_nx0, s_ny, s_nz, s_out;
+                for (size_t u = 0; u < order.size();) {
+                    const int k0 = order[u];
+                    const int nx0 = kv[3 * k0], ny = kv[3 * k0 + 1], nz = kv[3 * k0 + 2];
+                    int slots[kSegWidth];
+                    for (int w = 0; w < kSegWidth; ++w) slots[w] = -1;
+                    while (u < order.size()) {
+                        const int kq = order[u];
+                        const int w = kv[3 * kq] - nx0;
+                        if (kv[3 * kq + 1] != ny || kv[3 * kq + 2] != nz || w >= kSegWidth ||
+                            slots[w] >= 0)
+                            break;
+                        slots[w] = kq;
+                        ++u;
+                    }
+                    s_nx0.push_back(nx0);
+                    s_ny.push_back(ny);
+                    s_nz.push_back(nz);
+                    for (int w = 0; w < kSegWidth; ++w) s_out.push_back(slots[w]);
+                }
+                const int n_seg = (int)s_nx0.size();
+                std::vector<int32_t> packed;
+                packed.insert(packed.end(), s_nx0.begin(), s_nx0.end());
+                packed.insert(packed.end(), s_ny.begin(), s_ny.end());
+                packed.insert(packed.end(), s_nz.begin(), s_nz.end());
+                packed.insert(packed.end(), s_out.begin(), s_out.end());
+                CREATE_HIP(hipMalloc(&g.d_seg, packed.size() * sizeof(int32_t)));
+                CREATE_HIP(hipMemcpy(g.d_seg, packed.data(), packed.size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice));
+                CREATE_HIP(hipMalloc(&g.d_partial,
+                                     (size_t)n_ab * n_seg * kSegWidth * 2 * sizeof(double)));
+                RhokArgs &r = g.rargs;
+                r.pos = nullptr;
+                r.n_atoms = g.d.n_atoms;
+                r.seg_nx0 = g.d_seg;
+                r.seg_ny = g.d_seg + n_seg;
+                r.seg_nz = g.d_seg + 2 * n_seg;
+                r.slot_out = g.d_seg + 3 * n_seg;
+                r.n_seg = n_seg;
+                r.nmax = nmax;
+                r.inv_box = 1.0 / g.d.box;
+                r.partial = g.d_partial;
+                r.n_atom_blocks = n_ab;
+                r.atoms_per_block = (int32_t)apb;
+                r.out = g.rhok_out;
+                r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
+            }
         } else {
             g.input_bytes = (size_t)g.n_ch * g.s_bytes;
         }

@@ -127,19 +127,21 @@ def test_snapshot_is_non_destructive(corrmod):
         gate(mid, o, TOL[("f32", "kahan")], label="mid-run")
 
 
-def test_rhok_magnitude_and_phase(corrmod):
+@pytest.mark.parametrize("rhok_valu", [False, True])
+def test_rhok_magnitude_and_phase(corrmod, rhok_valu):
     """One push: C(0) of k = |n(k)|^2 / N.  Two pushes with every atom moved by
-    d: C(lag 1) = exp(i k.d) |n(k)|^2 / N (later times conj(earlier))."""
+    d: C(lag 1) = exp(i k.d) |n(k)|^2 / N (later times conj(earlier)).  Both
+    producers: matrix cores (default) and vector units."""
     kv = synth.kvectors(300)
     N, box = 5000, 100.0
-    say(f"[rho(k)] N={N} nk={len(kv)}")
+    say(f"[rho(k)] N={N} nk={len(kv)} valu={rhok_valu}")
     ps = synth.PositionSpec(4, 4, N, box)
     r0 = ps.r0.copy()
     d = np.array([0.37, -1.25, 2.5], dtype=np.float32)
     r1 = (r0 + d[:, None]).astype(np.float32)
     g = corrmod.GroupDesc(len(kv), 3, 8, 2, dtype="cf32", accum="f64", source="rhok", kvec=kv,
                           n_atoms=N, box=box)
-    with corrmod.Correlator([g]) as c:
+    with corrmod.Correlator([g], rhok_valu=rhok_valu) as c:
         _push_all(c, [r0[None]])
         res = c.finalize(0, slice_=(0, len(kv)))
         rho0 = oracle.rhok(r0, kv, box)
@@ -154,11 +156,50 @@ def test_rhok_magnitude_and_phase(corrmod):
         assert np.max(np.abs(got1 - expect1)) / np.max(np.abs(expect1)) < 2e-6
 
 
-def test_batched_mixed_groups_and_modes(corrmod):
+@pytest.mark.parametrize("case", ["wide_nz", "large_n", "duplicates", "ragged_atoms"])
+def test_rhok_kset_shapes(corrmod, case):
+    """k-sets outside the matrix-core limits (more than 32 distinct n_z, a
+    component above 15) take the vector-unit producer; repeated k-vectors and
+    atom counts that are not a multiple of the atom tile: every listed k gets
+    |n(k)|^2 / N at lag 0, and both producers agree where both apply."""
+    rng = np.random.default_rng(11)
+    N, box = 3001, 50.0
+    if case == "wide_nz":
+        kv = np.stack([rng.integers(-3, 4, 200), rng.integers(-3, 4, 200),
+                       rng.integers(-20, 21, 200)], axis=1).astype(np.int32)
+    elif case == "large_n":
+        kv = np.stack([rng.integers(-16, 17, 150), rng.integers(-2, 3, 150),
+                       rng.integers(-2, 3, 150)], axis=1).astype(np.int32)
+        kv[0] = (16, 0, 0)
+    elif case == "duplicates":
+        base = synth.kvectors(100)
+        kv = np.concatenate([base, base[::7], base[:3]]).astype(np.int32)
+    else:
+        kv = synth.kvectors(257)
+        N = 64 * 37 + 19
+    kv = kv[np.any(kv != 0, axis=1)]  # k = 0 would only measure N
+    say(f"[rho(k) k-set] {case} nk={len(kv)} N={N}")
+    ps = synth.PositionSpec(9, 1, N, box)
+    r0 = ps.r0.copy()
+    expect = np.abs(oracle.rhok(r0, kv, box)) ** 2 / N
+    got = {}
+    for valu in (False, True):
+        g = corrmod.GroupDesc(len(kv), 2, 4, 2, dtype="cf32", accum="f64", source="rhok",
+                              kvec=kv, n_atoms=N, box=box)
+        with corrmod.Correlator([g], rhok_valu=valu) as c:
+            _push_all(c, [r0[None]])
+            got[valu] = c.finalize(0, slice_=(0, len(kv)))["c_per_channel"][:, 0]
+        err = np.max(np.abs(got[valu] - expect)) / np.max(expect)
+        assert err < 2e-6, (case, valu, err)
+    assert np.max(np.abs(got[False] - got[True])) / np.max(expect) < 2e-6
+
+
+@pytest.mark.parametrize("rhok_valu", [False, True])
+def test_batched_mixed_groups_and_modes(corrmod, rhok_valu):
     """Three uneven groups in one context (compensated FP32 velocities, the
     k-space density, FP64 global channels): parity with the oracle, and
     bit-identical state from the batched launch, the per-group launches and the
-    HIP graph replay."""
+    HIP graph replay, with either k-density producer."""
     S, nv, N, box = 400, 2500, 3000, 100.0
     kv = synth.kvectors(200)
     say(f"[batched] S={S} nv={nv} N={N} nk={len(kv)}")
@@ -178,8 +219,8 @@ def test_batched_mixed_groups_and_modes(corrmod):
     results = {}
     for mode in ("batched", "per_group", "graph"):
         say(f"  mode {mode}")
-        with corrmod.Correlator(groups, graph=(mode == "graph"),
-                                per_group=(mode == "per_group")) as c:
+        with corrmod.Correlator(groups, graph=(mode == "graph"), per_group=(mode == "per_group"),
+                                rhok_valu=rhok_valu) as c:
             dev = torch.device("cuda:0")
             tv = torch.from_numpy(xv).to(dev)
             tg = torch.from_numpy(xg).to(dev)
