@@ -73,11 +73,11 @@ enum corr_flags {
                                  form is available                              */
     CORR_FLAG_RHOK_VALU = 16u /* evaluate n(k) on the vector units for every
                                  k-density group; by default a group whose
-                                 k-set has |n component| <= 15 and at most 32
-                                 distinct n_z is evaluated as a matrix product
-                                 on the matrix cores (fp16 hi/lo operand split,
-                                 about 22 significant bits per product, fp32
-                                 tile sums added in fp64)                       */
+                                 k-set has |n component| <= 15 is evaluated as
+                                 a matrix product on the matrix cores (fp16
+                                 hi/lo operand split, about 22 significant
+                                 bits per product, fp32 tile sums added in
+                                 fp64)                                          */
 };
 
 typedef struct corr_group_desc {

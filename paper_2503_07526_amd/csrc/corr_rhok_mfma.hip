@@ -15,22 +15,27 @@
 // split into v_hi = fp16(v) and v_lo = fp16(v - v_hi) (about 22 significant
 // bits together) and a real product is a_hi b_hi + a_hi b_lo + a_lo b_hi (the
 // dropped a_lo b_lo is below 2^-22), i.e. three fp16 matrix products with
-// fp32 accumulation per sum, twelve per tile and K-step
-// (v_mfma_f32_16x16x16_f16).  The fp32 accumulators are added to double
-// accumulators after every tile of kMfmaTileAtoms atoms and the blocks write
-// double partials, reduced over the atom blocks in a fixed order as in the
-// vector-unit producer (corr_rhok.hip), so the result is reproducible.
+// fp32 accumulation per sum, twelve per K-step.  The fp32 accumulators are
+// added to double accumulators after every tile of kMfmaTileAtoms atoms and
+// the blocks write double partials, reduced over the atom blocks in a fixed
+// order as in the vector-unit producer (corr_rhok.hip), so the result is
+// reproducible.  The tables start from e^{2 pi i x / L} in double (a 64-entry
+// root table times a short Taylor series) and take the powers by a double
+// recurrence, each power rounded once to float.
 //
-// Operand layout of v_mfma_f32_16x16x16_f16 (checked on the device): lane l
-// holds A[l%16][4(l/16)+j] and B[4(l/16)+j][l%16] for j < 4 and receives
-// D[4(l/16)+v][l%16] for v < 4; K runs over 16 atoms.
+// Operand layout of the contraction (checked on the device): lane l holds
+// A[l%16][a(l/16)+j] and B[a(l/16)+j][l%16] for j < a, a = atoms per lane,
+// and receives D[4(l/16)+v][l%16] for v < 4.  Only the pairing of A and B
+// along K matters for the sum, and it is the same for both operands.
 //
 // Work split: block (chunk, atom block); each wave of a block owns one M tile
 // and all waves share the tile's LDS tables: X and Y powers as float2
 // [2 nmax + 1][kTabStride] (a row per power, atoms along the row, so a lane's
-// four atoms are two 16-byte reads; the row stride is padded so that the 16
-// rows a K-step reads start in different banks) and the split |n_z| powers
-// already in B-fragment order.
+// atoms are 16-byte reads; the row stride is padded so that the 16 rows a
+// K-step reads start in different banks) and the split |n_z| powers already
+// in B-fragment order.  The tables are double-buffered: the first waves build
+// the next tile's tables while every wave contracts the current one, one
+// barrier per tile, and the positions are loaded a tile ahead.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
@@ -39,51 +44,175 @@ namespace corr {
 
 namespace {
 
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+// The contraction instruction: K = 32 atoms per v_mfma_f32_16x16x32_f16 (lane
+// l holds 8 consecutive atoms, 8(l/16) .. 8(l/16)+7, of A row l%16 and of B
+// column l%16), or K = 16 with v_mfma_f32_16x16x16_f16 (4 atoms per lane).
+constexpr bool kWideK = true;
+constexpr int kAtomsPerLane = kWideK ? 8 : 4;
+constexpr int kKStep = 4 * kAtomsPerLane; // atoms per K-step
+
+typedef _Float16 halfv_t __attribute__((ext_vector_type(kAtomsPerLane)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaTileAtoms = 64; // atoms per LDS tile (4 K-steps of 16)
-constexpr int kMfmaKSteps = kMfmaTileAtoms / 16;
+constexpr int kMfmaTileAtoms = 64; // atoms per LDS tile
+constexpr int kMfmaKSteps = kMfmaTileAtoms / kKStep;
 constexpr int kTabStride = kMfmaTileAtoms + 2; // float2 per table row (4-bank shift)
-constexpr int kMfmaMaxWaves = 16;  // waves per block (one M tile each)
+constexpr int kMfmaMaxWaves = 12;  // waves per block (one M tile each)
+constexpr int kTableTasks = 3 * kMfmaTileAtoms; // (axis, atom) tasks per tile
+constexpr int kMfmaMinWaves = kTableTasks / 64; // every task has its own thread
 constexpr int kMfmaCols = 16;      // |n_z| = 0 .. 15
-// B fragments in LDS: [K-step][part: re hi, re lo, im hi, im lo][atom quad][column]
+constexpr int kRoots = 64;         // e^{2 pi i q / kRoots} table for the base phase
+// B fragments in LDS: [K-step][part: re hi, re lo, im hi, im lo][atom group][column]
 constexpr int kBParts = 4;
-constexpr int kBHalves = kMfmaKSteps * kBParts * 4 * kMfmaCols * 4;
+constexpr int kBFrags = kMfmaKSteps * kBParts * 4 * kMfmaCols;
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4_t mfma(half8_t a, half8_t b, float4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
 
 __device__ __forceinline__ float4_t mfma(half4_t a, half4_t b, float4_t c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ int bfrag_index(int ks, int part, int quad, int col)
+__device__ __forceinline__ int bfrag_index(int ks, int part, int grp, int col)
 {
-    return ((ks * kBParts + part) * 4 + quad) * kMfmaCols + col; // in half4 units
+    return ((ks * kBParts + part) * 4 + grp) * kMfmaCols + col; // in halfv_t units
+}
+
+// Two floats to two fp16 (round to nearest even), packed low | high.
+__device__ __forceinline__ uint32_t pack_half2(float a, float b)
+{
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, h2v));
+}
+
+// lo = fp16(a - hi.low) | fp16(b - hi.high) << 16, each from one fused
+// mixed-precision operation (the fp16 source negated, times 1, plus the fp32
+// value, rounded once to fp16).
+__device__ __forceinline__ void lo_half2(uint32_t &lo, uint32_t hi, float a, float b)
+{
+    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lo) : "v"(hi), "v"(a));
+    asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "+v"(lo)
+        : "v"(hi), "v"(b));
+}
+
+__device__ __forceinline__ void cmul(double &r, double &i, double br, double bi)
+{
+    const double t = r * br - i * bi;
+    i = r * bi + i * br;
+    r = t;
+}
+
+// e^{2 pi i f} in double: f = q / kRoots + u with q the nearest multiple and
+// |u| <= 1 / (2 kRoots); e^{2 pi i q / kRoots} from the block's table, e^{2 pi i u}
+// from its Taylor series (|2 pi u| < 0.05: the first omitted terms are below
+// 1e-19 relative).
+__device__ __forceinline__ void unit_phase(double f, const double2 *roots, double &c, double &s)
+{
+    const double t = (f - floor(f)) * kRoots; // exact scaling
+    const double q = rint(t);
+    const double th = (t - q) * (2.0 * 3.14159265358979323846 / kRoots);
+    const double t2 = th * th;
+    const double cu = 1.0 + t2 * (-1.0 / 2 + t2 * (1.0 / 24 + t2 * (-1.0 / 720 + t2 * (1.0 / 40320))));
+    const double su = th * (1.0 + t2 * (-1.0 / 6 + t2 * (1.0 / 120 + t2 * (-1.0 / 5040 +
+                                                                     t2 * (1.0 / 362880)))));
+    const double2 w = roots[(int)q & (kRoots - 1)];
+    c = w.x * cu - w.y * su;
+    s = w.x * su + w.y * cu;
+}
+
+struct TileBufs {
+    float2 *tabx;   // [nn][kTabStride]
+    float2 *taby;   // [nn][kTabStride]
+    halfv_t *bfr;   // [kBFrags]
+};
+
+// Build the tables of one tile: task (axis d, atom j), base phase from
+// unit_phase, powers by a double recurrence, each rounded once; X and Y rows
+// for both signs, Z^{0..nmax} split into fp16 hi/lo B fragments.  Atoms past
+// the end (live == false) get zero entries, so they add nothing.
+__device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool live, float x,
+                                           double inv_box, int nmax, const double2 *roots)
+{
+    const int d = task / kMfmaTileAtoms, j = task - d * kMfmaTileAtoms;
+    double cs = 0.0, sn = 0.0;
+    if (live) unit_phase((double)x * inv_box, roots, cs, sn);
+    const double one = live ? 1.0 : 0.0;
+    double pr = one, pi = 0.0;
+    if (d < 2) {
+        float2 *colp = (d == 0 ? tb.tabx : tb.taby) + j;
+        colp[nmax * kTabStride] = make_float2((float)one, 0.f);
+        for (int n = 1; n <= nmax; ++n) {
+            cmul(pr, pi, cs, sn);
+            colp[(nmax + n) * kTabStride] = make_float2((float)pr, (float)pi);
+            colp[(nmax - n) * kTabStride] = make_float2((float)pr, -(float)pi);
+        }
+    } else {
+        const int ks = j / kKStep, g = (j % kKStep) / kAtomsPerLane, h = j % kAtomsPerLane;
+        _Float16 *bh = reinterpret_cast<_Float16 *>(tb.bfr);
+        for (int n = 0; n <= nmax; ++n) {
+            if (n > 0) cmul(pr, pi, cs, sn);
+            float zr = (float)pr, zi = (float)pi;
+            // keep the float rounding step visible: otherwise double -> float
+            // -> half is folded into one double -> half conversion, which has
+            // no instruction and is expanded into integer code
+            asm volatile("" : "+v"(zr), "+v"(zi));
+            const _Float16 rh = (_Float16)zr, ih = (_Float16)zi;
+            const _Float16 rl = (_Float16)(zr - (float)rh), il = (_Float16)(zi - (float)ih);
+            bh[bfrag_index(ks, 0, g, n) * kAtomsPerLane + h] = rh;
+            bh[bfrag_index(ks, 1, g, n) * kAtomsPerLane + h] = rl;
+            bh[bfrag_index(ks, 2, g, n) * kAtomsPerLane + h] = ih;
+            bh[bfrag_index(ks, 3, g, n) * kAtomsPerLane + h] = il;
+        }
+    }
 }
 
 __global__ __launch_bounds__(kMfmaMaxWaves * 64) void rhok_mfma_kernel(RhokMfmaArgs a)
 {
-    extern __shared__ float2 lds[];
-    const int nn = 2 * a.nmax + 1;
-    float2 *tabx = lds;                        // [nn][kTabStride]
-    float2 *taby = tabx + nn * kTabStride;     // [nn][kTabStride]
-    half4_t *bfr = reinterpret_cast<half4_t *>(taby + nn * kTabStride);
-    _Float16 *bh = reinterpret_cast<_Float16 *>(bfr);
+    extern __shared__ double2 lds_roots[]; // [kRoots], then two tile buffers
+    const int nmax = a.nmax;
+    const int nn = 2 * nmax + 1;
+    // two tile buffers of buf_stride float2 each (a multiple of 2: 16-byte aligned)
+    float2 *const buf0 = reinterpret_cast<float2 *>(lds_roots + kRoots);
+    const int buf_stride = 2 * nn * kTabStride + kBFrags * (int)(sizeof(halfv_t) / sizeof(float2));
+    auto tile_bufs = [&](int b) {
+        TileBufs t;
+        t.tabx = buf0 + b * buf_stride;
+        t.taby = t.tabx + nn * kTabStride;
+        t.bfr = reinterpret_cast<halfv_t *>(t.taby + nn * kTabStride);
+        return t;
+    };
 
     const int waves = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15; // A row / B column within the tile
-    const int kq = lane >> 4;  // atom quad of the K-step
+    const int grp = lane >> 4; // atom group of the K-step
     const int mt = blockIdx.x * waves + wave;
     const bool active = mt < a.n_mtiles; // wave-uniform
     const int pm_row = mt * 16 + col;
-    const int ax = active ? a.pair_nx[pm_row] + a.nmax : a.nmax;
-    const int ay = active ? a.pair_ny[pm_row] + a.nmax : a.nmax;
-    // the lane's X and Y rows at its first atom, 16-byte aligned
-    const float4 *xrow = reinterpret_cast<const float4 *>(tabx + ax * kTabStride + kq * 4);
-    const float4 *yrow = reinterpret_cast<const float4 *>(taby + ay * kTabStride + kq * 4);
-    const half4_t *bl = bfr + kq * kMfmaCols + col;
+    const int ax = active ? a.pair_nx[pm_row] + nmax : nmax;
+    const int ay = active ? a.pair_ny[pm_row] + nmax : nmax;
+    // the lane's X and Y rows at its first atom (16-byte aligned) per buffer
+    const int xoff = ax * kTabStride + grp * kAtomsPerLane;
+    const int yoff = ay * kTabStride + grp * kAtomsPerLane;
+    const int boff = grp * kMfmaCols + col;
+
+    for (int q = threadIdx.x; q < kRoots; q += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * q / kRoots, &sn, &cs);
+        lds_roots[q] = make_double2(cs, sn);
+    }
+    // B columns above nmax are never stored; keep them zero
+    for (int f = threadIdx.x; f < 2 * kBFrags; f += blockDim.x)
+        if (f % kMfmaCols > nmax) tile_bufs(f / kBFrags).bfr[f % kBFrags] = halfv_t{};
 
     double acc[4][4];
 #pragma unroll
@@ -94,113 +223,118 @@ __global__ __launch_bounds__(kMfmaMaxWaves * 64) void rhok_mfma_kernel(RhokMfmaA
     const int64_t a_begin = (int64_t)blockIdx.y * a.atoms_per_block;
     int64_t a_end = a_begin + a.atoms_per_block;
     if (a_end > a.n_atoms) a_end = a.n_atoms;
+    const int n_tiles = a_end > a_begin ? (int)((a_end - a_begin + kMfmaTileAtoms - 1) / kMfmaTileAtoms) : 0;
 
-    for (int64_t t0 = a_begin; t0 < a_end; t0 += kMfmaTileAtoms) {
-        const int nt = (int)((a_end - t0) < kMfmaTileAtoms ? (a_end - t0) : kMfmaTileAtoms);
-        __syncthreads();
-        // Tables: task (axis d, atom j), d uniform per wave.  Base phase from a
-        // double sincospi, powers by a double recurrence, rounded once.  Atoms
-        // past the end of the range get zero entries (no contribution).
-        for (int task = threadIdx.x; task < 3 * kMfmaTileAtoms; task += blockDim.x) {
-            const int d = task / kMfmaTileAtoms, j = task - d * kMfmaTileAtoms;
-            const bool live = j < nt;
-            double sn = 0.0, cs = 1.0;
-            if (live) {
-                const double f = (double)a.pos[(int64_t)d * a.n_atoms + t0 + j] * a.inv_box;
-                sincospi(2.0 * f, &sn, &cs);
-            }
-            if (d < 2) {
-                float2 *colp = (d == 0 ? tabx : taby) + j;
-                if (!live) {
-                    for (int n = 0; n < nn; ++n) colp[n * kTabStride] = make_float2(0.f, 0.f);
-                    continue;
-                }
-                double pr = 1.0, pi = 0.0;
-                colp[a.nmax * kTabStride] = make_float2(1.f, 0.f);
-                for (int n = 1; n <= a.nmax; ++n) {
-                    const double r = pr * cs - pi * sn;
-                    const double i = pr * sn + pi * cs;
-                    pr = r;
-                    pi = i;
-                    colp[(a.nmax + n) * kTabStride] = make_float2((float)pr, (float)pi);
-                    colp[(a.nmax - n) * kTabStride] = make_float2((float)pr, -(float)pi);
-                }
-            } else {
-                // Z^{c}, c = |n_z| in [0, 15], split into fp16 hi/lo, stored at
-                // half j%4 of the fragment of (K-step, quad, column c)
-                const int ks = j >> 4, quad = (j >> 2) & 3, h = j & 3;
-                double pr = live ? 1.0 : 0.0, pi = 0.0;
-                for (int c = 0; c < kMfmaCols; ++c) {
-                    if (c > 0) {
-                        const double r = pr * cs - pi * sn;
-                        const double i = pr * sn + pi * cs;
-                        pr = r;
-                        pi = i;
+    // table task of this thread (blockDim >= kTableTasks) and its positions,
+    // loaded one tile ahead of their use
+    const int task = threadIdx.x;
+    const bool builder = task < kTableTasks;
+    const int td = task / kMfmaTileAtoms, tj = task - td * kMfmaTileAtoms;
+    auto load_pos = [&](int it, float &x) -> bool {
+        const int64_t at = a_begin + (int64_t)it * kMfmaTileAtoms + tj;
+        const bool live = builder && it < n_tiles && at < a_end;
+        x = live ? a.pos[(int64_t)td * a.n_atoms + at] : 0.f;
+        return live;
+    };
+    float x_cur, x_next;
+    bool live_cur = load_pos(0, x_cur);
+    bool live_next = load_pos(1, x_next);
+    __syncthreads(); // roots and zero columns
+    if (builder) build_tile(tile_bufs(0), task, live_cur, x_cur, a.inv_box, nmax, lds_roots);
+    __syncthreads();
+
+    for (int it = 0; it < n_tiles; ++it) {
+        const TileBufs cur = tile_bufs(it & 1);
+        // tables of the next tile into the other buffer
+        if (builder && it + 1 < n_tiles) {
+            float x_after;
+            const bool live_after = load_pos(it + 2, x_after);
+            build_tile(tile_bufs((it + 1) & 1), task, live_next, x_next, a.inv_box, nmax, lds_roots);
+            x_next = x_after;
+            live_next = live_after;
+        }
+        if (active) {
+            const float4 *xrow = reinterpret_cast<const float4 *>(cur.tabx + xoff);
+            const float4 *yrow = reinterpret_cast<const float4 *>(cur.taby + yoff);
+            const halfv_t *bl = cur.bfr + boff;
+            float4_t s1 = {0.f, 0.f, 0.f, 0.f}, s2 = s1, s3 = s1, s4 = s1;
+            // all K-steps of the tile: the entries of atoms past the end are zero
+#pragma unroll
+            for (int ks = 0; ks < kMfmaKSteps; ++ks) {
+                const halfv_t zrh = bl[bfrag_index(ks, 0, 0, 0)];
+                const halfv_t zrl = bl[bfrag_index(ks, 1, 0, 0)];
+                const halfv_t zih = bl[bfrag_index(ks, 2, 0, 0)];
+                const halfv_t zil = bl[bfrag_index(ks, 3, 0, 0)];
+                uint32_t wrh[kAtomsPerLane / 2], wrl[kAtomsPerLane / 2];
+                uint32_t wih[kAtomsPerLane / 2], wil[kAtomsPerLane / 2];
+#pragma unroll
+                for (int q2 = 0; q2 < kAtomsPerLane / 2; ++q2) {
+                    const float4 x = xrow[ks * (kKStep / 2) + q2];
+                    const float4 y = yrow[ks * (kKStep / 2) + q2];
+                    const float xr[2] = {x.x, x.z}, xi[2] = {x.y, x.w};
+                    const float yr[2] = {y.x, y.z}, yi[2] = {y.y, y.w};
+                    float pr[2], pi[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        pr[e] = __builtin_fmaf(xr[e], yr[e], -xi[e] * yi[e]);
+                        pi[e] = __builtin_fmaf(xr[e], yi[e], xi[e] * yr[e]);
                     }
-                    const float zr = c <= a.nmax ? (float)pr : 0.f;
-                    const float zi = c <= a.nmax ? (float)pi : 0.f;
-                    const _Float16 rh = (_Float16)zr, ih = (_Float16)zi;
-                    const _Float16 rl = (_Float16)(zr - (float)rh), il = (_Float16)(zi - (float)ih);
-                    bh[bfrag_index(ks, 0, quad, c) * 4 + h] = rh;
-                    bh[bfrag_index(ks, 1, quad, c) * 4 + h] = rl;
-                    bh[bfrag_index(ks, 2, quad, c) * 4 + h] = ih;
-                    bh[bfrag_index(ks, 3, quad, c) * 4 + h] = il;
+                    // hi = fp16(v) for both atoms in one packed conversion; lo =
+                    // fp16(v - hi) by a mixed-precision fma that reads hi as fp16
+                    // (one instruction per value, no round trip through fp32)
+                    const uint32_t hr = pack_half2(pr[0], pr[1]);
+                    const uint32_t hi = pack_half2(pi[0], pi[1]);
+                    uint32_t lr, li;
+                    lo_half2(lr, hr, pr[0], pr[1]);
+                    lo_half2(li, hi, pi[0], pi[1]);
+                    wrh[q2] = hr;
+                    wrl[q2] = lr;
+                    wih[q2] = hi;
+                    wil[q2] = li;
                 }
+                typedef uint32_t wv_t __attribute__((ext_vector_type(kAtomsPerLane / 2)));
+                wv_t vrh, vrl, vih, vil;
+#pragma unroll
+                for (int q2 = 0; q2 < kAtomsPerLane / 2; ++q2) {
+                    vrh[q2] = wrh[q2];
+                    vrl[q2] = wrl[q2];
+                    vih[q2] = wih[q2];
+                    vil[q2] = wil[q2];
+                }
+                const halfv_t prh = __builtin_bit_cast(halfv_t, vrh);
+                const halfv_t prl = __builtin_bit_cast(halfv_t, vrl);
+                const halfv_t pih = __builtin_bit_cast(halfv_t, vih);
+                const halfv_t pil = __builtin_bit_cast(halfv_t, vil);
+                // interleaved so that dependent products on one sum are apart
+                s1 = mfma(prh, zrh, s1);
+                s2 = mfma(pih, zih, s2);
+                s3 = mfma(prh, zih, s3);
+                s4 = mfma(pih, zrh, s4);
+                s1 = mfma(prh, zrl, s1);
+                s2 = mfma(pih, zil, s2);
+                s3 = mfma(prh, zil, s3);
+                s4 = mfma(pih, zrl, s4);
+                s1 = mfma(prl, zrh, s1);
+                s2 = mfma(pil, zih, s2);
+                s3 = mfma(prl, zih, s3);
+                s4 = mfma(pil, zrh, s4);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                acc[0][v] += (double)s1[v];
+                acc[1][v] += (double)s2[v];
+                acc[2][v] += (double)s3[v];
+                acc[3][v] += (double)s4[v];
             }
         }
-        __syncthreads();
-        if (!active) continue;
-        float4_t s1 = {0.f, 0.f, 0.f, 0.f}, s2 = s1, s3 = s1, s4 = s1;
-        // all four K-steps: the entries of atoms past nt are zero
-#pragma unroll
-        for (int ks = 0; ks < kMfmaKSteps; ++ks) {
-            const half4_t zrh = bl[bfrag_index(ks, 0, 0, 0)];
-            const half4_t zrl = bl[bfrag_index(ks, 1, 0, 0)];
-            const half4_t zih = bl[bfrag_index(ks, 2, 0, 0)];
-            const half4_t zil = bl[bfrag_index(ks, 3, 0, 0)];
-            const float4 x01 = xrow[ks * 8], x23 = xrow[ks * 8 + 1];
-            const float4 y01 = yrow[ks * 8], y23 = yrow[ks * 8 + 1];
-            const float xr[4] = {x01.x, x01.z, x23.x, x23.z}, xi[4] = {x01.y, x01.w, x23.y, x23.w};
-            const float yr[4] = {y01.x, y01.z, y23.x, y23.z}, yi[4] = {y01.y, y01.w, y23.y, y23.w};
-            half4_t prh, prl, pih, pil;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float pr = __builtin_fmaf(xr[q], yr[q], -xi[q] * yi[q]);
-                const float pi = __builtin_fmaf(xr[q], yi[q], xi[q] * yr[q]);
-                const _Float16 rh = (_Float16)pr, ih = (_Float16)pi;
-                prh[q] = rh;
-                pih[q] = ih;
-                prl[q] = (_Float16)(pr - (float)rh);
-                pil[q] = (_Float16)(pi - (float)ih);
-            }
-            // interleaved so that dependent products on one sum are apart
-            s1 = mfma(prh, zrh, s1);
-            s2 = mfma(pih, zih, s2);
-            s3 = mfma(prh, zih, s3);
-            s4 = mfma(pih, zrh, s4);
-            s1 = mfma(prh, zrl, s1);
-            s2 = mfma(pih, zil, s2);
-            s3 = mfma(prh, zil, s3);
-            s4 = mfma(pih, zrl, s4);
-            s1 = mfma(prl, zrh, s1);
-            s2 = mfma(pil, zih, s2);
-            s3 = mfma(prl, zih, s3);
-            s4 = mfma(pil, zrh, s4);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            acc[0][v] += (double)s1[v];
-            acc[1][v] += (double)s2[v];
-            acc[2][v] += (double)s3[v];
-            acc[3][v] += (double)s4[v];
-        }
+        __syncthreads(); // next buffer complete; this one free for the tile after
     }
     if (!active) return;
     // Row pm = pair, column col = |n_z|: only slots that are k-vectors of the
     // group are stored, in partial[k][atom block].
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int pm = mt * 16 + kq * 4 + v;
+        const int pm = mt * 16 + grp * 4 + v;
         const int32_t *sk = a.slot_k + ((size_t)pm * kMfmaCols + col) * 2;
         const int kp = sk[0], km = sk[1];
         if (kp >= 0) {
@@ -248,17 +382,32 @@ __global__ __launch_bounds__(256) void rhok_mfma_final_kernel(RhokMfmaArgs a)
 int rhok_mfma_cols() { return kMfmaCols; }
 int rhok_mfma_max_nmax() { return kMfmaCols - 1; }
 
+size_t rhok_mfma_lds_bytes(int nmax)
+{
+    const int nn = 2 * nmax + 1;
+    return (size_t)kRoots * sizeof(double2) +
+           2 * ((size_t)2 * nn * kTabStride * sizeof(float2) + (size_t)kBFrags * sizeof(halfv_t));
+}
+
+hipError_t rhok_mfma_prepare(int nmax)
+{
+    if (nmax > kMfmaCols - 1) return hipErrorInvalidValue;
+    const size_t lds = rhok_mfma_lds_bytes(nmax);
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&rhok_mfma_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 hipError_t launch_rhok_mfma(const RhokMfmaArgs &a, hipStream_t st)
 {
     if (a.nmax > kMfmaCols - 1 || a.n_mtiles < 1) return hipErrorInvalidValue;
-    const int nn = 2 * a.nmax + 1;
-    const size_t lds = (size_t)2 * nn * kTabStride * sizeof(float2) +
-                       (size_t)kBHalves * sizeof(_Float16);
-    // waves per block: the M tiles dealt evenly over the fewest blocks
+    // waves per block: the M tiles dealt evenly over the fewest blocks, at
+    // least one thread per table task
     const int chunks = (a.n_mtiles + kMfmaMaxWaves - 1) / kMfmaMaxWaves;
-    const int waves = (a.n_mtiles + chunks - 1) / chunks;
+    int waves = (a.n_mtiles + chunks - 1) / chunks;
+    if (waves < kMfmaMinWaves) waves = kMfmaMinWaves;
     hipLaunchKernelGGL(rhok_mfma_kernel, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
-                       dim3(waves * 64), lds, st, a);
+                       dim3(waves * 64), rhok_mfma_lds_bytes(a.nmax), st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rhok_mfma_final_kernel, dim3((unsigned)((a.nk + 3) / 4)), dim3(256), 0, st,

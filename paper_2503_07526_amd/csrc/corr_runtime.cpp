@@ -618,6 +618,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 CREATE_HIP(hipMemcpy(g.d_mtab, packed.data(), packed.size() * sizeof(int32_t),
                                      hipMemcpyHostToDevice));
                 CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * nk * 2 * sizeof(double)));
+                CREATE_HIP(rhok_mfma_prepare(nmax));
                 RhokMfmaArgs &r = g.margs;
                 r.pos = nullptr;
                 r.n_atoms = g.d.n_atoms;

@@ -156,12 +156,12 @@ def test_rhok_magnitude_and_phase(corrmod, rhok_valu):
         assert np.max(np.abs(got1 - expect1)) / np.max(np.abs(expect1)) < 2e-6
 
 
-@pytest.mark.parametrize("case", ["wide_nz", "large_n", "duplicates", "ragged_atoms"])
+@pytest.mark.parametrize("case", ["wide_nz", "large_n", "nmax15", "duplicates", "ragged_atoms"])
 def test_rhok_kset_shapes(corrmod, case):
-    """k-sets outside the matrix-core limits (more than 32 distinct n_z, a
-    component above 15) take the vector-unit producer; repeated k-vectors and
-    atom counts that are not a multiple of the atom tile: every listed k gets
-    |n(k)|^2 / N at lag 0, and both producers agree where both apply."""
+    """A k-set with a component above 15 takes the vector-unit producer; wide
+    n_z ranges, components up to the matrix-core limit of 15, repeated
+    k-vectors and atom counts that are not a multiple of the atom tile: every
+    listed k gets |n(k)|^2 / N at lag 0, and both producers agree."""
     rng = np.random.default_rng(11)
     N, box = 3001, 50.0
     if case == "wide_nz":
@@ -171,6 +171,10 @@ def test_rhok_kset_shapes(corrmod, case):
         kv = np.stack([rng.integers(-16, 17, 150), rng.integers(-2, 3, 150),
                        rng.integers(-2, 3, 150)], axis=1).astype(np.int32)
         kv[0] = (16, 0, 0)
+    elif case == "nmax15":
+        kv = np.stack([rng.integers(-15, 16, 300), rng.integers(-15, 16, 300),
+                       rng.integers(-15, 16, 300)], axis=1).astype(np.int32)
+        kv[0] = (15, -15, 15)
     elif case == "duplicates":
         base = synth.kvectors(100)
         kv = np.concatenate([base, base[::7], base[:3]]).astype(np.int32)
