@@ -18,11 +18,14 @@ Workloads (--config):
            batched push kernel per step (default)
   large    6x10^7 FP32 channels with compensated FP32 sums + 9 FP64 channels,
            12 levels x 16 points
+  rhok     the k-density group of `batched` alone (2048 k-vectors, 10^6 atoms):
+           the producer kernel's own roofline line
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +37,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+MFMA_F16_PEAK_TFS = 2500.0  # MI355X dense fp16 matrix peak
+RHOK_FLOP_PER_ATOM_K = 14  # factorised phases: 2 complex multiplies + 1 complex add
 
 
 def parse():
@@ -42,7 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--config", default="batched",
-                    choices=["plain", "batched", "large", "precision"])
+                    choices=["plain", "batched", "large", "rhok", "precision"])
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the launch-shape autotuner (library defaults)")
     ap.add_argument("--precision-steps", type=int, default=1_000_000)
@@ -94,7 +99,46 @@ def workload(name):
                          accum="kahan", comps=3, tau=(10, 1000), sigma=1.0, seed=4, stream=1),
                     dict(kind="ou", n=9, levels=12, points=16, m=2, dtype="f64", accum="f64",
                          comps=1, tau=(100, 100), sigma=1.0, seed=4, stream=2)])
+    if name == "rhok":
+        return dict(
+            name="rhok: n(k) of 2048 k-vectors (|n| <= 12 half-space) from 1e6 atoms in a box of 100, "
+                 "cFP32 compensated b=16 p=32 m=2",
+            steps=10_000,
+            groups=[dict(kind="rhok", n=2048, levels=16, points=32, m=2, dtype="cf32",
+                         accum="kahan", n_atoms=1_000_000, box=100.0, seed=3, stream=3,
+                         kvec=synth.kvectors(2048))])
     raise ValueError(name)
+
+
+# rocprofv3 counter records of the flush kernel (profiles/flush_traffic_<config>.md)
+# are valid only for the kernel source they were taken on.
+TRAFFIC_SOURCES = ("paper_2503_07526_amd/csrc/corr_deferred.hip",
+                   "paper_2503_07526_amd/csrc/corr_internal.h")
+
+
+def flush_source_hash():
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(config):
+    """HBM bytes per flush launch from the committed counter summary of this
+    workload (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
+    None when there is none or it was taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", f"flush_traffic_{config}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("record:"):
+                rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+    if rec is None or rec.get("source_sha256") != flush_source_hash():
+        return None
+    return rec
 
 
 SB = {"f32": 4, "f64": 8, "cf32": 8, "cf64": 16}
@@ -183,6 +227,8 @@ def cpu_baseline(wl):
     """The FP64 oracle on a bounded sample of the workload's largest group."""
     import oracle
     import synth
+    if all(g["kind"] == "rhok" for g in wl["groups"]):
+        return cpu_baseline_rhok(wl["groups"][0])
     g = max(wl["groups"], key=lambda x: x["n"])
     n_ch, S = 16000, 8000
     real = np.float32 if g["dtype"] == "f32" else np.float64
@@ -199,6 +245,26 @@ def cpu_baseline(wl):
             "sample": (f"{n_ch} channels x {S} pushes of the {g['dtype']} group "
                        f"(b={g['levels']}, p={g['points']}, m={g['m']}), single thread, "
                        f"{dt:.1f} s")}
+
+
+def cpu_baseline_rhok(g):
+    """The oracle's direct n(k) sum (one double cos and sin per atom and k) on a
+    bounded sample of atoms, scaled linearly to the workload's atom count; the
+    correlator update of 2048 channels per push is negligible beside it."""
+    import oracle
+    import synth
+    n_sample, reps = 50_000, 3
+    spec = synth.PositionSpec(g["seed"], g["stream"], n_sample, g["box"], 0.1, 50.0)
+    pos, _ = spec.series(0, reps)
+    t0 = time.perf_counter()
+    for r in range(reps):
+        oracle.rhok(pos[r], g["kvec"], g["box"])
+    dt = (time.perf_counter() - t0) / reps
+    per_push = dt * g["n_atoms"] / n_sample
+    return {"value": g["n"] / per_push, "unit": "channel-samples/s", "cores": 1, "kind": "oracle",
+            "sample": (f"n(k) of {g['n']} k-vectors over {n_sample} of {g['n_atoms']} atoms, "
+                       f"{reps} pushes, {dt:.2f} s each, scaled to the full atom count; "
+                       f"single thread")}
 
 
 # -------------------------------------------------------------------- GPU leg
@@ -287,9 +353,18 @@ def run(args):
     fl_bytes = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
                    for s in steps)
     fl_ms, fl_n = corr.kernel_time(which=1)
+    rk_ms, rk_n = corr.kernel_time(which=2)
     n_total = sum(g["n"] for g in wl["groups"])
     value = n_total * K / wall
-    if fl_n:
+    rhok_only = all(g["kind"] == "rhok" for g in wl["groups"])
+    if rhok_only:
+        g0 = wl["groups"][0]
+        flop = RHOK_FLOP_PER_ATOM_K * g0["n"] * g0["n_atoms"]
+        achieved = flop / (rk_ms / rk_n * 1e-3) / 1e12
+        kname = ("k-density producer (%s), HIP events per launch on its stream"
+                 % ("vector units" if args.rhok_valu else "matrix cores"))
+        per_launch_ms, per_launch_bytes = rk_ms / rk_n, None
+    elif fl_n:
         # dominant kernel: the flush of the block-deferred groups
         achieved = fl_bytes / (fl_ms * 1e-3) / 1e9
         kname = ("flush kernel (block-deferred fold of 64 pushes for 1/64 of the channels per "
@@ -327,8 +402,28 @@ def run(args):
                      "update_ms_per_step": kern_ms / kern_n,
                      "alg_bytes_per_step": (stage_bytes + fl_bytes) / K},
     }
+    if rk_n:
+        out["roofline"]["producer_ms_per_launch"] = rk_ms / rk_n
+    if rhok_only:
+        r = out["roofline"]
+        r.update({"bound": "mfma", "unit": "TFLOP/s", "peak": MFMA_F16_PEAK_TFS,
+                  "frac": achieved / MFMA_F16_PEAK_TFS,
+                  "alg_flop_per_launch": RHOK_FLOP_PER_ATOM_K * g0["n"] * g0["n_atoms"]})
+        for key in ("alg_bytes_per_launch", "update_kernels_GBs", "alg_bytes_per_step"):
+            r.pop(key, None)
+    elif fl_n:
+        rec = traffic_record(args.config)
+        if rec is not None:
+            tb = float(rec["read_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
+            out["roofline"]["traffic"] = tb
+            out["roofline"]["traffic_detail"] = {
+                "hbm_bytes_per_launch": tb,
+                "alg_bytes_per_launch_same_pushes": float(rec["alg_bytes_per_launch"]),
+                "ratio": tb / float(rec["alg_bytes_per_launch"]),
+                "pushes": rec["pushes"], "source": f"profiles/flush_traffic_{args.config}.md"}
     out["config"]["autotune_s"] = round(tune_s, 2)
-    out["error_vs_fp64"] = spot_check(corr, wl, W + K)
+    if not rhok_only:
+        out["error_vs_fp64"] = spot_check(corr, wl, W + K)
     corr.close()
     if args.compare_plain:
         out["plain_form"] = compare_plain(wl, K, W, chunk)

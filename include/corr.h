@@ -203,15 +203,17 @@ const char *corr_last_error(const corr_ctx *ctx);
 int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
 
 /* With CORR_FLAG_TIMING: synchronise and return summed device times from HIP
- * events recorded on the context's stream.  which = 0: per push, from before
- * the push kernel launch(es) to after the flush launch(es) of that push, i.e.
- * the correlator-update kernels of the main stream (excluding the forked
- * k-density producer and the step counter); *n = timed pushes.  which = 1:
- * the flush launches of block-deferred groups only (one per push); *n =
- * timed flushes.  In
- * graph mode the which = 0 events bracket the whole graph replay and no
- * flush-only times are recorded.  reset != 0 clears the counters of `which`
- * after reading.  CORR_E_STATE without the flag.
+ * events (created without a system-scope fence).  which = 0: per push, on the
+ * context's stream, from before the staging / push kernel launch(es) to after
+ * the flush launch(es) of that push, i.e. the correlator-update kernels of
+ * the main stream (excluding a forked k-density branch and the step
+ * counter); *n = timed pushes.  which = 1: the fold kernel of the scheduled
+ * flush of block-deferred groups only (one per push); *n = timed flushes.
+ * which = 2: each k-density producer launch, on the stream it runs on (the
+ * forked side stream when other groups share the context); *n = timed
+ * launches.  In graph mode the which = 0 events bracket the whole graph
+ * replay and no other times are recorded.  reset != 0 clears the counters of
+ * `which` after reading.  CORR_E_STATE without the flag.
  *
  * Block-deferred form: for groups of single-precision samples with p = 16 and
  * m = 2 (unless CORR_FLAG_DIRECT), a push stages the samples and flushes one

@@ -247,7 +247,8 @@ class Correlator:
 
     def kernel_time(self, which: int = 0, reset: bool = False):
         """(summed milliseconds, count) from the library's HIP events: which=0 the
-        update kernels of each push (incl. flushes), which=1 flush launches only."""
+        update kernels of each push (incl. flushes), which=1 the flush fold
+        kernels only, which=2 the k-density producer launches."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         self._check(lib().corr_kernel_time(self._h, int(which), ctypes.byref(ms), ctypes.byref(n),

@@ -487,12 +487,22 @@ bool deferred_supported(int kind, int p, int m)
     return m == 2 && p == 16 && (kind == K_F32_F64 || kind == K_F32_KAHAN || kind == K_F32_F32);
 }
 
-hipError_t launch_flush(const DeferredArgs &a, hipStream_t st)
+hipError_t launch_flush_fold(const DeferredArgs &a, hipStream_t st)
 {
-    hipError_t e = launch_deferred_t<false>(a, st);
-    if (e != hipSuccess) return e;
+    return launch_deferred_t<false>(a, st);
+}
+
+hipError_t launch_flush_commit(const DeferredArgs &a, hipStream_t st)
+{
     hipLaunchKernelGGL(flush_commit_kernel, dim3(1), dim3(64), 0, st, a);
     return hipGetLastError();
+}
+
+hipError_t launch_flush(const DeferredArgs &a, hipStream_t st)
+{
+    hipError_t e = launch_flush_fold(a, st);
+    if (e != hipSuccess) return e;
+    return launch_flush_commit(a, st);
 }
 
 int64_t deferred_readout_rows(const GroupArgs &g) { return g.n_tiles * (int64_t)g.tw / 64; }

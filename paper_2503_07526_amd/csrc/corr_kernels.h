@@ -23,7 +23,9 @@ hipError_t rhok_mfma_prepare(int nmax); // once per context, before the first la
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 bool deferred_supported(int kind, int p, int m);
 hipError_t launch_stage(const GroupArgs &g, const int64_t *step, hipStream_t st);
-hipError_t launch_flush(const DeferredArgs &a, hipStream_t st);
+hipError_t launch_flush(const DeferredArgs &a, hipStream_t st);        // fold + commit
+hipError_t launch_flush_fold(const DeferredArgs &a, hipStream_t st);   // the fold kernel
+hipError_t launch_flush_commit(const DeferredArgs &a, hipStream_t st); // flag update
 int64_t deferred_readout_rows(const GroupArgs &g);
 int64_t deferred_readout_groups(const GroupArgs &g);
 hipError_t launch_deferred_readout(const DeferredArgs &a, double *groups, double *sums,

@@ -76,13 +76,14 @@ struct corr_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<int> deferred_set; // context group indices in the block-deferred form
-    // update-kernel timing (CORR_FLAG_TIMING): pool 0 per push, pool 1 per flush
+    // kernel timing (CORR_FLAG_TIMING): pool 0 per push, pool 1 per flush
+    // fold, pool 2 per k-density producer launch
     struct EventPool {
         std::vector<hipEvent_t> start, end;
         size_t used = 0;
         double ms = 0.0;
         int64_t n = 0;
-    } pools[2];
+    } pools[3];
     // readout scratch
     void *d_scratch = nullptr;
     size_t scratch_bytes = 0;
@@ -256,9 +257,11 @@ int next_events(corr_ctx *c, int which, hipEvent_t *a, hipEvent_t *b)
         if (rc != CORR_OK) return rc;
     }
     if (pl.used == pl.start.size()) {
+        // timing only: no system-scope fence on record (no cache writeback
+        // between the bracketed kernels and their neighbours)
         hipEvent_t e0, e1;
-        HIP_TRY(c, hipEventCreate(&e0));
-        HIP_TRY(c, hipEventCreate(&e1));
+        HIP_TRY(c, hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+        HIP_TRY(c, hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
         pl.start.push_back(e0);
         pl.end.push_back(e1);
     }
@@ -282,9 +285,14 @@ DeferredArgs deferred_args(const corr_ctx *c, int i)
 
 // Scheduled flush of every block-deferred group for the push being issued
 // (tile group S mod kDeferT folds block S / kDeferT if not done yet).
-int launch_flushes(corr_ctx *c, hipStream_t st)
+// Scheduled flush of every block-deferred group; with events, f0/f1 bracket
+// the fold kernels only (the flag updates follow f1).
+int launch_flushes(corr_ctx *c, hipStream_t st, hipEvent_t f0, hipEvent_t f1)
 {
-    for (int i : c->deferred_set) HIP_TRY(c, launch_flush(deferred_args(c, i), st));
+    if (f0) HIP_TRY(c, hipEventRecord(f0, st));
+    for (int i : c->deferred_set) HIP_TRY(c, launch_flush_fold(deferred_args(c, i), st));
+    if (f1) HIP_TRY(c, hipEventRecord(f1, st));
+    for (int i : c->deferred_set) HIP_TRY(c, launch_flush_commit(deferred_args(c, i), st));
     return CORR_OK;
 }
 
@@ -369,6 +377,12 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
     hipStream_t pst = fork ? c->side_stream : st;
     for (int i : c->side_set) {
         const Group &g = c->groups[(size_t)i];
+        hipEvent_t r0 = nullptr, r1 = nullptr;
+        if (timed) {
+            int rc = next_events(c, 2, &r0, &r1);
+            if (rc != CORR_OK) return rc;
+            HIP_TRY(c, hipEventRecord(r0, pst));
+        }
         if (g.rhok_mfma) {
             RhokMfmaArgs ma = g.margs;
             ma.pos = static_cast<const float *>(src[i]);
@@ -378,6 +392,7 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
             ra.pos = static_cast<const float *>(src[i]);
             HIP_TRY(c, launch_rhok(ra, pst));
         }
+        if (timed) HIP_TRY(c, hipEventRecord(r1, pst));
     }
     if (fork) {
         int rc = launch_set(c, c->pa_side, c->side_set, resolved, pst);
@@ -400,11 +415,9 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
         if (timed) {
             int rc = next_events(c, 1, &f0, &f1);
             if (rc != CORR_OK) return rc;
-            HIP_TRY(c, hipEventRecord(f0, st));
         }
-        int rc = launch_flushes(c, st);
+        int rc = launch_flushes(c, st, f0, f1);
         if (rc != CORR_OK) return rc;
-        if (timed) HIP_TRY(c, hipEventRecord(f1, st));
     }
     if (timed) HIP_TRY(c, hipEventRecord(e1, st));
     if (fork) HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
@@ -853,7 +866,7 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes)
 int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n, int32_t reset)
 {
     if (!ctx) return CORR_E_INVALID;
-    if (which != 0 && which != 1) return set_err(ctx, CORR_E_INVALID, "which must be 0 or 1");
+    if (which < 0 || which > 2) return set_err(ctx, CORR_E_INVALID, "which must be 0, 1 or 2");
     if (!(ctx->flags & CORR_FLAG_TIMING))
         return set_err(ctx, CORR_E_STATE, "context created without CORR_FLAG_TIMING");
     DeviceGuard dg(ctx->device);

@@ -337,3 +337,25 @@ def test_autotune_picks_and_caches(corrmod, tmp_path):
         _push_all(c, [x])
         gate(c.finalize(0, slice_=(0, 3)), o, TOL[("f32", "kahan")], slice_=(0, 3),
              label="autotuned")
+
+
+def test_kernel_time_pools(corrmod):
+    """CORR_FLAG_TIMING: one push-event pair, one flush-fold pair and one
+    producer pair per push in a context with a block-deferred group and a
+    k-density group; positive summed times; reset clears the counters."""
+    S, nv, N, box = 70, 4096, 2000, 50.0
+    kv = synth.kvectors(64)
+    xv = ou_inputs(8, 1, nv, S, "f32")
+    xp, _ = synth.PositionSpec(8, 2, N, box).series(0, S)
+    groups = [corrmod.GroupDesc(nv, 6, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(len(kv), 4, 16, 2, dtype="cf32", accum="f64", source="rhok",
+                                kvec=kv, n_atoms=N, box=box)]
+    with corrmod.Correlator(groups, timing=True) as c:
+        _push_all(c, [xv, xp])
+        for which in (0, 1, 2):
+            ms, n = c.kernel_time(which)
+            assert n == S and ms > 0.0, (which, n, ms)
+        ms, n = c.kernel_time(2, reset=True)
+        assert c.kernel_time(2) == (0.0, 0)
+        with pytest.raises(corrmod.CorrError):
+            c.kernel_time(3)
