@@ -117,10 +117,16 @@ TRAFFIC_SOURCES = ("paper_2503_07526_amd/csrc/corr_deferred.hip",
 
 
 def flush_source_hash():
+    """Hash of the fold kernel's sources with comments and whitespace removed
+    (a comment edit does not change the kernel)."""
+    import re
     h = hashlib.sha256()
     for rel in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -499,9 +505,12 @@ def precision(args):
         xg, _ = gspec.series(0, S)
         ov = oracle.OracleCorrelator(len(sample), b, p, m)
         og = oracle.OracleCorrelator(9, b, p, m)
-        for r1, r2 in zip(xs, xg):
+        for i, (r1, r2) in enumerate(zip(xs, xg)):
             ov.push(r1.astype(np.float64))
             og.push(r2)
+            if (i + 1) % 100_000 == 0:
+                print(f"precision sigma={sigma:g}: oracle {i + 1}/{S} pushes", file=sys.stderr,
+                      flush=True)
         var = float(synth.stationary_variance(vspec.a[0], vspec.b[0]))
         a64 = float(vspec.a[0])
         for accum in ("kahan", "f64", "f32"):
@@ -519,6 +528,9 @@ def precision(args):
                 for j in range(n):
                     corr.push([bv[j], bg[j]])
                 done += n
+                if done % 102_400 == 0:
+                    print(f"precision sigma={sigma:g} {accum}: {done}/{S} pushes", file=sys.stderr,
+                          flush=True)
             torch.cuda.synchronize()
             res_s = [corr.finalize(0, slice_=(0, 16)), corr.finalize(0, slice_=(nv - 16, nv))]
             per = np.vstack([r["c_per_channel"] for r in res_s])

@@ -59,6 +59,8 @@ def lib():
         L.oracle_trapezoid.restype = dbl
         L.oracle_rhok.argtypes = [vp, i64, vp, i32, dbl, vp, vp]
         L.oracle_rhok.restype = None
+        L.oracle_currents.argtypes = [vp, vp, i64, vp, i32, dbl, vp, vp]
+        L.oracle_currents.restype = i32
         _lib = L
     return _lib
 
@@ -158,6 +160,35 @@ def rhok(pos_f32: np.ndarray, kvec: np.ndarray, box: float) -> np.ndarray:
     lib().oracle_rhok(_ptr(pos), int(pos.shape[1]), _ptr(kv), int(nk), float(box), _ptr(re),
                       _ptr(im))
     return re + 1j * im
+
+
+def currents(pos_f32: np.ndarray, vel_f32: np.ndarray, kvec: np.ndarray, box: float) -> np.ndarray:
+    """Longitudinal and transverse currents (Eqs. long-current, trans-current;
+    readings R19, R20 of the C source): [n_k][3] complex, column 0 = khat . J,
+    columns 1, 2 = e1 . J, e2 . J with J = sum_j v_j exp(i k.r_j), in FP64."""
+    pos = np.ascontiguousarray(pos_f32, dtype=np.float32)
+    vel = np.ascontiguousarray(vel_f32, dtype=np.float32)
+    assert pos.shape == vel.shape and pos.ndim == 2 and pos.shape[0] == 3
+    kv = np.ascontiguousarray(kvec, dtype=np.int32)
+    nk = kv.shape[0]
+    re = np.zeros(3 * nk)
+    im = np.zeros(3 * nk)
+    rc = lib().oracle_currents(_ptr(pos), _ptr(vel), int(pos.shape[1]), _ptr(kv), int(nk),
+                               float(box), _ptr(re), _ptr(im))
+    if rc != 0:
+        raise ValueError("the zero k-vector has no direction")
+    return (re + 1j * im).reshape(nk, 3)
+
+
+def current_basis(n) -> np.ndarray:
+    """(khat, e1, e2) rows of reading R20 for one integer k-vector (a plain
+    restatement used by the tests to check the basis properties)."""
+    n = np.asarray(n, dtype=np.float64)
+    khat = n / np.linalg.norm(n)
+    a = int(np.argmin(np.abs(khat)))
+    e1 = np.eye(3)[a] - khat[a] * khat
+    e1 /= np.linalg.norm(e1)
+    return np.stack([khat, e1, np.cross(khat, e1)])
 
 
 def green_kubo_viscosity(t, c_shear_mean, volume, kB, temperature, t_cut=None):

@@ -35,6 +35,17 @@
  *       interval when a cut-off falls between grid points.
  * The function that computes rho(k) follows the k-space density definition
  * of Section "Currents" (Eq. k-density): a direct sum of exp(i k.r) in double.
+ * The currents function follows Eqs. long-current and trans-current of the
+ * same section, with the readings
+ *   R19 the bracket of Eq. trans-current closes after the projection:
+ *       j_T = sum_i [v_i - (v_i . khat) khat] exp(i k.r_i);
+ *   R20 the correlated channels of a k-vector are the longitudinal amplitude
+ *       khat . j_L and the two transverse components e1 . j_T, e2 . j_T on a
+ *       fixed orthonormal basis (khat, e1, e2): a = the Cartesian axis with
+ *       the smallest |khat_a| (the first on ties), e1 = a - (a . khat) khat
+ *       normalised, e2 = khat x e1.  C_L is the correlation of the first,
+ *       C_T the mean of the other two (for k along z these are the paper's
+ *       z, and x, y components).
  *
  * parity pins: see tests/test_oracle_*.py (brute-force Eq. (1) on block
  * averaged series, closed forms, invariants, hand-worked golden example).
@@ -341,4 +352,68 @@ void oracle_rhok(const float *pos, int64_t n_atoms, const int32_t *kvec, int n_k
         re[q] = sr;
         im[q] = si;
     }
+}
+
+/* Orthonormal basis (khat, e1, e2) of reading R20 for the integer vector n. */
+static void current_basis(const int32_t *n, double khat[3], double e1[3], double e2[3])
+{
+    double len = sqrt((double)n[0] * n[0] + (double)n[1] * n[1] + (double)n[2] * n[2]);
+    int a = 0;
+    for (int d = 0; d < 3; ++d) {
+        khat[d] = (double)n[d] / len;
+    }
+    for (int d = 1; d < 3; ++d)
+        if (fabs(khat[d]) < fabs(khat[a])) a = d;
+    double dot = khat[a];
+    double nrm = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        e1[d] = (d == a ? 1.0 : 0.0) - dot * khat[d];
+        nrm += e1[d] * e1[d];
+    }
+    nrm = sqrt(nrm);
+    for (int d = 0; d < 3; ++d) e1[d] /= nrm;
+    e2[0] = khat[1] * e1[2] - khat[2] * e1[1];
+    e2[1] = khat[2] * e1[0] - khat[0] * e1[2];
+    e2[2] = khat[0] * e1[1] - khat[1] * e1[0];
+}
+
+/* Eqs. (long-current), (trans-current) with readings R19, R20: for every
+ * k-vector q the complex current J = sum_j v_j exp(i k . r_j) (double
+ * arguments, double sin/cos, sequential sums) and its components on the
+ * basis (khat, e1, e2): out[3q] = khat . J, out[3q+1] = e1 . J,
+ * out[3q+2] = e2 . J.  Positions and velocities are single precision planes
+ * [3][N] each.  The zero vector has no direction and is not accepted
+ * (returns -1); otherwise 0. */
+int oracle_currents(const float *pos, const float *vel, int64_t n_atoms, const int32_t *kvec,
+                    int n_k, double box, double *re, double *im)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int q = 0; q < n_k; ++q) {
+        const int32_t *n = kvec + 3 * q;
+        if (n[0] == 0 && n[1] == 0 && n[2] == 0) return -1;
+        double k[3], khat[3], e1[3], e2[3];
+        for (int d = 0; d < 3; ++d) k[d] = two_pi * (double)n[d] / box;
+        current_basis(n, khat, e1, e2);
+        double jr[3] = {0.0, 0.0, 0.0}, ji[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n_atoms; ++j) {
+            double ph = 0.0;
+            for (int d = 0; d < 3; ++d) ph += k[d] * (double)pos[d * n_atoms + j];
+            const double c = cos(ph), s = sin(ph);
+            for (int d = 0; d < 3; ++d) {
+                jr[d] += (double)vel[d * n_atoms + j] * c;
+                ji[d] += (double)vel[d * n_atoms + j] * s;
+            }
+        }
+        const double *dirs[3] = {khat, e1, e2};
+        for (int c = 0; c < 3; ++c) {
+            double r = 0.0, i = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                r += dirs[c][d] * jr[d];
+                i += dirs[c][d] * ji[d];
+            }
+            re[3 * q + c] = r;
+            im[3 * q + c] = i;
+        }
+    }
+    return 0;
 }

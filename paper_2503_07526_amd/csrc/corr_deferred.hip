@@ -4,27 +4,37 @@
 // the newest value with the p lagged values of each level that receives a
 // value.  The sums it builds are linear, so the products of T consecutive
 // pushes can be added in one pass: on every push the sample is only written
-// into a level-0 ring of P0 = T + p slots ("staging", 2 samples of traffic
-// per channel), and every T pushes (T a power of m) one flush pass per channel
-// walks the T new level-0 values in order, adds each one's lag products to
-// per-lag partial sums held in registers, forms the level-1 block means on
-// the fly, and repeats level by level with the new values of the level above
-// -- the same products, block means and counts as T single pushes, with the
-// partial sums added to the stored accumulators once per flush.  The stored
-// state after a flush is that of Algorithm 1 after the same pushes, up to the
+// into a level-0 ring ("staging", 2 samples of traffic per channel), and once
+// per block of T pushes (T a power of m) one flush pass per channel walks the
+// T values of the block in order, adds each one's lag products to per-lag
+// partial sums held in registers, forms the level-1 block means on the fly,
+// and repeats level by level with the new values of the level above -- the
+// same products, block means and counts as T single pushes, with the partial
+// sums added to the stored accumulators once per flush.  The stored state
+// after a flush is that of Algorithm 1 after the same pushes, up to the
 // grouping of the floating-point sums.
 //
-// State is touched once per flush and not again for 64 pushes, so the flush
-// streams it with non-temporal loads and stores (measured 5.1 -> 5.6 TB/s).
+// Staggering: the tiles are split into kFlushGroups groups and group j folds
+// block q (pushes T(q-1)+1 .. Tq) at push Tq + j, so every push flushes about
+// 1/kFlushGroups of the channels and the per-push cost is flat.  The level-0
+// ring therefore holds P0 = 2T + p slots: the block being folded, up to T - 1
+// pushes staged after it, and the p values before the block that its lags
+// reach back to.  Each group's last folded block is kept in a device array
+// (and mirrored on the host) so that a flush is never applied twice.
 //
-// A readout between flushes folds the pending pushes the same way without
+// State is touched once per flush and not again for T pushes, so the flush
+// streams it with non-temporal loads and stores.
+//
+// A readout between flushes first lets every group catch up to the last
+// complete block, then folds the pushes after it the same way without
 // writing any state (so a readout never changes later results) and reduces
-// the resulting per-channel accumulators over the block's channels in a
-// fixed order.
+// the resulting per-channel accumulators over 64-channel chunks and then
+// over chunks in a fixed order (the group mean does not depend on the tile
+// width).
 //
-// Supported here: single-precision real samples, m = 2, p = 16, T = 64.  Levels k <= 6
-// receive T / 2^k new values per flush (compile-time counts); deeper levels
-// receive at most one.
+// Supported here: single-precision real samples, m = 2, p = 16, T = 64.
+// Levels k <= 6 receive T / 2^k new values per flush (compile-time counts);
+// deeper levels receive at most one.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
