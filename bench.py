@@ -433,6 +433,7 @@ def run(args):
     corr.close()
     if args.compare_plain:
         out["plain_form"] = compare_plain(wl, K, W, chunk)
+        out["plain_form"]["speedup_of_this_form"] = value / out["plain_form"]["value"]
     return out, wl
 
 
@@ -596,9 +597,16 @@ def compare_plain(wl, K, W, chunk):
         if done >= W:
             wall += time.perf_counter() - t0
         done += n
+    kern_ms, kern_n = corr.kernel_time(0)
     corr.close()
-    return {"value": g["n"] * (W + K - W) / wall, "unit": "channel-samples/s",
-            "form": "FP32 samples, FP64 sums, per-step update, per-group launch"}
+    alg = sum(step_bytes(g, s) for s in range(W + 1, W + K + 1)) / K
+    return {"value": g["n"] * K / wall, "unit": "channel-samples/s",
+            "ms_per_step": wall / K * 1e3,
+            "push_kernel_ms": kern_ms / kern_n if kern_n else None,
+            "push_kernel_GBs": alg / (kern_ms / kern_n * 1e-3) / 1e9 if kern_n else None,
+            "channels": g["n"],
+            "form": "the largest group alone: FP32 samples, FP64 sums, per-step update of every "
+                    "channel, one launch per group and push"}
 
 
 def main():

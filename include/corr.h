@@ -58,7 +58,20 @@ enum corr_accum { CORR_ACC_F64 = 1, CORR_ACC_KAHAN_F32 = 2, CORR_ACC_F32 = 3 };
 /* Where a group's samples come from on each push. */
 enum corr_source {
     CORR_SRC_SAMPLES = 0, /* caller provides n_channels samples per push        */
-    CORR_SRC_RHOK = 1     /* caller provides positions; channels = k-vectors     */
+    CORR_SRC_RHOK = 1,    /* caller provides positions; channels = k-vectors     */
+    CORR_SRC_CURRENTS = 2 /* caller provides positions and velocities; three
+                             channels per k-vector: the longitudinal current
+                             khat . j and the transverse current on the basis
+                             vectors e1, e2 (Section "Currents", Eqs.
+                             long-current, trans-current): with J(k) =
+                             sum_j v_j exp(i k.r_j), channel 3q = khat . J,
+                             3q+1 = e1 . J, 3q+2 = e2 . J, where e1 = the
+                             Cartesian axis least aligned with khat (the
+                             first on ties) made orthogonal to khat and
+                             normalised, e2 = khat x e1.  C_L is the
+                             correlation of channel 3q, C_T the mean of
+                             channels 3q+1 and 3q+2.  Components of n must
+                             lie within +-15; n = 0 is rejected.          */
 };
 
 /* corr_create flags. */
@@ -81,7 +94,8 @@ enum corr_flags {
 };
 
 typedef struct corr_group_desc {
-    int64_t n_channels;     /* channels; for CORR_SRC_RHOK the number of k-vectors */
+    int64_t n_channels;     /* channels; CORR_SRC_RHOK: the number of k-vectors;
+                               CORR_SRC_CURRENTS: 3 x the number of k-vectors */
     int32_t levels;         /* b >= 1 blocks                                       */
     int32_t points;         /* p >= 2 values per block                             */
     int32_t m;              /* averaging factor, 2 <= m < p                        */
@@ -91,10 +105,12 @@ typedef struct corr_group_desc {
     int32_t update_every;   /* u >= 1: scales reported lag times only (Sec. 2.2)  */
     int32_t reserved;
     double dt;              /* simulation time step; lag time = L m^k u dt        */
-    /* CORR_SRC_RHOK only (ignored otherwise): */
-    const int32_t *kvec;    /* host [n_channels][3] integer n, k = 2 pi n / box;
+    /* CORR_SRC_RHOK and CORR_SRC_CURRENTS only (ignored otherwise): */
+    const int32_t *kvec;    /* host [n_k][3] integer n, k = 2 pi n / box, n_k =
+                               n_channels (RHOK) or n_channels / 3 (CURRENTS);
                                copied during corr_create                          */
-    int64_t n_atoms;        /* positions per push, layout float [3][n_atoms]      */
+    int64_t n_atoms;        /* atoms per push: input float [3][n_atoms] positions,
+                               CURRENTS: then [3][n_atoms] velocities             */
     double box;             /* cubic box edge L                                   */
 } corr_group_desc;
 

@@ -21,7 +21,7 @@ CORR_OK, CORR_E_INVALID, CORR_E_OOM, CORR_E_DEVICE, CORR_E_STATE, CORR_E_UNSUPPO
     0, -1, -2, -3, -4, -5
 DTYPES = {"f32": 1, "f64": 2, "cf32": 3, "cf64": 4}
 ACCUMS = {"f64": 1, "kahan": 2, "f32": 3}
-SOURCES = {"samples": 0, "rhok": 1}
+SOURCES = {"samples": 0, "rhok": 1, "currents": 2}
 FLAG_GRAPH, FLAG_PER_GROUP, FLAG_TIMING, FLAG_DIRECT, FLAG_RHOK_VALU = 1, 2, 4, 8, 16
 _TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64, "cf32": torch.complex64,
                 "cf64": torch.complex128}

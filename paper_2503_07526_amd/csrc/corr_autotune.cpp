@@ -51,7 +51,7 @@ std::string tune_key(const corr_group_desc *g, int n, uint32_t flags, int device
     for (int i = 0; i < n; ++i) {
         os << ";g" << i << "=" << g[i].n_channels << "," << g[i].levels << "," << g[i].points << ","
            << g[i].m << "," << g[i].dtype << "," << g[i].accum << "," << g[i].source;
-        if (g[i].source == CORR_SRC_RHOK) os << "," << g[i].n_atoms;
+        if (g[i].source != CORR_SRC_SAMPLES) os << "," << g[i].n_atoms;
     }
     return os.str();
 }
@@ -116,7 +116,7 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
     if (max_trial_channels <= 0) max_trial_channels = 8 << 20;
     std::vector<corr_group_desc> trial(groups, groups + n_groups);
     for (auto &g : trial) {
-        if (g.source == CORR_SRC_RHOK)
+        if (g.source != CORR_SRC_SAMPLES)
             g.n_atoms = std::min<int64_t>(g.n_atoms, 1 << 18);
         else
             g.n_channels = std::min<int64_t>(g.n_channels, max_trial_channels);

@@ -132,7 +132,7 @@ struct RhokArgs {
 // of the k-set, padded to whole 16-row tiles) and Z^{|n_z|} (16 columns,
 // |n_z| = 0 .. 15); the sign of n_z selects how the sums combine.
 struct RhokMfmaArgs {
-    const float *pos;        // [3][n_atoms]
+    const float *pos;        // [3][n_atoms] positions; currents: then [3][n_atoms] velocities
     int64_t n_atoms;
     const int32_t *pair_nx;  // [n_mtiles * 16], padding pairs (0, 0)
     const int32_t *pair_ny;  // [n_mtiles * 16]
@@ -142,12 +142,15 @@ struct RhokMfmaArgs {
     int32_t n_mtiles;
     int32_t nmax;            // max |n component|, at most 15
     double inv_box;          // 1 / L
-    double *partial;         // [nk][n_atom_blocks][2] FP64 partial sums
+    double *partial;         // [nk][nw][n_atom_blocks][2] FP64 partial sums
     int32_t n_atom_blocks;
     int32_t atoms_per_block;
-    void *out;               // [nk] complex samples (float2 or double2)
+    void *out;               // [nk * nw] complex samples (float2 or double2)
     int32_t out_double;      // 1: double2 output
-    int32_t nk;
+    int32_t nk;              // k-vectors
+    int32_t nw;              // weight sets: 1 = n(k), 3 = current components
+    int32_t pad_;
+    const double *basis;     // nw == 3: [nk][3][3] rows khat, e1, e2
 };
 
 // Readout reduction arguments.

@@ -19,7 +19,7 @@ int rhok_block_threads(int n_seg);
 hipError_t launch_rhok_mfma(const RhokMfmaArgs &a, hipStream_t st);
 int rhok_mfma_cols();        // |n_z| columns of the matrix-core producer
 int rhok_mfma_max_nmax();    // largest |n component| it takes
-hipError_t rhok_mfma_prepare(int nmax); // once per context, before the first launch
+hipError_t rhok_mfma_prepare(int nmax, int nw); // once per context, before the first launch
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 bool deferred_supported(int kind, int p, int m);
 hipError_t launch_stage(const GroupArgs &g, const int64_t *step, hipStream_t st);

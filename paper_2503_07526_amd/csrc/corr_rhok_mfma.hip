@@ -131,15 +131,19 @@ __device__ __forceinline__ void unit_phase(double f, const double2 *roots, doubl
 struct TileBufs {
     float2 *tabx;   // [nn][kTabStride]
     float2 *taby;   // [nn][kTabStride]
-    halfv_t *bfr;   // [kBFrags]
+    halfv_t *bfr;   // [NW][kBFrags]
 };
 
 // Build the tables of one tile: task (axis d, atom j), base phase from
 // unit_phase, powers by a double recurrence, each rounded once; X and Y rows
-// for both signs, Z^{0..nmax} split into fp16 hi/lo B fragments.  Atoms past
-// the end (live == false) get zero entries, so they add nothing.
+// for both signs, and for each weight set w the products w * Z^{0..nmax}
+// split into fp16 hi/lo B fragments (NW = 1: w = 1; NW = 3: the atom's
+// velocity components).  Atoms past the end (live == false) get zero
+// entries, so they add nothing.
+template <int NW>
 __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool live, float x,
-                                           double inv_box, int nmax, const double2 *roots)
+                                           const float (&w)[NW], double inv_box, int nmax,
+                                           const double2 *roots)
 {
     const int d = task / kMfmaTileAtoms, j = task - d * kMfmaTileAtoms;
     double cs = 0.0, sn = 0.0;
@@ -159,29 +163,42 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
         _Float16 *bh = reinterpret_cast<_Float16 *>(tb.bfr);
         for (int n = 0; n <= nmax; ++n) {
             if (n > 0) cmul(pr, pi, cs, sn);
-            float zr = (float)pr, zi = (float)pi;
-            // keep the float rounding step visible: otherwise double -> float
-            // -> half is folded into one double -> half conversion, which has
-            // no instruction and is expanded into integer code
-            asm volatile("" : "+v"(zr), "+v"(zi));
-            const _Float16 rh = (_Float16)zr, ih = (_Float16)zi;
-            const _Float16 rl = (_Float16)(zr - (float)rh), il = (_Float16)(zi - (float)ih);
-            bh[bfrag_index(ks, 0, g, n) * kAtomsPerLane + h] = rh;
-            bh[bfrag_index(ks, 1, g, n) * kAtomsPerLane + h] = rl;
-            bh[bfrag_index(ks, 2, g, n) * kAtomsPerLane + h] = ih;
-            bh[bfrag_index(ks, 3, g, n) * kAtomsPerLane + h] = il;
+#pragma unroll
+            for (int s = 0; s < NW; ++s) {
+                const double wd = NW == 1 ? 1.0 : (double)w[s];
+                float zr = (float)(pr * wd), zi = (float)(pi * wd);
+                // keep the float rounding step visible: otherwise double ->
+                // float -> half is folded into one double -> half conversion,
+                // which has no instruction and is expanded into integer code
+                asm volatile("" : "+v"(zr), "+v"(zi));
+                const _Float16 rh = (_Float16)zr, ih = (_Float16)zi;
+                const _Float16 rl = (_Float16)(zr - (float)rh), il = (_Float16)(zi - (float)ih);
+                _Float16 *bs = bh + (size_t)s * kBFrags * kAtomsPerLane;
+                bs[bfrag_index(ks, 0, g, n) * kAtomsPerLane + h] = rh;
+                bs[bfrag_index(ks, 1, g, n) * kAtomsPerLane + h] = rl;
+                bs[bfrag_index(ks, 2, g, n) * kAtomsPerLane + h] = ih;
+                bs[bfrag_index(ks, 3, g, n) * kAtomsPerLane + h] = il;
+            }
         }
     }
 }
 
-__global__ __launch_bounds__(kMfmaMaxWaves * 64) void rhok_mfma_kernel(RhokMfmaArgs a)
+// Waves per block: one M tile per wave.  With three weight sets a wave holds
+// three times the accumulators, so blocks stay at two waves per SIMD.
+template <int NW> struct MfmaShape {
+    static constexpr int max_waves = NW == 1 ? kMfmaMaxWaves : 8;
+};
+
+template <int NW>
+__global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kernel(RhokMfmaArgs a)
 {
     extern __shared__ double2 lds_roots[]; // [kRoots], then two tile buffers
     const int nmax = a.nmax;
     const int nn = 2 * nmax + 1;
     // two tile buffers of buf_stride float2 each (a multiple of 2: 16-byte aligned)
     float2 *const buf0 = reinterpret_cast<float2 *>(lds_roots + kRoots);
-    const int buf_stride = 2 * nn * kTabStride + kBFrags * (int)(sizeof(halfv_t) / sizeof(float2));
+    const int buf_stride =
+        2 * nn * kTabStride + NW * kBFrags * (int)(sizeof(halfv_t) / sizeof(float2));
     auto tile_bufs = [&](int b) {
         TileBufs t;
         t.tabx = buf0 + b * buf_stride;
@@ -211,60 +228,69 @@ __global__ __launch_bounds__(kMfmaMaxWaves * 64) void rhok_mfma_kernel(RhokMfmaA
         lds_roots[q] = make_double2(cs, sn);
     }
     // B columns above nmax are never stored; keep them zero
-    for (int f = threadIdx.x; f < 2 * kBFrags; f += blockDim.x)
-        if (f % kMfmaCols > nmax) tile_bufs(f / kBFrags).bfr[f % kBFrags] = halfv_t{};
+    for (int f = threadIdx.x; f < 2 * NW * kBFrags; f += blockDim.x)
+        if (f % kMfmaCols > nmax) tile_bufs(f / (NW * kBFrags)).bfr[f % (NW * kBFrags)] = halfv_t{};
 
-    double acc[4][4];
+    double acc[NW][4][4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int w = 0; w < NW; ++w)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[s][v] = 0.0;
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[w][s][v] = 0.0;
 
     const int64_t a_begin = (int64_t)blockIdx.y * a.atoms_per_block;
     int64_t a_end = a_begin + a.atoms_per_block;
     if (a_end > a.n_atoms) a_end = a.n_atoms;
-    const int n_tiles = a_end > a_begin ? (int)((a_end - a_begin + kMfmaTileAtoms - 1) / kMfmaTileAtoms) : 0;
+    const int n_tiles =
+        a_end > a_begin ? (int)((a_end - a_begin + kMfmaTileAtoms - 1) / kMfmaTileAtoms) : 0;
 
-    // table task of this thread (blockDim >= kTableTasks) and its positions,
-    // loaded one tile ahead of their use
+    // table task of this thread (blockDim >= kTableTasks) and its inputs,
+    // loaded one tile ahead of their use; the Z task also loads the weights
     const int task = threadIdx.x;
     const bool builder = task < kTableTasks;
     const int td = task / kMfmaTileAtoms, tj = task - td * kMfmaTileAtoms;
-    auto load_pos = [&](int it, float &x) -> bool {
+    const bool weighted = NW > 1 && td == 2;
+    auto load_in = [&](int it, float &x, float (&w)[NW]) -> bool {
         const int64_t at = a_begin + (int64_t)it * kMfmaTileAtoms + tj;
         const bool live = builder && it < n_tiles && at < a_end;
         x = live ? a.pos[(int64_t)td * a.n_atoms + at] : 0.f;
+#pragma unroll
+        for (int s = 0; s < NW; ++s)
+            w[s] = live && weighted ? a.pos[(int64_t)(3 + s) * a.n_atoms + at] : 1.f;
         return live;
     };
-    float x_cur, x_next;
-    bool live_cur = load_pos(0, x_cur);
-    bool live_next = load_pos(1, x_next);
+    float x_cur, x_next, w_cur[NW], w_next[NW];
+    const bool live_cur = load_in(0, x_cur, w_cur);
+    bool live_next = load_in(1, x_next, w_next);
     __syncthreads(); // roots and zero columns
-    if (builder) build_tile(tile_bufs(0), task, live_cur, x_cur, a.inv_box, nmax, lds_roots);
+    if (builder) build_tile<NW>(tile_bufs(0), task, live_cur, x_cur, w_cur, a.inv_box, nmax, lds_roots);
     __syncthreads();
 
     for (int it = 0; it < n_tiles; ++it) {
         const TileBufs cur = tile_bufs(it & 1);
         // tables of the next tile into the other buffer
         if (builder && it + 1 < n_tiles) {
-            float x_after;
-            const bool live_after = load_pos(it + 2, x_after);
-            build_tile(tile_bufs((it + 1) & 1), task, live_next, x_next, a.inv_box, nmax, lds_roots);
+            float x_after, w_after[NW];
+            const bool live_after = load_in(it + 2, x_after, w_after);
+            build_tile<NW>(tile_bufs((it + 1) & 1), task, live_next, x_next, w_next, a.inv_box,
+                           nmax, lds_roots);
             x_next = x_after;
+#pragma unroll
+            for (int s = 0; s < NW; ++s) w_next[s] = w_after[s];
             live_next = live_after;
         }
         if (active) {
             const float4 *xrow = reinterpret_cast<const float4 *>(cur.tabx + xoff);
             const float4 *yrow = reinterpret_cast<const float4 *>(cur.taby + yoff);
-            const halfv_t *bl = cur.bfr + boff;
-            float4_t s1 = {0.f, 0.f, 0.f, 0.f}, s2 = s1, s3 = s1, s4 = s1;
+            float4_t sum[NW][4];
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) sum[w][s] = float4_t{0.f, 0.f, 0.f, 0.f};
             // all K-steps of the tile: the entries of atoms past the end are zero
 #pragma unroll
             for (int ks = 0; ks < kMfmaKSteps; ++ks) {
-                const halfv_t zrh = bl[bfrag_index(ks, 0, 0, 0)];
-                const halfv_t zrl = bl[bfrag_index(ks, 1, 0, 0)];
-                const halfv_t zih = bl[bfrag_index(ks, 2, 0, 0)];
-                const halfv_t zil = bl[bfrag_index(ks, 3, 0, 0)];
                 uint32_t wrh[kAtomsPerLane / 2], wrl[kAtomsPerLane / 2];
                 uint32_t wih[kAtomsPerLane / 2], wil[kAtomsPerLane / 2];
 #pragma unroll
@@ -305,76 +331,113 @@ __global__ __launch_bounds__(kMfmaMaxWaves * 64) void rhok_mfma_kernel(RhokMfmaA
                 const halfv_t prl = __builtin_bit_cast(halfv_t, vrl);
                 const halfv_t pih = __builtin_bit_cast(halfv_t, vih);
                 const halfv_t pil = __builtin_bit_cast(halfv_t, vil);
-                // interleaved so that dependent products on one sum are apart
-                s1 = mfma(prh, zrh, s1);
-                s2 = mfma(pih, zih, s2);
-                s3 = mfma(prh, zih, s3);
-                s4 = mfma(pih, zrh, s4);
-                s1 = mfma(prh, zrl, s1);
-                s2 = mfma(pih, zil, s2);
-                s3 = mfma(prh, zil, s3);
-                s4 = mfma(pih, zrl, s4);
-                s1 = mfma(prl, zrh, s1);
-                s2 = mfma(pil, zih, s2);
-                s3 = mfma(prl, zih, s3);
-                s4 = mfma(pil, zrh, s4);
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const halfv_t *bl = cur.bfr + w * kBFrags + boff;
+                    const halfv_t zrh = bl[bfrag_index(ks, 0, 0, 0)];
+                    const halfv_t zrl = bl[bfrag_index(ks, 1, 0, 0)];
+                    const halfv_t zih = bl[bfrag_index(ks, 2, 0, 0)];
+                    const halfv_t zil = bl[bfrag_index(ks, 3, 0, 0)];
+                    float4_t *sw = sum[w];
+                    // interleaved so that dependent products on one sum are apart
+                    sw[0] = mfma(prh, zrh, sw[0]);
+                    sw[1] = mfma(pih, zih, sw[1]);
+                    sw[2] = mfma(prh, zih, sw[2]);
+                    sw[3] = mfma(pih, zrh, sw[3]);
+                    sw[0] = mfma(prh, zrl, sw[0]);
+                    sw[1] = mfma(pih, zil, sw[1]);
+                    sw[2] = mfma(prh, zil, sw[2]);
+                    sw[3] = mfma(pih, zrl, sw[3]);
+                    sw[0] = mfma(prl, zrh, sw[0]);
+                    sw[1] = mfma(pil, zih, sw[1]);
+                    sw[2] = mfma(prl, zih, sw[2]);
+                    sw[3] = mfma(pil, zrh, sw[3]);
+                }
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                acc[0][v] += (double)s1[v];
-                acc[1][v] += (double)s2[v];
-                acc[2][v] += (double)s3[v];
-                acc[3][v] += (double)s4[v];
-            }
+            for (int w = 0; w < NW; ++w)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[w][s][v] += (double)sum[w][s][v];
         }
         __syncthreads(); // next buffer complete; this one free for the tile after
     }
     if (!active) return;
     // Row pm = pair, column col = |n_z|: only slots that are k-vectors of the
-    // group are stored, in partial[k][atom block].
+    // group are stored, in partial[k][weight set][atom block].
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int pm = mt * 16 + grp * 4 + v;
         const int32_t *sk = a.slot_k + ((size_t)pm * kMfmaCols + col) * 2;
         const int kp = sk[0], km = sk[1];
-        if (kp >= 0) {
-            double *dst = a.partial + ((size_t)kp * a.n_atom_blocks + blockIdx.y) * 2;
-            dst[0] = acc[0][v] - acc[1][v];
-            dst[1] = acc[2][v] + acc[3][v];
-        }
-        if (km >= 0) {
-            double *dst = a.partial + ((size_t)km * a.n_atom_blocks + blockIdx.y) * 2;
-            dst[0] = acc[0][v] + acc[1][v];
-            dst[1] = acc[3][v] - acc[2][v];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (kp >= 0) {
+                double *dst = a.partial + (((size_t)kp * NW + w) * a.n_atom_blocks + blockIdx.y) * 2;
+                dst[0] = acc[w][0][v] - acc[w][1][v];
+                dst[1] = acc[w][2][v] + acc[w][3][v];
+            }
+            if (km >= 0) {
+                double *dst = a.partial + (((size_t)km * NW + w) * a.n_atom_blocks + blockIdx.y) * 2;
+                dst[0] = acc[w][0][v] + acc[w][1][v];
+                dst[1] = acc[w][3][v] - acc[w][2][v];
+            }
         }
     }
 }
 
 // One wave per k-vector: sum the partials of its slot over the atom blocks in
-// a fixed order and store n(k) at the caller's index.  A k-vector listed
-// twice reads the partials stored under its first index.
+// a fixed order and store the result at the caller's index (a k-vector listed
+// twice reads the partials stored under its first index).  NW = 1: n(k).
+// NW = 3: the current vector J(k), stored as its components on the k-vector's
+// basis (khat, e1, e2) at channels 3k, 3k+1, 3k+2.
+template <int NW>
 __global__ __launch_bounds__(256) void rhok_mfma_final_kernel(RhokMfmaArgs a)
 {
     const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (k >= a.nk) return; // whole wave
     const size_t row = (size_t)a.k_src[k];
-    const double *src = a.partial + row * a.n_atom_blocks * 2;
-    double sr = 0.0, si = 0.0;
-    for (int b = lane; b < a.n_atom_blocks; b += 64) {
-        sr += src[2 * b];
-        si += src[2 * b + 1];
-    }
+    double sr[NW], si[NW];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        sr += __shfl_down(sr, off, 64);
-        si += __shfl_down(si, off, 64);
+    for (int w = 0; w < NW; ++w) {
+        const double *src = a.partial + (row * NW + w) * a.n_atom_blocks * 2;
+        double r = 0.0, i = 0.0;
+        for (int b = lane; b < a.n_atom_blocks; b += 64) {
+            r += src[2 * b];
+            i += src[2 * b + 1];
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            r += __shfl_down(r, off, 64);
+            i += __shfl_down(i, off, 64);
+        }
+        sr[w] = r;
+        si[w] = i;
     }
     if (lane != 0) return;
-    if (a.out_double)
-        static_cast<double2 *>(a.out)[k] = make_double2(sr, si);
-    else
-        static_cast<float2 *>(a.out)[k] = make_float2((float)sr, (float)si);
+    if constexpr (NW == 1) {
+        if (a.out_double)
+            static_cast<double2 *>(a.out)[k] = make_double2(sr[0], si[0]);
+        else
+            static_cast<float2 *>(a.out)[k] = make_float2((float)sr[0], (float)si[0]);
+    } else {
+        const double *bas = a.basis + (size_t)k * 9;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double r = 0.0, i = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                r += bas[3 * c + w] * sr[w];
+                i += bas[3 * c + w] * si[w];
+            }
+            if (a.out_double)
+                static_cast<double2 *>(a.out)[3 * k + c] = make_double2(r, i);
+            else
+                static_cast<float2 *>(a.out)[3 * k + c] = make_float2((float)r, (float)i);
+        }
+    }
 }
 
 } // namespace
@@ -382,37 +445,47 @@ __global__ __launch_bounds__(256) void rhok_mfma_final_kernel(RhokMfmaArgs a)
 int rhok_mfma_cols() { return kMfmaCols; }
 int rhok_mfma_max_nmax() { return kMfmaCols - 1; }
 
-size_t rhok_mfma_lds_bytes(int nmax)
+size_t rhok_mfma_lds_bytes(int nmax, int nw)
 {
     const int nn = 2 * nmax + 1;
     return (size_t)kRoots * sizeof(double2) +
-           2 * ((size_t)2 * nn * kTabStride * sizeof(float2) + (size_t)kBFrags * sizeof(halfv_t));
+           2 * ((size_t)2 * nn * kTabStride * sizeof(float2) +
+                (size_t)nw * kBFrags * sizeof(halfv_t));
 }
 
-hipError_t rhok_mfma_prepare(int nmax)
+hipError_t rhok_mfma_prepare(int nmax, int nw)
 {
-    if (nmax > kMfmaCols - 1) return hipErrorInvalidValue;
-    const size_t lds = rhok_mfma_lds_bytes(nmax);
+    if (nmax > kMfmaCols - 1 || (nw != 1 && nw != 3)) return hipErrorInvalidValue;
+    const size_t lds = rhok_mfma_lds_bytes(nmax, nw);
     if (lds <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&rhok_mfma_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *fn = nw == 1 ? reinterpret_cast<const void *>(&rhok_mfma_kernel<1>)
+                             : reinterpret_cast<const void *>(&rhok_mfma_kernel<3>);
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int NW> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t st)
+{
+    // waves per block: the M tiles dealt evenly over the fewest blocks, at
+    // least one thread per table task
+    const int maxw = MfmaShape<NW>::max_waves;
+    const int chunks = (a.n_mtiles + maxw - 1) / maxw;
+    int waves = (a.n_mtiles + chunks - 1) / chunks;
+    if (waves < kMfmaMinWaves) waves = kMfmaMinWaves;
+    hipLaunchKernelGGL(rhok_mfma_kernel<NW>, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
+                       dim3(waves * 64), rhok_mfma_lds_bytes(a.nmax, NW), st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(rhok_mfma_final_kernel<NW>, dim3((unsigned)((a.nk + 3) / 4)), dim3(256), 0,
+                       st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_rhok_mfma(const RhokMfmaArgs &a, hipStream_t st)
 {
     if (a.nmax > kMfmaCols - 1 || a.n_mtiles < 1) return hipErrorInvalidValue;
-    // waves per block: the M tiles dealt evenly over the fewest blocks, at
-    // least one thread per table task
-    const int chunks = (a.n_mtiles + kMfmaMaxWaves - 1) / kMfmaMaxWaves;
-    int waves = (a.n_mtiles + chunks - 1) / chunks;
-    if (waves < kMfmaMinWaves) waves = kMfmaMinWaves;
-    hipLaunchKernelGGL(rhok_mfma_kernel, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
-                       dim3(waves * 64), rhok_mfma_lds_bytes(a.nmax), st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(rhok_mfma_final_kernel, dim3((unsigned)((a.nk + 3) / 4)), dim3(256), 0, st,
-                       a);
-    return hipGetLastError();
+    if (a.nw == 1) return launch_nw<1>(a, st);
+    if (a.nw == 3) return launch_nw<3>(a, st);
+    return hipErrorInvalidValue;
 }
 
 } // namespace corr

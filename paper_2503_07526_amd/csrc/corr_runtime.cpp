@@ -47,7 +47,9 @@ struct Group {
     double *d_partial = nullptr;
     RhokArgs rargs{};
     bool rhok_mfma = false;       // matrix-core producer (else rargs, vector units)
-    int32_t *d_mtab = nullptr;    // pair_nx | pair_ny | nz_list | slot_k | k_src
+    int nw = 1;                   // producer weight sets: 1 n(k), 3 currents
+    int32_t *d_mtab = nullptr;    // pair_nx | pair_ny | slot_k | k_src
+    double *d_basis = nullptr;    // currents: [nk][3][3] khat, e1, e2
     RhokMfmaArgs margs{};
 };
 
@@ -159,7 +161,8 @@ int validate(const corr_group_desc &g, int idx)
     if (g.update_every < 1) return bad("update_every must be >= 1");
     if (g.dtype < CORR_F32 || g.dtype > CORR_CF64) return bad("unknown dtype");
     if (g.accum < CORR_ACC_F64 || g.accum > CORR_ACC_F32) return bad("unknown accumulator");
-    if (g.source != CORR_SRC_SAMPLES && g.source != CORR_SRC_RHOK) return bad("unknown source");
+    if (g.source != CORR_SRC_SAMPLES && g.source != CORR_SRC_RHOK && g.source != CORR_SRC_CURRENTS)
+        return bad("unknown source");
     if ((g.dtype == CORR_F64 || g.dtype == CORR_CF64) && g.accum != CORR_ACC_F64)
         return bad("double samples need double accumulators");
     if (g.source == CORR_SRC_RHOK) {
@@ -172,6 +175,21 @@ int validate(const corr_group_desc &g, int idx)
                 if (g.kvec[3 * q + d] > 64 || g.kvec[3 * q + d] < -64)
                     return set_err(nullptr, CORR_E_UNSUPPORTED,
                                    "group %d: k-vector components beyond +-64", idx);
+    }
+    if (g.source == CORR_SRC_CURRENTS) {
+        if (g.dtype != CORR_CF32 && g.dtype != CORR_CF64) return bad("currents need a complex dtype");
+        if (g.n_channels % 3 != 0) return bad("currents: n_channels must be 3 x k-vectors");
+        if (!g.kvec) return bad("currents group without k-vectors");
+        if (g.n_atoms < 1) return bad("currents group needs n_atoms >= 1");
+        if (!(g.box > 0.0)) return bad("currents group needs box > 0");
+        for (int64_t q = 0; q < g.n_channels / 3; ++q) {
+            const int32_t *n = g.kvec + 3 * q;
+            if (n[0] == 0 && n[1] == 0 && n[2] == 0) return bad("currents: zero k-vector");
+            for (int d = 0; d < 3; ++d)
+                if (n[d] > 15 || n[d] < -15)
+                    return set_err(nullptr, CORR_E_UNSUPPORTED,
+                                   "group %d: currents need k-vector components within +-15", idx);
+        }
     }
     if (g.points > 4096) return set_err(nullptr, CORR_E_UNSUPPORTED, "group %d: p > 4096", idx);
     if (g.levels > 40) return set_err(nullptr, CORR_E_UNSUPPORTED, "group %d: b > 40", idx);
@@ -205,6 +223,7 @@ void free_group(Group &g)
     if (g.d_seg) (void)hipFree(g.d_seg);
     if (g.d_partial) (void)hipFree(g.d_partial);
     if (g.d_mtab) (void)hipFree(g.d_mtab);
+    if (g.d_basis) (void)hipFree(g.d_basis);
     if (g.d_flushed) (void)hipFree(g.d_flushed);
     g = Group{};
 }
@@ -584,10 +603,12 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
             CREATE_HIP(hipMemsetAsync(g.d_flushed, 0, kFlushGroups * sizeof(int64_t), c->stream));
         }
 
-        g.rhok = g.d.source == CORR_SRC_RHOK;
+        g.rhok = g.d.source == CORR_SRC_RHOK || g.d.source == CORR_SRC_CURRENTS;
         if (g.rhok) {
-            g.input_bytes = (size_t)3 * (size_t)g.d.n_atoms * sizeof(float);
-            const int nk = (int)g.n_ch;
+            g.nw = g.d.source == CORR_SRC_CURRENTS ? 3 : 1;
+            // positions [3][N]; currents: then velocities [3][N]
+            g.input_bytes = (size_t)(g.nw == 3 ? 6 : 3) * (size_t)g.d.n_atoms * sizeof(float);
+            const int nk = (int)(g.n_ch / g.nw);
             const int32_t *kv = groups[i].kvec;
             int nmax = 0;
             for (int q = 0; q < nk; ++q)
@@ -595,10 +616,13 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
             // Atom blocks: about 1000 atoms or more each, at most 512 blocks.
             const int n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(512, g.d.n_atoms / 1024));
             const int64_t apb = (g.d.n_atoms + n_ab - 1) / n_ab;
-            CREATE_HIP(hipMalloc(&g.rhok_out, (size_t)nk * g.s_bytes));
-            CREATE_HIP(hipMemsetAsync(g.rhok_out, 0, (size_t)nk * g.s_bytes, c->stream));
-            // Matrix-core form: rows = distinct (n_x, n_y), columns = |n_z|.
-            g.rhok_mfma = !(flags & CORR_FLAG_RHOK_VALU) && nmax <= rhok_mfma_max_nmax();
+            CREATE_HIP(hipMalloc(&g.rhok_out, (size_t)g.n_ch * g.s_bytes));
+            CREATE_HIP(hipMemsetAsync(g.rhok_out, 0, (size_t)g.n_ch * g.s_bytes, c->stream));
+            // Matrix-core form: rows = distinct (n_x, n_y), columns = |n_z|
+            // (the only form for currents; validation keeps their components
+            // within its range).
+            g.rhok_mfma = g.nw == 3 ||
+                          (!(flags & CORR_FLAG_RHOK_VALU) && nmax <= rhok_mfma_max_nmax());
             if (g.rhok_mfma) {
                 std::map<std::pair<int, int>, int> pair_ix;
                 for (int q = 0; q < nk; ++q)
@@ -630,8 +654,42 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 CREATE_HIP(hipMalloc(&g.d_mtab, packed.size() * sizeof(int32_t)));
                 CREATE_HIP(hipMemcpy(g.d_mtab, packed.data(), packed.size() * sizeof(int32_t),
                                      hipMemcpyHostToDevice));
-                CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * nk * 2 * sizeof(double)));
-                CREATE_HIP(rhok_mfma_prepare(nmax));
+                CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * nk * g.nw * 2 * sizeof(double)));
+                CREATE_HIP(rhok_mfma_prepare(nmax, g.nw));
+                if (g.nw == 3) {
+                    // basis of each k-vector: khat, then e1 = the Cartesian axis
+                    // least aligned with khat, made orthogonal to it and
+                    // normalised, then e2 = khat x e1
+                    std::vector<double> bas((size_t)nk * 9);
+                    for (int q = 0; q < nk; ++q) {
+                        double kh[3], e1[3], e2[3];
+                        const double len = std::sqrt((double)kv[3 * q] * kv[3 * q] +
+                                                     (double)kv[3 * q + 1] * kv[3 * q + 1] +
+                                                     (double)kv[3 * q + 2] * kv[3 * q + 2]);
+                        int ax = 0;
+                        for (int d = 0; d < 3; ++d) kh[d] = kv[3 * q + d] / len;
+                        for (int d = 1; d < 3; ++d)
+                            if (std::fabs(kh[d]) < std::fabs(kh[ax])) ax = d;
+                        double nrm = 0.0;
+                        for (int d = 0; d < 3; ++d) {
+                            e1[d] = (d == ax ? 1.0 : 0.0) - kh[ax] * kh[d];
+                            nrm += e1[d] * e1[d];
+                        }
+                        nrm = std::sqrt(nrm);
+                        for (int d = 0; d < 3; ++d) e1[d] /= nrm;
+                        e2[0] = kh[1] * e1[2] - kh[2] * e1[1];
+                        e2[1] = kh[2] * e1[0] - kh[0] * e1[2];
+                        e2[2] = kh[0] * e1[1] - kh[1] * e1[0];
+                        for (int d = 0; d < 3; ++d) {
+                            bas[(size_t)q * 9 + d] = kh[d];
+                            bas[(size_t)q * 9 + 3 + d] = e1[d];
+                            bas[(size_t)q * 9 + 6 + d] = e2[d];
+                        }
+                    }
+                    CREATE_HIP(hipMalloc(&g.d_basis, bas.size() * sizeof(double)));
+                    CREATE_HIP(hipMemcpy(g.d_basis, bas.data(), bas.size() * sizeof(double),
+                                         hipMemcpyHostToDevice));
+                }
                 RhokMfmaArgs &r = g.margs;
                 r.pos = nullptr;
                 r.n_atoms = g.d.n_atoms;
@@ -648,6 +706,8 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 r.out = g.rhok_out;
                 r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
                 r.nk = nk;
+                r.nw = g.nw;
+                r.basis = g.d_basis;
             } else {
                 // Segments: k-vectors sharing (n_y, n_z) with n_x in a window of
                 // kSegWidth, rows ordered by (n_z, n_y).
@@ -1068,7 +1128,8 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
     }
 
     const bool cplx = kind_complex(g.kind);
-    const double norm = g.rhok ? 1.0 / (double)g.d.n_atoms : 1.0; // F(k,t) = <n n*> / N
+    // F(k,t) = <n n*> / N; currents likewise per atom
+    const double norm = g.rhok ? 1.0 / (double)g.d.n_atoms : 1.0;
     const double tunit = (double)g.d.update_every * g.d.dt;
     std::vector<double> tt((size_t)ne), cre((size_t)ne);
     for (int i = 0; i < ne; ++i) {

@@ -79,6 +79,19 @@ def test_rhok_descriptor_needs_positions_and_box(corrmod):
     assert rc == -1 and "box" in msg
 
 
+@pytest.mark.parametrize("kv,n_channels,rc_want,needle", [
+    ([[1, 0, 0], [0, 0, 0]], 6, -1, "zero k-vector"),
+    ([[1, 0, 0], [16, 0, 0]], 6, -5, "+-15"),
+    ([[1, 0, 0]], 4, -1, "3 x k-vectors"),
+])
+def test_currents_descriptor_checks(corrmod, kv, n_channels, rc_want, needle):
+    rc, msg = _create(corrmod, corrmod.GroupDesc(n_channels, 4, 16, dtype="cf32",
+                                                 source="currents",
+                                                 kvec=np.array(kv, dtype=np.int32),
+                                                 n_atoms=10, box=10.0))
+    assert rc == rc_want and needle in msg, (rc, msg)
+
+
 @pytest.mark.parametrize("tuning", [
     dict(tile_channels=100, chans_per_thread=1, lag_chunk=16, grid_blocks=0),
     dict(tile_channels=256, chans_per_thread=3, lag_chunk=8, grid_blocks=0),

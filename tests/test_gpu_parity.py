@@ -359,3 +359,103 @@ def test_kernel_time_pools(corrmod):
         assert c.kernel_time(2) == (0.0, 0)
         with pytest.raises(corrmod.CorrError):
             c.kernel_time(3)
+
+
+def _currents_inputs(seed, N, box, S):
+    """[S][6][N] float32: positions (seeded lattice-free uniform + OU drift)
+    then velocities (unit-variance OU series, tau 20)."""
+    pos, _ = synth.PositionSpec(seed, 1, N, box).series(0, S)
+    vel = ou_inputs(seed, 7, 3 * N, S, "f32").reshape(S, 3, N)
+    return np.ascontiguousarray(np.concatenate([pos, vel], axis=1))
+
+
+def test_currents_lag0_against_oracle(corrmod):
+    """One push: C(0) of channel 3q+c = |J_c(k_q)|^2 / N with J from the
+    oracle's direct double sums, for a k-set spanning |n| up to 15 and
+    repeated vectors; a second push checks the phase of C(lag 1)."""
+    N, box = 3001, 50.0
+    kv = synth.kvectors(120)
+    kv = np.concatenate([kv, [[15, -15, 15], [0, 0, -7]], kv[:3]]).astype(np.int32)
+    say(f"[currents] N={N} nk={len(kv)}")
+    x = _currents_inputs(21, N, box, 2)
+    g = corrmod.GroupDesc(3 * len(kv), 3, 8, 2, dtype="cf32", accum="f64", source="currents",
+                          kvec=kv, n_atoms=N, box=box)
+    with corrmod.Correlator([g]) as c:
+        _push_all(c, [x[:1]])
+        res = c.finalize(0, slice_=(0, 3 * len(kv)))
+        j0 = oracle.currents(x[0, :3], x[0, 3:], kv, box).reshape(-1)
+        expect = np.abs(j0) ** 2 / N
+        got = res["c_per_channel"][:, 0]
+        err = np.max(np.abs(got - expect)) / np.max(expect)
+        say(f"  lag-0 error {err:.2e}")
+        assert err < 2e-6
+        _push_all(c, [x[1:2]])
+        res = c.finalize(0, slice_=(0, 3 * len(kv)))
+        j1 = oracle.currents(x[1, :3], x[1, 3:], kv, box).reshape(-1)
+        expect1 = j1 * np.conj(j0) / N
+        got1 = res["c_per_channel"][:, 1]
+        assert np.max(np.abs(got1 - expect1)) / np.max(np.abs(expect1)) < 2e-6
+
+
+@pytest.mark.parametrize("accum", ["kahan", "f64"])
+def test_currents_correlator_parity(corrmod, accum):
+    """S pushes of moving atoms: the currents group against the oracle
+    correlator fed the oracle's currents; times and counts exact, C within the
+    tolerance of the accumulator."""
+    S, N, box = 200, 1500, 40.0
+    kv = synth.kvectors(48)
+    x = _currents_inputs(22, N, box, S)
+    say(f"[currents parity] S={S} N={N} nk={len(kv)} accum={accum}")
+    o = oracle.OracleCorrelator(3 * len(kv), 5, 16, 2, complex_=True)
+    for s in range(S):
+        o.push(oracle.currents(x[s, :3], x[s, 3:], kv, box).reshape(-1))
+    g = corrmod.GroupDesc(3 * len(kv), 5, 16, 2, dtype="cf32", accum=accum, source="currents",
+                          kvec=kv, n_atoms=N, box=box)
+    with corrmod.Correlator([g]) as c:
+        _push_all(c, [x])
+        res = c.finalize(0, slice_=(0, 6))
+    e = gate(res, o, TOL[("cf32", accum)], scale=1.0 / N, slice_=(0, 6), label="currents")
+    say(f"  error {e:.2e}")
+
+
+def test_currents_with_other_groups_all_launch_modes(corrmod):
+    """A currents group next to a k-density group and a velocity group: the
+    batched launch, the per-group launches and the graph replay give
+    bit-identical state."""
+    S, N, box, nv = 130, 1200, 30.0, 3000
+    kv = synth.kvectors(40)
+    x = _currents_inputs(23, N, box, S)
+    xv = ou_inputs(23, 3, nv, S, "f32")
+    pos = np.ascontiguousarray(x[:, :3])
+    groups = [corrmod.GroupDesc(3 * len(kv), 4, 16, 2, dtype="cf32", accum="kahan",
+                                source="currents", kvec=kv, n_atoms=N, box=box),
+              corrmod.GroupDesc(len(kv), 4, 16, 2, dtype="cf32", accum="kahan", source="rhok",
+                                kvec=kv, n_atoms=N, box=box),
+              corrmod.GroupDesc(nv, 6, 16, 2, dtype="f32", accum="kahan")]
+    out = {}
+    dev = torch.device("cuda:0")
+    for mode in ("batched", "per_group", "graph"):
+        with corrmod.Correlator(groups, graph=(mode == "graph"),
+                                per_group=(mode == "per_group")) as c:
+            tx, tp, tv = (torch.from_numpy(a).to(dev) for a in (x, pos, xv))
+            if mode == "graph":
+                bx, bp, bv = torch.empty_like(tx[0]), torch.empty_like(tp[0]), torch.empty_like(tv[0])
+                c.bind_input(0, bx); c.bind_input(1, bp); c.bind_input(2, bv)
+                for s in range(S):
+                    bx.copy_(tx[s]); bp.copy_(tp[s]); bv.copy_(tv[s])
+                    c.push()
+            else:
+                for s in range(S):
+                    c.push([tx[s], tp[s], tv[s]])
+            torch.cuda.synchronize()
+            out[mode] = [c.finalize(g, slice_=(0, 6)) for g in range(3)]
+    for mode in ("per_group", "graph"):
+        for g in range(3):
+            assert np.array_equal(out[mode][g]["c_per_channel"], out["batched"][g]["c_per_channel"])
+    # the longitudinal current with all velocities = khat would be n(k); here
+    # check the density group against the oracle instead
+    orh = oracle.OracleCorrelator(len(kv), 4, 16, 2, complex_=True)
+    for s in range(S):
+        orh.push(oracle.rhok(pos[s], kv, box))
+    gate(out["batched"][1], orh, TOL[("cf32", "kahan")], scale=1.0 / N, slice_=(0, 6),
+         label="rho(k) beside currents")
