@@ -20,6 +20,8 @@ Workloads (--config):
            12 levels x 16 points
   rhok     the k-density group of `batched` alone (2048 k-vectors, 10^6 atoms):
            the producer kernel's own roofline line
+  currents longitudinal and transverse currents of the same 2048 k-vectors and
+           10^6 atoms (6144 complex channels), the current producer's line
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -38,7 +40,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 MFMA_F16_PEAK_TFS = 2500.0  # MI355X dense fp16 matrix peak
+VALU_F32_PEAK_TFS = 157.3   # MI355X fp32 vector peak
 RHOK_FLOP_PER_ATOM_K = 14  # factorised phases: 2 complex multiplies + 1 complex add
+# currents: the phase as for n(k) plus, per velocity component, a real x complex
+# multiply-add (4 flop)
+CURRENTS_FLOP_PER_ATOM_K = RHOK_FLOP_PER_ATOM_K + 3 * 4
+PRODUCER_KINDS = ("rhok", "currents")
 
 
 def parse():
@@ -47,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--config", default="batched",
-                    choices=["plain", "batched", "large", "rhok", "precision"])
+                    choices=["plain", "batched", "large", "rhok", "currents", "precision"])
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the launch-shape autotuner (library defaults)")
     ap.add_argument("--precision-steps", type=int, default=1_000_000)
@@ -107,7 +114,34 @@ def workload(name):
             groups=[dict(kind="rhok", n=2048, levels=16, points=32, m=2, dtype="cf32",
                          accum="kahan", n_atoms=1_000_000, box=100.0, seed=3, stream=3,
                          kvec=synth.kvectors(2048))])
+    if name == "currents":
+        return dict(
+            name="currents: j_L and j_T of 2048 k-vectors (|n| <= 12 half-space) from 1e6 atoms in "
+                 "a box of 100 with OU velocities (tau 20..200), 6144 cFP32 channels compensated "
+                 "b=16 p=32 m=2",
+            steps=10_000,
+            groups=[dict(kind="currents", n=3 * 2048, levels=16, points=32, m=2, dtype="cf32",
+                         accum="kahan", n_atoms=1_000_000, box=100.0, seed=5, stream=3,
+                         vtau=(20, 200), kvec=synth.kvectors(2048))])
     raise ValueError(name)
+
+
+class CurrentsInput:
+    """Positions then velocities, [steps][6][N] float32, generated on the GPU."""
+
+    def __init__(self, g):
+        import synth
+        self.n = g["n_atoms"]
+        self.pos = synth.GpuPositions(synth.PositionSpec(g["seed"], g["stream"], self.n, g["box"],
+                                                         0.1, 50.0))
+        self.vel = synth.GpuOU(synth.OUSpec.make(g["seed"], g["stream"] + 1, 3 * self.n, comps=3,
+                                                 tau=g["vtau"][0], tau_hi=g["vtau"][1],
+                                                 sigma=1.0))
+
+    def fill(self, buf, n_steps):
+        flat = buf.view(buf.shape[0], 6 * self.n)
+        self.pos.fill(flat[:, :3 * self.n], n_steps)
+        self.vel.fill(flat[:, 3 * self.n:], n_steps)
 
 
 # rocprofv3 counter records of the flush kernel (profiles/flush_traffic_<config>.md)
@@ -233,7 +267,7 @@ def cpu_baseline(wl):
     """The FP64 oracle on a bounded sample of the workload's largest group."""
     import oracle
     import synth
-    if all(g["kind"] == "rhok" for g in wl["groups"]):
+    if all(g["kind"] in PRODUCER_KINDS for g in wl["groups"]):
         return cpu_baseline_rhok(wl["groups"][0])
     g = max(wl["groups"], key=lambda x: x["n"])
     n_ch, S = 16000, 8000
@@ -254,21 +288,27 @@ def cpu_baseline(wl):
 
 
 def cpu_baseline_rhok(g):
-    """The oracle's direct n(k) sum (one double cos and sin per atom and k) on a
-    bounded sample of atoms, scaled linearly to the workload's atom count; the
-    correlator update of 2048 channels per push is negligible beside it."""
+    """The oracle's direct n(k) (or current) sums (one double cos and sin per
+    atom and k) on a bounded sample of atoms, scaled linearly to the workload's
+    atom count; the correlator update of the k-channels is negligible beside
+    it."""
     import oracle
     import synth
     n_sample, reps = 50_000, 3
     spec = synth.PositionSpec(g["seed"], g["stream"], n_sample, g["box"], 0.1, 50.0)
     pos, _ = spec.series(0, reps)
+    vel = np.random.default_rng(0).standard_normal((reps, 3, n_sample)).astype(np.float32)
     t0 = time.perf_counter()
     for r in range(reps):
-        oracle.rhok(pos[r], g["kvec"], g["box"])
+        if g["kind"] == "currents":
+            oracle.currents(pos[r], vel[r], g["kvec"], g["box"])
+        else:
+            oracle.rhok(pos[r], g["kvec"], g["box"])
     dt = (time.perf_counter() - t0) / reps
     per_push = dt * g["n_atoms"] / n_sample
     return {"value": g["n"] / per_push, "unit": "channel-samples/s", "cores": 1, "kind": "oracle",
-            "sample": (f"n(k) of {g['n']} k-vectors over {n_sample} of {g['n_atoms']} atoms, "
+            "sample": (f"{g['kind']} of {len(g['kvec'])} k-vectors over {n_sample} of "
+                       f"{g['n_atoms']} atoms, "
                        f"{reps} pushes, {dt:.2f} s each, scaled to the full atom count; "
                        f"single thread")}
 
@@ -291,7 +331,13 @@ def run(args):
     descs, gens, bufs = [], [], []
     chunk = max(1, min(args.chunk, K))
     for g in wl["groups"]:
-        if g["kind"] == "rhok":
+        if g["kind"] == "currents":
+            descs.append(GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype=g["dtype"],
+                                   accum=g["accum"], source="currents", kvec=g["kvec"],
+                                   n_atoms=g["n_atoms"], box=g["box"]))
+            gens.append(CurrentsInput(g))
+            bufs.append(torch.empty((chunk, 6, g["n_atoms"]), dtype=torch.float32, device=dev))
+        elif g["kind"] == "rhok":
             descs.append(GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype=g["dtype"],
                                    accum=g["accum"], source="rhok", kvec=g["kvec"],
                                    n_atoms=g["n_atoms"], box=g["box"]))
@@ -349,9 +395,9 @@ def run(args):
     # The timed launch: with k-density groups next to other groups, those run
     # (producer + own push) on a forked side stream and the events bracket the
     # push launch of the other groups only.
-    has_rhok = any(g["kind"] == "rhok" for g in wl["groups"])
+    has_rhok = any(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
     timed = [g for g in wl["groups"]
-             if not (has_rhok and len(wl["groups"]) > 1 and g["kind"] == "rhok")]
+             if not (has_rhok and len(wl["groups"]) > 1 and g["kind"] in PRODUCER_KINDS)]
     steps = range(s_first, s_first + K)
     direct = args.direct
     stage_bytes = sum(push_bytes(g, s, direct) for g in timed for s in steps)
@@ -362,13 +408,17 @@ def run(args):
     rk_ms, rk_n = corr.kernel_time(which=2)
     n_total = sum(g["n"] for g in wl["groups"])
     value = n_total * K / wall
-    rhok_only = all(g["kind"] == "rhok" for g in wl["groups"])
+    rhok_only = all(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
     if rhok_only:
         g0 = wl["groups"][0]
-        flop = RHOK_FLOP_PER_ATOM_K * g0["n"] * g0["n_atoms"]
-        achieved = flop / (rk_ms / rk_n * 1e-3) / 1e12
-        kname = ("k-density producer (%s), HIP events per launch on its stream"
-                 % ("vector units" if args.rhok_valu else "matrix cores"))
+        if g0["kind"] == "currents":
+            flop_per = CURRENTS_FLOP_PER_ATOM_K * (g0["n"] // 3) * g0["n_atoms"]
+            kname = "current producer (matrix cores), HIP events per launch on its stream"
+        else:
+            flop_per = RHOK_FLOP_PER_ATOM_K * g0["n"] * g0["n_atoms"]
+            kname = ("k-density producer (%s), HIP events per launch on its stream"
+                     % ("vector units" if args.rhok_valu else "matrix cores"))
+        achieved = flop_per / (rk_ms / rk_n * 1e-3) / 1e12
         per_launch_ms, per_launch_bytes = rk_ms / rk_n, None
     elif fl_n:
         # dominant kernel: the flush of the block-deferred groups
@@ -412,9 +462,9 @@ def run(args):
         out["roofline"]["producer_ms_per_launch"] = rk_ms / rk_n
     if rhok_only:
         r = out["roofline"]
-        r.update({"bound": "mfma", "unit": "TFLOP/s", "peak": MFMA_F16_PEAK_TFS,
-                  "frac": achieved / MFMA_F16_PEAK_TFS,
-                  "alg_flop_per_launch": RHOK_FLOP_PER_ATOM_K * g0["n"] * g0["n_atoms"]})
+        bound, peak = ("alu", VALU_F32_PEAK_TFS) if args.rhok_valu else ("mfma", MFMA_F16_PEAK_TFS)
+        r.update({"bound": bound, "unit": "TFLOP/s", "peak": peak, "frac": achieved / peak,
+                  "alg_flop_per_launch": flop_per})
         for key in ("alg_bytes_per_launch", "update_kernels_GBs", "alg_bytes_per_step"):
             r.pop(key, None)
     elif fl_n:
