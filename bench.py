@@ -72,6 +72,9 @@ def parse():
                     help="per-step update of every channel (no block-deferred form)")
     ap.add_argument("--rhok-valu", action="store_true",
                     help="k-density producer on the vector units instead of the matrix cores")
+    ap.add_argument("--overlap", type=int, choices=[0, 1], default=None,
+                    help="force producers onto a forked stream (1) or the context's stream (0) "
+                         "instead of the autotuner's choice")
     return ap.parse_args()
 
 
@@ -145,22 +148,43 @@ class CurrentsInput:
 
 
 # rocprofv3 counter records of the flush kernel (profiles/flush_traffic_<config>.md)
-# are valid only for the kernel source they were taken on.
-TRAFFIC_SOURCES = ("paper_2503_07526_amd/csrc/corr_deferred.hip",
-                   "paper_2503_07526_amd/csrc/corr_internal.h")
+# are valid only for the kernel source they were taken on: the fold kernel's
+# file and, of the shared header, the definitions it uses.
+TRAFFIC_SOURCE = "paper_2503_07526_amd/csrc/corr_deferred.hip"
+TRAFFIC_HEADER = "paper_2503_07526_amd/csrc/corr_internal.h"
+TRAFFIC_HEADER_PARTS = ("enum Kind", "struct GroupArgs", "struct DeferredArgs", "kDeferT",
+                        "kFlushGroups", "acc_planes", "kind_complex", "kind_sample_bytes",
+                        "kind_acc_bytes")
+
+
+def _strip_comments(src):
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    return re.sub(r"//[^\n]*", " ", src)
 
 
 def flush_source_hash():
-    """Hash of the fold kernel's sources with comments and whitespace removed
-    (a comment edit does not change the kernel)."""
-    import re
+    """Hash of the fold kernel's source and of the header definitions it uses,
+    with comments and whitespace removed (a comment edit, or a change to other
+    kernels' argument structs, does not change this kernel)."""
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, rel)) as f:
-            src = f.read()
-        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
-        src = re.sub(r"//[^\n]*", " ", src)
-        h.update(" ".join(src.split()).encode())
+    with open(os.path.join(ROOT, TRAFFIC_SOURCE)) as f:
+        h.update(" ".join(_strip_comments(f.read()).split()).encode())
+    with open(os.path.join(ROOT, TRAFFIC_HEADER)) as f:
+        header = _strip_comments(f.read())
+    # top-level declarations: split at lines that start a new definition
+    decls, cur = [], []
+    for line in header.splitlines():
+        if line and not line[0].isspace() and line[0] not in "{}" and cur:
+            decls.append("\n".join(cur))
+            cur = []
+        cur.append(line)
+    decls.append("\n".join(cur))
+    for part in TRAFFIC_HEADER_PARTS:
+        for d in decls:
+            first = d.strip().split("\n", 1)[0]
+            if part in first:
+                h.update(" ".join(d.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -270,7 +294,7 @@ def cpu_baseline(wl):
     if all(g["kind"] in PRODUCER_KINDS for g in wl["groups"]):
         return cpu_baseline_rhok(wl["groups"][0])
     g = max(wl["groups"], key=lambda x: x["n"])
-    n_ch, S = 16000, 8000
+    n_ch, S = 12000, 6000
     real = np.float32 if g["dtype"] == "f32" else np.float64
     spec = synth.OUSpec.make(g["seed"], g["stream"], n_ch, comps=g.get("comps", 1),
                              tau=g["tau"][0], tau_hi=g["tau"][1], dtype=real)
@@ -361,6 +385,8 @@ def run(args):
         tuning = autotune(descs, per_group=(mode == "per_group"), direct=args.direct,
                           rhok_valu=args.rhok_valu)
         tune_s = time.perf_counter() - t0
+    if args.overlap is not None:
+        tuning = dict(tuning or {}, overlap_producers=args.overlap)
     corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuning, timing=True,
                       direct=args.direct, rhok_valu=args.rhok_valu)
     state_gb = sum(corr.state_bytes(i) for i in range(len(descs))) / 1e9
@@ -449,6 +475,9 @@ def run(args):
         "config": {"workload": wl["name"], "channels": n_total, "launch": mode,
                    "update_form": "direct" if args.direct else "block-deferred where supported",
                    "rhok_producer": "vector units" if args.rhok_valu else "matrix cores",
+                   "producer_stream": ("forked, overlapping the other updates"
+                                       if corr.tuning()["overlap_producers"]
+                                       else "the context's stream, before the other updates"),
                    "tuning": corr.tuning(), "state_GB": round(state_gb, 2)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,

@@ -114,18 +114,23 @@ typedef struct corr_group_desc {
     double box;             /* cubic box edge L                                   */
 } corr_group_desc;
 
-/* Launch shape of the push kernel.  Channels are stored in tiles of
- * tile_channels consecutive channels (the state layout depends on it, so it
- * is fixed at create); each thread handles chans_per_thread consecutive
- * channels of a tile; the batched kernel runs grid_blocks blocks that stride
- * over all tiles of all groups (0 = one block per tile).  Zeros everywhere
- * select the library defaults (or the autotuner's cached choice). */
+/* Launch shape.  Channels are stored in tiles of tile_channels consecutive
+ * channels (the state layout depends on it, so it is fixed at create); each
+ * thread handles chans_per_thread consecutive channels of a tile; the batched
+ * kernel runs grid_blocks blocks that stride over all tiles of all groups
+ * (0 = one block per tile).  overlap_producers chooses how the n(k) / current
+ * producers of a context that also has sample-fed groups are issued.  Zeros
+ * everywhere select the library defaults (or the autotuner's cached
+ * choice). */
 typedef struct corr_tuning {
     int32_t tile_channels;    /* multiple of 64 * chans_per_thread, at most
                                  256 * chans_per_thread (256 threads per block) */
     int32_t chans_per_thread; /* 1, 2 or 4                                          */
     int32_t lag_chunk;        /* lags loaded per batch: 4, 8 or 16                  */
     int32_t grid_blocks;      /* 0 = one block per tile                              */
+    int32_t overlap_producers; /* 0: producers (and their groups' updates) run on
+                                  the context's stream before the other updates;
+                                  1: on a forked stream, concurrently with them */
 } corr_tuning;
 
 /*

@@ -44,7 +44,8 @@ class _GroupDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_channels", ctypes.c_int32), ("chans_per_thread", ctypes.c_int32),
-                ("lag_chunk", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+                ("lag_chunk", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("overlap_producers", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -81,6 +81,7 @@ bool tune_cache_lookup(const std::string &path, const std::string &key, corr_tun
             parse_int(line, "chans_per_thread", &c.chans_per_thread) &&
             parse_int(line, "lag_chunk", &c.lag_chunk) &&
             parse_int(line, "grid_blocks", &c.grid_blocks)) {
+            if (!parse_int(line, "overlap_producers", &c.overlap_producers)) c.overlap_producers = 0;
             t = c; // the last entry for a key wins
             found = true;
         }
@@ -97,7 +98,8 @@ static void tune_cache_store(const std::string &path, const std::string &key, co
     if (!f) return;
     f << "{\"key\":\"" << key << "\",\"tile_channels\":" << t.tile_channels
       << ",\"chans_per_thread\":" << t.chans_per_thread << ",\"lag_chunk\":" << t.lag_chunk
-      << ",\"grid_blocks\":" << t.grid_blocks << ",\"ms_per_push\":" << ms_per_push << "}\n";
+      << ",\"grid_blocks\":" << t.grid_blocks << ",\"overlap_producers\":" << t.overlap_producers
+      << ",\"ms_per_push\":" << ms_per_push << "}\n";
 }
 
 } // namespace corr
@@ -133,13 +135,12 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
         return CORR_E_DEVICE;
     }
     const int period = 64; // whole flush periods of the block-deferred form
-    double best = 1e300;
-    corr_tuning best_t{};
-    for (const corr_tuning &cand : cands) {
+    // ms for 2 periods of pushes after one period of warm-up, or < 0
+    auto trial_ms = [&](const corr_tuning &cand) -> double {
         corr_ctx *ctx = nullptr;
         const uint32_t tflags = flags & ~(uint32_t)CORR_FLAG_TIMING;
         if (corr_create(trial.data(), n_groups, device, stream, tflags, &cand, &ctx) != CORR_OK)
-            continue; // e.g. out of memory for this layout
+            return -1.0; // e.g. out of memory for this layout
         bool ok = true;
         for (int s = 0; s < period && ok; ++s) ok = corr_push(ctx, nullptr) == CORR_OK;
         ok = ok && hipEventRecord(e0, st) == hipSuccess;
@@ -148,9 +149,28 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
         float ms = 0.f;
         if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
         corr_destroy(ctx);
-        if (ok && ms < best) {
+        return ok ? (double)ms : -1.0;
+    };
+    double best = 1e300;
+    corr_tuning best_t{};
+    for (const corr_tuning &cand : cands) {
+        const double ms = trial_ms(cand);
+        if (ms >= 0.0 && ms < best) {
             best = ms;
             best_t = cand;
+        }
+    }
+    // Producers next to sample-fed groups: also try overlapping them on a
+    // forked stream with the best shape.
+    bool producer = false, sampled = false;
+    for (int i = 0; i < n_groups; ++i) (groups[i].source == CORR_SRC_SAMPLES ? sampled : producer) = true;
+    if (best < 1e300 && producer && sampled) {
+        corr_tuning ov = best_t;
+        ov.overlap_producers = 1;
+        const double ms = trial_ms(ov);
+        if (ms >= 0.0 && ms < best) {
+            best = ms;
+            best_t = ov;
         }
     }
     (void)hipEventDestroy(e0);

@@ -212,6 +212,8 @@ int validate_tuning(const corr_tuning &t)
         return set_err(nullptr, CORR_E_INVALID, "tuning: tile_channels %d invalid for %d channels/thread",
                        t.tile_channels, cpt);
     if (t.grid_blocks < 0) return set_err(nullptr, CORR_E_INVALID, "tuning: grid_blocks < 0");
+    if (t.overlap_producers != 0 && t.overlap_producers != 1)
+        return set_err(nullptr, CORR_E_INVALID, "tuning: overlap_producers must be 0 or 1");
     return CORR_OK;
 }
 
@@ -377,7 +379,8 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
     for (size_t i = 0; i < ng; ++i) resolved[i] = c->groups[i].rhok ? c->groups[i].rhok_out : src[i];
     // Events are only recorded on direct launches, never while capturing.
     const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream;
-    const bool fork = !c->side_set.empty() && (!c->main_set.empty() || !c->deferred_set.empty());
+    const bool fork = c->tuning.overlap_producers && !c->side_set.empty() &&
+                      (!c->main_set.empty() || !c->deferred_set.empty());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         int rc = next_events(c, 0, &e0, &e1);
@@ -521,10 +524,12 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         if (rc != CORR_OK) return rc;
     }
     // Default launch shape: 512-channel tiles, 2 channels per thread (256-thread
-    // blocks), 8 lags per load batch, a persistent grid of 8 blocks per CU.
-    corr_tuning tn{512, 2, 8, 2048};
+    // blocks), 8 lags per load batch, a persistent grid of 8 blocks per CU,
+    // producers on the context's stream.
+    corr_tuning tn{512, 2, 8, 2048, 0};
     const bool given = tuning && (tuning->tile_channels || tuning->chans_per_thread ||
-                                  tuning->lag_chunk || tuning->grid_blocks);
+                                  tuning->lag_chunk || tuning->grid_blocks ||
+                                  tuning->overlap_producers);
     if (!given) {
         // the autotuner's cached choice for these groups, if any
         corr_tuning cached{};

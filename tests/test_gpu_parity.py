@@ -221,15 +221,17 @@ def test_batched_mixed_groups_and_modes(corrmod, rhok_valu):
     for s in range(S):
         orh.push(oracle.rhok(xp[s], kv, box))
     results = {}
-    for mode in ("batched", "per_group", "graph"):
+    for mode in ("batched", "per_group", "graph", "overlap", "overlap_graph"):
         say(f"  mode {mode}")
-        with corrmod.Correlator(groups, graph=(mode == "graph"), per_group=(mode == "per_group"),
-                                rhok_valu=rhok_valu) as c:
+        tuning = {"overlap_producers": 1} if mode.startswith("overlap") else None
+        with corrmod.Correlator(groups, graph=mode.endswith("graph"),
+                                per_group=(mode == "per_group"), rhok_valu=rhok_valu,
+                                tuning=tuning) as c:
             dev = torch.device("cuda:0")
             tv = torch.from_numpy(xv).to(dev)
             tg = torch.from_numpy(xg).to(dev)
             tp = torch.from_numpy(xp).to(dev)
-            if mode == "graph":
+            if mode.endswith("graph"):
                 bv = torch.empty_like(tv[0]); bp = torch.empty_like(tp[0]); bg = torch.empty_like(tg[0])
                 c.bind_input(0, bv); c.bind_input(1, bp); c.bind_input(2, bg)
                 for s in range(S):
@@ -239,7 +241,7 @@ def test_batched_mixed_groups_and_modes(corrmod, rhok_valu):
                 for s in range(S):
                     c.push([tv[s], tp[s], tg[s]])
             results[mode] = [c.finalize(g, slice_=(0, 5)) for g in range(3)]
-    for mode in ("per_group", "graph"):
+    for mode in ("per_group", "graph", "overlap", "overlap_graph"):
         for g in range(3):
             assert np.array_equal(results[mode][g]["c"], results["batched"][g]["c"]), (mode, g)
             assert np.array_equal(results[mode][g]["c_per_channel"],
