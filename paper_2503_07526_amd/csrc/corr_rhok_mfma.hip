@@ -58,8 +58,14 @@ constexpr int kMfmaTileAtoms = 64; // atoms per LDS tile
 constexpr int kMfmaKSteps = kMfmaTileAtoms / kKStep;
 constexpr int kTabStride = kMfmaTileAtoms + 2; // float2 per table row (4-bank shift)
 constexpr int kMfmaMaxWaves = 12;  // waves per block (one M tile each)
-constexpr int kTableTasks = 3 * kMfmaTileAtoms; // (axis, atom) tasks per tile
-constexpr int kMfmaMinWaves = kTableTasks / 64; // every task has its own thread
+// Table tasks per tile: (power part, axis, atom).  With three weight sets the
+// Z task carries three times the work, so every axis's powers are split in
+// two parts on separate threads; a single set keeps one part per axis.
+template <int NW> struct TableShape {
+    static constexpr int parts = NW == 1 ? 1 : 2;
+    static constexpr int tasks = parts * 3 * kMfmaTileAtoms;
+    static constexpr int min_waves = tasks / 64; // every task has its own thread
+};
 constexpr int kMfmaCols = 16;      // |n_z| = 0 .. 15
 constexpr int kRoots = 64;         // e^{2 pi i q / kRoots} table for the base phase
 // B fragments in LDS: [K-step][part: re hi, re lo, im hi, im lo][atom group][column]
@@ -134,26 +140,37 @@ struct TileBufs {
     halfv_t *bfr;   // [NW][kBFrags]
 };
 
-// Build the tables of one tile: task (axis d, atom j), base phase from
-// unit_phase, powers by a double recurrence, each rounded once; X and Y rows
-// for both signs, and for each weight set w the products w * Z^{0..nmax}
-// split into fp16 hi/lo B fragments (NW = 1: w = 1; NW = 3: the atom's
-// velocity components).  Atoms past the end (live == false) get zero
-// entries, so they add nothing.
+// Build the tables of one tile.  Task (power part hf, axis d, atom j): with
+// two parts, part 0 takes n = 0 .. n1 and part 1 takes n = n1+1 .. nmax
+// starting from its own e^{2 pi i n1 x / L} (both from unit_phase).  Powers
+// by a double recurrence, each rounded once; X and Y rows for both signs, and
+// for each weight set w the products w * Z^n split into fp16 hi/lo B
+// fragments (NW = 1: w = 1; NW = 3: the atom's velocity components).  Atoms
+// past the end (live == false) get zero entries, so they add nothing.
 template <int NW>
 __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool live, float x,
                                            const float (&w)[NW], double inv_box, int nmax,
                                            const double2 *roots)
 {
-    const int d = task / kMfmaTileAtoms, j = task - d * kMfmaTileAtoms;
-    double cs = 0.0, sn = 0.0;
-    if (live) unit_phase((double)x * inv_box, roots, cs, sn);
-    const double one = live ? 1.0 : 0.0;
-    double pr = one, pi = 0.0;
+    const int hf = task / (3 * kMfmaTileAtoms);
+    const int rem = task - hf * 3 * kMfmaTileAtoms;
+    const int d = rem / kMfmaTileAtoms, j = rem - d * kMfmaTileAtoms;
+    const int n1 = TableShape<NW>::parts == 1 ? nmax : (nmax + 1) / 2;
+    const int n_begin = hf == 0 ? 0 : n1 + 1, n_end = hf == 0 ? n1 : nmax;
+    const double f = (double)x * inv_box;
+    double cs = 0.0, sn = 0.0, pr = 0.0, pi = 0.0;
+    if (live) {
+        unit_phase(f, roots, cs, sn);
+        if (hf == 0) {
+            pr = 1.0;
+        } else {
+            unit_phase(f * n1, roots, pr, pi); // e^{i n1 theta}; n1 f is exact to 1 ulp
+        }
+    }
     if (d < 2) {
         float2 *colp = (d == 0 ? tb.tabx : tb.taby) + j;
-        colp[nmax * kTabStride] = make_float2((float)one, 0.f);
-        for (int n = 1; n <= nmax; ++n) {
+        if (hf == 0) colp[nmax * kTabStride] = make_float2((float)pr, 0.f);
+        for (int n = n_begin > 0 ? n_begin : 1; n <= n_end; ++n) {
             cmul(pr, pi, cs, sn);
             colp[(nmax + n) * kTabStride] = make_float2((float)pr, (float)pi);
             colp[(nmax - n) * kTabStride] = make_float2((float)pr, -(float)pi);
@@ -161,7 +178,7 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
     } else {
         const int ks = j / kKStep, g = (j % kKStep) / kAtomsPerLane, h = j % kAtomsPerLane;
         _Float16 *bh = reinterpret_cast<_Float16 *>(tb.bfr);
-        for (int n = 0; n <= nmax; ++n) {
+        for (int n = n_begin; n <= n_end; ++n) {
             if (n > 0) cmul(pr, pi, cs, sn);
 #pragma unroll
             for (int s = 0; s < NW; ++s) {
@@ -245,11 +262,12 @@ __global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kerne
     const int n_tiles =
         a_end > a_begin ? (int)((a_end - a_begin + kMfmaTileAtoms - 1) / kMfmaTileAtoms) : 0;
 
-    // table task of this thread (blockDim >= kTableTasks) and its inputs,
+    // table task of this thread (blockDim >= TableShape<NW>::tasks) and its inputs,
     // loaded one tile ahead of their use; the Z task also loads the weights
     const int task = threadIdx.x;
-    const bool builder = task < kTableTasks;
-    const int td = task / kMfmaTileAtoms, tj = task - td * kMfmaTileAtoms;
+    const bool builder = task < TableShape<NW>::tasks;
+    const int trem = task % (3 * kMfmaTileAtoms);
+    const int td = trem / kMfmaTileAtoms, tj = trem - td * kMfmaTileAtoms;
     const bool weighted = NW > 1 && td == 2;
     auto load_in = [&](int it, float &x, float (&w)[NW]) -> bool {
         const int64_t at = a_begin + (int64_t)it * kMfmaTileAtoms + tj;
@@ -470,7 +488,7 @@ template <int NW> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t
     const int maxw = MfmaShape<NW>::max_waves;
     const int chunks = (a.n_mtiles + maxw - 1) / maxw;
     int waves = (a.n_mtiles + chunks - 1) / chunks;
-    if (waves < kMfmaMinWaves) waves = kMfmaMinWaves;
+    if (waves < TableShape<NW>::min_waves) waves = TableShape<NW>::min_waves;
     hipLaunchKernelGGL(rhok_mfma_kernel<NW>, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
                        dim3(waves * 64), rhok_mfma_lds_bytes(a.nmax, NW), st, a);
     hipError_t e = hipGetLastError();
