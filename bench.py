@@ -22,6 +22,9 @@ Workloads (--config):
            the producer kernel's own roofline line
   currents longitudinal and transverse currents of the same 2048 k-vectors and
            10^6 atoms (6144 complex channels), the current producer's line
+  kgap     the long single-window form: currents and n(k) of the same k-vectors
+           and atoms, one block of 10240 points updated every 10 MD steps
+           (8192 complex channels); the correlator update's line
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -54,7 +57,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--config", default="batched",
-                    choices=["plain", "batched", "large", "rhok", "currents", "precision"])
+                    choices=["plain", "batched", "large", "rhok", "currents", "kgap", "precision"])
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the launch-shape autotuner (library defaults)")
     ap.add_argument("--precision-steps", type=int, default=1_000_000)
@@ -126,6 +129,18 @@ def workload(name):
             groups=[dict(kind="currents", n=3 * 2048, levels=16, points=32, m=2, dtype="cf32",
                          accum="kahan", n_atoms=1_000_000, box=100.0, seed=5, stream=3,
                          vtau=(20, 200), kvec=synth.kvectors(2048))])
+    if name == "kgap":
+        kv = synth.kvectors(2048)
+        return dict(
+            name="kgap: j_L, j_T and n(k) of 2048 k-vectors from 1e6 atoms, one window of p=10240 "
+                 "points (b=1), u=10, 8192 cFP32 channels compensated",
+            steps=1024, warmup=10240, dominant="push",  # timed once the window is full
+            groups=[dict(kind="currents", n=3 * 2048, levels=1, points=10240, m=2, dtype="cf32",
+                         accum="kahan", n_atoms=1_000_000, box=100.0, seed=6, stream=3,
+                         vtau=(20, 200), kvec=kv, update_every=10),
+                    dict(kind="rhok", n=2048, levels=1, points=10240, m=2, dtype="cf32",
+                         accum="kahan", n_atoms=1_000_000, box=100.0, seed=6, stream=3, kvec=kv,
+                         update_every=10, shares_positions=True)])
     raise ValueError(name)
 
 
@@ -346,7 +361,7 @@ def run(args):
 
     wl = workload(args.config)
     K = args.steps if args.steps is not None else wl["steps"]
-    W = args.warmup if args.warmup is not None else 256
+    W = args.warmup if args.warmup is not None else wl.get("warmup", 256)
     mode = args.mode or ("per_group" if args.config == "plain" else "batched")
     args.direct = args.direct or wl.get("direct", False)
     dev = torch.device("cuda:0")
@@ -355,16 +370,26 @@ def run(args):
     descs, gens, bufs = [], [], []
     chunk = max(1, min(args.chunk, K))
     for g in wl["groups"]:
-        if g["kind"] == "currents":
+        if g.get("shares_positions"):
+            # positions are the first [3][N] floats of the previous group's input
+            descs.append(GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype=g["dtype"],
+                                   accum=g["accum"], source="rhok", kvec=g["kvec"],
+                                   n_atoms=g["n_atoms"], box=g["box"],
+                                   update_every=g.get("update_every", 1)))
+            gens.append(None)
+            bufs.append(bufs[-1])
+        elif g["kind"] == "currents":
             descs.append(GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype=g["dtype"],
                                    accum=g["accum"], source="currents", kvec=g["kvec"],
-                                   n_atoms=g["n_atoms"], box=g["box"]))
+                                   n_atoms=g["n_atoms"], box=g["box"],
+                                   update_every=g.get("update_every", 1)))
             gens.append(CurrentsInput(g))
             bufs.append(torch.empty((chunk, 6, g["n_atoms"]), dtype=torch.float32, device=dev))
         elif g["kind"] == "rhok":
             descs.append(GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype=g["dtype"],
                                    accum=g["accum"], source="rhok", kvec=g["kvec"],
-                                   n_atoms=g["n_atoms"], box=g["box"]))
+                                   n_atoms=g["n_atoms"], box=g["box"],
+                                   update_every=g.get("update_every", 1)))
             spec = synth.PositionSpec(g["seed"], g["stream"], g["n_atoms"], g["box"], 0.1, 50.0)
             gens.append(synth.GpuPositions(spec))
             bufs.append(torch.empty((chunk, 3, g["n_atoms"]), dtype=torch.float32, device=dev))
@@ -393,7 +418,8 @@ def run(args):
 
     def push_chunk(n):
         for gen, buf in zip(gens, bufs):
-            gen.fill(buf, n)
+            if gen is not None:
+                gen.fill(buf, n)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for j in range(n):
@@ -409,6 +435,7 @@ def run(args):
         done += n
     corr.kernel_time(0, reset=True)
     corr.kernel_time(1, reset=True)
+    corr.kernel_time(2, reset=True)
     s_first = W + 1
     wall = 0.0
     done = 0
@@ -434,8 +461,19 @@ def run(args):
     rk_ms, rk_n = corr.kernel_time(which=2)
     n_total = sum(g["n"] for g in wl["groups"])
     value = n_total * K / wall
-    rhok_only = all(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
-    if rhok_only:
+    rhok_only = (all(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
+                 and wl.get("dominant") != "push")
+    push_dominant = wl.get("dominant") == "push"
+    if push_dominant:
+        # the per-step correlator update of every group (direct form): the
+        # push events minus the producer launches they contain
+        push_ms = (kern_ms - rk_ms) / K
+        push_bytes_step = sum(step_bytes(g, s) for g in wl["groups"] for s in steps) / K
+        achieved = push_bytes_step / (push_ms * 1e-3) / 1e9
+        kname = ("push kernel (per-step update of every channel's window), HIP events per push "
+                 "less the producer launches")
+        per_launch_ms, per_launch_bytes = push_ms, push_bytes_step
+    elif rhok_only:
         g0 = wl["groups"][0]
         if g0["kind"] == "currents":
             flop_per = CURRENTS_FLOP_PER_ATOM_K * (g0["n"] // 3) * g0["n_atoms"]
@@ -507,7 +545,7 @@ def run(args):
                 "ratio": tb / float(rec["alg_bytes_per_launch"]),
                 "pushes": rec["pushes"], "source": f"profiles/flush_traffic_{args.config}.md"}
     out["config"]["autotune_s"] = round(tune_s, 2)
-    if not rhok_only:
+    if max(wl["groups"], key=lambda x: x["n"])["kind"] == "ou":
         out["error_vs_fp64"] = spot_check(corr, wl, W + K)
     corr.close()
     if args.compare_plain:

@@ -12,6 +12,8 @@ hipError_t launch_push_batched(const PushArgs &a, int cpt, int lch, int grid, in
                                hipStream_t st);
 hipError_t launch_push_group(const GroupArgs &g, const int64_t *step, int cpt, int lch, int block,
                              hipStream_t st);
+hipError_t launch_push_window(const GroupArgs &g, const int64_t *step, int cpt, int lch,
+                              int block, int lags_per_block, hipStream_t st);
 hipError_t launch_step_increment(int64_t *step, hipStream_t st);
 hipError_t launch_rhok(const RhokArgs &a, hipStream_t st);
 int rhok_tile_atoms(int nmax);

@@ -341,6 +341,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     push_tile<K, CPT, LCH>(g, (int64_t)blockIdx.x, s);
 }
 
+// One-level group with a long window: one push, with the lag range split
+// over blockIdx.y (lags [y * lags_per_block, ...)) so that the grid has
+// enough blocks when there are few channels.  Lag L >= 1 reads ring slot
+// (slot - L) mod p, never the slot this push writes (that would be lag p), so
+// the chunks are independent; chunk 0 writes the new sample.
+template <int K, int CPT, int LCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void push_window_kernel(GroupArgs g, const int64_t *step, int lags_per_block)
+{
+    using S = typename KT<K>::S;
+    using A = typename KT<K>::A;
+    const int64_t s = *step + 1;
+    const int64_t tile = blockIdx.x;
+    const int tw = g.tw, p = g.p;
+    const int lane_off = (int)threadIdx.x * CPT;
+    const int64_t ch0 = tile * (int64_t)tw + lane_off;
+    S x[CPT];
+    const S *src = static_cast<const S *>(g.samples);
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) x[i] = (ch0 + i < g.n_ch) ? src[ch0 + i] : szero<S>();
+    char *tb = g.state + tile * g.tile_bytes;
+    const int64_t rowS = (int64_t)tw * (int64_t)sizeof(S);
+    S *ring = reinterpret_cast<S *>(tb);
+    A *hi = reinterpret_cast<A *>(tb + (int64_t)p * rowS);
+    A *lo = hi + (size_t)p * tw;
+    const int slot = (int)((s - 1) % p);
+    if (blockIdx.y == 0) vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, x);
+    const int nlag = (int)(s < p ? s : p);
+    const int l_begin = (int)blockIdx.y * lags_per_block;
+    const int l_end = l_begin + lags_per_block < nlag ? l_begin + lags_per_block : nlag;
+    if (l_begin < l_end) lag_loop<K, CPT, LCH>(x, ring, hi, lo, slot, p, l_begin, l_end, 0, tw, lane_off);
+}
+
 __global__ void step_increment_kernel(int64_t *step)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *step = *step + 1;
@@ -393,6 +425,37 @@ hipError_t launch_push_group(const GroupArgs &g, const int64_t *step, int cpt, i
     if (cpt == 2 && lch == 4) return launch_group_t<2, 4>(g, step, block, st);
     if (cpt == 4 && lch == 4) return launch_group_t<4, 4>(g, step, block, st);
     if (cpt == 4 && lch == 8) return launch_group_t<4, 8>(g, step, block, st);
+    return hipErrorInvalidValue;
+}
+
+template <int CPT, int LCH>
+static hipError_t launch_window_t(const GroupArgs &g, const int64_t *step, int block,
+                                  int lags_per_block, hipStream_t st)
+{
+    const dim3 grid((unsigned)g.n_tiles, (unsigned)((g.p + lags_per_block - 1) / lags_per_block));
+    switch (g.kind) {
+    case K_F32_F64: hipLaunchKernelGGL((push_window_kernel<K_F32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F32_KAHAN: hipLaunchKernelGGL((push_window_kernel<K_F32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F32_F32: hipLaunchKernelGGL((push_window_kernel<K_F32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F64_F64: hipLaunchKernelGGL((push_window_kernel<K_F64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_CF32_F64: hipLaunchKernelGGL((push_window_kernel<K_CF32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_CF32_KAHAN: hipLaunchKernelGGL((push_window_kernel<K_CF32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_CF32_F32: hipLaunchKernelGGL((push_window_kernel<K_CF32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    default: hipLaunchKernelGGL((push_window_kernel<K_CF64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_push_window(const GroupArgs &g, const int64_t *step, int cpt, int lch,
+                              int block, int lags_per_block, hipStream_t st)
+{
+    if (lags_per_block < 1 || g.levels != 1) return hipErrorInvalidValue;
+    if (cpt == 1 && lch == 16) return launch_window_t<1, 16>(g, step, block, lags_per_block, st);
+    if (cpt == 1 && lch == 8) return launch_window_t<1, 8>(g, step, block, lags_per_block, st);
+    if (cpt == 2 && lch == 8) return launch_window_t<2, 8>(g, step, block, lags_per_block, st);
+    if (cpt == 2 && lch == 4) return launch_window_t<2, 4>(g, step, block, lags_per_block, st);
+    if (cpt == 4 && lch == 4) return launch_window_t<4, 4>(g, step, block, lags_per_block, st);
+    if (cpt == 4 && lch == 8) return launch_window_t<4, 8>(g, step, block, lags_per_block, st);
     return hipErrorInvalidValue;
 }
 

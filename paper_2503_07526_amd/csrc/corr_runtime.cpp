@@ -191,7 +191,7 @@ int validate(const corr_group_desc &g, int idx)
                                    "group %d: currents need k-vector components within +-15", idx);
         }
     }
-    if (g.points > 4096) return set_err(nullptr, CORR_E_UNSUPPORTED, "group %d: p > 4096", idx);
+    if (g.points > 16384) return set_err(nullptr, CORR_E_UNSUPPORTED, "group %d: p > 16384", idx);
     if (g.levels > 40) return set_err(nullptr, CORR_E_UNSUPPORTED, "group %d: b > 40", idx);
     return CORR_OK;
 }
@@ -346,8 +346,16 @@ int catch_up_flushes(corr_ctx *c, int gi)
     return CORR_OK;
 }
 
+// One-level groups with at least this many points take the window kernel,
+// which also splits the lag range over the grid (kWindowLags lags per block).
+constexpr int kWindowMinP = 512;
+constexpr int kWindowLags = 256;
+
+bool is_window(const GroupArgs &g) { return g.levels == 1 && g.p >= kWindowMinP && !g.deferred; }
+
 // Push kernel launch(es) for the groups of one set (batched: one launch;
-// per-group form: one launch per group).
+// per-group form: one launch per group; long one-level windows: one window
+// launch each).
 int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
                const std::vector<const void *> &resolved, hipStream_t st)
 {
@@ -355,6 +363,26 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
     for (size_t j = 0; j < idx.size(); ++j) a.g[j].samples = resolved[(size_t)idx[j]];
     const int cpt = c->tuning.chans_per_thread, lch = c->tuning.lag_chunk;
     const int block = c->tuning.tile_channels / cpt;
+    {
+        // take the window groups out of the batched / per-group launch
+        PushArgs rest = a;
+        int n = 0;
+        int64_t tf = 0;
+        for (int i = 0; i < a.n_groups; ++i) {
+            if (is_window(a.g[i])) {
+                HIP_TRY(c, launch_push_window(a.g[i], c->d_step, cpt, lch, block, kWindowLags, st));
+                continue;
+            }
+            rest.g[n] = a.g[i];
+            rest.g[n].tile_first = tf;
+            tf += a.g[i].n_tiles;
+            ++n;
+        }
+        if (n == 0) return CORR_OK;
+        rest.n_groups = n;
+        rest.total_tiles = tf;
+        a = rest;
+    }
     if (c->flags & CORR_FLAG_PER_GROUP) {
         for (int i = 0; i < a.n_groups; ++i)
             HIP_TRY(c, launch_push_group(a.g[i], c->d_step, cpt, lch, block, st));

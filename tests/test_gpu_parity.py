@@ -461,3 +461,23 @@ def test_currents_with_other_groups_all_launch_modes(corrmod):
         orh.push(oracle.rhok(pos[s], kv, box))
     gate(out["batched"][1], orh, TOL[("cf32", "kahan")], scale=1.0 / N, slice_=(0, 6),
          label="rho(k) beside currents")
+
+
+@pytest.mark.parametrize("dtype,accum", [("cf32", "kahan"), ("f32", "f64"), ("f64", "f64")])
+def test_large_window(corrmod, dtype, accum):
+    """One block of p = 10240 points updated every push (the paper's long
+    single-window correlations, p = 10240 with u = 10): parity with the oracle
+    after the ring has wrapped; lag times carry u = 10."""
+    n, S, p = 16, 10500, 10240
+    say(f"[large window] n={n} S={S} p={p} {dtype}/{accum}")
+    x = ou_inputs(31, 2, n, S, dtype, tau=200.0, tau_hi=None)
+    o = oracle_run(x, 1, p, 2)
+    with corrmod.Correlator([corrmod.GroupDesc(n, 1, p, 2, dtype=dtype, accum=accum,
+                                               update_every=10, dt=0.001)]) as c:
+        _push_all(c, [x])
+        res = c.finalize(0, slice_=(0, 4))
+    t, _, _ = o.readout()
+    np.testing.assert_allclose(res["t"], t * 10 * 0.001, rtol=1e-15)
+    res["t"] = t  # the oracle reports steps
+    e = gate(res, o, TOL[(dtype, accum)], slice_=(0, 4), label="large window")
+    say(f"  error {e:.2e}")

@@ -22,6 +22,8 @@ CASES = [
     (300, 8, 16, 2),
     (513, 3, 32, 2),
     (1024, 10, 16, 2),
+    (2600, 1, 1000, 2),  # one long window that wraps (the large-p form)
+    (1500, 2, 1200, 2),
 ]
 
 
