@@ -59,6 +59,8 @@ def lib():
         L.oracle_trapezoid.restype = dbl
         L.oracle_rhok.argtypes = [vp, i64, vp, i32, dbl, vp, vp]
         L.oracle_rhok.restype = None
+        L.oracle_push_pair.argtypes = [vp, vp, vp, vp, vp]
+        L.oracle_push_pair.restype = i32
         L.oracle_currents.argtypes = [vp, vp, i64, vp, i32, dbl, vp, vp]
         L.oracle_currents.restype = i32
         _lib = L
@@ -100,6 +102,26 @@ class OracleCorrelator:
             raise ValueError(f"expected {self.n_ch} samples, got {re.shape}")
         if lib().oracle_push(self._h, _ptr(re), _ptr(im)) != 0:
             raise RuntimeError("oracle_push failed")
+
+    def _planes(self, x):
+        x = np.asarray(x)
+        if self.complex:
+            xc = x.astype(np.complex128)
+            re, im = np.ascontiguousarray(xc.real), np.ascontiguousarray(xc.imag)
+        else:
+            if np.iscomplexobj(x):
+                raise TypeError("complex samples pushed into a real correlator")
+            re, im = np.ascontiguousarray(x, dtype=np.float64), None
+        if re.shape != (self.n_ch,):
+            raise ValueError(f"expected {self.n_ch} samples, got {re.shape}")
+        return re, im
+
+    def push_pair(self, x, y) -> None:
+        """Pair form of Algorithm 1: C(L) = <x(s) conj(y(s - L))> per channel."""
+        xr, xi = self._planes(x)
+        yr, yi = self._planes(y)
+        if lib().oracle_push_pair(self._h, _ptr(xr), _ptr(xi), _ptr(yr), _ptr(yi)) != 0:
+            raise RuntimeError("oracle_push_pair failed (a record is auto or pair from its first push)")
 
     def push_series(self, xs) -> None:
         """xs: [S][n_ch] -- push S steps in order."""

@@ -10,6 +10,9 @@
  * with the GPU library, and the GPU library never calls it.
  *
  * Everything is double precision (complex double for complex observables).
+ * A record correlates each channel with itself (oracle_push) or, in the pair
+ * form of Algorithm 1, a first value x with a second value y
+ * (oracle_push_pair): C(L) = <x(s) conj(y(s - L))>.
  * One independent correlator record per channel, updated recursively exactly
  * in the order Algorithm 1 gives (ring write, accumulate, cascade, lag loop,
  * cursor advance).  Where the printed algorithm is ambiguous the following
@@ -78,6 +81,10 @@ struct oracle_corr {
     cplx *acc;      /* [n_ch][b] */
     int *nacc;      /* [n_ch][b] */
     int *used;      /* [n_ch] */
+    /* pair form (Algorithm 1 with x != y): ring and acc above hold y, these
+     * hold x; allocated by the first oracle_push_pair */
+    cplx *ringx;    /* [n_ch][b][p] */
+    cplx *accx;     /* [n_ch][b] */
 };
 
 static size_t idx_bp(const oracle_corr *o, int64_t c, int k, int l)
@@ -132,6 +139,8 @@ void oracle_destroy(oracle_corr *o)
     free(o->acc);
     free(o->nacc);
     free(o->used);
+    free(o->ringx);
+    free(o->accx);
     free(o);
 }
 
@@ -171,9 +180,80 @@ static void update(oracle_corr *o, int64_t c, cplx v, int k)
     o->cursor[kb] = (cur + 1) % p;
 }
 
+/* Algorithm 1 with a pair of values: ring entry and block accumulator carry
+ * (x, y), the block mean of both is passed down, and the lag product is the
+ * newest x times conj(the lagged y) (R4), so C(L) = <x(s) conj(y(s - L))>. */
+static void update_pair(oracle_corr *o, int64_t c, cplx x, cplx y, int k)
+{
+    const int p = o->points;
+    const int m = o->m;
+    if (k >= o->levels)
+        return;
+    if (o->used[c] < k + 1)
+        o->used[c] = k + 1;
+
+    size_t kb = idx_b(o, c, k);
+    int cur = o->cursor[kb];
+    o->ringx[idx_bp(o, c, k, cur)] = x;
+    o->ring[idx_bp(o, c, k, cur)] = y;
+    if (o->filled[kb] < p) /* R1 */
+        o->filled[kb] += 1;
+
+    o->accx[kb] += x;
+    o->acc[kb] += y;
+    o->nacc[kb] += 1;
+    if (o->nacc[kb] == m) { /* R2 */
+        cplx ax = o->accx[kb] / (double)m;
+        cplx ay = o->acc[kb] / (double)m;
+        update_pair(o, c, ax, ay, k + 1);
+        o->accx[kb] = 0.0;
+        o->acc[kb] = 0.0;
+        o->nacc[kb] = 0;
+    }
+
+    int lag0 = (k == 0) ? 0 : p / m;
+    for (int L = lag0; L < p && L < o->filled[kb]; ++L) {
+        int slot = ((cur - L) % p + p) % p;
+        cplx r = o->ring[idx_bp(o, c, k, slot)];
+        o->sums[idx_bp(o, c, k, L)] += x * conj(r); /* R4 */
+        o->cnt[idx_bp(o, c, k, L)] += 1;
+    }
+    o->cursor[kb] = (cur + 1) % p;
+}
+
+int oracle_push_pair(oracle_corr *o, const double *x_re, const double *x_im, const double *y_re,
+                     const double *y_im)
+{
+    if (!o || !x_re || !y_re)
+        return -1;
+    if (o->is_complex && (!x_im || !y_im))
+        return -1;
+    if (!o->ringx) {
+        if (o->n_push > 0) /* a record is either auto or pair from its first push */
+            return -1;
+        size_t nbp = (size_t)o->n_ch * (size_t)o->levels * (size_t)o->points;
+        o->ringx = (cplx *)calloc(nbp, sizeof(cplx));
+        o->accx = (cplx *)calloc((size_t)o->n_ch * (size_t)o->levels, sizeof(cplx));
+        if (!o->ringx || !o->accx)
+            return -1;
+    }
+    for (int64_t c = 0; c < o->n_ch; ++c) {
+        cplx x = x_re[c], y = y_re[c];
+        if (o->is_complex) {
+            x = x_re[c] + x_im[c] * I;
+            y = y_re[c] + y_im[c] * I;
+        }
+        update_pair(o, c, x, y, 0);
+    }
+    o->n_push += 1;
+    return 0;
+}
+
 int oracle_push(oracle_corr *o, const double *x_re, const double *x_im)
 {
     if (!o || !x_re)
+        return -1;
+    if (o->ringx) /* pair record */
         return -1;
     if (o->is_complex && !x_im)
         return -1;

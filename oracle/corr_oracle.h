@@ -32,6 +32,8 @@ int oracle_raw(const oracle_corr *o, int64_t ch, double *sum_re, double *sum_im,
 double oracle_trapezoid(int n, const double *t, const double *c, double t_cut, double *running);
 void oracle_rhok(const float *pos, int64_t n_atoms, const int32_t *kvec, int n_k, double box,
                  double *re, double *im);
+int oracle_push_pair(oracle_corr *o, const double *x_re, const double *x_im, const double *y_re,
+                     const double *y_im);
 int oracle_currents(const float *pos, const float *vel, int64_t n_atoms, const int32_t *kvec,
                     int n_k, double box, double *re, double *im);
 

@@ -55,6 +55,24 @@ def multitau_bruteforce(x: np.ndarray, levels: int, points: int, m: int):
     return np.array(ts, dtype=np.float64), np.array(cs), np.array(ns, dtype=np.int64)
 
 
+def multitau_bruteforce_pair(x: np.ndarray, y: np.ndarray, levels: int, points: int, m: int):
+    """The same closed definition for a pair of series (the x, y form of
+    Algorithm 1): both are block-averaged level by level and
+    C_k(L) = 1/(S_k - L) * sum_{i=L}^{S_k-1} x_k[i] * conj(y_k[i-L])."""
+    xs, ys = np.asarray(x), np.asarray(y)
+    ts, cs, ns = [], [], []
+    for k in range(levels):
+        lag0 = 0 if k == 0 else points // m
+        S = xs.shape[0]
+        for L in range(lag0, points):
+            if S > L:
+                ts.append(L * m**k)
+                cs.append((xs[L:] * np.conj(ys[: S - L])).sum(axis=0) / (S - L))
+                ns.append(S - L)
+        xs, ys = block_average(xs, m), block_average(ys, m)
+    return np.array(ts, dtype=np.float64), np.array(cs), np.array(ns, dtype=np.int64)
+
+
 def ou_level_expectation(a: float, var: float, k: int, m: int, L: int) -> float:
     """E[C_k(L)] for a stationary AR(1)/OU series with autocorrelation a^|l| and
     variance var, after block averaging over M = m^k samples (derived from the

@@ -92,3 +92,53 @@ def test_max_lag_and_point_count(oracle_mod):
         assert len(t) == p + (b - 1) * (p - p // m)
         if p % m == 0:
             assert np.all(np.diff(t) > 0)
+
+
+@pytest.mark.parametrize("S,b,p,m", CASES)
+@pytest.mark.parametrize("complex_", [False, True])
+def test_oracle_pair_matches_bruteforce(oracle_mod, S, b, p, m, complex_):
+    """Pair form: C(L) = <x(s) conj(y(s - L))> with both series block-averaged."""
+    from tests.bruteforce import multitau_bruteforce_pair
+    rng = np.random.default_rng(7000 * S + 10 * p + m + complex_)
+    n_ch = 3
+    x = rng.standard_normal((S, n_ch))
+    y = 0.5 * x + rng.standard_normal((S, n_ch))
+    if complex_:
+        x = x + 1j * rng.standard_normal((S, n_ch))
+        y = y + 1j * rng.standard_normal((S, n_ch))
+    o = oracle_mod.OracleCorrelator(n_ch, b, p, m, complex_=complex_)
+    for s in range(S):
+        o.push_pair(x[s], y[s])
+    t_bf, c_bf, n_bf = multitau_bruteforce_pair(x, y, b, p, m)
+    for ch in range(n_ch):
+        t, c, n = o.readout(ch, ch + 1)
+        assert np.array_equal(t, t_bf) and np.array_equal(n, n_bf)
+        ref = c_bf[:, ch]
+        assert np.max(np.abs(c - ref)) <= 1e-12 * np.abs(ref).max()
+
+
+def test_oracle_pair_with_itself_is_the_autocorrelation(oracle_mod):
+    """pair(x, x) equals the autocorrelation of x bit for bit (same operations
+    in the same order), and the roles of x and y are not interchangeable."""
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((700, 4)) + 1j * rng.standard_normal((700, 4))
+    y = rng.standard_normal((700, 4)) + 1j * rng.standard_normal((700, 4))
+    a = oracle_mod.OracleCorrelator(4, 5, 16, 2, complex_=True)
+    q = oracle_mod.OracleCorrelator(4, 5, 16, 2, complex_=True)
+    xy = oracle_mod.OracleCorrelator(4, 5, 16, 2, complex_=True)
+    yx = oracle_mod.OracleCorrelator(4, 5, 16, 2, complex_=True)
+    for s in range(700):
+        a.push(x[s])
+        q.push_pair(x[s], x[s])
+        xy.push_pair(x[s], y[s])
+        yx.push_pair(y[s], x[s])
+    ta, ca, na = a.readout()
+    tq, cq, nq = q.readout()
+    assert np.array_equal(ta, tq) and np.array_equal(na, nq) and np.array_equal(ca, cq)
+    # C_xy(0) = conj(C_yx(0)); at L > 0 the two differ (x later vs y later)
+    _, cxy, _ = xy.readout()
+    _, cyx, _ = yx.readout()
+    assert abs(cxy[0] - np.conj(cyx[0])) < 1e-12 * abs(cxy[0])
+    assert np.max(np.abs(cxy[1:] - np.conj(cyx[1:]))) > 1e-3
+    with pytest.raises(RuntimeError):
+        q.push(x[0])  # a pair record takes pairs only
