@@ -103,7 +103,14 @@ typedef struct corr_group_desc {
     int32_t accum;          /* enum corr_accum                                     */
     int32_t source;         /* enum corr_source                                    */
     int32_t update_every;   /* u >= 1: scales reported lag times only (Sec. 2.2)  */
-    int32_t reserved;
+    int32_t pair;           /* 0: each channel is correlated with itself; 1: each
+                               channel correlates a pair of observables (x, y),
+                               the x, y form of Algorithm 1 (Appendix D): both are
+                               carried through the rings and the block means and
+                               C(L) = <x(s) conj(y(s - L))>.  A push then brings
+                               [2][n_channels] samples (all x, then all y).
+                               CORR_SRC_SAMPLES only; such groups always take
+                               the per-step (direct) form                        */
     double dt;              /* simulation time step; lag time = L m^k u dt        */
     /* CORR_SRC_RHOK and CORR_SRC_CURRENTS only (ignored otherwise): */
     const int32_t *kvec;    /* host [n_k][3] integer n, k = 2 pi n / box, n_k =

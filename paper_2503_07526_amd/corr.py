@@ -37,7 +37,7 @@ class _GroupDesc(ctypes.Structure):
     _fields_ = [("n_channels", ctypes.c_int64), ("levels", ctypes.c_int32),
                 ("points", ctypes.c_int32), ("m", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("accum", ctypes.c_int32), ("source", ctypes.c_int32),
-                ("update_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("update_every", ctypes.c_int32), ("pair", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("kvec", ctypes.POINTER(ctypes.c_int32)),
                 ("n_atoms", ctypes.c_int64), ("box", ctypes.c_double)]
 
@@ -114,6 +114,7 @@ class GroupDesc:
     kvec: np.ndarray | None = None
     n_atoms: int = 0
     box: float = 0.0
+    pair: bool = False  # correlate (x, y) per channel: samples [2][n_channels]
     _kbuf: object = field(default=None, repr=False)
 
     def to_c(self) -> _GroupDesc:
@@ -121,6 +122,7 @@ class GroupDesc:
         d.n_channels, d.levels, d.points, d.m = self.n_channels, self.levels, self.points, self.m
         d.dtype, d.accum, d.source = DTYPES[self.dtype], ACCUMS[self.accum], SOURCES[self.source]
         d.update_every, d.dt = self.update_every, self.dt
+        d.pair = 1 if self.pair else 0
         if self.kvec is not None:
             self._kbuf = np.ascontiguousarray(self.kvec, dtype=np.int32)
             d.kvec = self._kbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))

@@ -51,6 +51,9 @@ struct GroupArgs {
     int32_t a_bytes;     // bytes per accumulator plane element
     int32_t deferred;    // 1: block-deferred form (pushes only stage samples)
     int32_t p0;          // ring rows of level 0 (p, or kDeferT + p when deferred)
+    int32_t pair;        // 1: channels correlate (x, y): samples [2][n_ch], and each
+                         // level holds the lagged y ring, then an x ring
+    int32_t pad_;
 };
 
 // Pushes staged between two flushes of a block-deferred group.

@@ -136,9 +136,11 @@ template <> struct Acc<K_CF64_F64> {
 // NJ consecutive lags [L0, L0 + NJ) of one level, branch-free: all loads of
 // the chunk are issued before any arithmetic so that each lane has many
 // independent memory requests in flight.  Lag L reads ring slot
-// (slot - L) mod p; lag 0 (newest value times itself) takes x from registers.
+// (slot - L) mod p of the lagged series; lag 0 takes the newest lagged value
+// y0 from registers (y0 = x for an autocorrelation).
 template <int K, int CPT, int NJ>
 __device__ __forceinline__ void lag_chunk(const typename KT<K>::S (&x)[CPT],
+                                          const typename KT<K>::S (&y0)[CPT],
                                           const typename KT<K>::S *ring, typename KT<K>::A *hi,
                                           typename KT<K>::A *lo, int slot, int p, int L0,
                                           int row_base, int tw, int lane_off)
@@ -160,7 +162,7 @@ __device__ __forceinline__ void lag_chunk(const typename KT<K>::S (&x)[CPT],
     }
     if (L0 == 0) {
 #pragma unroll
-        for (int i = 0; i < CPT; ++i) r[0][i] = x[i];
+        for (int i = 0; i < CPT; ++i) r[0][i] = y0[i];
     }
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -176,6 +178,7 @@ __device__ __forceinline__ void lag_chunk(const typename KT<K>::S (&x)[CPT],
 // Full chunks of LCH lags, then chunks of 4, then single lags.
 template <int K, int CPT, int LCH>
 __device__ __forceinline__ void lag_loop(const typename KT<K>::S (&x)[CPT],
+                                         const typename KT<K>::S (&y0)[CPT],
                                          const typename KT<K>::S *ring, typename KT<K>::A *hi,
                                          typename KT<K>::A *lo, int slot, int p, int l_begin,
                                          int l_end, int row_base, int tw, int lane_off)
@@ -183,19 +186,21 @@ __device__ __forceinline__ void lag_loop(const typename KT<K>::S (&x)[CPT],
     int L = l_begin;
 #pragma unroll 1
     for (; L + LCH <= l_end; L += LCH)
-        lag_chunk<K, CPT, LCH>(x, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
+        lag_chunk<K, CPT, LCH>(x, y0, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
     if constexpr (LCH > 4) {
 #pragma unroll 1
         for (; L + 4 <= l_end; L += 4)
-            lag_chunk<K, CPT, 4>(x, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
+            lag_chunk<K, CPT, 4>(x, y0, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
     }
 #pragma unroll 1
     for (; L < l_end; ++L)
-        lag_chunk<K, CPT, 1>(x, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
+        lag_chunk<K, CPT, 1>(x, y0, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
 }
 
-// One push of one tile of one group.  s = 1-based push index.
-template <int K, int CPT, int LCH>
+// One push of one tile of one group.  s = 1-based push index.  PAIR: the
+// group correlates (x, y) pairs (its own launches; the batched kernel only
+// instantiates the autocorrelation form).
+template <int K, int CPT, int LCH, bool PAIR = false>
 __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int64_t s)
 {
     using S = typename KT<K>::S;
@@ -207,14 +212,19 @@ __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int6
     const int64_t ch0 = tile * (int64_t)tw + lane_off;
 
     // Samples of this push; channels past the end of the group read as 0 (the
-    // state of the padded tail is allocated and never read out).
-    S x[CPT];
+    // state of the padded tail is allocated and never read out).  Pair
+    // groups: x then y planes; otherwise y is x.
+    S x[CPT], y[CPT];
     const S *src = static_cast<const S *>(g.samples);
 #pragma unroll
     for (int i = 0; i < CPT; ++i) x[i] = (ch0 + i < g.n_ch) ? src[ch0 + i] : szero<S>();
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+        y[i] = PAIR ? ((ch0 + i < g.n_ch) ? src[g.n_ch + ch0 + i] : szero<S>()) : x[i];
 
     char *tb = g.state + tile * g.tile_bytes;
     const int64_t rowS = (int64_t)tw * (int64_t)sizeof(S);
+    constexpr int rings = PAIR ? 2 : 1;
 
     if (g.deferred) {
         // Block-deferred group: only stage the sample in the level-0 ring
@@ -225,15 +235,16 @@ __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int6
         return;
     }
 
-    // Level 0: ring write and lags 0..min(s, p)-1.
+    // Level 0: ring write(s) and lags 0..min(s, p)-1.
     {
         S *ring = reinterpret_cast<S *>(tb);
-        A *hi = reinterpret_cast<A *>(tb + (int64_t)p * rowS);
+        A *hi = reinterpret_cast<A *>(tb + (int64_t)rings * p * rowS);
         A *lo = hi + (size_t)p * tw;
         const int slot = (int)((s - 1) % p);
-        vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, x);
+        vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, y);
+        if constexpr (PAIR) vstore<S, CPT>(ring + (size_t)(p + slot) * tw + lane_off, x);
         const int nlag = (int)(s < p ? s : p);
-        lag_loop<K, CPT, LCH>(x, ring, hi, lo, slot, p, 0, nlag, 0, tw, lane_off);
+        lag_loop<K, CPT, LCH>(x, y, ring, hi, lo, slot, p, 0, nlag, 0, tw, lane_off);
     }
 
     // Cascade: level k receives a value when m^k divides s.
@@ -245,46 +256,62 @@ __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int6
             ++kmax;
         }
     }
-    S vprev[CPT];
+    // vprev: the newest value of level k-1 (y series; x series of pairs in vprevx)
+    S vprev[CPT], vprevx[CPT];
 #pragma unroll
-    for (int i = 0; i < CPT; ++i) vprev[i] = x[i];
+    for (int i = 0; i < CPT; ++i) {
+        vprev[i] = y[i];
+        vprevx[i] = x[i];
+    }
     int64_t s_prev = s;
     const char *lvl_prev = tb;
     const int lag0 = g.lag0;
     const int nlk = p - lag0;
+    // Mean of the last m values of one ring of level k-1, summed oldest first
+    // (the newest is in registers).
+    auto block_mean = [&](const S *ringp, int slotp, const S (&newest)[CPT], S (&v)[CPT]) {
+        int sl = slotp - (m - 1);
+        if (sl < 0) sl += p;
+        vload<S, CPT>(ringp + (size_t)sl * tw + lane_off, v);
+#pragma unroll 1
+        for (int j = m - 2; j >= 1; --j) {
+            int sj = slotp - j;
+            if (sj < 0) sj += p;
+            S t[CPT];
+            vload<S, CPT>(ringp + (size_t)sj * tw + lane_off, t);
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) v[i] = sadd(v[i], t[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) v[i] = sdiv(sadd(v[i], newest[i]), m);
+    };
 #pragma unroll 1
     for (int k = 1; k <= kmax; ++k) {
-        // Mean of the last m values of level k-1, summed oldest first.
         const S *ringp = reinterpret_cast<const S *>(lvl_prev);
         const int slotp = (int)((s_prev - 1) % p);
-        S v[CPT];
-        {
-            int sl = slotp - (m - 1);
-            if (sl < 0) sl += p;
-            vload<S, CPT>(ringp + (size_t)sl * tw + lane_off, v);
-#pragma unroll 1
-            for (int j = m - 2; j >= 1; --j) {
-                int sj = slotp - j;
-                if (sj < 0) sj += p;
-                S t[CPT];
-                vload<S, CPT>(ringp + (size_t)sj * tw + lane_off, t);
+        S v[CPT], vx[CPT];
+        block_mean(ringp, slotp, vprev, v);
+        if constexpr (PAIR)
+            block_mean(ringp + (size_t)p * tw, slotp, vprevx, vx);
+        else {
 #pragma unroll
-                for (int i = 0; i < CPT; ++i) v[i] = sadd(v[i], t[i]);
-            }
-#pragma unroll
-            for (int i = 0; i < CPT; ++i) v[i] = sdiv(sadd(v[i], vprev[i]), m);
+            for (int i = 0; i < CPT; ++i) vx[i] = v[i];
         }
         char *lvl = tb + g.lvl0_bytes + (int64_t)(k - 1) * g.lvlk_bytes;
         S *ring = reinterpret_cast<S *>(lvl);
-        A *hi = reinterpret_cast<A *>(lvl + (int64_t)p * rowS);
+        A *hi = reinterpret_cast<A *>(lvl + (int64_t)rings * p * rowS);
         A *lo = hi + (size_t)nlk * tw;
         const int64_t sk = s_prev / m;
         const int slot = (int)((sk - 1) % p);
         vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, v);
+        if constexpr (PAIR) vstore<S, CPT>(ring + (size_t)(p + slot) * tw + lane_off, vx);
         const int nl = (int)(sk < p ? sk : p);
-        if (nl > lag0) lag_loop<K, CPT, LCH>(v, ring, hi, lo, slot, p, lag0, nl, lag0, tw, lane_off);
+        if (nl > lag0) lag_loop<K, CPT, LCH>(vx, v, ring, hi, lo, slot, p, lag0, nl, lag0, tw, lane_off);
 #pragma unroll
-        for (int i = 0; i < CPT; ++i) vprev[i] = v[i];
+        for (int i = 0; i < CPT; ++i) {
+            vprev[i] = v[i];
+            vprevx[i] = vx[i];
+        }
         s_prev = sk;
         lvl_prev = lvl;
     }
@@ -334,11 +361,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
 }
 
 // Plain form: one group per launch, one block per tile, kind fixed at compile time.
-template <int K, int CPT, int LCH>
+template <int K, int CPT, int LCH, bool PAIR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void push_group_kernel(GroupArgs g, const int64_t *step)
 {
     const int64_t s = *step + 1;
-    push_tile<K, CPT, LCH>(g, (int64_t)blockIdx.x, s);
+    push_tile<K, CPT, LCH, PAIR>(g, (int64_t)blockIdx.x, s);
 }
 
 // One-level group with a long window: one push, with the lag range split
@@ -346,7 +373,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
 // enough blocks when there are few channels.  Lag L >= 1 reads ring slot
 // (slot - L) mod p, never the slot this push writes (that would be lag p), so
 // the chunks are independent; chunk 0 writes the new sample.
-template <int K, int CPT, int LCH>
+template <int K, int CPT, int LCH, bool PAIR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void push_window_kernel(GroupArgs g, const int64_t *step, int lags_per_block)
 {
     using S = typename KT<K>::S;
@@ -356,21 +383,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     const int tw = g.tw, p = g.p;
     const int lane_off = (int)threadIdx.x * CPT;
     const int64_t ch0 = tile * (int64_t)tw + lane_off;
-    S x[CPT];
+    S x[CPT], y[CPT];
     const S *src = static_cast<const S *>(g.samples);
 #pragma unroll
     for (int i = 0; i < CPT; ++i) x[i] = (ch0 + i < g.n_ch) ? src[ch0 + i] : szero<S>();
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+        y[i] = PAIR ? ((ch0 + i < g.n_ch) ? src[g.n_ch + ch0 + i] : szero<S>()) : x[i];
     char *tb = g.state + tile * g.tile_bytes;
     const int64_t rowS = (int64_t)tw * (int64_t)sizeof(S);
+    constexpr int rings = PAIR ? 2 : 1;
     S *ring = reinterpret_cast<S *>(tb);
-    A *hi = reinterpret_cast<A *>(tb + (int64_t)p * rowS);
+    A *hi = reinterpret_cast<A *>(tb + (int64_t)rings * p * rowS);
     A *lo = hi + (size_t)p * tw;
     const int slot = (int)((s - 1) % p);
-    if (blockIdx.y == 0) vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, x);
+    if (blockIdx.y == 0) {
+        vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, y);
+        if constexpr (PAIR) vstore<S, CPT>(ring + (size_t)(p + slot) * tw + lane_off, x);
+    }
     const int nlag = (int)(s < p ? s : p);
     const int l_begin = (int)blockIdx.y * lags_per_block;
     const int l_end = l_begin + lags_per_block < nlag ? l_begin + lags_per_block : nlag;
-    if (l_begin < l_end) lag_loop<K, CPT, LCH>(x, ring, hi, lo, slot, p, l_begin, l_end, 0, tw, lane_off);
+    if (l_begin < l_end)
+        lag_loop<K, CPT, LCH>(x, y, ring, hi, lo, slot, p, l_begin, l_end, 0, tw, lane_off);
 }
 
 __global__ void step_increment_kernel(int64_t *step)
@@ -398,65 +433,81 @@ hipError_t launch_push_batched(const PushArgs &a, int cpt, int lch, int grid, in
     return hipErrorInvalidValue;
 }
 
-template <int CPT, int LCH>
+template <int CPT, int LCH, bool PAIR>
 static hipError_t launch_group_t(const GroupArgs &g, const int64_t *step, int block,
                                  hipStream_t st)
 {
     const dim3 grid((unsigned)g.n_tiles);
     switch (g.kind) {
-    case K_F32_F64: hipLaunchKernelGGL((push_group_kernel<K_F32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
-    case K_F32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_F32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
-    case K_F32_F32: hipLaunchKernelGGL((push_group_kernel<K_F32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
-    case K_F64_F64: hipLaunchKernelGGL((push_group_kernel<K_F64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
-    case K_CF32_F64: hipLaunchKernelGGL((push_group_kernel<K_CF32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
-    case K_CF32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_CF32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
-    case K_CF32_F32: hipLaunchKernelGGL((push_group_kernel<K_CF32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
-    default: hipLaunchKernelGGL((push_group_kernel<K_CF64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step); break;
+    case K_F32_F64: hipLaunchKernelGGL((push_group_kernel<K_F32_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
+    case K_F32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_F32_KAHAN, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
+    case K_F32_F32: hipLaunchKernelGGL((push_group_kernel<K_F32_F32, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
+    case K_F64_F64: hipLaunchKernelGGL((push_group_kernel<K_F64_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
+    case K_CF32_F64: hipLaunchKernelGGL((push_group_kernel<K_CF32_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
+    case K_CF32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_CF32_KAHAN, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
+    case K_CF32_F32: hipLaunchKernelGGL((push_group_kernel<K_CF32_F32, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
+    default: hipLaunchKernelGGL((push_group_kernel<K_CF64_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
     }
     return hipGetLastError();
+}
+
+template <bool PAIR>
+static hipError_t launch_push_group_p(const GroupArgs &g, const int64_t *step, int cpt, int lch,
+                                      int block, hipStream_t st)
+{
+    if (cpt == 1 && lch == 16) return launch_group_t<1, 16, PAIR>(g, step, block, st);
+    if (cpt == 1 && lch == 8) return launch_group_t<1, 8, PAIR>(g, step, block, st);
+    if (cpt == 2 && lch == 8) return launch_group_t<2, 8, PAIR>(g, step, block, st);
+    if (cpt == 2 && lch == 4) return launch_group_t<2, 4, PAIR>(g, step, block, st);
+    if (cpt == 4 && lch == 4) return launch_group_t<4, 4, PAIR>(g, step, block, st);
+    if (cpt == 4 && lch == 8) return launch_group_t<4, 8, PAIR>(g, step, block, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_push_group(const GroupArgs &g, const int64_t *step, int cpt, int lch, int block,
                              hipStream_t st)
 {
-    if (cpt == 1 && lch == 16) return launch_group_t<1, 16>(g, step, block, st);
-    if (cpt == 1 && lch == 8) return launch_group_t<1, 8>(g, step, block, st);
-    if (cpt == 2 && lch == 8) return launch_group_t<2, 8>(g, step, block, st);
-    if (cpt == 2 && lch == 4) return launch_group_t<2, 4>(g, step, block, st);
-    if (cpt == 4 && lch == 4) return launch_group_t<4, 4>(g, step, block, st);
-    if (cpt == 4 && lch == 8) return launch_group_t<4, 8>(g, step, block, st);
-    return hipErrorInvalidValue;
+    return g.pair ? launch_push_group_p<true>(g, step, cpt, lch, block, st)
+                  : launch_push_group_p<false>(g, step, cpt, lch, block, st);
 }
 
-template <int CPT, int LCH>
+template <int CPT, int LCH, bool PAIR>
 static hipError_t launch_window_t(const GroupArgs &g, const int64_t *step, int block,
                                   int lags_per_block, hipStream_t st)
 {
     const dim3 grid((unsigned)g.n_tiles, (unsigned)((g.p + lags_per_block - 1) / lags_per_block));
     switch (g.kind) {
-    case K_F32_F64: hipLaunchKernelGGL((push_window_kernel<K_F32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
-    case K_F32_KAHAN: hipLaunchKernelGGL((push_window_kernel<K_F32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
-    case K_F32_F32: hipLaunchKernelGGL((push_window_kernel<K_F32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
-    case K_F64_F64: hipLaunchKernelGGL((push_window_kernel<K_F64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
-    case K_CF32_F64: hipLaunchKernelGGL((push_window_kernel<K_CF32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
-    case K_CF32_KAHAN: hipLaunchKernelGGL((push_window_kernel<K_CF32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
-    case K_CF32_F32: hipLaunchKernelGGL((push_window_kernel<K_CF32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
-    default: hipLaunchKernelGGL((push_window_kernel<K_CF64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F32_F64: hipLaunchKernelGGL((push_window_kernel<K_F32_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F32_KAHAN: hipLaunchKernelGGL((push_window_kernel<K_F32_KAHAN, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F32_F32: hipLaunchKernelGGL((push_window_kernel<K_F32_F32, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F64_F64: hipLaunchKernelGGL((push_window_kernel<K_F64_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_CF32_F64: hipLaunchKernelGGL((push_window_kernel<K_CF32_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_CF32_KAHAN: hipLaunchKernelGGL((push_window_kernel<K_CF32_KAHAN, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_CF32_F32: hipLaunchKernelGGL((push_window_kernel<K_CF32_F32, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    default: hipLaunchKernelGGL((push_window_kernel<K_CF64_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
     }
     return hipGetLastError();
+}
+
+template <bool PAIR>
+static hipError_t launch_push_window_p(const GroupArgs &g, const int64_t *step, int cpt, int lch,
+                                       int block, int lags_per_block, hipStream_t st)
+{
+    if (cpt == 1 && lch == 16) return launch_window_t<1, 16, PAIR>(g, step, block, lags_per_block, st);
+    if (cpt == 1 && lch == 8) return launch_window_t<1, 8, PAIR>(g, step, block, lags_per_block, st);
+    if (cpt == 2 && lch == 8) return launch_window_t<2, 8, PAIR>(g, step, block, lags_per_block, st);
+    if (cpt == 2 && lch == 4) return launch_window_t<2, 4, PAIR>(g, step, block, lags_per_block, st);
+    if (cpt == 4 && lch == 4) return launch_window_t<4, 4, PAIR>(g, step, block, lags_per_block, st);
+    if (cpt == 4 && lch == 8) return launch_window_t<4, 8, PAIR>(g, step, block, lags_per_block, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_push_window(const GroupArgs &g, const int64_t *step, int cpt, int lch,
                               int block, int lags_per_block, hipStream_t st)
 {
     if (lags_per_block < 1 || g.levels != 1) return hipErrorInvalidValue;
-    if (cpt == 1 && lch == 16) return launch_window_t<1, 16>(g, step, block, lags_per_block, st);
-    if (cpt == 1 && lch == 8) return launch_window_t<1, 8>(g, step, block, lags_per_block, st);
-    if (cpt == 2 && lch == 8) return launch_window_t<2, 8>(g, step, block, lags_per_block, st);
-    if (cpt == 2 && lch == 4) return launch_window_t<2, 4>(g, step, block, lags_per_block, st);
-    if (cpt == 4 && lch == 4) return launch_window_t<4, 4>(g, step, block, lags_per_block, st);
-    if (cpt == 4 && lch == 8) return launch_window_t<4, 8>(g, step, block, lags_per_block, st);
-    return hipErrorInvalidValue;
+    return g.pair ? launch_push_window_p<true>(g, step, cpt, lch, block, lags_per_block, st)
+                  : launch_push_window_p<false>(g, step, cpt, lch, block, lags_per_block, st);
 }
 
 hipError_t launch_step_increment(int64_t *step, hipStream_t st)

@@ -32,6 +32,7 @@ struct Group {
     int s_bytes = 0, a_bytes = 0, np = 1;
     bool deferred = false; // block-deferred form (stage per push, staggered flushes)
     int p0 = 0;            // ring rows of level 0
+    bool pair = false;     // channels correlate (x, y) pairs
     int64_t *d_flushed = nullptr;                // [kFlushGroups] blocks folded per tile group
     std::vector<int64_t> flushed;                // host mirror of d_flushed
     int64_t tiles_per_group = 0;
@@ -165,6 +166,8 @@ int validate(const corr_group_desc &g, int idx)
         return bad("unknown source");
     if ((g.dtype == CORR_F64 || g.dtype == CORR_CF64) && g.accum != CORR_ACC_F64)
         return bad("double samples need double accumulators");
+    if (g.pair != 0 && g.pair != 1) return bad("pair must be 0 or 1");
+    if (g.pair && g.source != CORR_SRC_SAMPLES) return bad("pair groups take samples");
     if (g.source == CORR_SRC_RHOK) {
         if (g.dtype != CORR_CF32 && g.dtype != CORR_CF64) return bad("k-density needs a complex dtype");
         if (!g.kvec) return bad("k-density group without k-vectors");
@@ -364,13 +367,17 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
     const int cpt = c->tuning.chans_per_thread, lch = c->tuning.lag_chunk;
     const int block = c->tuning.tile_channels / cpt;
     {
-        // take the window groups out of the batched / per-group launch
+        // take the window and pair groups out of the batched / per-group launch
         PushArgs rest = a;
         int n = 0;
         int64_t tf = 0;
         for (int i = 0; i < a.n_groups; ++i) {
             if (is_window(a.g[i])) {
                 HIP_TRY(c, launch_push_window(a.g[i], c->d_step, cpt, lch, block, kWindowLags, st));
+                continue;
+            }
+            if (a.g[i].pair) { // pair groups have their own kernels
+                HIP_TRY(c, launch_push_group(a.g[i], c->d_step, cpt, lch, block, st));
                 continue;
             }
             rest.g[n] = a.g[i];
@@ -620,11 +627,14 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         g.n_tiles = (g.n_ch + tw - 1) / tw;
         const int64_t rowS = (int64_t)tw * g.s_bytes;
         const int64_t rowA = (int64_t)tw * g.a_bytes;
-        g.deferred = !(flags & CORR_FLAG_DIRECT) && g.d.source == CORR_SRC_SAMPLES &&
+        g.pair = g.d.pair != 0;
+        g.deferred = !(flags & CORR_FLAG_DIRECT) && g.d.source == CORR_SRC_SAMPLES && !g.pair &&
                      deferred_supported(g.kind, g.p, g.m);
         g.p0 = g.deferred ? 2 * kDeferT + g.p : g.p;
-        g.lvl0_bytes = g.p0 * rowS + (int64_t)g.np * g.p * rowA;
-        g.lvlk_bytes = g.p * rowS + (int64_t)g.np * g.nlk * rowA;
+        // pair groups: each level holds the lagged y ring, then an x ring
+        const int rings = g.pair ? 2 : 1;
+        g.lvl0_bytes = rings * g.p0 * rowS + (int64_t)g.np * g.p * rowA;
+        g.lvlk_bytes = rings * g.p * rowS + (int64_t)g.np * g.nlk * rowA;
         g.tile_bytes = g.lvl0_bytes + (int64_t)(g.b - 1) * g.lvlk_bytes;
         const size_t state_bytes = (size_t)g.n_tiles * (size_t)g.tile_bytes;
         CREATE_HIP(hipMalloc(&g.state, state_bytes));
@@ -799,7 +809,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
             }
         } else {
-            g.input_bytes = (size_t)g.n_ch * g.s_bytes;
+            g.input_bytes = (size_t)(g.pair ? 2 : 1) * (size_t)g.n_ch * g.s_bytes;
         }
         CREATE_HIP(hipMalloc(&g.own_input, g.input_bytes));
         CREATE_HIP(hipMemsetAsync(g.own_input, 0, g.input_bytes, c->stream));
@@ -824,6 +834,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         ga.a_bytes = g.a_bytes;
         ga.deferred = g.deferred ? 1 : 0;
         ga.p0 = g.p0;
+        ga.pair = g.pair ? 1 : 0;
         if (g.deferred) c->deferred_set.push_back(i);
         tile_first += g.n_tiles;
     }
@@ -1044,7 +1055,7 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
                 e.level = k;
                 e.lag = L;
                 e.count = cnt;
-                const int ring_rows = k == 0 ? g.p0 : g.p;
+                const int ring_rows = (g.pair ? 2 : 1) * (k == 0 ? g.p0 : g.p);
                 e.hi_off = lvl + (int64_t)ring_rows * rowS + (int64_t)(L - l0) * rowA;
                 e.lo_off = e.hi_off + (int64_t)nl * rowA;
                 ent.push_back(e);

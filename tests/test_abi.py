@@ -110,3 +110,10 @@ def test_null_arguments(corrmod):
     assert L.corr_sync(None) == -1
     assert L.corr_destroy(None) == -1
     assert isinstance(L.corr_last_error(None), bytes)
+
+
+def test_pair_descriptor_checks(corrmod):
+    kv = np.array([[1, 0, 0]], dtype=np.int32)
+    rc, msg = _create(corrmod, corrmod.GroupDesc(1, 4, 16, dtype="cf32", source="rhok", kvec=kv,
+                                                 n_atoms=10, box=10.0, pair=True))
+    assert rc == -1 and "pair" in msg

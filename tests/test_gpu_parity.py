@@ -481,3 +481,88 @@ def test_large_window(corrmod, dtype, accum):
     res["t"] = t  # the oracle reports steps
     e = gate(res, o, TOL[(dtype, accum)], slice_=(0, 4), label="large window")
     say(f"  error {e:.2e}")
+
+
+def _pair_inputs(seed, n, S, dtype):
+    """x: OU series; y: 0.6 x + an independent OU series (cross-correlated)."""
+    x = ou_inputs(seed, 11, n, S, dtype)
+    z = ou_inputs(seed, 12, n, S, dtype)
+    y = (0.6 * x + z).astype(x.dtype)
+    return x, y
+
+
+@pytest.mark.parametrize("dtype,accum,b,p,m", [
+    ("f32", "kahan", 6, 16, 2), ("f32", "f64", 5, 16, 2), ("f64", "f64", 4, 9, 3),
+    ("cf32", "kahan", 5, 16, 2), ("cf64", "f64", 4, 8, 2), ("f32", "kahan", 1, 1024, 2)])
+def test_pair_parity(corrmod, dtype, accum, b, p, m):
+    """Pair groups, C(L) = <x(s) conj(y(s - L))>, against the oracle's pair
+    form: times and counts exact, values within the accumulator's tolerance.
+    The last case is a one-level window of 1024 points (window kernel)."""
+    n, S = 700, 1500
+    say(f"[pair] {dtype}/{accum} b={b} p={p} m={m}")
+    x, y = _pair_inputs(41, n, S, dtype)
+    o = oracle.OracleCorrelator(n, b, p, m, complex_=np.iscomplexobj(x))
+    for s in range(S):
+        o.push_pair(x[s], y[s])
+    xy = np.ascontiguousarray(np.stack([x, y], axis=1))  # [S][2][n]
+    with corrmod.Correlator([corrmod.GroupDesc(n, b, p, m, dtype=dtype, accum=accum,
+                                               pair=True)]) as c:
+        _push_all(c, [xy])
+        res = c.finalize(0, slice_=(0, 5))
+    e = gate(res, o, TOL[(dtype, accum)], slice_=(0, 5), label="pair")
+    say(f"  error {e:.2e}")
+
+
+def test_pair_with_itself_equals_direct_autocorrelation(corrmod):
+    """pair(x, x) and the per-step autocorrelation of x: identical arithmetic,
+    bit-identical state."""
+    n, S = 900, 700
+    x = ou_inputs(42, 1, n, S, "cf32")
+    xx = np.ascontiguousarray(np.stack([x, x], axis=1))
+    with corrmod.Correlator([corrmod.GroupDesc(n, 5, 16, 2, dtype="cf32", accum="kahan",
+                                               pair=True),
+                             corrmod.GroupDesc(n, 5, 16, 2, dtype="cf32", accum="kahan")],
+                            direct=True) as c:
+        _push_all(c, [xx, x])
+        a, b = c.finalize(0, slice_=(0, n)), c.finalize(1, slice_=(0, n))
+    assert np.array_equal(a["c_per_channel"], b["c_per_channel"])
+    assert np.array_equal(a["count"], b["count"])
+
+
+def test_pair_group_in_all_launch_modes(corrmod):
+    """A pair group next to a block-deferred group and a k-density group:
+    batched, per-group and graph launches give bit-identical pair results,
+    and they match the oracle."""
+    n, S, N, box = 500, 300, 1000, 30.0
+    kv = synth.kvectors(32)
+    x, y = _pair_inputs(43, n, S, "f32")
+    xy = np.ascontiguousarray(np.stack([x, y], axis=1))
+    xv = ou_inputs(43, 3, 2000, S, "f32")
+    pos, _ = synth.PositionSpec(43, 1, N, box).series(0, S)
+    groups = [corrmod.GroupDesc(n, 5, 16, 2, dtype="f32", accum="kahan", pair=True),
+              corrmod.GroupDesc(2000, 5, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(len(kv), 4, 16, 2, dtype="cf32", accum="f64", source="rhok",
+                                kvec=kv, n_atoms=N, box=box)]
+    out = {}
+    dev = torch.device("cuda:0")
+    for mode in ("batched", "per_group", "graph"):
+        with corrmod.Correlator(groups, graph=(mode == "graph"),
+                                per_group=(mode == "per_group")) as c:
+            ta, tb, tc = (torch.from_numpy(a).to(dev) for a in (xy, xv, pos))
+            if mode == "graph":
+                ba, bb, bc = torch.empty_like(ta[0]), torch.empty_like(tb[0]), torch.empty_like(tc[0])
+                c.bind_input(0, ba); c.bind_input(1, bb); c.bind_input(2, bc)
+                for s in range(S):
+                    ba.copy_(ta[s]); bb.copy_(tb[s]); bc.copy_(tc[s])
+                    c.push()
+            else:
+                for s in range(S):
+                    c.push([ta[s], tb[s], tc[s]])
+            torch.cuda.synchronize()
+            out[mode] = c.finalize(0, slice_=(0, 5))
+    for mode in ("per_group", "graph"):
+        assert np.array_equal(out[mode]["c_per_channel"], out["batched"]["c_per_channel"])
+    o = oracle.OracleCorrelator(n, 5, 16, 2)
+    for s in range(S):
+        o.push_pair(x[s], y[s])
+    gate(out["batched"], o, TOL[("f32", "kahan")], slice_=(0, 5), label="pair in mix")
