@@ -65,6 +65,9 @@ def parse():
                     help="run only a plain 1 GiB device-to-device copy 8 times (reference for "
                          "the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--chunk", type=int, default=128, help="pushes per generated input chunk")
+    ap.add_argument("--replay", action="store_true",
+                    help="push each generated chunk with one corr_push_steps call (a stored "
+                         "history replayed) instead of one corr_push per step")
     ap.add_argument("--mode", default=None, choices=["batched", "per_group"],
                     help="launch form (default: per_group for plain, batched otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -422,8 +425,11 @@ def run(args):
                 gen.fill(buf, n)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for j in range(n):
-            corr.push([buf[j] for buf in bufs])
+        if args.replay:
+            corr.push_steps([buf[:n] for buf in bufs])
+        else:
+            for j in range(n):
+                corr.push([buf[j] for buf in bufs])
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -513,6 +519,7 @@ def run(args):
         "config": {"workload": wl["name"], "channels": n_total, "launch": mode,
                    "update_form": "direct" if args.direct else "block-deferred where supported",
                    "rhok_producer": "vector units" if args.rhok_valu else "matrix cores",
+                   "push_calls": "one corr_push_steps per chunk" if args.replay else "one corr_push per step",
                    "producer_stream": ("forked, overlapping the other updates"
                                        if corr.tuning()["overlap_producers"]
                                        else "the context's stream, before the other updates"),

@@ -179,6 +179,19 @@ int corr_bind_input(corr_ctx *ctx, int32_t group, void *dev_ptr, size_t bytes);
  */
 int corr_push(corr_ctx *ctx, const void *const *samples);
 
+/* Replay of a stored history (the paper's comparison of on-the-fly analysis
+ * with replaying saved trajectories, Section "Benchmarks and Trade-offs"): n_steps
+ * consecutive pushes in one call.  samples[g] is group g's device history; row r (the input of push r)
+ * starts at samples[g] + r * strides[g] bytes (strides NULL: rows packed,
+ * stride = the group's per-push input size, see corr_input_buffer).  Exactly
+ * equivalent to n_steps corr_push calls with those pointers, in order (same
+ * kernels, same results bit for bit); a captured graph is not used.  Every
+ * group needs a history (CORR_E_INVALID otherwise, or for a stride below the
+ * push size).  Work is issued on the context's stream; the rows must stay
+ * valid until it has run. */
+int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
+                    const int64_t *strides);
+
 /* Number of pushes so far and the maximum number of readout points of a
  * group, p + (b - 1)(p - floor(p/m)) (Algorithm 2). */
 int corr_query(const corr_ctx *ctx, int32_t group, int64_t *n_pushes, int32_t *n_out_max);

@@ -59,7 +59,8 @@ class _ReadoutOpts(ctypes.Structure):
                 ("slice_begin", ctypes.c_int64), ("slice_end", ctypes.c_int64)]
 
 
-EXPORTS = ["corr_create", "corr_input_buffer", "corr_bind_input", "corr_push", "corr_query",
+EXPORTS = ["corr_create", "corr_input_buffer", "corr_bind_input", "corr_push", "corr_push_steps",
+           "corr_query",
            "corr_finalize", "corr_sync", "corr_destroy", "corr_last_error", "corr_state_bytes",
            "corr_get_tuning", "corr_kernel_time", "corr_autotune"]
 
@@ -79,6 +80,7 @@ def lib():
         L.corr_input_buffer.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(sz)]
         L.corr_bind_input.argtypes = [vp, i32, vp, sz]
         L.corr_push.argtypes = [vp, ctypes.POINTER(vp)]
+        L.corr_push_steps.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
         L.corr_query.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.corr_finalize.argtypes = [vp, i32, ctypes.POINTER(_ReadoutOpts), ctypes.POINTER(i32),
                                     vp, vp, vp, vp, vp, vp]
@@ -233,6 +235,17 @@ class Correlator:
             return
         arr = (ctypes.c_void_p * len(self.groups))(*[_ptr(s) for s in samples])
         self._check(lib().corr_push(self._h, arr))
+
+    def push_steps(self, histories):
+        """Replay n consecutive steps: histories = one tensor per group with the
+        steps along dim 0 ([n][...] with each row one push's input)."""
+        hs = list(histories)
+        n = int(hs[0].shape[0])
+        for h in hs:
+            assert h.is_cuda and h.shape[0] == n
+        arr = (ctypes.c_void_p * len(hs))(*[h.data_ptr() for h in hs])
+        st = (ctypes.c_int64 * len(hs))(*[h.stride(0) * h.element_size() for h in hs])
+        self._check(lib().corr_push_steps(self._h, n, arr, st))
 
     def sync(self):
         self._check(lib().corr_sync(self._h))

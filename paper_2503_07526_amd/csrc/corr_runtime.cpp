@@ -948,6 +948,33 @@ int corr_push(corr_ctx *ctx, const void *const *samples)
     return CORR_OK;
 }
 
+int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
+                    const int64_t *strides)
+{
+    if (!ctx || !samples || n_steps < 0) return CORR_E_INVALID;
+    DeviceGuard dg(ctx->device);
+    const size_t ng = ctx->groups.size();
+    std::vector<int64_t> stride(ng);
+    for (size_t i = 0; i < ng; ++i) {
+        if (!samples[i]) return set_err(ctx, CORR_E_INVALID, "push_steps: group %d has no history", (int)i);
+        stride[i] = strides ? strides[i] : (int64_t)ctx->groups[i].input_bytes;
+        if (stride[i] < (int64_t)ctx->groups[i].input_bytes)
+            return set_err(ctx, CORR_E_INVALID, "push_steps: stride of group %d below its push size",
+                           (int)i);
+    }
+    const bool with_flush = !ctx->deferred_set.empty();
+    std::vector<const void *> src(ng);
+    for (int32_t r = 0; r < n_steps; ++r) {
+        for (size_t i = 0; i < ng; ++i)
+            src[i] = static_cast<const char *>(samples[i]) + (int64_t)r * stride[i];
+        int rc = issue_push(ctx, src.data(), ctx->stream, with_flush);
+        if (rc != CORR_OK) return rc;
+        ctx->n_push += 1;
+        mirror_flushes(ctx, ctx->n_push);
+    }
+    return CORR_OK;
+}
+
 int corr_query(const corr_ctx *ctx, int32_t group, int64_t *n_pushes, int32_t *n_out_max)
 {
     if (!ctx) return CORR_E_INVALID;

@@ -566,3 +566,41 @@ def test_pair_group_in_all_launch_modes(corrmod):
     for s in range(S):
         o.push_pair(x[s], y[s])
     gate(out["batched"], o, TOL[("f32", "kahan")], slice_=(0, 5), label="pair in mix")
+
+
+def test_push_steps_equals_single_pushes(corrmod):
+    """corr_push_steps replays a stored history: the same state, bit for bit,
+    as one push per step -- for block-deferred, per-step, pair and k-density
+    groups in one context, across flush boundaries, with a readout between two
+    replays."""
+    S, nv, N, box = 200, 3000, 800, 25.0
+    kv = synth.kvectors(24)
+    xv = ou_inputs(51, 1, nv, S, "f32")
+    xg = ou_inputs(51, 2, 9, S, "f64")
+    x, y = _pair_inputs(51, 300, S, "f32")
+    xy = np.ascontiguousarray(np.stack([x, y], axis=1))
+    pos, _ = synth.PositionSpec(51, 3, N, box).series(0, S)
+    groups = [corrmod.GroupDesc(nv, 6, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(9, 8, 16, 2, dtype="f64", accum="f64"),
+              corrmod.GroupDesc(300, 5, 16, 2, dtype="f32", accum="kahan", pair=True),
+              corrmod.GroupDesc(len(kv), 4, 16, 2, dtype="cf32", accum="kahan", source="rhok",
+                                kvec=kv, n_atoms=N, box=box)]
+    dev = torch.device("cuda:0")
+    hs = [torch.from_numpy(a).to(dev) for a in (xv, xg, xy, pos)]
+    with corrmod.Correlator(groups) as a, corrmod.Correlator(groups) as b:
+        for s in range(S):
+            a.push([h[s] for h in hs])
+        b.push_steps([h[:77] for h in hs])
+        mid = [b.finalize(g, slice_=(0, 3)) for g in range(4)]
+        b.push_steps([h[77:] for h in hs])
+        torch.cuda.synchronize()
+        assert a.n_pushes() == b.n_pushes() == S
+        for g in range(4):
+            ra, rb = a.finalize(g, slice_=(0, 3)), b.finalize(g, slice_=(0, 3))
+            assert np.array_equal(ra["c"], rb["c"]), g
+            assert np.array_equal(ra["c_per_channel"], rb["c_per_channel"]), g
+        assert len(mid[0]["t"]) > 0
+        short = torch.zeros((2, 10), dtype=torch.float32, device=dev)  # rows below 3N floats
+        with pytest.raises(corrmod.CorrError):
+            b.push_steps([hs[0][:2], hs[1][:2], hs[2][:2], short])
+        assert b.n_pushes() == S  # rejected before anything was issued
