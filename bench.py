@@ -24,7 +24,8 @@ Workloads (--config):
            10^6 atoms (6144 complex channels), the current producer's line
   kgap     the long single-window form: currents and n(k) of the same k-vectors
            and atoms, one block of 10240 points updated every 10 MD steps
-           (8192 complex channels); the correlator update's line
+           (8192 complex channels, block-deferred window); the producers
+           dominate, and the window update is reported beside them
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -137,7 +138,7 @@ def workload(name):
         return dict(
             name="kgap: j_L, j_T and n(k) of 2048 k-vectors from 1e6 atoms, one window of p=10240 "
                  "points (b=1), u=10, 8192 cFP32 channels compensated",
-            steps=1024, warmup=10240, dominant="push",  # timed once the window is full
+            steps=1024, warmup=10240, dominant="producer",  # timed once the window is full
             groups=[dict(kind="currents", n=3 * 2048, levels=1, points=10240, m=2, dtype="cf32",
                          accum="kahan", n_atoms=1_000_000, box=100.0, seed=6, stream=3,
                          vtau=(20, 200), kvec=kv, update_every=10),
@@ -272,6 +273,33 @@ def staggered_flush_bytes(g, s, tw):
         return 0
     per_channel = flush_bytes(dict(g, n=1), q * DEFER_T)
     return per_channel * group_channels(g, tw, j)
+
+
+def window_deferred(g, direct=False):
+    """One-level groups of >= 512 points with single-precision samples: the
+    library stages each push and folds one of 64 lag blocks per push."""
+    return (not direct and g["levels"] == 1 and g["points"] >= 512
+            and g["dtype"] in ("f32", "cf32"))
+
+
+def window_push_cost(g):
+    """Algorithmic bytes and flop of one push of a block-deferred window, per
+    group: staging reads the sample and writes its ring slot; the fold of lag
+    block j (lpb = p / 64 lags) reads the 64 new and 63 + lpb older ring values
+    and reads+writes lpb accumulators, and does 64 x lpb products (complex: 4
+    fma = 8 flop each; real: 2 flop)."""
+    sb, ab = SB[g["dtype"]], AB[(g["dtype"], g["accum"])]
+    lpb = -(-g["points"] // DEFER_T)
+    per_ch = 2 * sb + (2 * DEFER_T - 1 + lpb) * sb + 2 * lpb * ab
+    flop = g["points"] * (8 if g["dtype"] == "cf32" else 2)
+    return per_ch * g["n"], flop * g["n"]
+
+
+def producer_flop(g):
+    """Algorithmic flop of one producer launch (matrix-core forms)."""
+    if g["kind"] == "currents":
+        return CURRENTS_FLOP_PER_ATOM_K * (g["n"] // 3) * g["n_atoms"]
+    return RHOK_FLOP_PER_ATOM_K * g["n"] * g["n_atoms"]
 
 
 def push_bytes(g, s, direct=False):
@@ -468,9 +496,19 @@ def run(args):
     n_total = sum(g["n"] for g in wl["groups"])
     value = n_total * K / wall
     rhok_only = (all(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
-                 and wl.get("dominant") != "push")
+                 and wl.get("dominant") not in ("push", "producer"))
+    producer_dominant = wl.get("dominant") == "producer"
     push_dominant = wl.get("dominant") == "push"
-    if push_dominant:
+    if producer_dominant:
+        # the producers of every k-space group, per push (HIP events on their
+        # stream; several producer launches per push)
+        flop_per = sum(producer_flop(g) for g in wl["groups"] if g["kind"] in PRODUCER_KINDS)
+        per_launch_ms = rk_ms / K
+        achieved = flop_per / (per_launch_ms * 1e-3) / 1e12
+        kname = ("k-space producers (matrix cores), HIP events around the %d producer launches of "
+                 "a push" % (rk_n // K))
+        per_launch_bytes = None
+    elif push_dominant:
         # the per-step correlator update of every group (direct form): the
         # push events minus the producer launches they contain
         push_ms = (kern_ms - rk_ms) / K
@@ -534,7 +572,20 @@ def run(args):
     }
     if rk_n:
         out["roofline"]["producer_ms_per_launch"] = rk_ms / rk_n
-    if rhok_only:
+    wins = [g for g in wl["groups"] if window_deferred(g, direct)]
+    if wins and len(wins) == len(wl["groups"]):
+        # the correlator update of the block-deferred windows: the push events
+        # less the producer launches they contain
+        wb = sum(window_push_cost(g)[0] for g in wins)
+        wf = sum(window_push_cost(g)[1] for g in wins)
+        wms = (kern_ms - rk_ms) / K
+        out["window_update"] = {
+            "kernels": "staging + one lag-block fold per group and push",
+            "ms_per_push": wms, "alg_bytes_per_push": wb, "alg_flop_per_push": wf,
+            "GBs": wb / (wms * 1e-3) / 1e9, "hbm_frac": wb / (wms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "TFLOPs": wf / (wms * 1e-3) / 1e12,
+            "alu_frac": wf / (wms * 1e-3) / 1e12 / VALU_F32_PEAK_TFS}
+    if rhok_only or producer_dominant:
         r = out["roofline"]
         bound, peak = ("alu", VALU_F32_PEAK_TFS) if args.rhok_valu else ("mfma", MFMA_F16_PEAK_TFS)
         r.update({"bound": bound, "unit": "TFLOP/s", "peak": peak, "frac": achieved / peak,

@@ -197,13 +197,16 @@ __device__ __forceinline__ void level0(Ctx &cx, typename RK<K>::S (&out)[T / 2])
     const int64_t f = cx.f;
     const int r = cx.r;
     S H[P - 1 + T];
-    // old values f-P+2 .. f, then new values f+1 .. f+r (zeros beyond r)
+    // old values f-P+2 .. f, then new values f+1 .. f+r (zeros beyond r);
+    // value j sits in slot (j - 1) mod P0, and P - 1 + T < P0, so one
+    // modulo and a wrap per row suffice
+    const int slot0 = (int)((f - (P - 2) - 1 + P0) % P0);
 #pragma unroll
     for (int i = 0; i < P - 1 + T; ++i) {
-        const int64_t j = f - (P - 2) + i;
         const int q = i - (P - 1);
         if (q < r) {
-            const int slot = (int)((j - 1 + P0) % P0);
+            int slot = slot0 + i;
+            if (slot >= P0) slot -= P0;
             H[i] = __builtin_nontemporal_load(&ring[(size_t)slot * tw + cx.lane]);
         } else {
             H[i] = S(0);

@@ -169,6 +169,12 @@ struct ReduceArgs {
     int64_t ch_begin, ch_end;
     double *partial;        // [n_entries][blocks_per_entry][2]
     double *out;            // [n_entries][2]
+    // One-level window in the block-deferred form (wlpb > 0): entry e is lag
+    // e, lag block e / wlpb; the pushes it has not folded are added from the
+    // level-0 ring of p0 rows.
+    int32_t wlpb;
+    int32_t p0;
+    int64_t n_push;         // pushes completed
 };
 
 } // namespace corr

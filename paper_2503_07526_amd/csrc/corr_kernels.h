@@ -22,6 +22,7 @@ hipError_t launch_rhok_mfma(const RhokMfmaArgs &a, hipStream_t st);
 int rhok_mfma_cols();        // |n_z| columns of the matrix-core producer
 int rhok_mfma_max_nmax();    // largest |n component| it takes
 hipError_t rhok_mfma_prepare(int nmax, int nw); // once per context, before the first launch
+int rhok_mfma_chunks(int n_mtiles, int nw); // blocks along the M tiles (grid.x)
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 bool deferred_supported(int kind, int p, int m);
 hipError_t launch_stage(const GroupArgs &g, const int64_t *step, hipStream_t st);
@@ -33,6 +34,9 @@ int64_t deferred_readout_groups(const GroupArgs &g);
 hipError_t launch_deferred_readout(const DeferredArgs &a, double *groups, double *sums,
                                    hipStream_t st);
 hipError_t launch_gather(const ReduceArgs &a, hipStream_t st);
+bool window_deferred_supported(int kind);
+int window_lags_per_block(int p);
+hipError_t launch_window_fold(const GroupArgs &g, const int64_t *step, hipStream_t st);
 
 } // namespace corr
 

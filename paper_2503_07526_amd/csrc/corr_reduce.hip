@@ -2,14 +2,56 @@
 // the accumulators over a channel range, in double precision, in a fixed
 // order (block partials, then partials in block order), plus a gather of the
 // accumulators of a channel slice.  A compensated accumulator is read as
-// value - compensation, evaluated in double.
+// value - compensation, evaluated in double; a one-level window in the
+// block-deferred form adds the products of its pending pushes.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
 
 namespace corr {
 
-__device__ __forceinline__ double2 read_acc(const ReduceArgs &a, int e, int64_t c)
+// Products of the pushes that a one-level window in the block-deferred form
+// (corr_window.hip) has staged but not yet folded into lag L = e: its lag
+// block j = L / wlpb has folded every block q with kDeferT q + j <= S, so the
+// pushes after f = kDeferT floor((S - j) / kDeferT) are pending.  Summed in
+// double in push order; pushes s <= L have no lagged value and add nothing.
+__device__ double2 window_pending(const ReduceArgs &a, int e, int64_t c)
+{
+    const int L = e;
+    const int j = L / a.wlpb;
+    const int64_t S = a.n_push;
+    const int64_t f = S >= j ? ((S - j) / kDeferT) * kDeferT : 0;
+    const int64_t s1 = f + 1 > (int64_t)L + 1 ? f + 1 : (int64_t)L + 1;
+    if (s1 > S) return make_double2(0.0, 0.0);
+    const int64_t tile = c / a.tw;
+    const int64_t lane = c - tile * a.tw;
+    const char *tb = a.state + tile * a.tile_bytes;
+    const int p0 = a.p0;
+    int sx = (int)((s1 - 1) % p0);
+    int sy = (int)((s1 - L - 1) % p0);
+    double re = 0.0, im = 0.0;
+    if (a.kind >= K_CF32_F64) {
+        const float2 *ring = reinterpret_cast<const float2 *>(tb) + lane;
+        for (int64_t s = s1; s <= S; ++s) {
+            const float2 x = ring[(size_t)sx * a.tw];
+            const float2 y = ring[(size_t)sy * a.tw];
+            re += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+            im += (double)x.y * (double)y.x - (double)x.x * (double)y.y;
+            sx = sx + 1 == p0 ? 0 : sx + 1;
+            sy = sy + 1 == p0 ? 0 : sy + 1;
+        }
+    } else {
+        const float *ring = reinterpret_cast<const float *>(tb) + lane;
+        for (int64_t s = s1; s <= S; ++s) {
+            re += (double)ring[(size_t)sx * a.tw] * (double)ring[(size_t)sy * a.tw];
+            sx = sx + 1 == p0 ? 0 : sx + 1;
+            sy = sy + 1 == p0 ? 0 : sy + 1;
+        }
+    }
+    return make_double2(re, im);
+}
+
+__device__ __forceinline__ double2 stored_acc(const ReduceArgs &a, int e, int64_t c)
 {
     const int64_t tile = c / a.tw;
     const int64_t lane = c - tile * a.tw;
@@ -38,6 +80,17 @@ __device__ __forceinline__ double2 read_acc(const ReduceArgs &a, int e, int64_t 
         return make_double2((double)h.x, (double)h.y);
     }
     }
+}
+
+__device__ __forceinline__ double2 read_acc(const ReduceArgs &a, int e, int64_t c)
+{
+    double2 v = stored_acc(a, e, c);
+    if (a.wlpb > 0) {
+        const double2 w = window_pending(a, e, c);
+        v.x += w.x;
+        v.y += w.y;
+    }
+    return v;
 }
 
 constexpr int kRedThreads = 256;

@@ -481,12 +481,17 @@ hipError_t rhok_mfma_prepare(int nmax, int nw)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+int rhok_mfma_chunks(int n_mtiles, int nw)
+{
+    const int maxw = nw == 3 ? MfmaShape<3>::max_waves : MfmaShape<1>::max_waves;
+    return (n_mtiles + maxw - 1) / maxw;
+}
+
 template <int NW> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t st)
 {
     // waves per block: the M tiles dealt evenly over the fewest blocks, at
     // least one thread per table task
-    const int maxw = MfmaShape<NW>::max_waves;
-    const int chunks = (a.n_mtiles + maxw - 1) / maxw;
+    const int chunks = rhok_mfma_chunks(a.n_mtiles, NW);
     int waves = (a.n_mtiles + chunks - 1) / chunks;
     if (waves < TableShape<NW>::min_waves) waves = TableShape<NW>::min_waves;
     hipLaunchKernelGGL(rhok_mfma_kernel<NW>, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),

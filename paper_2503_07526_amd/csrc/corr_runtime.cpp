@@ -25,12 +25,21 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// One-level groups with at least this many points take a window form: the
+// block-deferred window (corr_window.hip) where the kind allows, else the
+// per-step window kernel, which splits the lag range over the grid
+// (kWindowLags lags per block).
+constexpr int kWindowMinP = 512;
+constexpr int kWindowLags = 256;
+
 struct Group {
     corr_group_desc d{};
     int kind = 0;
     int p = 0, m = 0, b = 0, lag0 = 0, nlk = 0;
     int s_bytes = 0, a_bytes = 0, np = 1;
     bool deferred = false; // block-deferred form (stage per push, staggered flushes)
+    bool wdef = false;     // one-level window in the block-deferred form (staged per
+                           // push, one lag block folded per push)
     int p0 = 0;            // ring rows of level 0
     bool pair = false;     // channels correlate (x, y) pairs
     int64_t *d_flushed = nullptr;                // [kFlushGroups] blocks folded per tile group
@@ -349,12 +358,11 @@ int catch_up_flushes(corr_ctx *c, int gi)
     return CORR_OK;
 }
 
-// One-level groups with at least this many points take the window kernel,
-// which also splits the lag range over the grid (kWindowLags lags per block).
-constexpr int kWindowMinP = 512;
-constexpr int kWindowLags = 256;
-
 bool is_window(const GroupArgs &g) { return g.levels == 1 && g.p >= kWindowMinP && !g.deferred; }
+
+// One-level window in the block-deferred form: the push kernels stage the
+// sample (their deferred branch), then one lag block is folded.
+bool is_window_deferred(const GroupArgs &g) { return g.levels == 1 && g.deferred && g.p >= kWindowMinP; }
 
 // Push kernel launch(es) for the groups of one set (batched: one launch;
 // per-group form: one launch per group; long one-level windows: one window
@@ -372,6 +380,11 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
         int n = 0;
         int64_t tf = 0;
         for (int i = 0; i < a.n_groups; ++i) {
+            if (is_window_deferred(a.g[i])) {
+                HIP_TRY(c, launch_push_group(a.g[i], c->d_step, cpt, lch, block, st));
+                HIP_TRY(c, launch_window_fold(a.g[i], c->d_step, st));
+                continue;
+            }
             if (is_window(a.g[i])) {
                 HIP_TRY(c, launch_push_window(a.g[i], c->d_step, cpt, lch, block, kWindowLags, st));
                 continue;
@@ -630,7 +643,9 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         g.pair = g.d.pair != 0;
         g.deferred = !(flags & CORR_FLAG_DIRECT) && g.d.source == CORR_SRC_SAMPLES && !g.pair &&
                      deferred_supported(g.kind, g.p, g.m);
-        g.p0 = g.deferred ? 2 * kDeferT + g.p : g.p;
+        g.wdef = !(flags & CORR_FLAG_DIRECT) && !g.deferred && !g.pair && g.b == 1 &&
+                 g.p >= kWindowMinP && window_deferred_supported(g.kind);
+        g.p0 = (g.deferred || g.wdef) ? 2 * kDeferT + g.p : g.p;
         // pair groups: each level holds the lagged y ring, then an x ring
         const int rings = g.pair ? 2 : 1;
         g.lvl0_bytes = rings * g.p0 * rowS + (int64_t)g.np * g.p * rowA;
@@ -656,9 +671,6 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
             int nmax = 0;
             for (int q = 0; q < nk; ++q)
                 for (int d = 0; d < 3; ++d) nmax = std::max(nmax, std::abs(kv[3 * q + d]));
-            // Atom blocks: about 1000 atoms or more each, at most 512 blocks.
-            const int n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(512, g.d.n_atoms / 1024));
-            const int64_t apb = (g.d.n_atoms + n_ab - 1) / n_ab;
             CREATE_HIP(hipMalloc(&g.rhok_out, (size_t)g.n_ch * g.s_bytes));
             CREATE_HIP(hipMemsetAsync(g.rhok_out, 0, (size_t)g.n_ch * g.s_bytes, c->stream));
             // Matrix-core form: rows = distinct (n_x, n_y), columns = |n_z|
@@ -666,12 +678,23 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
             // within its range).
             g.rhok_mfma = g.nw == 3 ||
                           (!(flags & CORR_FLAG_RHOK_VALU) && nmax <= rhok_mfma_max_nmax());
+            // Atom blocks of about 1000 atoms or more; the vector-unit
+            // producer takes up to 512.
+            int n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(512, g.d.n_atoms / 1024));
             if (g.rhok_mfma) {
                 std::map<std::pair<int, int>, int> pair_ix;
                 for (int q = 0; q < nk; ++q)
                     pair_ix.emplace(std::make_pair(kv[3 * q], kv[3 * q + 1]), 0);
                 const int n_pairs = (int)pair_ix.size();
                 const int n_mtiles = (n_pairs + 15) / 16;
+                // The matrix-core producer runs fastest with one block per
+                // compute unit (its double-buffered LDS tables and one wave
+                // per M tile fill a CU): CUs / M-tile chunks atom blocks.
+                int n_cu = 0;
+                CREATE_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
+                const int per_cu = std::max(1, n_cu / rhok_mfma_chunks(n_mtiles, g.nw));
+                n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(512, per_cu),
+                                                                   g.d.n_atoms / 1024));
                 const int ncol = rhok_mfma_cols();
                 std::vector<int32_t> pnx((size_t)n_mtiles * 16, 0), pny((size_t)n_mtiles * 16, 0);
                 int u = 0;
@@ -745,7 +768,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 r.inv_box = 1.0 / g.d.box;
                 r.partial = g.d_partial;
                 r.n_atom_blocks = n_ab;
-                r.atoms_per_block = (int32_t)apb;
+                r.atoms_per_block = (int32_t)((g.d.n_atoms + n_ab - 1) / n_ab);
                 r.out = g.rhok_out;
                 r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
                 r.nk = nk;
@@ -804,7 +827,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 r.inv_box = 1.0 / g.d.box;
                 r.partial = g.d_partial;
                 r.n_atom_blocks = n_ab;
-                r.atoms_per_block = (int32_t)apb;
+                r.atoms_per_block = (int32_t)((g.d.n_atoms + n_ab - 1) / n_ab);
                 r.out = g.rhok_out;
                 r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
             }
@@ -832,7 +855,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         ga.tw = tw;
         ga.s_bytes = g.s_bytes;
         ga.a_bytes = g.a_bytes;
-        ga.deferred = g.deferred ? 1 : 0;
+        ga.deferred = (g.deferred || g.wdef) ? 1 : 0;
         ga.p0 = g.p0;
         ga.pair = g.pair ? 1 : 0;
         if (g.deferred) c->deferred_set.push_back(i);
@@ -1183,6 +1206,9 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
     ra.ch_end = ce;
     ra.partial = d_part;
     ra.out = d_sum;
+    ra.wlpb = g.wdef ? window_lags_per_block(g.p) : 0;
+    ra.p0 = g.p0;
+    ra.n_push = S;
     HIP_TRY(ctx, launch_reduce(ra, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(sums.data(), d_sum, sum_bytes, hipMemcpyDeviceToHost, ctx->stream));
     if (want_slice) {

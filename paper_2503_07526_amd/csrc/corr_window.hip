@@ -1,0 +1,314 @@
+// corr_window.hip -- block-deferred form of a long one-level window.
+//
+// A one-level group with p points (Algorithm 1 with b = 1: lags 0..p-1 of the
+// raw series) costs p products per channel per push, and updating all p
+// accumulators on every push moves every accumulator row through HBM once per
+// push.  The sums are linear, so the products of kDeferT consecutive pushes
+// can be added in one pass: each push only stages its sample in a ring of
+// P0 = p + 2 kDeferT slots (the push kernels' staging branch), and the lag
+// range is cut into kDeferT lag blocks of lpb = ceil(p / kDeferT) lags.  At
+// push kDeferT q + j, lag block j folds block q (pushes kDeferT (q-1) + 1 ..
+// kDeferT q) of every channel: the kDeferT x lpb products x_s conj(x_{s-L})
+// are summed in registers and added once to the stored accumulators.  Every
+// push therefore does the same work (p products per channel, 1/kDeferT of the
+// accumulator rows), and each accumulator row is read and written once per
+// kDeferT pushes.
+//
+// Ring: value v (1-based) sits in slot (v - 1) mod P0.  When lag block j
+// folds block q at push kDeferT q + j, the oldest value it reads is
+// kDeferT (q - 1) + 1 - (p - 1), and the slots still hold every value from
+// kDeferT q + j - P0 + 1 on, which is older for every j < kDeferT.  Values
+// before the first push (v <= 0) map to slots that have not been written
+// yet and read as the zeros the state is created with, so the products of
+// lags longer than the series add nothing, as the counts max(0, S - L) say.
+//
+// A readout adds, for lag L of lag block j, the products of the pushes after
+// the last block that lag block folded (at most 2 kDeferT - 2 of them) on the
+// fly from the ring, without writing state (corr_reduce.hip).
+//
+// Threads: a wave holds 64 consecutive channels (one per lane) and a
+// sub-block of LB consecutive lags of lag block j (LB = 8, or 4 when the
+// grid would be small); the waves of a block (and blockIdx.y) cover the
+// sub-blocks.  Each lane keeps LB partial sums and a sliding window of
+// LB - 1 + U lagged values in registers: per U pushes it loads U new and U
+// lagged values (one step ahead of the products) and does U x LB products.
+#include <hip/hip_runtime.h>
+
+#include "corr_kernels.h"
+
+namespace corr {
+
+namespace {
+
+// Sample type S, accumulator element A, partial-sum precision PT, planes NP.
+template <int K> struct WK;
+template <> struct WK<K_F32_F64>    { using S = float;  using A = double;  using PT = double; static constexpr int NP = 1; };
+template <> struct WK<K_F32_KAHAN>  { using S = float;  using A = float;   using PT = float;  static constexpr int NP = 2; };
+template <> struct WK<K_F32_F32>    { using S = float;  using A = float;   using PT = float;  static constexpr int NP = 1; };
+template <> struct WK<K_CF32_F64>   { using S = float2; using A = double2; using PT = double; static constexpr int NP = 1; };
+template <> struct WK<K_CF32_KAHAN> { using S = float2; using A = float2;  using PT = float;  static constexpr int NP = 2; };
+template <> struct WK<K_CF32_F32>   { using S = float2; using A = float2;  using PT = float;  static constexpr int NP = 1; };
+
+// Partial sum of one lag: (re, im); real kinds use re only.
+template <typename PT> struct Part { PT re, im; };
+
+// part += x * conj(y) in the partial-sum precision (single-precision
+// products are exact in double).
+__device__ __forceinline__ void mac(Part<float> &p, float x, float y) { p.re = __builtin_fmaf(x, y, p.re); }
+__device__ __forceinline__ void mac(Part<double> &p, float x, float y)
+{
+    p.re = __builtin_fma((double)x, (double)y, p.re);
+}
+__device__ __forceinline__ void mac(Part<float> &p, float2 x, float2 y)
+{
+    p.re = __builtin_fmaf(x.x, y.x, __builtin_fmaf(x.y, y.y, p.re));
+    p.im = __builtin_fmaf(x.y, y.x, __builtin_fmaf(-x.x, y.y, p.im));
+}
+__device__ __forceinline__ void mac(Part<double> &p, float2 x, float2 y)
+{
+    const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+    p.re = __builtin_fma(xr, yr, __builtin_fma(xi, yi, p.re));
+    p.im = __builtin_fma(xi, yr, __builtin_fma(-xr, yi, p.im));
+}
+
+// Add a partial sum to a stored accumulator element (compensated kinds: one
+// Kahan step per component, true value h - c).
+__device__ __forceinline__ void kahan(float &h, float &c, float v)
+{
+    const float y = v - c;
+    const float t = h + y;
+    c = (t - h) - y;
+    h = t;
+}
+template <int K> struct Fold;
+template <> struct Fold<K_F32_F64> {
+    static __device__ __forceinline__ void add(double &h, double &, const Part<double> &p) { h += p.re; }
+};
+template <> struct Fold<K_F32_KAHAN> {
+    static __device__ __forceinline__ void add(float &h, float &c, const Part<float> &p) { kahan(h, c, p.re); }
+};
+template <> struct Fold<K_F32_F32> {
+    static __device__ __forceinline__ void add(float &h, float &, const Part<float> &p) { h += p.re; }
+};
+template <> struct Fold<K_CF32_F64> {
+    static __device__ __forceinline__ void add(double2 &h, double2 &, const Part<double> &p)
+    {
+        h.x += p.re;
+        h.y += p.im;
+    }
+};
+template <> struct Fold<K_CF32_KAHAN> {
+    static __device__ __forceinline__ void add(float2 &h, float2 &c, const Part<float> &p)
+    {
+        kahan(h.x, c.x, p.re);
+        kahan(h.y, c.y, p.im);
+    }
+};
+template <> struct Fold<K_CF32_F32> {
+    static __device__ __forceinline__ void add(float2 &h, float2 &, const Part<float> &p)
+    {
+        h.x += p.re;
+        h.y += p.im;
+    }
+};
+
+// Streaming loads and stores of accumulator elements (touched once per
+// kDeferT pushes); the complex types go through clang vector types.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float nt_load(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double nt_load(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float2 nt_load(const float2 *p)
+{
+    const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 nt_load(const double2 *p)
+{
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void nt_store(float v, float *p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(double v, double *p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(float2 v, float2 *p)
+{
+    __builtin_nontemporal_store(f2v{v.x, v.y}, reinterpret_cast<f2v *>(p));
+}
+__device__ __forceinline__ void nt_store(double2 v, double2 *p)
+{
+    __builtin_nontemporal_store(d2v{v.x, v.y}, reinterpret_cast<d2v *>(p));
+}
+
+// Pushes per register window step.
+constexpr int kWinU = 8;
+
+__device__ __forceinline__ int wrap_slot(int64_t v, int p0)
+{
+    // slot of value v (1-based; v may be <= 0): (v - 1) mod p0 in [0, p0)
+    int64_t r = (v - 1) % p0;
+    if (r < 0) r += p0;
+    return (int)r;
+}
+
+__device__ __forceinline__ int next_slot(int s, int p0) { return s + 1 == p0 ? 0 : s + 1; }
+
+template <int K, int LB>
+__global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int64_t *step, int lpb,
+                                                          int subs_per_block)
+{
+    using S = typename WK<K>::S;
+    using A = typename WK<K>::A;
+    using PT = typename WK<K>::PT;
+    constexpr int NP = WK<K>::NP;
+    constexpr int U = kWinU;
+
+    // Push P = *step + 1 (its sample is already staged): lag block j folds
+    // block q.
+    const int64_t P = *step + 1;
+    const int j = (int)(P % kDeferT);
+    const int64_t q = P / kDeferT;
+    if (q < 1) return;
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const int sub = (int)blockIdx.y * subs_per_block + wave;
+    const int lag_end = min((j + 1) * lpb, g.p);
+    const int L0 = j * lpb + sub * LB;
+    if (L0 >= lag_end) return; // whole wave
+    const int nl = min(LB, lag_end - L0);
+
+    const int64_t ch = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t tile = ch / g.tw;
+    const int tl = (int)(ch - tile * g.tw);
+    const int tw = g.tw;
+    const int p0 = g.p0;
+    char *tb = g.state + tile * g.tile_bytes;
+    const S *ring = reinterpret_cast<const S *>(tb) + tl;
+
+    // New values s0 .. s0 + kDeferT - 1; the window starts at value
+    // s0 - L0 - (LB - 1).
+    const int64_t s0 = (q - 1) * kDeferT + 1;
+    int sn = wrap_slot(s0, p0);
+    int so = wrap_slot(s0 - L0 - (LB - 1), p0);
+    S W[LB - 1 + U];
+#pragma unroll
+    for (int k = 0; k < LB - 1; ++k) {
+        W[k] = ring[(size_t)so * tw];
+        so = next_slot(so, p0);
+    }
+    Part<PT> part[LB];
+#pragma unroll
+    for (int l = 0; l < LB; ++l) part[l] = Part<PT>{PT(0), PT(0)};
+    // The loads of step i + U are issued before the products of step i.
+    S Nn[U], Wn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        Nn[u] = ring[(size_t)sn * tw];
+        sn = next_slot(sn, p0);
+        Wn[u] = ring[(size_t)so * tw];
+        so = next_slot(so, p0);
+    }
+#pragma unroll 1
+    for (int i = 0; i < kDeferT; i += U) {
+        S N[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            N[u] = Nn[u];
+            W[LB - 1 + u] = Wn[u];
+        }
+        if (i + U < kDeferT) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                Nn[u] = ring[(size_t)sn * tw];
+                sn = next_slot(sn, p0);
+                Wn[u] = ring[(size_t)so * tw];
+                so = next_slot(so, p0);
+            }
+        }
+        // push s = s0 + i + u, lag L0 + l: lagged value s - L0 - l = W[LB - 1 + u - l]
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int l = 0; l < LB; ++l) mac(part[l], N[u], W[LB - 1 + u - l]);
+#pragma unroll
+        for (int k = 0; k < LB - 1; ++k) W[k] = W[k + U];
+    }
+
+    A *hi = reinterpret_cast<A *>(tb + (int64_t)p0 * tw * (int64_t)sizeof(S)) + tl;
+    A *lo = hi + (size_t)g.p * tw;
+#pragma unroll
+    for (int l = 0; l < LB; ++l) {
+        if (l < nl) {
+            const size_t r = (size_t)(L0 + l) * tw;
+            A h = nt_load(&hi[r]);
+            A c{};
+            if constexpr (NP == 2) c = nt_load(&lo[r]);
+            Fold<K>::add(h, c, part[l]);
+            nt_store(h, &hi[r]);
+            if constexpr (NP == 2) nt_store(c, &lo[r]);
+        }
+    }
+}
+
+// Waves of the eight-lag form from which it is preferred (4 per SIMD of a
+// 256-CU device).
+constexpr int64_t kWindowWideWaves = 4096;
+
+struct WindowShape {
+    int lpb, subs_per_block;
+    unsigned grid_x, grid_y, block;
+};
+
+WindowShape window_shape(const GroupArgs &g, int lb)
+{
+    WindowShape w{};
+    w.lpb = (g.p + kDeferT - 1) / kDeferT;
+    const int n_sub = (w.lpb + lb - 1) / lb;
+    const int by = (n_sub + 7) / 8; // at most 8 waves per block
+    w.subs_per_block = (n_sub + by - 1) / by;
+    w.grid_x = (unsigned)(g.n_tiles * g.tw / 64);
+    w.grid_y = (unsigned)by;
+    w.block = (unsigned)(64 * w.subs_per_block);
+    return w;
+}
+
+template <int LB>
+hipError_t launch_fold_lb(const GroupArgs &g, const int64_t *step, hipStream_t st)
+{
+    const WindowShape w = window_shape(g, LB);
+    const dim3 grid(w.grid_x, w.grid_y), block(w.block);
+    switch (g.kind) {
+    case K_F32_F64: hipLaunchKernelGGL((window_fold_kernel<K_F32_F64, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
+    case K_F32_KAHAN: hipLaunchKernelGGL((window_fold_kernel<K_F32_KAHAN, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
+    case K_F32_F32: hipLaunchKernelGGL((window_fold_kernel<K_F32_F32, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
+    case K_CF32_F64: hipLaunchKernelGGL((window_fold_kernel<K_CF32_F64, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
+    case K_CF32_KAHAN: hipLaunchKernelGGL((window_fold_kernel<K_CF32_KAHAN, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
+    case K_CF32_F32: hipLaunchKernelGGL((window_fold_kernel<K_CF32_F32, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+} // namespace
+
+bool window_deferred_supported(int kind)
+{
+    return kind == K_F32_F64 || kind == K_F32_KAHAN || kind == K_F32_F32 || kind == K_CF32_F64 ||
+           kind == K_CF32_KAHAN || kind == K_CF32_F32;
+}
+
+int window_lags_per_block(int p) { return (p + kDeferT - 1) / kDeferT; }
+
+hipError_t launch_window_fold(const GroupArgs &g, const int64_t *step, hipStream_t st)
+{
+    if (g.levels != 1 || !g.deferred || g.pair || g.tw % 64 != 0 || g.p0 != g.p + 2 * kDeferT)
+        return hipErrorInvalidValue;
+    // Eight lags per wave reuse each loaded value more; four give twice the
+    // waves, which wins while the grid holds fewer than four waves per SIMD
+    // (a few thousand channels, the k-space groups of long windows).
+    const WindowShape w8 = window_shape(g, 8);
+    const int64_t waves8 = (int64_t)w8.grid_x * w8.grid_y * w8.subs_per_block;
+    if (waves8 < kWindowWideWaves) return launch_fold_lb<4>(g, step, st);
+    return launch_fold_lb<8>(g, step, st);
+}
+
+} // namespace corr

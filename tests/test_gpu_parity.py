@@ -463,17 +463,20 @@ def test_currents_with_other_groups_all_launch_modes(corrmod):
          label="rho(k) beside currents")
 
 
-@pytest.mark.parametrize("dtype,accum", [("cf32", "kahan"), ("f32", "f64"), ("f64", "f64")])
-def test_large_window(corrmod, dtype, accum):
-    """One block of p = 10240 points updated every push (the paper's long
-    single-window correlations, p = 10240 with u = 10): parity with the oracle
-    after the ring has wrapped; lag times carry u = 10."""
+@pytest.mark.parametrize("dtype,accum,direct", [("cf32", "kahan", False), ("cf32", "kahan", True),
+                                                ("f32", "f64", False), ("f64", "f64", False)])
+def test_large_window(corrmod, dtype, accum, direct):
+    """One block of p = 10240 points (the paper's long single-window
+    correlations, p = 10240 with u = 10): parity with the oracle after the
+    ring has wrapped, in the block-deferred window form (single-precision
+    samples) and the per-step window kernel (direct, or double samples); lag
+    times carry u = 10."""
     n, S, p = 16, 10500, 10240
-    say(f"[large window] n={n} S={S} p={p} {dtype}/{accum}")
+    say(f"[large window] n={n} S={S} p={p} {dtype}/{accum} direct={direct}")
     x = ou_inputs(31, 2, n, S, dtype, tau=200.0, tau_hi=None)
     o = oracle_run(x, 1, p, 2)
     with corrmod.Correlator([corrmod.GroupDesc(n, 1, p, 2, dtype=dtype, accum=accum,
-                                               update_every=10, dt=0.001)]) as c:
+                                               update_every=10, dt=0.001)], direct=direct) as c:
         _push_all(c, [x])
         res = c.finalize(0, slice_=(0, 4))
     t, _, _ = o.readout()
@@ -481,6 +484,107 @@ def test_large_window(corrmod, dtype, accum):
     res["t"] = t  # the oracle reports steps
     e = gate(res, o, TOL[(dtype, accum)], slice_=(0, 4), label="large window")
     say(f"  error {e:.2e}")
+
+
+WINDOW_KINDS = [("cf32", "kahan"), ("cf32", "f64"), ("cf32", "f32"),
+                ("f32", "kahan"), ("f32", "f64"), ("f32", "f32")]
+
+
+@pytest.mark.parametrize("dtype,accum", WINDOW_KINDS)
+def test_window_deferred_readouts(corrmod, dtype, accum):
+    """One-level windows of p >= 512 points with single-precision samples run
+    block-deferred: each push stages its sample and folds one of 64 lag blocks
+    of the last complete block of 64 pushes.  Readouts before the first fold,
+    at block boundaries, with up to 126 pending pushes, before and after the
+    window fills all match the oracle at that push count, and never change
+    later results (bitwise against an uninterrupted run).  p = 600 is not a
+    multiple of 64 (lag blocks of 10 lags, the last four empty); 300 channels
+    leave a ragged tile."""
+    n, p = 300, 600
+    marks = [1, 2, 63, 64, 65, 127, 128, 129, 190, 599, 600, 601, 700, 777, 1400]
+    S = marks[-1]
+    say(f"[window deferred readouts] {dtype}/{accum} n={n} p={p}")
+    x = ou_inputs(41, 3, n, S, dtype, tau=50.0, tau_hi=None)
+    cplx = np.iscomplexobj(x)
+    o = oracle.OracleCorrelator(n, 1, p, 2, complex_=cplx)
+    dev = torch.device("cuda:0")
+    tx = torch.from_numpy(x).to(dev)
+    g = [corrmod.GroupDesc(n, 1, p, 2, dtype=dtype, accum=accum)]
+    with corrmod.Correlator(g) as c, corrmod.Correlator(g) as ref:
+        done = 0
+        for mk in marks:
+            for s in range(done, mk):
+                c.push([tx[s]])
+                ref.push([tx[s]])
+                o.push(x[s].astype(np.complex128 if cplx else np.float64))
+            done = mk
+            res = c.finalize(0, slice_=(n - 3, n))
+            gate(res, o, TOL[(dtype, accum)], slice_=(n - 3, n), label=f"S={mk}")
+        a, r = c.finalize(0, slice_=(0, n)), ref.finalize(0, slice_=(0, n))
+        assert np.array_equal(a["c"], r["c"])
+        assert np.array_equal(a["c_per_channel"], r["c_per_channel"])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "cf32"])
+def test_window_deferred_equals_direct(corrmod, dtype):
+    """The block-deferred window regroups the sums of the per-step window
+    kernel: with FP64 sums of exact single-precision products the two agree to
+    rounding, per channel and for the group mean."""
+    n, S, p = 1000, 1500, 1024
+    say(f"[window deferred vs direct] {dtype}")
+    x = ou_inputs(42, 5, n, S, dtype, tau=80.0, tau_hi=None)
+    g = [corrmod.GroupDesc(n, 1, p, 2, dtype=dtype, accum="f64")]
+    with corrmod.Correlator(g) as d, corrmod.Correlator(g, direct=True) as e:
+        _push_all(d, [x])
+        _push_all(e, [x])
+        rd, re_ = d.finalize(0, slice_=(0, 40)), e.finalize(0, slice_=(0, 40))
+    assert np.array_equal(rd["count"], re_["count"])
+    assert np.max(np.abs(rd["c"] - re_["c"])) <= 1e-12 * abs(re_["c"][0])
+    scale = np.abs(re_["c_per_channel"][:, :1])
+    assert np.max(np.abs(rd["c_per_channel"] - re_["c_per_channel"]) / scale) <= 1e-12
+
+
+def test_window_deferred_fed_by_producer_all_launch_modes(corrmod):
+    """A long window fed by the k-density producer (staged after the
+    producer), next to a block-deferred group and a per-step group: batched,
+    per-group, graph and overlapped-producer launches give bit-identical window
+    results, which match the oracle."""
+    S, N, box, p = 700, 1000, 30.0, 512
+    kv = synth.kvectors(48)
+    xv = ou_inputs(44, 1, 1500, S, "f32")
+    xg = ou_inputs(44, 2, 9, S, "f64")
+    pos, _ = synth.PositionSpec(44, 3, N, box).series(0, S)
+    groups = [corrmod.GroupDesc(1500, 5, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(9, 6, 16, 2, dtype="f64", accum="f64"),
+              corrmod.GroupDesc(len(kv), 1, p, 2, dtype="cf32", accum="kahan", source="rhok",
+                                kvec=kv, n_atoms=N, box=box)]
+    dev = torch.device("cuda:0")
+    out = {}
+    for mode in ("batched", "per_group", "graph", "overlap"):
+        say(f"[window fed by producer] mode={mode}")
+        tuning = {"overlap_producers": 1} if mode == "overlap" else None
+        with corrmod.Correlator(groups, graph=(mode == "graph"), per_group=(mode == "per_group"),
+                                tuning=tuning) as c:
+            ta, tb, tc = (torch.from_numpy(a).to(dev) for a in (xv, xg, pos))
+            if mode == "graph":
+                ba, bb, bc = torch.empty_like(ta[0]), torch.empty_like(tb[0]), torch.empty_like(tc[0])
+                c.bind_input(0, ba); c.bind_input(1, bb); c.bind_input(2, bc)
+                for s in range(S):
+                    ba.copy_(ta[s]); bb.copy_(tb[s]); bc.copy_(tc[s])
+                    c.push()
+            else:
+                for s in range(S):
+                    c.push([ta[s], tb[s], tc[s]])
+            torch.cuda.synchronize()
+            out[mode] = c.finalize(2, slice_=(0, 4))
+    for mode in ("per_group", "graph", "overlap"):
+        assert np.array_equal(out[mode]["c_per_channel"], out["batched"]["c_per_channel"]), mode
+        assert np.array_equal(out[mode]["c"], out["batched"]["c"]), mode
+    o = oracle.OracleCorrelator(len(kv), 1, p, 2, complex_=True)
+    for s in range(S):
+        o.push(oracle.rhok(pos[s], kv, box))
+    gate(out["batched"], o, TOL[("cf32", "kahan")], scale=1.0 / N, slice_=(0, 4),
+         label="window fed by rho(k)")
 
 
 def _pair_inputs(seed, n, S, dtype):
@@ -570,9 +674,9 @@ def test_pair_group_in_all_launch_modes(corrmod):
 
 def test_push_steps_equals_single_pushes(corrmod):
     """corr_push_steps replays a stored history: the same state, bit for bit,
-    as one push per step -- for block-deferred, per-step, pair and k-density
-    groups in one context, across flush boundaries, with a readout between two
-    replays."""
+    as one push per step -- for block-deferred, per-step, pair, k-density and
+    long-window groups in one context, across flush boundaries, with a readout
+    between two replays."""
     S, nv, N, box = 200, 3000, 800, 25.0
     kv = synth.kvectors(24)
     xv = ou_inputs(51, 1, nv, S, "f32")
@@ -580,27 +684,29 @@ def test_push_steps_equals_single_pushes(corrmod):
     x, y = _pair_inputs(51, 300, S, "f32")
     xy = np.ascontiguousarray(np.stack([x, y], axis=1))
     pos, _ = synth.PositionSpec(51, 3, N, box).series(0, S)
+    xw = ou_inputs(51, 4, 200, S, "cf32")
     groups = [corrmod.GroupDesc(nv, 6, 16, 2, dtype="f32", accum="kahan"),
               corrmod.GroupDesc(9, 8, 16, 2, dtype="f64", accum="f64"),
               corrmod.GroupDesc(300, 5, 16, 2, dtype="f32", accum="kahan", pair=True),
               corrmod.GroupDesc(len(kv), 4, 16, 2, dtype="cf32", accum="kahan", source="rhok",
-                                kvec=kv, n_atoms=N, box=box)]
+                                kvec=kv, n_atoms=N, box=box),
+              corrmod.GroupDesc(200, 1, 640, 2, dtype="cf32", accum="kahan")]
     dev = torch.device("cuda:0")
-    hs = [torch.from_numpy(a).to(dev) for a in (xv, xg, xy, pos)]
+    hs = [torch.from_numpy(a).to(dev) for a in (xv, xg, xy, pos, xw)]
     with corrmod.Correlator(groups) as a, corrmod.Correlator(groups) as b:
         for s in range(S):
             a.push([h[s] for h in hs])
         b.push_steps([h[:77] for h in hs])
-        mid = [b.finalize(g, slice_=(0, 3)) for g in range(4)]
+        mid = [b.finalize(g, slice_=(0, 3)) for g in range(5)]
         b.push_steps([h[77:] for h in hs])
         torch.cuda.synchronize()
         assert a.n_pushes() == b.n_pushes() == S
-        for g in range(4):
+        for g in range(5):
             ra, rb = a.finalize(g, slice_=(0, 3)), b.finalize(g, slice_=(0, 3))
             assert np.array_equal(ra["c"], rb["c"]), g
             assert np.array_equal(ra["c_per_channel"], rb["c_per_channel"]), g
         assert len(mid[0]["t"]) > 0
         short = torch.zeros((2, 10), dtype=torch.float32, device=dev)  # rows below 3N floats
         with pytest.raises(corrmod.CorrError):
-            b.push_steps([hs[0][:2], hs[1][:2], hs[2][:2], short])
+            b.push_steps([hs[0][:2], hs[1][:2], hs[2][:2], short, hs[4][:2]])
         assert b.n_pushes() == S  # rejected before anything was issued
