@@ -263,7 +263,17 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
  * block means and counts as Algorithm 1, only the grouping of the
  * floating-point sums differs.  A readout first folds complete blocks a
  * subset has not folded yet (exactly what its scheduled flush would do), then
- * folds the pushes after the last block without modifying state. */
+ * folds the pushes after the last block without modifying state.
+ *
+ * Block-deferred window: a group with one level (b = 1), p >= 512 points and
+ * single-precision samples (real or complex, any accumulator; not pair
+ * groups; unless CORR_FLAG_DIRECT) keeps a ring of p + 128 samples; a push
+ * stages its sample and, at push 64q + j, adds the products of block q
+ * (pushes 64(q-1)+1 .. 64q) to the lags of lag block j (lags j ceil(p/64)
+ * .. (j+1) ceil(p/64) - 1).  A readout adds the products of the pushes each
+ * lag block has not folded yet from the ring, without modifying state.
+ * Other one-level groups with p >= 512 take a per-step window kernel that
+ * splits the lag range over the grid. */
 int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n, int32_t reset);
 
 /* Launch shape in use. */
