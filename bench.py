@@ -79,9 +79,9 @@ def parse():
                     help="per-step update of every channel (no block-deferred form)")
     ap.add_argument("--rhok-valu", action="store_true",
                     help="k-density producer on the vector units instead of the matrix cores")
-    ap.add_argument("--overlap", type=int, choices=[0, 1], default=None,
-                    help="force producers onto a forked stream (1) or the context's stream (0) "
-                         "instead of the autotuner's choice")
+    ap.add_argument("--overlap", type=int, choices=[0, 1, 2], default=None,
+                    help="issue order instead of the autotuner's choice: 0 one stream, 1 producers "
+                         "forked, 2 per-step updates forked beside the flush")
     return ap.parse_args()
 
 
@@ -558,9 +558,10 @@ def run(args):
                    "update_form": "direct" if args.direct else "block-deferred where supported",
                    "rhok_producer": "vector units" if args.rhok_valu else "matrix cores",
                    "push_calls": "one corr_push_steps per chunk" if args.replay else "one corr_push per step",
-                   "producer_stream": ("forked, overlapping the other updates"
-                                       if corr.tuning()["overlap_producers"]
-                                       else "the context's stream, before the other updates"),
+                   "producer_stream": {0: "the context's stream, before the other updates",
+                                       1: "forked, overlapping the other updates",
+                                       2: "the context's stream; the per-step updates forked "
+                                          "beside the flush"}[corr.tuning()["overlap_producers"]],
                    "tuning": corr.tuning(), "state_GB": round(state_gb, 2)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,

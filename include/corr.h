@@ -125,8 +125,8 @@ typedef struct corr_group_desc {
  * channels (the state layout depends on it, so it is fixed at create); each
  * thread handles chans_per_thread consecutive channels of a tile; the batched
  * kernel runs grid_blocks blocks that stride over all tiles of all groups
- * (0 = one block per tile).  overlap_producers chooses how the n(k) / current
- * producers of a context that also has sample-fed groups are issued.  Zeros
+ * (0 = one block per tile).  overlap_producers chooses which work of a push
+ * is issued on a second stream (results are the same in every mode).  Zeros
  * everywhere select the library defaults (or the autotuner's cached
  * choice). */
 typedef struct corr_tuning {
@@ -135,9 +135,14 @@ typedef struct corr_tuning {
     int32_t chans_per_thread; /* 1, 2 or 4                                          */
     int32_t lag_chunk;        /* lags loaded per batch: 4, 8 or 16                  */
     int32_t grid_blocks;      /* 0 = one block per tile                              */
-    int32_t overlap_producers; /* 0: producers (and their groups' updates) run on
-                                  the context's stream before the other updates;
-                                  1: on a forked stream, concurrently with them */
+    int32_t overlap_producers; /* 0: everything on the context's stream:
+                                  staging, producers, per-step updates, flush;
+                                  1: producers (and their groups' updates) on a
+                                  forked stream, concurrently with the other
+                                  updates; 2: producers first, then the
+                                  per-step updates on a forked stream,
+                                  concurrently with the flush of the
+                                  block-deferred groups                        */
 } corr_tuning;
 
 /*
@@ -247,8 +252,10 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
  * events (created without a system-scope fence).  which = 0: per push, on the
  * context's stream, from before the staging / push kernel launch(es) to after
  * the flush launch(es) of that push, i.e. the correlator-update kernels of
- * the main stream (excluding a forked k-density branch and the step
- * counter); *n = timed pushes.  which = 1: the fold kernel of the scheduled
+ * the main stream (excluding a k-density branch forked with
+ * overlap_producers = 1, including the per-step updates forked with
+ * overlap_producers = 2, and excluding the push's end kernel); *n = timed
+ * pushes.  which = 1: the fold kernel of the scheduled
  * flush of block-deferred groups only (one per push); *n = timed flushes.
  * which = 2: each k-density producer launch, on the stream it runs on (the
  * forked side stream when other groups share the context); *n = timed

@@ -160,13 +160,17 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
             best_t = cand;
         }
     }
-    // Producers next to sample-fed groups: also try overlapping them on a
-    // forked stream with the best shape.
+    // With the best shape, also try the forked issue orders: the producers
+    // (next to sample-fed groups) on a side stream, and the per-step pushes
+    // beside the flush of block-deferred groups.  The trial timing covers
+    // every stream (the events bracket whole pushes).
     bool producer = false, sampled = false;
     for (int i = 0; i < n_groups; ++i) (groups[i].source == CORR_SRC_SAMPLES ? sampled : producer) = true;
-    if (best < 1e300 && producer && sampled) {
+    for (int mode = 1; mode <= 2 && best < 1e300; ++mode) {
+        if (mode == 1 && !(producer && sampled)) continue;
+        if (mode == 2 && n_groups < 2) continue;
         corr_tuning ov = best_t;
-        ov.overlap_producers = 1;
+        ov.overlap_producers = mode;
         const double ms = trial_ms(ov);
         if (ms >= 0.0 && ms < best) {
             best = ms;

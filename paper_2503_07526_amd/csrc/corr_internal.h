@@ -156,6 +156,15 @@ struct RhokMfmaArgs {
     const double *basis;     // nw == 3: [nk][3][3] rows khat, e1, e2
 };
 
+// End of a push: record the scheduled flush of each block-deferred group,
+// then advance the device push counter.
+struct PushEndArgs {
+    int64_t *step;
+    int32_t n_flushed;                 // block-deferred groups
+    int32_t pad_;
+    int64_t *flushed[kMaxGroups];      // their [kFlushGroups] last-folded arrays
+};
+
 // Readout reduction arguments.
 struct ReduceArgs {
     const char *state;

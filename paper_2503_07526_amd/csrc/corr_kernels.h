@@ -14,7 +14,7 @@ hipError_t launch_push_group(const GroupArgs &g, const int64_t *step, int cpt, i
                              hipStream_t st);
 hipError_t launch_push_window(const GroupArgs &g, const int64_t *step, int cpt, int lch,
                               int block, int lags_per_block, hipStream_t st);
-hipError_t launch_step_increment(int64_t *step, hipStream_t st);
+hipError_t launch_push_end(const PushEndArgs &a, hipStream_t st); // flush records + step counter
 hipError_t launch_rhok(const RhokArgs &a, hipStream_t st);
 int rhok_tile_atoms(int nmax);
 int rhok_block_threads(int n_seg);

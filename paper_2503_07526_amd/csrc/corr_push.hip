@@ -408,9 +408,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
         lag_loop<K, CPT, LCH>(x, y, ring, hi, lo, slot, p, l_begin, l_end, 0, tw, lane_off);
 }
 
-__global__ void step_increment_kernel(int64_t *step)
+// Last kernel of a push S = *step + 1: tile group S mod kDeferT of every
+// block-deferred group has folded block S / kDeferT (its flush ran earlier
+// in this push), then the counter advances.
+__global__ void push_end_kernel(PushEndArgs a)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *step = *step + 1;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t S = *a.step + 1;
+    const int j = (int)(S % kDeferT);
+    const int64_t q = S / kDeferT;
+    for (int i = 0; i < a.n_flushed; ++i)
+        if (q >= 1 && a.flushed[i][j] < q) a.flushed[i][j] = q;
+    *a.step = S;
 }
 
 // ------------------------------------------------------------ host launchers
@@ -510,9 +519,10 @@ hipError_t launch_push_window(const GroupArgs &g, const int64_t *step, int cpt, 
                   : launch_push_window_p<false>(g, step, cpt, lch, block, lags_per_block, st);
 }
 
-hipError_t launch_step_increment(int64_t *step, hipStream_t st)
+hipError_t launch_push_end(const PushEndArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(step_increment_kernel, dim3(1), dim3(64), 0, st, step);
+    if (a.n_flushed < 0 || a.n_flushed > kMaxGroups) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(push_end_kernel, dim3(1), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -224,8 +224,8 @@ int validate_tuning(const corr_tuning &t)
         return set_err(nullptr, CORR_E_INVALID, "tuning: tile_channels %d invalid for %d channels/thread",
                        t.tile_channels, cpt);
     if (t.grid_blocks < 0) return set_err(nullptr, CORR_E_INVALID, "tuning: grid_blocks < 0");
-    if (t.overlap_producers != 0 && t.overlap_producers != 1)
-        return set_err(nullptr, CORR_E_INVALID, "tuning: overlap_producers must be 0 or 1");
+    if (t.overlap_producers < 0 || t.overlap_producers > 2)
+        return set_err(nullptr, CORR_E_INVALID, "tuning: overlap_producers must be 0, 1 or 2");
     return CORR_OK;
 }
 
@@ -317,15 +317,14 @@ DeferredArgs deferred_args(const corr_ctx *c, int i)
 }
 
 // Scheduled flush of every block-deferred group for the push being issued
-// (tile group S mod kDeferT folds block S / kDeferT if not done yet).
-// Scheduled flush of every block-deferred group; with events, f0/f1 bracket
-// the fold kernels only (the flag updates follow f1).
+// (tile group S mod kDeferT folds block S / kDeferT if not done yet); with
+// events, f0/f1 bracket the fold kernels.  The flush is recorded as done by
+// the push's last kernel (push_end).
 int launch_flushes(corr_ctx *c, hipStream_t st, hipEvent_t f0, hipEvent_t f1)
 {
     if (f0) HIP_TRY(c, hipEventRecord(f0, st));
     for (int i : c->deferred_set) HIP_TRY(c, launch_flush_fold(deferred_args(c, i), st));
     if (f1) HIP_TRY(c, hipEventRecord(f1, st));
-    for (int i : c->deferred_set) HIP_TRY(c, launch_flush_commit(deferred_args(c, i), st));
     return CORR_OK;
 }
 
@@ -417,9 +416,12 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
 
 // Issue one push of every group on stream `st` with the given per-group
 // sample pointers (already resolved, never NULL).  Order on the main stream:
-// staging of block-deferred groups, fork of the k-density branch (producer +
-// push of the k-density groups on the side stream), per-step push of the
-// other groups, flush (every kDeferT pushes), join, step counter.
+// staging of block-deferred groups, the producers, the per-step push of the
+// other groups, the flush of the block-deferred groups, the push end (flush
+// records and step counter).  overlap_producers = 1 forks the producers and
+// their groups' pushes onto the side stream; 2 keeps the producers on the
+// main stream and forks the per-step pushes, which then run beside the
+// flush.
 int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_flush)
 {
     const size_t ng = c->groups.size();
@@ -427,8 +429,11 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
     for (size_t i = 0; i < ng; ++i) resolved[i] = c->groups[i].rhok ? c->groups[i].rhok_out : src[i];
     // Events are only recorded on direct launches, never while capturing.
     const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream;
-    const bool fork = c->tuning.overlap_producers && !c->side_set.empty() &&
+    const bool fork = c->tuning.overlap_producers == 1 && !c->side_set.empty() &&
                       (!c->main_set.empty() || !c->deferred_set.empty());
+    const bool fork_updates = c->tuning.overlap_producers == 2 && with_flush &&
+                              !c->deferred_set.empty() &&
+                              (!c->main_set.empty() || !c->side_set.empty());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         int rc = next_events(c, 0, &e0, &e1);
@@ -476,8 +481,15 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
         std::vector<int> idx(c->main_set);
         idx.insert(idx.end(), c->side_set.begin(), c->side_set.end());
         if (!idx.empty()) {
-            int rc = launch_set(c, c->pa_direct, idx, resolved, st);
+            hipStream_t ust = st;
+            if (fork_updates) {
+                HIP_TRY(c, hipEventRecord(c->ev_fork, st));
+                HIP_TRY(c, hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+                ust = c->side_stream;
+            }
+            int rc = launch_set(c, c->pa_direct, idx, resolved, ust);
             if (rc != CORR_OK) return rc;
+            if (fork_updates) HIP_TRY(c, hipEventRecord(c->ev_join, ust));
         }
     }
     if (with_flush && !c->deferred_set.empty()) {
@@ -489,9 +501,14 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
         int rc = launch_flushes(c, st, f0, f1);
         if (rc != CORR_OK) return rc;
     }
+    if (fork_updates) HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
     if (timed) HIP_TRY(c, hipEventRecord(e1, st));
     if (fork) HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
-    HIP_TRY(c, launch_step_increment(c->d_step, st));
+    PushEndArgs pe{};
+    pe.step = c->d_step;
+    if (with_flush)
+        for (int i : c->deferred_set) pe.flushed[pe.n_flushed++] = c->groups[(size_t)i].d_flushed;
+    HIP_TRY(c, launch_push_end(pe, st));
     return CORR_OK;
 }
 
@@ -890,7 +907,9 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
             pa.total_tiles = tf;
         }
     }
-    if (!c->side_set.empty() && (!c->main_set.empty() || !c->deferred_set.empty())) {
+    const bool direct_groups = !c->main_set.empty() || !c->side_set.empty();
+    if ((!c->side_set.empty() && (!c->main_set.empty() || !c->deferred_set.empty())) ||
+        (!c->deferred_set.empty() && direct_groups)) {
         CREATE_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
         CREATE_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         CREATE_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));

@@ -98,6 +98,8 @@ def test_currents_descriptor_checks(corrmod, kv, n_channels, rc_want, needle):
     dict(tile_channels=4096, chans_per_thread=1, lag_chunk=16, grid_blocks=0),
     dict(tile_channels=512, chans_per_thread=1, lag_chunk=16, grid_blocks=0),
     dict(tile_channels=2048, chans_per_thread=4, lag_chunk=4, grid_blocks=0),
+    dict(tile_channels=256, chans_per_thread=1, lag_chunk=8, grid_blocks=0, overlap_producers=3),
+    dict(tile_channels=256, chans_per_thread=1, lag_chunk=8, grid_blocks=0, overlap_producers=-1),
 ])
 def test_invalid_tuning_rejected(corrmod, tuning):
     rc, msg = _create(corrmod, corrmod.GroupDesc(64, 4, 16), tuning)

@@ -202,8 +202,9 @@ def test_rhok_kset_shapes(corrmod, case):
 def test_batched_mixed_groups_and_modes(corrmod, rhok_valu):
     """Three uneven groups in one context (compensated FP32 velocities, the
     k-space density, FP64 global channels): parity with the oracle, and
-    bit-identical state from the batched launch, the per-group launches and the
-    HIP graph replay, with either k-density producer."""
+    bit-identical state from the batched launch, the per-group launches, the
+    HIP graph replay and both forked issue orders (producers forked; per-step
+    updates forked beside the flush), with either k-density producer."""
     S, nv, N, box = 400, 2500, 3000, 100.0
     kv = synth.kvectors(200)
     say(f"[batched] S={S} nv={nv} N={N} nk={len(kv)}")
@@ -221,9 +222,13 @@ def test_batched_mixed_groups_and_modes(corrmod, rhok_valu):
     for s in range(S):
         orh.push(oracle.rhok(xp[s], kv, box))
     results = {}
-    for mode in ("batched", "per_group", "graph", "overlap", "overlap_graph"):
+    modes = ("batched", "per_group", "graph", "overlap", "overlap_graph", "overlap2",
+             "overlap2_graph")
+    for mode in modes:
         say(f"  mode {mode}")
-        tuning = {"overlap_producers": 1} if mode.startswith("overlap") else None
+        tuning = None
+        if mode.startswith("overlap"):
+            tuning = {"overlap_producers": 2 if mode.startswith("overlap2") else 1}
         with corrmod.Correlator(groups, graph=mode.endswith("graph"),
                                 per_group=(mode == "per_group"), rhok_valu=rhok_valu,
                                 tuning=tuning) as c:
@@ -241,7 +246,7 @@ def test_batched_mixed_groups_and_modes(corrmod, rhok_valu):
                 for s in range(S):
                     c.push([tv[s], tp[s], tg[s]])
             results[mode] = [c.finalize(g, slice_=(0, 5)) for g in range(3)]
-    for mode in ("per_group", "graph", "overlap", "overlap_graph"):
+    for mode in modes[1:]:
         for g in range(3):
             assert np.array_equal(results[mode][g]["c"], results["batched"][g]["c"]), (mode, g)
             assert np.array_equal(results[mode][g]["c_per_channel"],
@@ -560,9 +565,10 @@ def test_window_deferred_fed_by_producer_all_launch_modes(corrmod):
                                 kvec=kv, n_atoms=N, box=box)]
     dev = torch.device("cuda:0")
     out = {}
-    for mode in ("batched", "per_group", "graph", "overlap"):
+    for mode in ("batched", "per_group", "graph", "overlap", "overlap2"):
         say(f"[window fed by producer] mode={mode}")
-        tuning = {"overlap_producers": 1} if mode == "overlap" else None
+        tuning = {"overlap": {"overlap_producers": 1},
+                  "overlap2": {"overlap_producers": 2}}.get(mode)
         with corrmod.Correlator(groups, graph=(mode == "graph"), per_group=(mode == "per_group"),
                                 tuning=tuning) as c:
             ta, tb, tc = (torch.from_numpy(a).to(dev) for a in (xv, xg, pos))
@@ -577,7 +583,7 @@ def test_window_deferred_fed_by_producer_all_launch_modes(corrmod):
                     c.push([ta[s], tb[s], tc[s]])
             torch.cuda.synchronize()
             out[mode] = c.finalize(2, slice_=(0, 4))
-    for mode in ("per_group", "graph", "overlap"):
+    for mode in ("per_group", "graph", "overlap", "overlap2"):
         assert np.array_equal(out[mode]["c_per_channel"], out["batched"]["c_per_channel"]), mode
         assert np.array_equal(out[mode]["c"], out["batched"]["c"]), mode
     o = oracle.OracleCorrelator(len(kv), 1, p, 2, complex_=True)
