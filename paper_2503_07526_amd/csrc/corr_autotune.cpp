@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/corr.h"
+#include "corr_internal.h"
 #include "corr_tune.h"
 
 namespace corr {
@@ -134,7 +135,7 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
         if (e0) (void)hipEventDestroy(e0);
         return CORR_E_DEVICE;
     }
-    const int period = 64; // whole flush periods of the block-deferred form
+    const int period = kDeferT; // whole flush periods of the block-deferred form
     // ms for 2 periods of pushes after one period of warm-up, or < 0
     auto trial_ms = [&](const corr_tuning &cand) -> double {
         corr_ctx *ctx = nullptr;

@@ -183,12 +183,18 @@ __device__ __forceinline__ void fold_level(Ctx &cx, int k, const typename RK<K>:
 }
 
 // Level 0: fold the r pending pushes (f, f + r] into the lag sums and form the
-// level-1 block means.  out[q] = mean of new values 2q, 2q+1.
+// level-1 block means.  out[q] = mean of new values 2q, 2q+1.  The pushes are
+// taken in chunks of kL0Chunk with a sliding window of the P - 1 values
+// before each chunk, so that only P - 1 + kL0Chunk ring values are live.
+constexpr int kL0Chunk = 64;
+
 template <int K, int P, int T, bool READ>
 __device__ __forceinline__ void level0(Ctx &cx, typename RK<K>::S (&out)[T / 2])
 {
     using S = typename RK<K>::S;
     using PT = typename RK<K>::PT;
+    constexpr int C = T < kL0Chunk ? T : kL0Chunk;
+    static_assert(T % C == 0 && C % 2 == 0, "chunks of whole pairs");
     const DeferredArgs &a = *cx.a;
     const GroupArgs &g = a.g;
     const int tw = g.tw;
@@ -196,35 +202,42 @@ __device__ __forceinline__ void level0(Ctx &cx, typename RK<K>::S (&out)[T / 2])
     const S *ring = reinterpret_cast<const S *>(cx.tb);
     const int64_t f = cx.f;
     const int r = cx.r;
-    S H[P - 1 + T];
-    // old values f-P+2 .. f, then new values f+1 .. f+r (zeros beyond r);
-    // value j sits in slot (j - 1) mod P0, and P - 1 + T < P0, so one
-    // modulo and a wrap per row suffice
+    // W: old values f-P+2 .. f, then the chunk's new values (zeros beyond r);
+    // value j sits in slot (j - 1) mod P0, and P - 1 + T < P0, so one modulo
+    // and a wrap per row suffice
+    S W[P - 1 + C];
     const int slot0 = (int)((f - (P - 2) - 1 + P0) % P0);
+    auto row = [&](int i) -> S { // i-th value from f - P + 2
+        int slot = slot0 + i;
+        if (slot >= P0) slot -= P0;
+        return __builtin_nontemporal_load(&ring[(size_t)slot * tw + cx.lane]);
+    };
 #pragma unroll
-    for (int i = 0; i < P - 1 + T; ++i) {
-        const int q = i - (P - 1);
-        if (q < r) {
-            int slot = slot0 + i;
-            if (slot >= P0) slot -= P0;
-            H[i] = __builtin_nontemporal_load(&ring[(size_t)slot * tw + cx.lane]);
-        } else {
-            H[i] = S(0);
-        }
-    }
+    for (int i = 0; i < P - 1; ++i) W[i] = row(i);
     PT part[P];
 #pragma unroll
     for (int L = 0; L < P; ++L) part[L] = PT(0);
 #pragma unroll
-    for (int q = 0; q < T; ++q) {
-        if (q < r) {
-            const S x = H[P - 1 + q];
+    for (int c0 = 0; c0 < T; c0 += C) {
+        // keep the next chunk's loads after this chunk's products (otherwise
+        // they are hoisted and every chunk's values are live at once)
+        if (c0 > 0) asm volatile("" ::: "memory");
 #pragma unroll
-            for (int L = 0; L < P; ++L) pmac(part[L], x, H[P - 1 + q - L]);
+        for (int q = 0; q < C; ++q) W[P - 1 + q] = c0 + q < r ? row(P - 1 + c0 + q) : S(0);
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            if (c0 + q < r) {
+                const S x = W[P - 1 + q];
+#pragma unroll
+                for (int L = 0; L < P; ++L) pmac(part[L], x, W[P - 1 + q - L]);
+            }
         }
-    }
 #pragma unroll
-    for (int q = 0; q < T / 2; ++q) out[q] = (H[P - 1 + 2 * q] + H[P + 2 * q]) / S(2);
+        for (int q = 0; q < C / 2; ++q)
+            out[c0 / 2 + q] = (W[P - 1 + 2 * q] + W[P + 2 * q]) / S(2);
+#pragma unroll
+        for (int i = 0; i < P - 1; ++i) W[i] = W[i + C];
+    }
     fold_level<K, P, P, READ>(cx, 0, part, r > 0);
 }
 
@@ -318,7 +331,7 @@ __device__ __forceinline__ void cascade(Ctx &cx, int k, const typename RK<K>::S 
 }
 
 template <int K, int P, int T, bool READ>
-__global__ __launch_bounds__(256) void deferred_kernel(DeferredArgs a)
+__device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
 {
     const GroupArgs &g = a.g;
     int64_t f;
@@ -369,6 +382,21 @@ __global__ __launch_bounds__(256) void deferred_kernel(DeferredArgs a)
     }
 }
 
+// The scheduled (or requested) flush: at most two waves per SIMD, so that the
+// register budget covers the whole block of pushes without spilling.
+template <int K, int P, int T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void deferred_kernel(DeferredArgs a)
+{
+    deferred_pass<K, P, T, false>(a);
+}
+
+// The readout pass (no state written).
+template <int K, int P, int T>
+__global__ __launch_bounds__(256) void deferred_read_kernel(DeferredArgs a)
+{
+    deferred_pass<K, P, T, true>(a);
+}
+
 // Column sums of rows [n_rows][ne] in a fixed order: groups of kColGroup rows
 // (grid.y), then the groups in order.
 constexpr int kColGroup = 1024;
@@ -417,8 +445,12 @@ hipError_t launch_deferred_kp(const DeferredArgs &a, hipStream_t st)
     const int block = a.g.tw < 256 ? a.g.tw : 256;
     const int64_t grid = READ ? a.g.n_tiles : a.tiles_per_group;
     if (grid < 1) return hipSuccess;
-    hipLaunchKernelGGL((deferred_kernel<K, P, kDeferT, READ>), dim3((unsigned)grid), dim3(block),
-                       0, st, a);
+    if constexpr (READ)
+        hipLaunchKernelGGL((deferred_read_kernel<K, P, kDeferT>), dim3((unsigned)grid), dim3(block),
+                           0, st, a);
+    else
+        hipLaunchKernelGGL((deferred_kernel<K, P, kDeferT>), dim3((unsigned)grid), dim3(block), 0,
+                           st, a);
     return hipGetLastError();
 }
 

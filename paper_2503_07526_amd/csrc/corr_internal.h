@@ -50,14 +50,17 @@ struct GroupArgs {
     int32_t s_bytes;     // bytes per sample
     int32_t a_bytes;     // bytes per accumulator plane element
     int32_t deferred;    // 1: block-deferred form (pushes only stage samples)
-    int32_t p0;          // ring rows of level 0 (p, or kDeferT + p when deferred)
+    int32_t p0;          // ring rows of level 0 (p; 2 kDeferT + p when block-deferred;
+                         // 2 kWindowT + p for a block-deferred window)
     int32_t pair;        // 1: channels correlate (x, y): samples [2][n_ch], and each
                          // level holds the lagged y ring, then an x ring
     int32_t pad_;
 };
 
 // Pushes staged between two flushes of a block-deferred group.
-constexpr int kDeferT = 64;
+constexpr int kDeferT = 128;
+// Pushes per block of the block-deferred one-level window (corr_window.hip).
+constexpr int kWindowT = 64;
 // Tile groups of a block-deferred group: tile group j folds block q (pushes
 // (kDeferT (q-1), kDeferT q]) at push kDeferT q + j, so every push flushes one
 // group; the level-0 ring keeps 2 kDeferT + p slots.

@@ -227,8 +227,9 @@ __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int6
     constexpr int rings = PAIR ? 2 : 1;
 
     if (g.deferred) {
-        // Block-deferred group: only stage the sample in the level-0 ring
-        // (kDeferT + p slots); the flush pass folds kDeferT pushes at once.
+        // Block-deferred group (or window): only stage the sample in the
+        // level-0 ring of p0 slots; the flush pass folds a block of pushes at
+        // once.
         S *ring = reinterpret_cast<S *>(tb);
         const int slot = (int)((s - 1) % g.p0);
         vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, x);

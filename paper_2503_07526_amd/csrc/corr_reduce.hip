@@ -12,15 +12,15 @@ namespace corr {
 
 // Products of the pushes that a one-level window in the block-deferred form
 // (corr_window.hip) has staged but not yet folded into lag L = e: its lag
-// block j = L / wlpb has folded every block q with kDeferT q + j <= S, so the
-// pushes after f = kDeferT floor((S - j) / kDeferT) are pending.  Summed in
+// block j = L / wlpb has folded every block q with kWindowT q + j <= S, so the
+// pushes after f = kWindowT floor((S - j) / kWindowT) are pending.  Summed in
 // double in push order; pushes s <= L have no lagged value and add nothing.
 __device__ double2 window_pending(const ReduceArgs &a, int e, int64_t c)
 {
     const int L = e;
     const int j = L / a.wlpb;
     const int64_t S = a.n_push;
-    const int64_t f = S >= j ? ((S - j) / kDeferT) * kDeferT : 0;
+    const int64_t f = S >= j ? ((S - j) / kWindowT) * kWindowT : 0;
     const int64_t s1 = f + 1 > (int64_t)L + 1 ? f + 1 : (int64_t)L + 1;
     if (s1 > S) return make_double2(0.0, 0.0);
     const int64_t tile = c / a.tw;

@@ -662,7 +662,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                      deferred_supported(g.kind, g.p, g.m);
         g.wdef = !(flags & CORR_FLAG_DIRECT) && !g.deferred && !g.pair && g.b == 1 &&
                  g.p >= kWindowMinP && window_deferred_supported(g.kind);
-        g.p0 = (g.deferred || g.wdef) ? 2 * kDeferT + g.p : g.p;
+        g.p0 = g.deferred ? 2 * kDeferT + g.p : g.wdef ? 2 * kWindowT + g.p : g.p;
         // pair groups: each level holds the lagged y ring, then an x ring
         const int rings = g.pair ? 2 : 1;
         g.lvl0_bytes = rings * g.p0 * rowS + (int64_t)g.np * g.p * rowA;

@@ -3,27 +3,27 @@
 // A one-level group with p points (Algorithm 1 with b = 1: lags 0..p-1 of the
 // raw series) costs p products per channel per push, and updating all p
 // accumulators on every push moves every accumulator row through HBM once per
-// push.  The sums are linear, so the products of kDeferT consecutive pushes
+// push.  The sums are linear, so the products of kWindowT consecutive pushes
 // can be added in one pass: each push only stages its sample in a ring of
-// P0 = p + 2 kDeferT slots (the push kernels' staging branch), and the lag
-// range is cut into kDeferT lag blocks of lpb = ceil(p / kDeferT) lags.  At
-// push kDeferT q + j, lag block j folds block q (pushes kDeferT (q-1) + 1 ..
-// kDeferT q) of every channel: the kDeferT x lpb products x_s conj(x_{s-L})
+// P0 = p + 2 kWindowT slots (the push kernels' staging branch), and the lag
+// range is cut into kWindowT lag blocks of lpb = ceil(p / kWindowT) lags.  At
+// push kWindowT q + j, lag block j folds block q (pushes kWindowT (q-1) + 1 ..
+// kWindowT q) of every channel: the kWindowT x lpb products x_s conj(x_{s-L})
 // are summed in registers and added once to the stored accumulators.  Every
-// push therefore does the same work (p products per channel, 1/kDeferT of the
+// push therefore does the same work (p products per channel, 1/kWindowT of the
 // accumulator rows), and each accumulator row is read and written once per
-// kDeferT pushes.
+// kWindowT pushes.
 //
 // Ring: value v (1-based) sits in slot (v - 1) mod P0.  When lag block j
-// folds block q at push kDeferT q + j, the oldest value it reads is
-// kDeferT (q - 1) + 1 - (p - 1), and the slots still hold every value from
-// kDeferT q + j - P0 + 1 on, which is older for every j < kDeferT.  Values
+// folds block q at push kWindowT q + j, the oldest value it reads is
+// kWindowT (q - 1) + 1 - (p - 1), and the slots still hold every value from
+// kWindowT q + j - P0 + 1 on, which is older for every j < kWindowT.  Values
 // before the first push (v <= 0) map to slots that have not been written
 // yet and read as the zeros the state is created with, so the products of
 // lags longer than the series add nothing, as the counts max(0, S - L) say.
 //
 // A readout adds, for lag L of lag block j, the products of the pushes after
-// the last block that lag block folded (at most 2 kDeferT - 2 of them) on the
+// the last block that lag block folded (at most 2 kWindowT - 2 of them) on the
 // fly from the ring, without writing state (corr_reduce.hip).
 //
 // Threads: a wave holds 64 consecutive channels (one per lane) and a
@@ -113,7 +113,7 @@ template <> struct Fold<K_CF32_F32> {
 };
 
 // Streaming loads and stores of accumulator elements (touched once per
-// kDeferT pushes); the complex types go through clang vector types.
+// kWindowT pushes); the complex types go through clang vector types.
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef double d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float nt_load(const float *p) { return __builtin_nontemporal_load(p); }
@@ -165,8 +165,8 @@ __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int
     // Push P = *step + 1 (its sample is already staged): lag block j folds
     // block q.
     const int64_t P = *step + 1;
-    const int j = (int)(P % kDeferT);
-    const int64_t q = P / kDeferT;
+    const int j = (int)(P % kWindowT);
+    const int64_t q = P / kWindowT;
     if (q < 1) return;
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
@@ -184,9 +184,9 @@ __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int
     char *tb = g.state + tile * g.tile_bytes;
     const S *ring = reinterpret_cast<const S *>(tb) + tl;
 
-    // New values s0 .. s0 + kDeferT - 1; the window starts at value
+    // New values s0 .. s0 + kWindowT - 1; the window starts at value
     // s0 - L0 - (LB - 1).
-    const int64_t s0 = (q - 1) * kDeferT + 1;
+    const int64_t s0 = (q - 1) * kWindowT + 1;
     int sn = wrap_slot(s0, p0);
     int so = wrap_slot(s0 - L0 - (LB - 1), p0);
     S W[LB - 1 + U];
@@ -208,14 +208,14 @@ __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int
         so = next_slot(so, p0);
     }
 #pragma unroll 1
-    for (int i = 0; i < kDeferT; i += U) {
+    for (int i = 0; i < kWindowT; i += U) {
         S N[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             N[u] = Nn[u];
             W[LB - 1 + u] = Wn[u];
         }
-        if (i + U < kDeferT) {
+        if (i + U < kWindowT) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 Nn[u] = ring[(size_t)sn * tw];
@@ -261,7 +261,7 @@ struct WindowShape {
 WindowShape window_shape(const GroupArgs &g, int lb)
 {
     WindowShape w{};
-    w.lpb = (g.p + kDeferT - 1) / kDeferT;
+    w.lpb = (g.p + kWindowT - 1) / kWindowT;
     const int n_sub = (w.lpb + lb - 1) / lb;
     const int by = (n_sub + 7) / 8; // at most 8 waves per block
     w.subs_per_block = (n_sub + by - 1) / by;
@@ -296,11 +296,11 @@ bool window_deferred_supported(int kind)
            kind == K_CF32_KAHAN || kind == K_CF32_F32;
 }
 
-int window_lags_per_block(int p) { return (p + kDeferT - 1) / kDeferT; }
+int window_lags_per_block(int p) { return (p + kWindowT - 1) / kWindowT; }
 
 hipError_t launch_window_fold(const GroupArgs &g, const int64_t *step, hipStream_t st)
 {
-    if (g.levels != 1 || !g.deferred || g.pair || g.tw % 64 != 0 || g.p0 != g.p + 2 * kDeferT)
+    if (g.levels != 1 || !g.deferred || g.pair || g.tw % 64 != 0 || g.p0 != g.p + 2 * kWindowT)
         return hipErrorInvalidValue;
     // Eight lags per wave reuse each loaded value more; four give twice the
     // waves, which wins while the grid holds fewer than four waves per SIMD
