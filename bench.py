@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--compare-plain", action="store_true",
                     help="also time the plain FP64 per-group form on the same velocity channels")
     ap.add_argument("--tuning", default=None, help="JSON dict of corr_tuning fields")
+    ap.add_argument("--timing-stride", type=int, default=8,
+                    help="record the HIP timing events on one push in this many (each event pair "
+                         "costs a few microseconds of the push it brackets)")
     ap.add_argument("--direct", action="store_true",
                     help="per-step update of every channel (no block-deferred form)")
     ap.add_argument("--rhok-valu", action="store_true",
@@ -447,6 +450,7 @@ def run(args):
     corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuning, timing=True,
                       direct=args.direct, rhok_valu=args.rhok_valu)
     state_gb = sum(corr.state_bytes(i) for i in range(len(descs))) / 1e9
+    corr.set_timing_stride(args.timing_stride)
 
     def push_chunk(n):
         for gen, buf in zip(gens, bufs):
@@ -479,19 +483,22 @@ def run(args):
         wall += push_chunk(n)
         done += n
     kern_ms, kern_n = corr.kernel_time(0)
-    assert kern_n == K, (kern_n, K)
+    # the library times push s (1-based) when s - 1 is a multiple of the stride
+    steps = range(s_first, s_first + K)
+    sampled = [s for s in steps if (s - 1) % args.timing_stride == 0]
+    assert kern_n == len(sampled), (kern_n, len(sampled))
     # The timed launch: with k-density groups next to other groups, those run
     # (producer + own push) on a forked side stream and the events bracket the
     # push launch of the other groups only.
     has_rhok = any(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
     timed = [g for g in wl["groups"]
              if not (has_rhok and len(wl["groups"]) > 1 and g["kind"] in PRODUCER_KINDS)]
-    steps = range(s_first, s_first + K)
     direct = args.direct
-    stage_bytes = sum(push_bytes(g, s, direct) for g in timed for s in steps)
+    # algorithmic bytes of the timed (sampled) pushes, to go with their event times
+    stage_bytes = sum(push_bytes(g, s, direct) for g in timed for s in sampled)
     tw = corr.tuning()["tile_channels"]
     fl_bytes = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
-                   for s in steps)
+                   for s in sampled)
     fl_ms, fl_n = corr.kernel_time(which=1)
     rk_ms, rk_n = corr.kernel_time(which=2)
     n_total = sum(g["n"] for g in wl["groups"])
@@ -504,16 +511,16 @@ def run(args):
         # the producers of every k-space group, per push (HIP events on their
         # stream; several producer launches per push)
         flop_per = sum(producer_flop(g) for g in wl["groups"] if g["kind"] in PRODUCER_KINDS)
-        per_launch_ms = rk_ms / K
+        per_launch_ms = rk_ms / kern_n
         achieved = flop_per / (per_launch_ms * 1e-3) / 1e12
         kname = ("k-space producers (matrix cores), HIP events around the %d producer launches of "
-                 "a push" % (rk_n // K))
+                 "a push" % (rk_n // kern_n))
         per_launch_bytes = None
     elif push_dominant:
         # the per-step correlator update of every group (direct form): the
         # push events minus the producer launches they contain
-        push_ms = (kern_ms - rk_ms) / K
-        push_bytes_step = sum(step_bytes(g, s) for g in wl["groups"] for s in steps) / K
+        push_ms = (kern_ms - rk_ms) / kern_n
+        push_bytes_step = sum(step_bytes(g, s) for g in wl["groups"] for s in sampled) / kern_n
         achieved = push_bytes_step / (push_ms * 1e-3) / 1e9
         kname = ("push kernel (per-step update of every channel's window), HIP events per push "
                  "less the producer launches")
@@ -539,7 +546,7 @@ def run(args):
         achieved = (stage_bytes + fl_bytes) / (kern_ms * 1e-3) / 1e9
         kname = ("push kernel (correlator update of %d of %d groups), HIP events per launch"
                  % (len(timed), len(wl["groups"])))
-        per_launch_ms, per_launch_bytes = kern_ms / kern_n, (stage_bytes + fl_bytes) / K
+        per_launch_ms, per_launch_bytes = kern_ms / kern_n, (stage_bytes + fl_bytes) / kern_n
     update_gbs = (stage_bytes + fl_bytes) / (kern_ms * 1e-3) / 1e9
     out = {
         "metric": "channel-samples/sec into correlators",
@@ -570,7 +577,8 @@ def run(args):
                      "alg_bytes_per_launch": per_launch_bytes,
                      "update_kernels_GBs": update_gbs,
                      "update_ms_per_step": kern_ms / kern_n,
-                     "alg_bytes_per_step": (stage_bytes + fl_bytes) / K},
+                     "alg_bytes_per_step": (stage_bytes + fl_bytes) / kern_n,
+                     "timed_pushes": kern_n, "timing_stride": args.timing_stride},
     }
     if rk_n:
         out["roofline"]["producer_ms_per_launch"] = rk_ms / rk_n
@@ -580,7 +588,7 @@ def run(args):
         # less the producer launches they contain
         wb = sum(window_push_cost(g)[0] for g in wins)
         wf = sum(window_push_cost(g)[1] for g in wins)
-        wms = (kern_ms - rk_ms) / K
+        wms = (kern_ms - rk_ms) / kern_n
         out["window_update"] = {
             "kernels": "staging + one lag-block fold per group and push",
             "ms_per_push": wms, "alg_bytes_per_push": wb, "alg_flop_per_push": wf,
@@ -609,7 +617,7 @@ def run(args):
         out["error_vs_fp64"] = spot_check(corr, wl, W + K)
     corr.close()
     if args.compare_plain:
-        out["plain_form"] = compare_plain(wl, K, W, chunk)
+        out["plain_form"] = compare_plain(wl, K, W, chunk, args.timing_stride)
         out["plain_form"]["speedup_of_this_form"] = value / out["plain_form"]["value"]
     return out, wl
 
@@ -749,7 +757,7 @@ def precision(args):
             "runs": runs}
 
 
-def compare_plain(wl, K, W, chunk):
+def compare_plain(wl, K, W, chunk, stride):
     """The velocity group alone in the plain form (FP64 sums, per-group launch)."""
     import torch
 
@@ -762,6 +770,7 @@ def compare_plain(wl, K, W, chunk):
     buf = torch.empty((chunk, g["n"]), dtype=torch.float32, device="cuda")
     corr = Correlator([GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype="f32",
                                  accum="f64")], per_group=True, timing=True, direct=True)
+    corr.set_timing_stride(stride)
     wall, done = 0.0, 0
     while done < W + K:
         n = min(chunk, W + K - done)

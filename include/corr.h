@@ -283,6 +283,15 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
  * splits the lag range over the grid. */
 int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n, int32_t reset);
 
+/* With CORR_FLAG_TIMING: record the timing events (all three kinds of
+ * corr_kernel_time) only on pushes whose index n (pushes completed before it)
+ * satisfies n % stride == 0, so that the events themselves (each one a
+ * completion signal between two kernels) slow the other pushes down by
+ * nothing; the times and counts of corr_kernel_time then cover those pushes
+ * only.  stride >= 1 (default 1: every push); CORR_E_INVALID otherwise,
+ * CORR_E_STATE without the flag.  Takes effect from the next push. */
+int corr_set_timing_stride(corr_ctx *ctx, int32_t stride);
+
 /* Launch shape in use. */
 int corr_get_tuning(const corr_ctx *ctx, corr_tuning *out);
 

@@ -62,7 +62,7 @@ class _ReadoutOpts(ctypes.Structure):
 EXPORTS = ["corr_create", "corr_input_buffer", "corr_bind_input", "corr_push", "corr_push_steps",
            "corr_query",
            "corr_finalize", "corr_sync", "corr_destroy", "corr_last_error", "corr_state_bytes",
-           "corr_get_tuning", "corr_kernel_time", "corr_autotune"]
+           "corr_get_tuning", "corr_kernel_time", "corr_set_timing_stride", "corr_autotune"]
 
 _lib = None
 
@@ -92,6 +92,7 @@ def lib():
         L.corr_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.corr_kernel_time.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i64), i32]
+        L.corr_set_timing_stride.argtypes = [vp, i32]
         L.corr_autotune.argtypes = [ctypes.POINTER(_GroupDesc), i32, i32, vp, ctypes.c_uint32,
                                     ctypes.c_char_p, i64, i32, ctypes.POINTER(Tuning)]
         for name in EXPORTS:
@@ -270,6 +271,10 @@ class Correlator:
         self._check(lib().corr_kernel_time(self._h, int(which), ctypes.byref(ms), ctypes.byref(n),
                                            int(reset)))
         return float(ms.value), int(n.value)
+
+    def set_timing_stride(self, stride: int) -> None:
+        """Record the timing events on one push in `stride` only."""
+        self._check(lib().corr_set_timing_stride(self._h, int(stride)))
 
     def tuning(self) -> dict:
         t = Tuning()

@@ -73,6 +73,7 @@ struct corr_ctx {
     std::vector<Group> groups;
     int64_t *d_step = nullptr;
     int64_t n_push = 0;
+    int32_t timing_stride = 1; // CORR_FLAG_TIMING: events on pushes with n_push % stride == 0
     PushArgs pargs{};
     int64_t total_tiles = 0;
     hipStream_t cap_stream = nullptr;
@@ -427,8 +428,10 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
     const size_t ng = c->groups.size();
     std::vector<const void *> resolved(ng);
     for (size_t i = 0; i < ng; ++i) resolved[i] = c->groups[i].rhok ? c->groups[i].rhok_out : src[i];
-    // Events are only recorded on direct launches, never while capturing.
-    const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream;
+    // Events are only recorded on direct launches, never while capturing, on
+    // one push in timing_stride.
+    const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream &&
+                       c->n_push % c->timing_stride == 0;
     const bool fork = c->tuning.overlap_producers == 1 && !c->side_set.empty() &&
                       (!c->main_set.empty() || !c->deferred_set.empty());
     const bool fork_updates = c->tuning.overlap_producers == 2 && with_flush &&
@@ -974,7 +977,7 @@ int corr_push(corr_ctx *ctx, const void *const *samples)
     const bool with_flush = !ctx->deferred_set.empty();
     if (ctx->gexec && all_default) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (ctx->flags & CORR_FLAG_TIMING) {
+        if ((ctx->flags & CORR_FLAG_TIMING) && ctx->n_push % ctx->timing_stride == 0) {
             int rc = next_events(ctx, 0, &e0, &e1);
             if (rc != CORR_OK) return rc;
             HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
@@ -1052,6 +1055,16 @@ int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n,
         pl.ms = 0.0;
         pl.n = 0;
     }
+    return CORR_OK;
+}
+
+int corr_set_timing_stride(corr_ctx *ctx, int32_t stride)
+{
+    if (!ctx) return CORR_E_INVALID;
+    if (stride < 1) return set_err(ctx, CORR_E_INVALID, "timing stride must be >= 1");
+    if (!(ctx->flags & CORR_FLAG_TIMING))
+        return set_err(ctx, CORR_E_STATE, "timing stride without CORR_FLAG_TIMING");
+    ctx->timing_stride = stride;
     return CORR_OK;
 }
 

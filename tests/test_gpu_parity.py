@@ -349,7 +349,8 @@ def test_autotune_picks_and_caches(corrmod, tmp_path):
 def test_kernel_time_pools(corrmod):
     """CORR_FLAG_TIMING: one push-event pair, one flush-fold pair and one
     producer pair per push in a context with a block-deferred group and a
-    k-density group; positive summed times; reset clears the counters."""
+    k-density group; positive summed times; reset clears the counters; with a
+    timing stride only one push in `stride` is timed, and state is unchanged."""
     S, nv, N, box = 70, 4096, 2000, 50.0
     kv = synth.kvectors(64)
     xv = ou_inputs(8, 1, nv, S, "f32")
@@ -366,6 +367,20 @@ def test_kernel_time_pools(corrmod):
         assert c.kernel_time(2) == (0.0, 0)
         with pytest.raises(corrmod.CorrError):
             c.kernel_time(3)
+    # one push in 8 timed (pushes 0, 8, ..., 64 of 70): same state as every push timed
+    with corrmod.Correlator(groups, timing=True) as c, corrmod.Correlator(groups) as ref:
+        c.set_timing_stride(8)
+        with pytest.raises(corrmod.CorrError):
+            c.set_timing_stride(0)
+        _push_all(c, [xv, xp])
+        _push_all(ref, [xv, xp])
+        for which in (0, 1, 2):
+            ms, n = c.kernel_time(which)
+            assert n == 9 and ms > 0.0, (which, n, ms)
+        assert np.array_equal(c.finalize(0, slice_=(0, 3))["c_per_channel"],
+                              ref.finalize(0, slice_=(0, 3))["c_per_channel"])
+        with pytest.raises(corrmod.CorrError):
+            ref.set_timing_stride(4)  # no CORR_FLAG_TIMING
 
 
 def _currents_inputs(seed, N, box, S):
