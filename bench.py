@@ -232,7 +232,7 @@ AB = {("f32", "f64"): 8, ("f32", "kahan"): 8, ("f32", "f32"): 4, ("f64", "f64"):
       ("cf32", "f64"): 16, ("cf32", "kahan"): 16, ("cf32", "f32"): 8, ("cf64", "f64"): 16}
 
 
-DEFER_T = 128   # pushes per block of the block-deferred form
+DEFER_T = 256   # pushes per block of the block-deferred form
 WINDOW_T = 64   # pushes per block of the block-deferred window
 
 
@@ -243,8 +243,8 @@ def deferred(g, direct=False):
 
 
 def flush_bytes(g, s):
-    """Algorithmic HBM bytes of the flush at push s (s a multiple of 128) for one
-    block-deferred group: level 0 reads the 128 new and 15 older ring values and
+    """Algorithmic HBM bytes of the flush at push s (s a multiple of 256) for one
+    block-deferred group: level 0 reads the 256 new and 15 older ring values and
     reads+writes its 16 accumulators; every level k that receives n_k > 0 new
     values reads its 15 older ring values, writes min(n_k, 16) slots and
     reads+writes its 8 accumulators."""
@@ -260,7 +260,7 @@ def flush_bytes(g, s):
 
 
 def group_channels(g, tw, j):
-    """Channels of tile group j (128 groups of contiguous tiles) of a block-deferred group."""
+    """Channels of tile group j (256 groups of contiguous tiles) of a block-deferred group."""
     n_tiles = -(-g["n"] // tw)
     tpg = -(-n_tiles // DEFER_T)
     t0, t1 = j * tpg, min((j + 1) * tpg, n_tiles)
@@ -270,8 +270,8 @@ def group_channels(g, tw, j):
 
 
 def staggered_flush_bytes(g, s, tw):
-    """Bytes of the flush issued with push s: tile group s mod 128 folds block
-    s // 128 (pushes (128 (q-1), 128 q])."""
+    """Bytes of the flush issued with push s: tile group s mod 256 folds block
+    s // 256 (pushes (256 (q-1), 256 q])."""
     j, q = s % DEFER_T, s // DEFER_T
     if q < 1:
         return 0
@@ -539,7 +539,7 @@ def run(args):
     elif fl_n:
         # dominant kernel: the flush of the block-deferred groups
         achieved = fl_bytes / (fl_ms * 1e-3) / 1e9
-        kname = ("flush kernel (block-deferred fold of 128 pushes for 1/128 of the channels per "
+        kname = ("flush kernel (block-deferred fold of 256 pushes for 1/256 of the channels per "
                  "push), HIP events per launch")
         per_launch_ms, per_launch_bytes = fl_ms / fl_n, fl_bytes / fl_n
     else:

@@ -187,6 +187,10 @@ __device__ __forceinline__ void fold_level(Ctx &cx, int k, const typename RK<K>:
 // taken in chunks of kL0Chunk with a sliding window of the P - 1 values
 // before each chunk, so that only P - 1 + kL0Chunk ring values are live.
 constexpr int kL0Chunk = 64;
+// Threads per block of the fold kernels (at most): a tile wider than this is
+// split over several blocks, so that a flush of 1/kFlushGroups of the
+// channels still spreads over every CU (and the per-block LDS stays small).
+constexpr int kFoldThreads = 128;
 
 template <int K, int P, int T, bool READ>
 __device__ __forceinline__ void level0(Ctx &cx, typename RK<K>::S (&out)[T / 2])
@@ -239,6 +243,109 @@ __device__ __forceinline__ void level0(Ctx &cx, typename RK<K>::S (&out)[T / 2])
         for (int i = 0; i < P - 1; ++i) W[i] = W[i + C];
     }
     fold_level<K, P, P, READ>(cx, 0, part, r > 0);
+}
+
+// Levels 0 and 1 together, for blocks of more than kL0Chunk pushes: the r
+// pending pushes are taken in chunks of kL0Chunk; each chunk adds its level-0
+// lag products, forms its kL0Chunk / 2 level-1 means, adds their level-1 lag
+// products at once (sliding windows of the P - 1 older values of both levels
+// stay in registers) and forms the level-2 means, which are collected in
+// the thread's column of the LDS array out[T / 4][blockDim.x] for the cascade
+// (in registers they would crowd out the windows).  Only the last P level-1
+// values of the block are written to the level-1 ring (the earlier ones would
+// be overwritten).
+template <int K, int P, int T, bool READ>
+__device__ __forceinline__ void levels01(Ctx &cx, typename RK<K>::S *out)
+{
+    using S = typename RK<K>::S;
+    using PT = typename RK<K>::PT;
+    constexpr int C = kL0Chunk;
+    constexpr int C1 = C / 2;   // level-1 values per chunk
+    constexpr int NL1 = P - P / 2;
+    static_assert(T % C == 0 && C1 % 2 == 0, "chunks of whole pairs");
+    const DeferredArgs &a = *cx.a;
+    const GroupArgs &g = a.g;
+    const int tw = g.tw;
+    const int P0 = g.p0;
+    const S *ring0 = reinterpret_cast<const S *>(cx.tb);
+    S *ring1 = reinterpret_cast<S *>(cx.tb + g.lvl0_bytes);
+    const int64_t f = cx.f;
+    const int r = cx.r;
+    const bool has1 = g.levels > 1;     // a one-level group has no level-1 state
+    const int n1 = has1 ? r / 2 : 0;    // level-1 values of this pass
+    const int64_t f1 = f >> 1;          // level-1 values already in the ring
+    // level 0: value j in slot (j - 1) mod P0 (one modulo, then a wrap per row)
+    const int slot0 = (int)((f - (P - 2) - 1 + P0) % P0);
+    auto row0 = [&](int i) -> S {
+        int slot = slot0 + i;
+        if (slot >= P0) slot -= P0;
+        return __builtin_nontemporal_load(&ring0[(size_t)slot * tw + cx.lane]);
+    };
+    S W0[P - 1 + C], W1[P - 1 + C1];
+#pragma unroll
+    for (int i = 0; i < P - 1; ++i) W0[i] = row0(i);
+#pragma unroll
+    for (int i = 0; i < P - 1; ++i) {
+        const int64_t v = f1 - (P - 2) + i; // level-1 value number (1-based)
+        const int slot = (int)((v - 1 + P) % P);
+        W1[i] = has1 ? __builtin_nontemporal_load(&ring1[(size_t)slot * tw + cx.lane]) : S(0);
+    }
+    PT part0[P], part1[NL1];
+#pragma unroll
+    for (int L = 0; L < P; ++L) part0[L] = PT(0);
+#pragma unroll
+    for (int j = 0; j < NL1; ++j) part1[j] = PT(0);
+    // one chunk at a time (a rolled loop: only one chunk's values are live)
+#pragma unroll 1
+    for (int c0 = 0; c0 < T; c0 += C) {
+#pragma unroll
+        for (int q = 0; q < C; ++q) W0[P - 1 + q] = c0 + q < r ? row0(P - 1 + c0 + q) : S(0);
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            if (c0 + q < r) {
+                const S x = W0[P - 1 + q];
+#pragma unroll
+                for (int L = 0; L < P; ++L) pmac(part0[L], x, W0[P - 1 + q - L]);
+            }
+        }
+        // level-1 values c0/2 + q of the block
+        const int b1 = c0 / 2;
+#pragma unroll
+        for (int q = 0; q < C1; ++q)
+            W1[P - 1 + q] = b1 + q < n1 ? (W0[P - 1 + 2 * q] + W0[P + 2 * q]) / S(2) : S(0);
+#pragma unroll
+        for (int q = 0; q < C1; ++q) {
+            if (b1 + q < n1) {
+                const S x = W1[P - 1 + q];
+#pragma unroll
+                for (int j = 0; j < NL1; ++j) pmac(part1[j], x, W1[P - 1 + q - (P / 2 + j)]);
+            }
+        }
+        if constexpr (!READ) {
+            // ring slots of the last P level-1 values of the block
+#pragma unroll
+            for (int q = 0; q < C1; ++q) {
+                const int idx = b1 + q;
+                if (idx < n1 && idx >= n1 - P) {
+                    const int64_t v = f1 + 1 + idx;
+                    const int slot = (int)((v - 1) % P);
+                    __builtin_nontemporal_store(W1[P - 1 + q], &ring1[(size_t)slot * tw + cx.lane]);
+                }
+            }
+        }
+        // level-2 means of this chunk's level-1 pairs (f1 is even: pairs align)
+#pragma unroll
+        for (int q = 0; q < C1 / 2; ++q)
+            out[(size_t)(b1 / 2 + q) * blockDim.x + threadIdx.x] =
+                (W1[P - 1 + 2 * q] + W1[P + 2 * q]) / S(2);
+#pragma unroll
+        for (int i = 0; i < P - 1; ++i) {
+            W0[i] = W0[i + C];
+            W1[i] = W1[i + C1];
+        }
+    }
+    fold_level<K, P, P, READ>(cx, 0, part0, r > 0);
+    if (has1) fold_level<K, P, NL1, READ>(cx, 1, part1, n1 > 0);
 }
 
 // Level k >= 1 receiving n_in <= N new values in[0..n_in) (level-k values
@@ -334,6 +441,10 @@ template <int K, int P, int T, bool READ>
 __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
 {
     const GroupArgs &g = a.g;
+    // block = (tile slot, part of the tile); parts of blockDim.x channels
+    const int parts = (g.tw + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int64_t slot = blockIdx.x / parts;
+    const int part = (int)(blockIdx.x % parts);
     int64_t f;
     int r;
     int64_t tile;
@@ -343,7 +454,7 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
         const int64_t S = *a.step;
         f = (S / kDeferT) * kDeferT;
         r = (int)(S - f);
-        tile = blockIdx.x;
+        tile = slot;
     } else {
         // Flush of tile group j, block q: scheduled at push kDeferT q + j
         // (fixed_group < 0; the counter is advanced after this push) or
@@ -359,14 +470,15 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
             q = S / kDeferT;
         }
         if (q < 1 || a.flushed[j] >= q) return;
-        tile = (int64_t)j * a.tiles_per_group + blockIdx.x;
-        if (tile >= g.n_tiles || blockIdx.x >= a.tiles_per_group) return;
+        tile = (int64_t)j * a.tiles_per_group + slot;
+        if (tile >= g.n_tiles || slot >= a.tiles_per_group) return;
         f = (q - 1) * kDeferT;
         r = kDeferT;
     }
-    for (int sub = 0; sub * (int)blockDim.x < g.tw; ++sub) {
+    {
+        const int sub = part;
         // whole waves past the tile's end skip the pass (tw is a multiple of 64)
-        if (sub * (int)blockDim.x + (int)(threadIdx.x & ~63u) >= g.tw) continue;
+        if (sub * (int)blockDim.x + (int)(threadIdx.x & ~63u) >= g.tw) return;
         Ctx cx;
         cx.a = &a;
         cx.f = f;
@@ -376,23 +488,36 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
         cx.ch = tile * g.tw + cx.lane;
         cx.valid = cx.ch < g.n_ch;
         cx.reduce_me = cx.valid && cx.ch >= a.ch_begin && cx.ch < a.ch_end;
-        typename RK<K>::S l1[T / 2];
-        level0<K, P, T, READ>(cx, l1);
-        cascade<K, P, T / 2, READ>(cx, 1, l1, r / 2);
+        if constexpr (T > kL0Chunk) {
+            // levels 0 and 1 streamed chunk by chunk, then the cascade from
+            // level 2 (f is a multiple of T, so level-1 pairs align); each
+            // thread reads back only its own column of l2s
+            using S = typename RK<K>::S;
+            __shared__ S l2s[(T / 4) * kFoldThreads];
+            levels01<K, P, T, READ>(cx, l2s);
+            S l2[T / 4];
+#pragma unroll
+            for (int q = 0; q < T / 4; ++q) l2[q] = l2s[(size_t)q * blockDim.x + threadIdx.x];
+            cascade<K, P, T / 4, READ>(cx, 2, l2, (r / 2) / 2);
+        } else {
+            typename RK<K>::S l1[T / 2];
+            level0<K, P, T, READ>(cx, l1);
+            cascade<K, P, T / 2, READ>(cx, 1, l1, r / 2);
+        }
     }
 }
 
 // The scheduled (or requested) flush: at most two waves per SIMD, so that the
 // register budget covers the whole block of pushes without spilling.
 template <int K, int P, int T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void deferred_kernel(DeferredArgs a)
+__global__ __launch_bounds__(kFoldThreads) __attribute__((amdgpu_waves_per_eu(2))) void deferred_kernel(DeferredArgs a)
 {
     deferred_pass<K, P, T, false>(a);
 }
 
 // The readout pass (no state written).
 template <int K, int P, int T>
-__global__ __launch_bounds__(256) void deferred_read_kernel(DeferredArgs a)
+__global__ __launch_bounds__(kFoldThreads) void deferred_read_kernel(DeferredArgs a)
 {
     deferred_pass<K, P, T, true>(a);
 }
@@ -442,8 +567,9 @@ __global__ void flush_commit_kernel(DeferredArgs a)
 template <int K, int P, bool READ>
 hipError_t launch_deferred_kp(const DeferredArgs &a, hipStream_t st)
 {
-    const int block = a.g.tw < 256 ? a.g.tw : 256;
-    const int64_t grid = READ ? a.g.n_tiles : a.tiles_per_group;
+    const int block = a.g.tw < kFoldThreads ? a.g.tw : kFoldThreads;
+    const int parts = (a.g.tw + block - 1) / block;
+    const int64_t grid = (READ ? a.g.n_tiles : a.tiles_per_group) * parts;
     if (grid < 1) return hipSuccess;
     if constexpr (READ)
         hipLaunchKernelGGL((deferred_read_kernel<K, P, kDeferT>), dim3((unsigned)grid), dim3(block),

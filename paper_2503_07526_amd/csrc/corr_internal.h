@@ -58,7 +58,7 @@ struct GroupArgs {
 };
 
 // Pushes staged between two flushes of a block-deferred group.
-constexpr int kDeferT = 128;
+constexpr int kDeferT = 256;
 // Pushes per block of the block-deferred one-level window (corr_window.hip).
 constexpr int kWindowT = 64;
 // Tile groups of a block-deferred group: tile group j folds block q (pushes
