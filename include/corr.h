@@ -299,8 +299,11 @@ int corr_get_tuning(const corr_ctx *ctx, corr_tuning *out);
  * Autotuner: choose the launch shape for these groups on `device` by timing
  * trial contexts (same descriptors with at most max_trial_channels channels
  * per group, zero samples; all trial memory is freed before returning) over
- * whole flush periods for every candidate shape, and return the fastest in
- * *out.  The choice is cached in a text file of JSON lines (cache_path, or
+ * whole flush periods for every candidate shape; then, with the fastest
+ * shape, choose overlap_producers on trial contexts whose sample-fed groups
+ * and producer atom counts are scaled by one factor so that the largest group
+ * has at most 2^25 channels (the concurrent kernels keep their balance), and
+ * return the result in *out.  The choice is cached in a text file of JSON lines (cache_path, or
  * NULL for $CORR_TUNE_CACHE, else $HOME/.cache/corr_gfx950_tune.jsonl, else
  * no cache) keyed by the device architecture, the flags and the group
  * descriptors; a cached entry is returned without timing unless force != 0.

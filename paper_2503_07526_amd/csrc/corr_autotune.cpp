@@ -136,11 +136,14 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
         return CORR_E_DEVICE;
     }
     const int period = kDeferT; // whole flush periods of the block-deferred form
+    // Channels up to which the issue-order trials run a group at full size.
+    constexpr int64_t kOrderTrialChannels = int64_t(32) << 20;
     // ms for 2 periods of pushes after one period of warm-up, or < 0
-    auto trial_ms = [&](const corr_tuning &cand) -> double {
+    auto trial_ms_on = [&](const std::vector<corr_group_desc> &descs,
+                           const corr_tuning &cand) -> double {
         corr_ctx *ctx = nullptr;
         const uint32_t tflags = flags & ~(uint32_t)CORR_FLAG_TIMING;
-        if (corr_create(trial.data(), n_groups, device, stream, tflags, &cand, &ctx) != CORR_OK)
+        if (corr_create(descs.data(), n_groups, device, stream, tflags, &cand, &ctx) != CORR_OK)
             return -1.0; // e.g. out of memory for this layout
         bool ok = true;
         for (int s = 0; s < period && ok; ++s) ok = corr_push(ctx, nullptr) == CORR_OK;
@@ -152,6 +155,7 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
         corr_destroy(ctx);
         return ok ? (double)ms : -1.0;
     };
+    auto trial_ms = [&](const corr_tuning &cand) { return trial_ms_on(trial, cand); };
     double best = 1e300;
     corr_tuning best_t{};
     for (const corr_tuning &cand : cands) {
@@ -161,22 +165,43 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
             best_t = cand;
         }
     }
-    // With the best shape, also try the forked issue orders: the producers
-    // (next to sample-fed groups) on a side stream, and the per-step pushes
-    // beside the flush of block-deferred groups.  The trial timing covers
-    // every stream (the events bracket whole pushes).
+    // With the best shape, choose the issue order: everything on one stream,
+    // the producers (next to sample-fed groups) on a side stream, or the
+    // per-step pushes beside the flush of block-deferred groups.  Which wins
+    // depends on the balance of the concurrent kernels, so these trials keep
+    // it: every sample-fed group and every producer's atom count are scaled
+    // by one factor (groups up to kOrderTrialChannels channels run at full
+    // size).  The trial timing covers every stream (the events bracket whole
+    // pushes).
     bool producer = false, sampled = false;
-    for (int i = 0; i < n_groups; ++i) (groups[i].source == CORR_SRC_SAMPLES ? sampled : producer) = true;
-    for (int mode = 1; mode <= 2 && best < 1e300; ++mode) {
-        if (mode == 1 && !(producer && sampled)) continue;
-        if (mode == 2 && n_groups < 2) continue;
-        corr_tuning ov = best_t;
-        ov.overlap_producers = mode;
-        const double ms = trial_ms(ov);
-        if (ms >= 0.0 && ms < best) {
-            best = ms;
-            best_t = ov;
+    int64_t n_max = 0;
+    for (int i = 0; i < n_groups; ++i) {
+        (groups[i].source == CORR_SRC_SAMPLES ? sampled : producer) = true;
+        if (groups[i].source == CORR_SRC_SAMPLES) n_max = std::max<int64_t>(n_max, groups[i].n_channels);
+    }
+    if (best < 1e300 && n_groups >= 2) {
+        const double scale = n_max > kOrderTrialChannels ? (double)kOrderTrialChannels / (double)n_max : 1.0;
+        std::vector<corr_group_desc> order(groups, groups + n_groups);
+        for (auto &g : order) {
+            if (g.source != CORR_SRC_SAMPLES)
+                g.n_atoms = std::max<int64_t>(std::min<int64_t>(g.n_atoms, 1024),
+                                              (int64_t)(scale * (double)g.n_atoms));
+            else
+                g.n_channels = std::max<int64_t>(1, (int64_t)(scale * (double)g.n_channels));
         }
+        double best_o = 1e300;
+        corr_tuning best_o_t = best_t;
+        for (int mode = 0; mode <= 2; ++mode) {
+            if (mode == 1 && !(producer && sampled)) continue;
+            corr_tuning ov = best_t;
+            ov.overlap_producers = mode;
+            const double ms = trial_ms_on(order, ov);
+            if (ms >= 0.0 && ms < best_o) {
+                best_o = ms;
+                best_o_t = ov;
+            }
+        }
+        if (best_o < 1e300) best_t = best_o_t;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
