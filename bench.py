@@ -75,9 +75,10 @@ def parse():
     ap.add_argument("--compare-plain", action="store_true",
                     help="also time the plain FP64 per-group form on the same velocity channels")
     ap.add_argument("--tuning", default=None, help="JSON dict of corr_tuning fields")
-    ap.add_argument("--timing-stride", type=int, default=8,
+    ap.add_argument("--timing-stride", type=int, default=7,
                     help="record the HIP timing events on one push in this many (each event pair "
-                         "costs a few microseconds of the push it brackets)")
+                         "costs a few microseconds of the push it brackets); odd, so that the "
+                         "timed pushes cycle through every level schedule (m^k | s) and flush group")
     ap.add_argument("--direct", action="store_true",
                     help="per-step update of every channel (no block-deferred form)")
     ap.add_argument("--rhok-valu", action="store_true",
@@ -582,6 +583,17 @@ def run(args):
     }
     if rk_n:
         out["roofline"]["producer_ms_per_launch"] = rk_ms / rk_n
+        if not (rhok_only or producer_dominant):
+            # the producers beside the dominant kernel (forked, they may be the
+            # longer branch of the step)
+            pf = sum(producer_flop(g) for g in wl["groups"] if g["kind"] in PRODUCER_KINDS)
+            pms = rk_ms / kern_n
+            out["producers"] = {
+                "ms_per_push": pms, "alg_flop_per_push": pf,
+                "TFLOPs": pf / (pms * 1e-3) / 1e12,
+                "frac_of_fp16_matrix_peak": pf / (pms * 1e-3) / 1e12 / MFMA_F16_PEAK_TFS,
+                "stream": "forked beside the other updates"
+                          if corr.tuning()["overlap_producers"] == 1 else "the context's stream"}
     wins = [g for g in wl["groups"] if window_deferred(g, direct)]
     if wins and len(wins) == len(wl["groups"]):
         # the correlator update of the block-deferred windows: the push events
@@ -771,8 +783,11 @@ def compare_plain(wl, K, W, chunk, stride):
     corr = Correlator([GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype="f32",
                                  accum="f64")], per_group=True, timing=True, direct=True)
     corr.set_timing_stride(stride)
-    wall, done = 0.0, 0
+    wall, done, reset = 0.0, 0, False
     while done < W + K:
+        if done >= W and not reset:
+            corr.kernel_time(0, reset=True)  # time the chunks that count as timed
+            w_first, reset = done + 1, True
         n = min(chunk, W + K - done)
         gen.fill(buf, n)
         torch.cuda.synchronize()
@@ -785,7 +800,9 @@ def compare_plain(wl, K, W, chunk, stride):
         done += n
     kern_ms, kern_n = corr.kernel_time(0)
     corr.close()
-    alg = sum(step_bytes(g, s) for s in range(W + 1, W + K + 1)) / K
+    # bytes of the timed pushes the events cover (push s is timed when s - 1 % stride == 0)
+    timed_s = [s for s in range(w_first, W + K + 1) if (s - 1) % stride == 0]
+    alg = sum(step_bytes(g, s) for s in timed_s) / max(len(timed_s), 1)
     return {"value": g["n"] * K / wall, "unit": "channel-samples/s",
             "ms_per_step": wall / K * 1e3,
             "push_kernel_ms": kern_ms / kern_n if kern_n else None,
