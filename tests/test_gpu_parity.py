@@ -64,6 +64,7 @@ def test_parity_each_kind(corrmod, dtype, accum, direct):
     (600, 700, 4, 9, 4),      # m = 4
     (1100, 600, 6, 32, 2),    # p = 32 (two lag chunks)
     (520, 1000, 1, 16, 2),    # single level
+    (520, 1000, 2, 16, 2),    # two levels
     (1030, 2048, 12, 16, 2),  # pushes = 2^11: deepest level just reached
 ])
 def test_parity_shapes(corrmod, n, S, b, p, m):
@@ -282,7 +283,8 @@ def test_deferred_readout_at_many_push_counts(corrmod, accum):
     boundaries and with pending pushes all match the oracle at that push count,
     and never change later results (bitwise against an uninterrupted run)."""
     n, b, p, m = 700, 12, 16, 2
-    marks = [1, 2, 15, 16, 17, 63, 64, 65, 100, 127, 128, 129, 255, 256, 511, 700, 1024, 1500]
+    marks = [1, 2, 15, 16, 17, 63, 64, 65, 100, 127, 128, 129, 255, 256, 257, 511, 512, 513, 700,
+             767, 768, 769, 1024, 1500]
     S = marks[-1]
     say(f"[deferred readouts] accum={accum} n={n}")
     x = ou_inputs(4, 4, n, S, "f32")
@@ -303,6 +305,29 @@ def test_deferred_readout_at_many_push_counts(corrmod, accum):
         a, r = c.finalize(0, slice_=(0, n)), ref.finalize(0, slice_=(0, n))
         assert np.array_equal(a["c"], r["c"])
         assert np.array_equal(a["c_per_channel"], r["c_per_channel"])
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 9])
+def test_deferred_level_counts(corrmod, b):
+    """The block-deferred fold streams levels 0 and 1 through each block and
+    runs the cascade from level 2: groups with one, two and three levels (no
+    level 1, no cascade, a one-level cascade) and a deep one, across several
+    blocks, read out at a block boundary and with pushes pending."""
+    n = 300
+    say(f"[deferred levels] b={b}")
+    x = ou_inputs(6, 9, n, 1300, "f32")
+    o = oracle.OracleCorrelator(n, b, 16, 2)
+    dev = torch.device("cuda:0")
+    tx = torch.from_numpy(x).to(dev)
+    with corrmod.Correlator([corrmod.GroupDesc(n, b, 16, 2, dtype="f32", accum="kahan")]) as c:
+        done = 0
+        for mk in (768, 1300):
+            for s in range(done, mk):
+                c.push([tx[s]])
+                o.push(x[s].astype(np.float64))
+            done = mk
+            res = c.finalize(0, slice_=(0, 3))
+            gate(res, o, TOL[("f32", "kahan")], slice_=(0, 3), label=f"b={b} S={mk}")
 
 
 def test_deferred_equals_direct_within_rounding(corrmod):
