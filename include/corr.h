@@ -265,8 +265,8 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
  *
  * Block-deferred form: for groups of single-precision samples with p = 16 and
  * m = 2 (unless CORR_FLAG_DIRECT), a push stages the samples and flushes one
- * of 128 channel subsets: subset j adds the lag products of block q (pushes
- * 128(q-1)+1 .. 128q) level by level at push 128q + j -- the same products,
+ * of 256 channel subsets: subset j adds the lag products of block q (pushes
+ * 256(q-1)+1 .. 256q) level by level at push 256q + j -- the same products,
  * block means and counts as Algorithm 1, only the grouping of the
  * floating-point sums differs.  A readout first folds complete blocks a
  * subset has not folded yet (exactly what its scheduled flush would do), then

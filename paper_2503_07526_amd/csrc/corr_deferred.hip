@@ -32,9 +32,11 @@
 // over chunks in a fixed order (the group mean does not depend on the tile
 // width).
 //
-// Supported here: single-precision real samples, m = 2, p = 16, T = 64.
-// Levels k <= 6 receive T / 2^k new values per flush (compile-time counts);
-// deeper levels receive at most one.
+// Supported here: single-precision real samples, m = 2, p = 16, T = kDeferT
+// (256).  Levels 0 and 1 are folded together, streamed through chunks of 64
+// pushes (levels01); from level 2 on the cascade takes the T / 4 level-2
+// values at once.  Levels k <= 8 receive T / 2^k new values per flush
+// (compile-time counts); deeper levels receive at most one.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
