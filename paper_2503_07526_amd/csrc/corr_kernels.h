@@ -14,6 +14,8 @@ hipError_t launch_push_group(const GroupArgs &g, const int64_t *step, int cpt, i
                              hipStream_t st);
 hipError_t launch_push_window(const GroupArgs &g, const int64_t *step, int cpt, int lch,
                               int block, int lags_per_block, hipStream_t st);
+hipError_t launch_push_split(const GroupArgs &g, const int64_t *step, int cpt, int lch, int block,
+                             int lags_per_block, hipStream_t st);
 hipError_t launch_push_end(const PushEndArgs &a, hipStream_t st); // flush records + step counter
 hipError_t launch_rhok(const RhokArgs &a, hipStream_t st);
 int rhok_tile_atoms(int nmax);

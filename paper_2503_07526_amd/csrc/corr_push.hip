@@ -199,9 +199,13 @@ __device__ __forceinline__ void lag_loop(const typename KT<K>::S (&x)[CPT],
 
 // One push of one tile of one group.  s = 1-based push index.  PAIR: the
 // group correlates (x, y) pairs (its own launches; the batched kernel only
-// instantiates the autocorrelation form).
+// instantiates the autocorrelation form).  [lag_lo, lag_hi) restricts the
+// level-0 lags this call adds; head: the call also writes the ring slots and
+// runs the cascade (one head call per tile and push; the level-0 lags of a
+// push never read the slot it writes, so the calls are independent).
 template <int K, int CPT, int LCH, bool PAIR = false>
-__device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int64_t s)
+__device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int64_t s,
+                                          int lag_lo = 0, int lag_hi = 1 << 30, bool head = true)
 {
     using S = typename KT<K>::S;
     using A = typename KT<K>::A;
@@ -242,11 +246,16 @@ __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int6
         A *hi = reinterpret_cast<A *>(tb + (int64_t)rings * p * rowS);
         A *lo = hi + (size_t)p * tw;
         const int slot = (int)((s - 1) % p);
-        vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, y);
-        if constexpr (PAIR) vstore<S, CPT>(ring + (size_t)(p + slot) * tw + lane_off, x);
+        if (head) {
+            vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, y);
+            if constexpr (PAIR) vstore<S, CPT>(ring + (size_t)(p + slot) * tw + lane_off, x);
+        }
         const int nlag = (int)(s < p ? s : p);
-        lag_loop<K, CPT, LCH>(x, y, ring, hi, lo, slot, p, 0, nlag, 0, tw, lane_off);
+        const int l_end = lag_hi < nlag ? lag_hi : nlag;
+        if (lag_lo < l_end)
+            lag_loop<K, CPT, LCH>(x, y, ring, hi, lo, slot, p, lag_lo, l_end, 0, tw, lane_off);
     }
+    if (!head) return;
 
     // Cascade: level k receives a value when m^k divides s.
     int kmax = 0;
@@ -335,9 +344,11 @@ __device__ __forceinline__ void dispatch_tile(const GroupArgs &g, int64_t tile, 
 
 // Batched form: every group of the context in one launch.  Blocks stride over
 // the concatenated tile space of all groups (a persistent grid when
-// gridDim.x is smaller than the number of tiles).
+// gridDim.x is smaller than the number of tiles).  Every kind is compiled
+// into this kernel, so its register budget is that of the widest (complex
+// double samples); it has no occupancy bound, which would make those spill.
 template <int CPT, int LCH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void push_batched_kernel(PushArgs a)
+__global__ __launch_bounds__(256) void push_batched_kernel(PushArgs a)
 {
     const int64_t s = *a.step + 1;
 #pragma unroll 1
@@ -367,6 +378,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
 {
     const int64_t s = *step + 1;
     push_tile<K, CPT, LCH, PAIR>(g, (int64_t)blockIdx.x, s);
+}
+
+// Group with few tiles: the level-0 lags of a push split over blockIdx.y
+// (lags_per_block each), so that more than one block per tile works on it;
+// block y = 0 also writes the ring slots and runs the cascade.
+template <int K, int CPT, int LCH>
+__global__ __launch_bounds__(256) void push_split_kernel(GroupArgs g, const int64_t *step, int lags_per_block)
+{
+    const int64_t s = *step + 1;
+    const int lo = (int)blockIdx.y * lags_per_block;
+    push_tile<K, CPT, LCH>(g, (int64_t)blockIdx.x, s, lo, lo + lags_per_block, blockIdx.y == 0);
 }
 
 // One-level group with a long window: one push, with the lag range split
@@ -509,6 +531,38 @@ static hipError_t launch_push_window_p(const GroupArgs &g, const int64_t *step, 
     if (cpt == 2 && lch == 4) return launch_window_t<2, 4, PAIR>(g, step, block, lags_per_block, st);
     if (cpt == 4 && lch == 4) return launch_window_t<4, 4, PAIR>(g, step, block, lags_per_block, st);
     if (cpt == 4 && lch == 8) return launch_window_t<4, 8, PAIR>(g, step, block, lags_per_block, st);
+    return hipErrorInvalidValue;
+}
+
+template <int CPT, int LCH>
+static hipError_t launch_split_t(const GroupArgs &g, const int64_t *step, int block,
+                                 int lags_per_block, hipStream_t st)
+{
+    const dim3 grid((unsigned)g.n_tiles, (unsigned)((g.p + lags_per_block - 1) / lags_per_block));
+    switch (g.kind) {
+    case K_F32_F64: hipLaunchKernelGGL((push_split_kernel<K_F32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F32_KAHAN: hipLaunchKernelGGL((push_split_kernel<K_F32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F32_F32: hipLaunchKernelGGL((push_split_kernel<K_F32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_F64_F64: hipLaunchKernelGGL((push_split_kernel<K_F64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_CF32_F64: hipLaunchKernelGGL((push_split_kernel<K_CF32_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_CF32_KAHAN: hipLaunchKernelGGL((push_split_kernel<K_CF32_KAHAN, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    case K_CF32_F32: hipLaunchKernelGGL((push_split_kernel<K_CF32_F32, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    default: hipLaunchKernelGGL((push_split_kernel<K_CF64_F64, CPT, LCH>), grid, dim3(block), 0, st, g, step, lags_per_block); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_push_split(const GroupArgs &g, const int64_t *step, int cpt, int lch, int block,
+                             int lags_per_block, hipStream_t st)
+{
+    if (lags_per_block < 1 || g.pair || g.deferred) return hipErrorInvalidValue;
+    // a block holds lags_per_block lags: longer lag chunks would never run
+    if (lch > 8 && lags_per_block <= 8) lch = 8;
+    if (cpt == 1 && lch == 8) return launch_split_t<1, 8>(g, step, block, lags_per_block, st);
+    if (cpt == 2 && lch == 8) return launch_split_t<2, 8>(g, step, block, lags_per_block, st);
+    if (cpt == 2 && lch == 4) return launch_split_t<2, 4>(g, step, block, lags_per_block, st);
+    if (cpt == 4 && lch == 4) return launch_split_t<4, 4>(g, step, block, lags_per_block, st);
+    if (cpt == 4 && lch == 8) return launch_split_t<4, 8>(g, step, block, lags_per_block, st);
     return hipErrorInvalidValue;
 }
 
