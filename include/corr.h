@@ -259,8 +259,12 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
  * flush of block-deferred groups only (one per push); *n = timed flushes.
  * which = 2: each k-density producer launch, on the stream it runs on (the
  * forked side stream when other groups share the context); *n = timed
- * launches.  In graph mode the which = 0 events bracket the whole graph
- * replay and no other times are recorded.  reset != 0 clears the counters of
+ * launches.  which = 3: the scheduled fold kernels of block-deferred groups
+ * timed by the kernels themselves on every push (the earliest block start to
+ * the latest block end, device wall clock), so that no event sits between
+ * the kernels of a push; *n = pushes with a fold launch.  In graph mode the
+ * which = 0 events bracket the whole graph replay and the which = 3 stamps
+ * are kept; no other times are recorded.  reset != 0 clears the counters of
  * `which` after reading.  CORR_E_STATE without the flag.
  *
  * Block-deferred form: for groups of single-precision samples with p = 16 and

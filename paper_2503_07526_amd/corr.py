@@ -263,9 +263,11 @@ class Correlator:
         return int(n.value)
 
     def kernel_time(self, which: int = 0, reset: bool = False):
-        """(summed milliseconds, count) from the library's HIP events: which=0 the
-        update kernels of each push (incl. flushes), which=1 the flush fold
-        kernels only, which=2 the k-density producer launches."""
+        """(summed milliseconds, count): which=0 the update kernels of each push
+        (incl. flushes), which=1 the flush fold kernels only, which=2 the
+        k-density producer launches (HIP events, on the timed pushes); which=3
+        the flush fold kernels of every push, from the kernels' own device
+        stamps."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         self._check(lib().corr_kernel_time(self._h, int(which), ctypes.byref(ms), ctypes.byref(n),

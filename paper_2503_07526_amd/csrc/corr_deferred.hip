@@ -514,7 +514,15 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
 template <int K, int P, int T>
 __global__ __launch_bounds__(kFoldThreads) __attribute__((amdgpu_waves_per_eu(2))) void deferred_kernel(DeferredArgs a)
 {
+    // with timing: earliest block start and latest block end of the push's
+    // folds (device wall clock; no event between kernels)
+    FoldStamps *st = a.stamps;
+    if (st && threadIdx.x == 0) atomicMin(&st->start, (unsigned long long)wall_clock64());
     deferred_pass<K, P, T, false>(a);
+    if (st) {
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(&st->end, (unsigned long long)wall_clock64());
+    }
 }
 
 // The readout pass (no state written).

@@ -66,6 +66,15 @@ constexpr int kWindowT = 64;
 // group; the level-0 ring keeps 2 kDeferT + p slots.
 constexpr int kFlushGroups = kDeferT;
 
+// Device timestamps of the scheduled fold kernels of a push (timing only):
+// the earliest block start and the latest block end of this push's folds, in
+// wall-clock ticks, and their running sum over pushes (the push's end kernel
+// adds and resets them).
+struct FoldStamps {
+    unsigned long long start, end;
+    unsigned long long total, count;
+};
+
 // Flush / readout of a block-deferred group.
 struct DeferredArgs {
     GroupArgs g;
@@ -80,6 +89,7 @@ struct DeferredArgs {
     int64_t slice_begin, slice_end; // readout: channels written to slice_out
     double *chunk_partial;  // readout: [n_tiles * tw / 64][ne] sums over 64-channel chunks
     double *slice_out;      // readout: [(c - slice_begin) * ne + e]
+    FoldStamps *stamps;     // scheduled flush with timing: block start / end stamps, else null
 };
 
 struct PushArgs {
@@ -166,6 +176,7 @@ struct PushEndArgs {
     int32_t n_flushed;                 // block-deferred groups
     int32_t pad_;
     int64_t *flushed[kMaxGroups];      // their [kFlushGroups] last-folded arrays
+    FoldStamps *stamps;                // timing: the push's fold stamps, else null
 };
 
 // Readout reduction arguments.

@@ -442,6 +442,15 @@ __global__ void push_end_kernel(PushEndArgs a)
     const int64_t q = S / kDeferT;
     for (int i = 0; i < a.n_flushed; ++i)
         if (q >= 1 && a.flushed[i][j] < q) a.flushed[i][j] = q;
+    if (a.stamps) {
+        FoldStamps &st = *a.stamps;
+        if (st.end > st.start) {
+            st.total += st.end - st.start;
+            st.count += 1;
+        }
+        st.start = ~0ull;
+        st.end = 0;
+    }
     *a.step = S;
 }
 

@@ -74,6 +74,8 @@ struct corr_ctx {
     int64_t *d_step = nullptr;
     int64_t n_push = 0;
     int32_t timing_stride = 1; // CORR_FLAG_TIMING: events on pushes with n_push % stride == 0
+    FoldStamps *d_stamps = nullptr; // CORR_FLAG_TIMING: device stamps of the scheduled folds
+    double stamp_khz = 0.0;         // wall-clock rate of the stamps
     PushArgs pargs{};
     int64_t total_tiles = 0;
     hipStream_t cap_stream = nullptr;
@@ -256,6 +258,7 @@ void free_ctx(corr_ctx *c)
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (auto &g : c->groups) free_group(g);
     if (c->d_step) (void)hipFree(c->d_step);
+    if (c->d_stamps) (void)hipFree(c->d_stamps);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     for (auto &pl : c->pools) {
         for (auto e : pl.start) (void)hipEventDestroy(e);
@@ -324,7 +327,11 @@ DeferredArgs deferred_args(const corr_ctx *c, int i)
 int launch_flushes(corr_ctx *c, hipStream_t st, hipEvent_t f0, hipEvent_t f1)
 {
     if (f0) HIP_TRY(c, hipEventRecord(f0, st));
-    for (int i : c->deferred_set) HIP_TRY(c, launch_flush_fold(deferred_args(c, i), st));
+    for (int i : c->deferred_set) {
+        DeferredArgs da = deferred_args(c, i);
+        da.stamps = c->d_stamps; // the catch-up flushes of a readout carry none
+        HIP_TRY(c, launch_flush_fold(da, st));
+    }
     if (f1) HIP_TRY(c, hipEventRecord(f1, st));
     return CORR_OK;
 }
@@ -531,6 +538,7 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
     pe.step = c->d_step;
     if (with_flush)
         for (int i : c->deferred_set) pe.flushed[pe.n_flushed++] = c->groups[(size_t)i].d_flushed;
+    if (with_flush && !c->deferred_set.empty()) pe.stamps = c->d_stamps;
     HIP_TRY(c, launch_push_end(pe, st));
     return CORR_OK;
 }
@@ -939,6 +947,14 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     }
     CREATE_HIP(hipMalloc(&c->d_step, sizeof(int64_t)));
     CREATE_HIP(hipMemsetAsync(c->d_step, 0, sizeof(int64_t), c->stream));
+    if (flags & CORR_FLAG_TIMING) {
+        int khz = 0;
+        CREATE_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
+        c->stamp_khz = khz > 0 ? (double)khz : 0.0;
+        const FoldStamps init{~0ull, 0ull, 0ull, 0ull};
+        CREATE_HIP(hipMalloc(&c->d_stamps, sizeof(FoldStamps)));
+        CREATE_HIP(hipMemcpy(c->d_stamps, &init, sizeof(FoldStamps), hipMemcpyHostToDevice));
+    }
     c->pargs.step = c->d_step;
     c->pa_main.step = c->d_step;
     c->pa_side.step = c->d_step;
@@ -1062,10 +1078,23 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes)
 int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n, int32_t reset)
 {
     if (!ctx) return CORR_E_INVALID;
-    if (which < 0 || which > 2) return set_err(ctx, CORR_E_INVALID, "which must be 0, 1 or 2");
+    if (which < 0 || which > 3) return set_err(ctx, CORR_E_INVALID, "which must be 0, 1, 2 or 3");
     if (!(ctx->flags & CORR_FLAG_TIMING))
         return set_err(ctx, CORR_E_STATE, "context created without CORR_FLAG_TIMING");
     DeviceGuard dg(ctx->device);
+    if (which == 3) {
+        // device stamps of the scheduled folds, every push
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        FoldStamps h{};
+        HIP_TRY(ctx, hipMemcpy(&h, ctx->d_stamps, sizeof(FoldStamps), hipMemcpyDeviceToHost));
+        if (ms_total) *ms_total = ctx->stamp_khz > 0 ? (double)h.total / ctx->stamp_khz : 0.0;
+        if (n) *n = (int64_t)h.count;
+        if (reset) {
+            const FoldStamps init{~0ull, 0ull, 0ull, 0ull};
+            HIP_TRY(ctx, hipMemcpy(ctx->d_stamps, &init, sizeof(FoldStamps), hipMemcpyHostToDevice));
+        }
+        return CORR_OK;
+    }
     int rc = fold_events(ctx, which);
     if (rc != CORR_OK) return rc;
     auto &pl = ctx->pools[which];

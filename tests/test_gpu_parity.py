@@ -385,13 +385,17 @@ def test_kernel_time_pools(corrmod):
                                 kvec=kv, n_atoms=N, box=box)]
     with corrmod.Correlator(groups, timing=True) as c:
         _push_all(c, [xv, xp])
-        for which in (0, 1, 2):
+        for which in (0, 1, 2, 3):
             ms, n = c.kernel_time(which)
             assert n == S and ms > 0.0, (which, n, ms)
+        # the device stamps of the fold span its events' interval at most
+        assert c.kernel_time(3)[0] <= c.kernel_time(1)[0] * 1.05 + 0.01
         ms, n = c.kernel_time(2, reset=True)
         assert c.kernel_time(2) == (0.0, 0)
+        c.kernel_time(3, reset=True)
+        assert c.kernel_time(3) == (0.0, 0)
         with pytest.raises(corrmod.CorrError):
-            c.kernel_time(3)
+            c.kernel_time(4)
     # one push in 8 timed (pushes 0, 8, ..., 64 of 70): same state as every push timed
     with corrmod.Correlator(groups, timing=True) as c, corrmod.Correlator(groups) as ref:
         c.set_timing_stride(8)
@@ -402,6 +406,7 @@ def test_kernel_time_pools(corrmod):
         for which in (0, 1, 2):
             ms, n = c.kernel_time(which)
             assert n == 9 and ms > 0.0, (which, n, ms)
+        assert c.kernel_time(3)[1] == S  # device stamps on every push
         assert np.array_equal(c.finalize(0, slice_=(0, 3))["c_per_channel"],
                               ref.finalize(0, slice_=(0, 3))["c_per_channel"])
         with pytest.raises(corrmod.CorrError):
