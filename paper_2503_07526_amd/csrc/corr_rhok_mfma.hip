@@ -16,10 +16,10 @@
 // bits together) and a real product is a_hi b_hi + a_hi b_lo + a_lo b_hi (the
 // dropped a_lo b_lo is below 2^-22), i.e. three fp16 matrix products with
 // fp32 accumulation per sum, twelve per K-step.  The fp32 accumulators are
-// added to double accumulators after every tile of kMfmaTileAtoms atoms and
-// the blocks write double partials, reduced over the atom blocks in a fixed
-// order as in the vector-unit producer (corr_rhok.hip), so the result is
-// reproducible.  The tables start from e^{2 pi i x / L} in double (a 64-entry
+// added to double accumulators after every kAccAtoms atoms (an fp32 partial
+// sum of at most 128 terms of magnitude <= 1 each) and the blocks write double
+// partials, reduced over the atom blocks in a fixed order as in the
+// vector-unit producer (corr_rhok.hip), so the result is reproducible.  The tables start from e^{2 pi i x / L} in double (a 64-entry
 // root table times a short Taylor series) and take the powers by a double
 // recurrence, each power rounded once to float.
 //
@@ -30,7 +30,8 @@
 //
 // Work split: block (chunk, atom block); each wave of a block owns one M tile
 // and all waves share the tile's LDS tables: X and Y powers as float2
-// [2 nmax + 1][kTabStride] (a row per power, atoms along the row, so a lane's
+// [rows][Tile::stride] (a row per power that a pair of the k-set uses: n_x in
+// [x_lo, x_lo + x_rows), n_y likewise; atoms along the row, so a lane's
 // atoms are 16-byte reads; the row stride is padded so that the 16 rows a
 // K-step reads start in different banks) and the split |n_z| powers already
 // in B-fragment order.  The tables are double-buffered: the first waves build
@@ -54,23 +55,36 @@ constexpr int kKStep = 4 * kAtomsPerLane; // atoms per K-step
 typedef _Float16 halfv_t __attribute__((ext_vector_type(kAtomsPerLane)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaTileAtoms = 64; // atoms per LDS tile
-constexpr int kMfmaKSteps = kMfmaTileAtoms / kKStep;
-constexpr int kTabStride = kMfmaTileAtoms + 2; // float2 per table row (4-bank shift)
 constexpr int kMfmaMaxWaves = 12;  // waves per block (one M tile each)
+constexpr int kMfmaCols = 16;      // |n_z| = 0 .. 15
+constexpr int kRoots = 64;         // e^{2 pi i q / kRoots} table for the base phase
+// B fragments in LDS: [K-step][part: re hi, re lo, im hi, im lo][atom group][column]
+constexpr int kBParts = 4;
+// atoms whose products the fp32 matrix accumulators sum before they are added
+// to the double accumulators
+constexpr int kAccAtoms = 128;
+
+// The LDS tile: atoms per tile, K-steps, table row stride (float2; atoms + 2
+// shifts consecutive rows by 4 banks) and B fragments per weight set.  One
+// weight set takes 128-atom tiles: half the block-wide barriers of 64-atom
+// tiles, 10% faster.  Three sets keep 64-atom tiles: their B fragments are
+// three times larger, and two 128-atom buffers would not fit in 160 KB of LDS.
+template <int NW> struct Tile {
+    static constexpr int atoms = NW == 1 ? 128 : 64;
+    static constexpr int ksteps = atoms / kKStep;
+    static constexpr int stride = atoms + 2;
+    static constexpr int bfrags = ksteps * kBParts * 4 * kMfmaCols;
+    static constexpr int acc_tiles = kAccAtoms / atoms;
+};
+
 // Table tasks per tile: (power part, axis, atom).  With three weight sets the
 // Z task carries three times the work, so every axis's powers are split in
 // two parts on separate threads; a single set keeps one part per axis.
 template <int NW> struct TableShape {
     static constexpr int parts = NW == 1 ? 1 : 2;
-    static constexpr int tasks = parts * 3 * kMfmaTileAtoms;
+    static constexpr int tasks = parts * 3 * Tile<NW>::atoms;
     static constexpr int min_waves = tasks / 64; // every task has its own thread
 };
-constexpr int kMfmaCols = 16;      // |n_z| = 0 .. 15
-constexpr int kRoots = 64;         // e^{2 pi i q / kRoots} table for the base phase
-// B fragments in LDS: [K-step][part: re hi, re lo, im hi, im lo][atom group][column]
-constexpr int kBParts = 4;
-constexpr int kBFrags = kMfmaKSteps * kBParts * 4 * kMfmaCols;
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
@@ -135,9 +149,9 @@ __device__ __forceinline__ void unit_phase(double f, const double2 *roots, doubl
 }
 
 struct TileBufs {
-    float2 *tabx;   // [nn][kTabStride]
-    float2 *taby;   // [nn][kTabStride]
-    halfv_t *bfr;   // [NW][kBFrags]
+    float2 *tabx;   // [nn][Tile::stride]
+    float2 *taby;   // [nn][Tile::stride]
+    halfv_t *bfr;   // [NW][Tile::bfrags]
 };
 
 // Build the tables of one tile.  Task (power part hf, axis d, atom j): with
@@ -150,11 +164,11 @@ struct TileBufs {
 template <int NW>
 __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool live, float x,
                                            const float (&w)[NW], double inv_box, int nmax,
-                                           const double2 *roots)
+                                           int2 xrows, int2 yrows, const double2 *roots)
 {
-    const int hf = task / (3 * kMfmaTileAtoms);
-    const int rem = task - hf * 3 * kMfmaTileAtoms;
-    const int d = rem / kMfmaTileAtoms, j = rem - d * kMfmaTileAtoms;
+    const int hf = task / (3 * Tile<NW>::atoms);
+    const int rem = task - hf * 3 * Tile<NW>::atoms;
+    const int d = rem / Tile<NW>::atoms, j = rem - d * Tile<NW>::atoms;
     const int n1 = TableShape<NW>::parts == 1 ? nmax : (nmax + 1) / 2;
     const int n_begin = hf == 0 ? 0 : n1 + 1, n_end = hf == 0 ? n1 : nmax;
     const double f = (double)x * inv_box;
@@ -168,12 +182,16 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
         }
     }
     if (d < 2) {
-        float2 *colp = (d == 0 ? tb.tabx : tb.taby) + j;
-        if (hf == 0) colp[nmax * kTabStride] = make_float2((float)pr, 0.f);
-        for (int n = n_begin > 0 ? n_begin : 1; n <= n_end; ++n) {
+        // rows lo .. hi of this axis; row of power m at zero + m * stride
+        const int lo = d == 0 ? xrows.x : yrows.x;
+        const int hi = lo + (d == 0 ? xrows.y : yrows.y) - 1;
+        float2 *zero = (d == 0 ? tb.tabx : tb.taby) + j - lo * Tile<NW>::stride;
+        if (hf == 0 && lo <= 0 && hi >= 0) zero[0] = make_float2((float)pr, 0.f);
+        const int n_last = min(n_end, max(-lo, hi));
+        for (int n = n_begin > 0 ? n_begin : 1; n <= n_last; ++n) {
             cmul(pr, pi, cs, sn);
-            colp[(nmax + n) * kTabStride] = make_float2((float)pr, (float)pi);
-            colp[(nmax - n) * kTabStride] = make_float2((float)pr, -(float)pi);
+            if (n >= lo && n <= hi) zero[n * Tile<NW>::stride] = make_float2((float)pr, (float)pi);
+            if (-n >= lo && -n <= hi) zero[-n * Tile<NW>::stride] = make_float2((float)pr, -(float)pi);
         }
     } else {
         const int ks = j / kKStep, g = (j % kKStep) / kAtomsPerLane, h = j % kAtomsPerLane;
@@ -190,7 +208,7 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
                 asm volatile("" : "+v"(zr), "+v"(zi));
                 const _Float16 rh = (_Float16)zr, ih = (_Float16)zi;
                 const _Float16 rl = (_Float16)(zr - (float)rh), il = (_Float16)(zi - (float)ih);
-                _Float16 *bs = bh + (size_t)s * kBFrags * kAtomsPerLane;
+                _Float16 *bs = bh + (size_t)s * Tile<NW>::bfrags * kAtomsPerLane;
                 bs[bfrag_index(ks, 0, g, n) * kAtomsPerLane + h] = rh;
                 bs[bfrag_index(ks, 1, g, n) * kAtomsPerLane + h] = rl;
                 bs[bfrag_index(ks, 2, g, n) * kAtomsPerLane + h] = ih;
@@ -206,21 +224,21 @@ template <int NW> struct MfmaShape {
     static constexpr int max_waves = NW == 1 ? kMfmaMaxWaves : 8;
 };
 
-template <int NW>
-__global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kernel(RhokMfmaArgs a)
+template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaArgs &a)
 {
     extern __shared__ double2 lds_roots[]; // [kRoots], then two tile buffers
     const int nmax = a.nmax;
-    const int nn = 2 * nmax + 1;
+    const int2 xrows = make_int2(a.x_lo, a.x_rows), yrows = make_int2(a.y_lo, a.y_rows);
     // two tile buffers of buf_stride float2 each (a multiple of 2: 16-byte aligned)
     float2 *const buf0 = reinterpret_cast<float2 *>(lds_roots + kRoots);
     const int buf_stride =
-        2 * nn * kTabStride + NW * kBFrags * (int)(sizeof(halfv_t) / sizeof(float2));
+        (a.x_rows + a.y_rows) * Tile<NW>::stride +
+        NW * Tile<NW>::bfrags * (int)(sizeof(halfv_t) / sizeof(float2));
     auto tile_bufs = [&](int b) {
         TileBufs t;
         t.tabx = buf0 + b * buf_stride;
-        t.taby = t.tabx + nn * kTabStride;
-        t.bfr = reinterpret_cast<halfv_t *>(t.taby + nn * kTabStride);
+        t.taby = t.tabx + a.x_rows * Tile<NW>::stride;
+        t.bfr = reinterpret_cast<halfv_t *>(t.taby + a.y_rows * Tile<NW>::stride);
         return t;
     };
 
@@ -232,11 +250,11 @@ __global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kerne
     const int mt = blockIdx.x * waves + wave;
     const bool active = mt < a.n_mtiles; // wave-uniform
     const int pm_row = mt * 16 + col;
-    const int ax = active ? a.pair_nx[pm_row] + nmax : nmax;
-    const int ay = active ? a.pair_ny[pm_row] + nmax : nmax;
+    const int ax = active ? a.pair_nx[pm_row] - a.x_lo : 0; // table rows
+    const int ay = active ? a.pair_ny[pm_row] - a.y_lo : 0;
     // the lane's X and Y rows at its first atom (16-byte aligned) per buffer
-    const int xoff = ax * kTabStride + grp * kAtomsPerLane;
-    const int yoff = ay * kTabStride + grp * kAtomsPerLane;
+    const int xoff = ax * Tile<NW>::stride + grp * kAtomsPerLane;
+    const int yoff = ay * Tile<NW>::stride + grp * kAtomsPerLane;
     const int boff = grp * kMfmaCols + col;
 
     for (int q = threadIdx.x; q < kRoots; q += blockDim.x) {
@@ -245,32 +263,35 @@ __global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kerne
         lds_roots[q] = make_double2(cs, sn);
     }
     // B columns above nmax are never stored; keep them zero
-    for (int f = threadIdx.x; f < 2 * NW * kBFrags; f += blockDim.x)
-        if (f % kMfmaCols > nmax) tile_bufs(f / (NW * kBFrags)).bfr[f % (NW * kBFrags)] = halfv_t{};
+    for (int f = threadIdx.x; f < 2 * NW * Tile<NW>::bfrags; f += blockDim.x)
+        if (f % kMfmaCols > nmax) tile_bufs(f / (NW * Tile<NW>::bfrags)).bfr[f % (NW * Tile<NW>::bfrags)] = halfv_t{};
 
     double acc[NW][4][4];
+    float4_t sum[NW][4]; // products of the last Tile::acc_tiles tiles at most
 #pragma unroll
     for (int w = 0; w < NW; ++w)
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[w][s][v] = 0.0;
+            sum[w][s] = float4_t{0.f, 0.f, 0.f, 0.f};
+        }
 
     const int64_t a_begin = (int64_t)blockIdx.y * a.atoms_per_block;
     int64_t a_end = a_begin + a.atoms_per_block;
     if (a_end > a.n_atoms) a_end = a.n_atoms;
     const int n_tiles =
-        a_end > a_begin ? (int)((a_end - a_begin + kMfmaTileAtoms - 1) / kMfmaTileAtoms) : 0;
+        a_end > a_begin ? (int)((a_end - a_begin + Tile<NW>::atoms - 1) / Tile<NW>::atoms) : 0;
 
     // table task of this thread (blockDim >= TableShape<NW>::tasks) and its inputs,
     // loaded one tile ahead of their use; the Z task also loads the weights
     const int task = threadIdx.x;
     const bool builder = task < TableShape<NW>::tasks;
-    const int trem = task % (3 * kMfmaTileAtoms);
-    const int td = trem / kMfmaTileAtoms, tj = trem - td * kMfmaTileAtoms;
+    const int trem = task % (3 * Tile<NW>::atoms);
+    const int td = trem / Tile<NW>::atoms, tj = trem - td * Tile<NW>::atoms;
     const bool weighted = NW > 1 && td == 2;
     auto load_in = [&](int it, float &x, float (&w)[NW]) -> bool {
-        const int64_t at = a_begin + (int64_t)it * kMfmaTileAtoms + tj;
+        const int64_t at = a_begin + (int64_t)it * Tile<NW>::atoms + tj;
         const bool live = builder && it < n_tiles && at < a_end;
         x = live ? a.pos[(int64_t)td * a.n_atoms + at] : 0.f;
 #pragma unroll
@@ -282,7 +303,9 @@ __global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kerne
     const bool live_cur = load_in(0, x_cur, w_cur);
     bool live_next = load_in(1, x_next, w_next);
     __syncthreads(); // roots and zero columns
-    if (builder) build_tile<NW>(tile_bufs(0), task, live_cur, x_cur, w_cur, a.inv_box, nmax, lds_roots);
+    if (builder)
+        build_tile<NW>(tile_bufs(0), task, live_cur, x_cur, w_cur, a.inv_box, nmax, xrows, yrows,
+                       lds_roots);
     __syncthreads();
 
     for (int it = 0; it < n_tiles; ++it) {
@@ -292,7 +315,7 @@ __global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kerne
             float x_after, w_after[NW];
             const bool live_after = load_in(it + 2, x_after, w_after);
             build_tile<NW>(tile_bufs((it + 1) & 1), task, live_next, x_next, w_next, a.inv_box,
-                           nmax, lds_roots);
+                           nmax, xrows, yrows, lds_roots);
             x_next = x_after;
 #pragma unroll
             for (int s = 0; s < NW; ++s) w_next[s] = w_after[s];
@@ -301,14 +324,9 @@ __global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kerne
         if (active) {
             const float4 *xrow = reinterpret_cast<const float4 *>(cur.tabx + xoff);
             const float4 *yrow = reinterpret_cast<const float4 *>(cur.taby + yoff);
-            float4_t sum[NW][4];
-#pragma unroll
-            for (int w = 0; w < NW; ++w)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) sum[w][s] = float4_t{0.f, 0.f, 0.f, 0.f};
             // all K-steps of the tile: the entries of atoms past the end are zero
 #pragma unroll
-            for (int ks = 0; ks < kMfmaKSteps; ++ks) {
+            for (int ks = 0; ks < Tile<NW>::ksteps; ++ks) {
                 uint32_t wrh[kAtomsPerLane / 2], wrl[kAtomsPerLane / 2];
                 uint32_t wih[kAtomsPerLane / 2], wil[kAtomsPerLane / 2];
 #pragma unroll
@@ -351,7 +369,7 @@ __global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kerne
                 const halfv_t pil = __builtin_bit_cast(halfv_t, vil);
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
-                    const halfv_t *bl = cur.bfr + w * kBFrags + boff;
+                    const halfv_t *bl = cur.bfr + w * Tile<NW>::bfrags + boff;
                     const halfv_t zrh = bl[bfrag_index(ks, 0, 0, 0)];
                     const halfv_t zrl = bl[bfrag_index(ks, 1, 0, 0)];
                     const halfv_t zih = bl[bfrag_index(ks, 2, 0, 0)];
@@ -372,12 +390,16 @@ __global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kerne
                     sw[3] = mfma(pil, zrh, sw[3]);
                 }
             }
+            if ((it + 1) % Tile<NW>::acc_tiles == 0 || it + 1 == n_tiles) {
 #pragma unroll
-            for (int w = 0; w < NW; ++w)
+                for (int w = 0; w < NW; ++w)
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
+                    for (int s = 0; s < 4; ++s) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[w][s][v] += (double)sum[w][s][v];
+                        for (int v = 0; v < 4; ++v) acc[w][s][v] += (double)sum[w][s][v];
+                        sum[w][s] = float4_t{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
         }
         __syncthreads(); // next buffer complete; this one free for the tile after
     }
@@ -403,6 +425,24 @@ __global__ __launch_bounds__(MfmaShape<NW>::max_waves * 64) void rhok_mfma_kerne
             }
         }
     }
+}
+
+template <int NW> __global__ void rhok_mfma_kernel(RhokMfmaArgs a);
+
+// One weight set: at most 120 registers, so that a SIMD holding three of its
+// waves (360 registers) keeps room for a wave of a flush kernel that runs
+// beside it on another stream.
+template <>
+__global__ __launch_bounds__(MfmaShape<1>::max_waves * 64) __attribute__((amdgpu_num_vgpr(60)))
+void rhok_mfma_kernel<1>(RhokMfmaArgs a)
+{
+    rhok_mfma_body<1>(a);
+}
+
+template <>
+__global__ __launch_bounds__(MfmaShape<3>::max_waves * 64) void rhok_mfma_kernel<3>(RhokMfmaArgs a)
+{
+    rhok_mfma_body<3>(a);
 }
 
 // One wave per k-vector: sum the partials of its slot over the atom blocks in
@@ -463,18 +503,22 @@ __global__ __launch_bounds__(256) void rhok_mfma_final_kernel(RhokMfmaArgs a)
 int rhok_mfma_cols() { return kMfmaCols; }
 int rhok_mfma_max_nmax() { return kMfmaCols - 1; }
 
-size_t rhok_mfma_lds_bytes(int nmax, int nw)
+template <int NW> static size_t lds_bytes(int table_rows)
 {
-    const int nn = 2 * nmax + 1;
     return (size_t)kRoots * sizeof(double2) +
-           2 * ((size_t)2 * nn * kTabStride * sizeof(float2) +
-                (size_t)nw * kBFrags * sizeof(halfv_t));
+           2 * ((size_t)table_rows * Tile<NW>::stride * sizeof(float2) +
+                (size_t)NW * Tile<NW>::bfrags * sizeof(halfv_t));
 }
 
-hipError_t rhok_mfma_prepare(int nmax, int nw)
+size_t rhok_mfma_lds_bytes(int table_rows, int nw)
 {
-    if (nmax > kMfmaCols - 1 || (nw != 1 && nw != 3)) return hipErrorInvalidValue;
-    const size_t lds = rhok_mfma_lds_bytes(nmax, nw);
+    return nw == 1 ? lds_bytes<1>(table_rows) : lds_bytes<3>(table_rows);
+}
+
+hipError_t rhok_mfma_prepare(int table_rows, int nw)
+{
+    if (table_rows > 4 * kMfmaCols - 2 || (nw != 1 && nw != 3)) return hipErrorInvalidValue;
+    const size_t lds = rhok_mfma_lds_bytes(table_rows, nw);
     if (lds <= 64 * 1024) return hipSuccess;
     const void *fn = nw == 1 ? reinterpret_cast<const void *>(&rhok_mfma_kernel<1>)
                              : reinterpret_cast<const void *>(&rhok_mfma_kernel<3>);
@@ -495,7 +539,7 @@ template <int NW> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t
     int waves = (a.n_mtiles + chunks - 1) / chunks;
     if (waves < TableShape<NW>::min_waves) waves = TableShape<NW>::min_waves;
     hipLaunchKernelGGL(rhok_mfma_kernel<NW>, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
-                       dim3(waves * 64), rhok_mfma_lds_bytes(a.nmax, NW), st, a);
+                       dim3(waves * 64), rhok_mfma_lds_bytes(a.x_rows + a.y_rows, NW), st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rhok_mfma_final_kernel<NW>, dim3((unsigned)((a.nk + 3) / 4)), dim3(256), 0,
@@ -505,7 +549,9 @@ template <int NW> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t
 
 hipError_t launch_rhok_mfma(const RhokMfmaArgs &a, hipStream_t st)
 {
-    if (a.nmax > kMfmaCols - 1 || a.n_mtiles < 1) return hipErrorInvalidValue;
+    if (a.nmax > kMfmaCols - 1 || a.n_mtiles < 1 || a.x_rows < 1 || a.y_rows < 1 ||
+        a.x_rows + a.y_rows > 4 * kMfmaCols - 2)
+        return hipErrorInvalidValue;
     if (a.nw == 1) return launch_nw<1>(a, st);
     if (a.nw == 3) return launch_nw<3>(a, st);
     return hipErrorInvalidValue;

@@ -744,7 +744,16 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(512, per_cu),
                                                                    g.d.n_atoms / 1024));
                 const int ncol = rhok_mfma_cols();
-                std::vector<int32_t> pnx((size_t)n_mtiles * 16, 0), pny((size_t)n_mtiles * 16, 0);
+                // table rows: the n_x and n_y ranges of the pairs (padding
+                // pairs take the first row of each)
+                int x_lo = kv[0], x_hi = kv[0], y_lo = kv[1], y_hi = kv[1];
+                for (int q = 0; q < nk; ++q) {
+                    x_lo = std::min(x_lo, kv[3 * q]);
+                    x_hi = std::max(x_hi, kv[3 * q]);
+                    y_lo = std::min(y_lo, kv[3 * q + 1]);
+                    y_hi = std::max(y_hi, kv[3 * q + 1]);
+                }
+                std::vector<int32_t> pnx((size_t)n_mtiles * 16, x_lo), pny((size_t)n_mtiles * 16, y_lo);
                 int u = 0;
                 for (auto &e : pair_ix) {
                     e.second = u;
@@ -769,7 +778,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 CREATE_HIP(hipMemcpy(g.d_mtab, packed.data(), packed.size() * sizeof(int32_t),
                                      hipMemcpyHostToDevice));
                 CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * nk * g.nw * 2 * sizeof(double)));
-                CREATE_HIP(rhok_mfma_prepare(nmax, g.nw));
+                CREATE_HIP(rhok_mfma_prepare((x_hi - x_lo + 1) + (y_hi - y_lo + 1), g.nw));
                 if (g.nw == 3) {
                     // basis of each k-vector: khat, then e1 = the Cartesian axis
                     // least aligned with khat, made orthogonal to it and
@@ -813,6 +822,10 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 r.k_src = r.slot_k + slot_k.size();
                 r.n_mtiles = n_mtiles;
                 r.nmax = nmax;
+                r.x_lo = x_lo;
+                r.x_rows = x_hi - x_lo + 1;
+                r.y_lo = y_lo;
+                r.y_rows = y_hi - y_lo + 1;
                 r.inv_box = 1.0 / g.d.box;
                 r.partial = g.d_partial;
                 r.n_atom_blocks = n_ab;
