@@ -64,25 +64,28 @@ constexpr int kBParts = 4;
 // to the double accumulators
 constexpr int kAccAtoms = 128;
 
-// The LDS tile: atoms per tile, K-steps, table row stride (float2; atoms + 2
-// shifts consecutive rows by 4 banks) and B fragments per weight set.  One
-// weight set takes 128-atom tiles: half the block-wide barriers of 64-atom
-// tiles, 10% faster.  Three sets keep 64-atom tiles: their B fragments are
-// three times larger, and two 128-atom buffers would not fit in 160 KB of LDS.
-template <int NW> struct Tile {
-    static constexpr int atoms = NW == 1 ? 128 : 64;
+// The LDS tile of TA atoms: K-steps, table row stride (float2; TA + 2 shifts
+// consecutive rows by 4 banks) and B fragments per weight set.  128-atom tiles
+// meet half the block-wide barriers of 64-atom tiles (n(k) 130 -> 108 us,
+// currents 366 -> 333 us at 10^6 atoms).  One weight set always takes them;
+// three weight sets triple the B fragments and take them only when two
+// buffers fit in the 160 KB of LDS (k-sets with few table rows), else 64.
+template <int TA> struct Tile {
+    static constexpr int atoms = TA;
     static constexpr int ksteps = atoms / kKStep;
     static constexpr int stride = atoms + 2;
     static constexpr int bfrags = ksteps * kBParts * 4 * kMfmaCols;
     static constexpr int acc_tiles = kAccAtoms / atoms;
 };
+constexpr size_t kLdsBytes = 160 * 1024; // LDS of a CU (and most one block may take)
 
 // Table tasks per tile: (power part, axis, atom).  With three weight sets the
-// Z task carries three times the work, so every axis's powers are split in
-// two parts on separate threads; a single set keeps one part per axis.
-template <int NW> struct TableShape {
-    static constexpr int parts = NW == 1 ? 1 : 2;
-    static constexpr int tasks = parts * 3 * Tile<NW>::atoms;
+// Z task carries three times the work, so with 64-atom tiles every axis's
+// powers are split in two parts on separate threads; otherwise one part per
+// axis (128-atom tiles already give every thread of six waves a task).
+template <int NW, int TA> struct TableShape {
+    static constexpr int parts = NW == 1 || TA == 128 ? 1 : 2;
+    static constexpr int tasks = parts * 3 * TA;
     static constexpr int min_waves = tasks / 64; // every task has its own thread
 };
 
@@ -161,15 +164,15 @@ struct TileBufs {
 // for each weight set w the products w * Z^n split into fp16 hi/lo B
 // fragments (NW = 1: w = 1; NW = 3: the atom's velocity components).  Atoms
 // past the end (live == false) get zero entries, so they add nothing.
-template <int NW>
+template <int NW, int TA>
 __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool live, float x,
                                            const float (&w)[NW], double inv_box, int nmax,
                                            int2 xrows, int2 yrows, const double2 *roots)
 {
-    const int hf = task / (3 * Tile<NW>::atoms);
-    const int rem = task - hf * 3 * Tile<NW>::atoms;
-    const int d = rem / Tile<NW>::atoms, j = rem - d * Tile<NW>::atoms;
-    const int n1 = TableShape<NW>::parts == 1 ? nmax : (nmax + 1) / 2;
+    const int hf = task / (3 * Tile<TA>::atoms);
+    const int rem = task - hf * 3 * Tile<TA>::atoms;
+    const int d = rem / Tile<TA>::atoms, j = rem - d * Tile<TA>::atoms;
+    const int n1 = TableShape<NW, TA>::parts == 1 ? nmax : (nmax + 1) / 2;
     const int n_begin = hf == 0 ? 0 : n1 + 1, n_end = hf == 0 ? n1 : nmax;
     const double f = (double)x * inv_box;
     double cs = 0.0, sn = 0.0, pr = 0.0, pi = 0.0;
@@ -185,13 +188,13 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
         // rows lo .. hi of this axis; row of power m at zero + m * stride
         const int lo = d == 0 ? xrows.x : yrows.x;
         const int hi = lo + (d == 0 ? xrows.y : yrows.y) - 1;
-        float2 *zero = (d == 0 ? tb.tabx : tb.taby) + j - lo * Tile<NW>::stride;
+        float2 *zero = (d == 0 ? tb.tabx : tb.taby) + j - lo * Tile<TA>::stride;
         if (hf == 0 && lo <= 0 && hi >= 0) zero[0] = make_float2((float)pr, 0.f);
         const int n_last = min(n_end, max(-lo, hi));
         for (int n = n_begin > 0 ? n_begin : 1; n <= n_last; ++n) {
             cmul(pr, pi, cs, sn);
-            if (n >= lo && n <= hi) zero[n * Tile<NW>::stride] = make_float2((float)pr, (float)pi);
-            if (-n >= lo && -n <= hi) zero[-n * Tile<NW>::stride] = make_float2((float)pr, -(float)pi);
+            if (n >= lo && n <= hi) zero[n * Tile<TA>::stride] = make_float2((float)pr, (float)pi);
+            if (-n >= lo && -n <= hi) zero[-n * Tile<TA>::stride] = make_float2((float)pr, -(float)pi);
         }
     } else {
         const int ks = j / kKStep, g = (j % kKStep) / kAtomsPerLane, h = j % kAtomsPerLane;
@@ -208,7 +211,7 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
                 asm volatile("" : "+v"(zr), "+v"(zi));
                 const _Float16 rh = (_Float16)zr, ih = (_Float16)zi;
                 const _Float16 rl = (_Float16)(zr - (float)rh), il = (_Float16)(zi - (float)ih);
-                _Float16 *bs = bh + (size_t)s * Tile<NW>::bfrags * kAtomsPerLane;
+                _Float16 *bs = bh + (size_t)s * Tile<TA>::bfrags * kAtomsPerLane;
                 bs[bfrag_index(ks, 0, g, n) * kAtomsPerLane + h] = rh;
                 bs[bfrag_index(ks, 1, g, n) * kAtomsPerLane + h] = rl;
                 bs[bfrag_index(ks, 2, g, n) * kAtomsPerLane + h] = ih;
@@ -224,7 +227,7 @@ template <int NW> struct MfmaShape {
     static constexpr int max_waves = NW == 1 ? kMfmaMaxWaves : 8;
 };
 
-template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaArgs &a)
+template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaArgs &a)
 {
     extern __shared__ double2 lds_roots[]; // [kRoots], then two tile buffers
     const int nmax = a.nmax;
@@ -232,13 +235,13 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
     // two tile buffers of buf_stride float2 each (a multiple of 2: 16-byte aligned)
     float2 *const buf0 = reinterpret_cast<float2 *>(lds_roots + kRoots);
     const int buf_stride =
-        (a.x_rows + a.y_rows) * Tile<NW>::stride +
-        NW * Tile<NW>::bfrags * (int)(sizeof(halfv_t) / sizeof(float2));
+        (a.x_rows + a.y_rows) * Tile<TA>::stride +
+        NW * Tile<TA>::bfrags * (int)(sizeof(halfv_t) / sizeof(float2));
     auto tile_bufs = [&](int b) {
         TileBufs t;
         t.tabx = buf0 + b * buf_stride;
-        t.taby = t.tabx + a.x_rows * Tile<NW>::stride;
-        t.bfr = reinterpret_cast<halfv_t *>(t.taby + a.y_rows * Tile<NW>::stride);
+        t.taby = t.tabx + a.x_rows * Tile<TA>::stride;
+        t.bfr = reinterpret_cast<halfv_t *>(t.taby + a.y_rows * Tile<TA>::stride);
         return t;
     };
 
@@ -253,8 +256,8 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
     const int ax = active ? a.pair_nx[pm_row] - a.x_lo : 0; // table rows
     const int ay = active ? a.pair_ny[pm_row] - a.y_lo : 0;
     // the lane's X and Y rows at its first atom (16-byte aligned) per buffer
-    const int xoff = ax * Tile<NW>::stride + grp * kAtomsPerLane;
-    const int yoff = ay * Tile<NW>::stride + grp * kAtomsPerLane;
+    const int xoff = ax * Tile<TA>::stride + grp * kAtomsPerLane;
+    const int yoff = ay * Tile<TA>::stride + grp * kAtomsPerLane;
     const int boff = grp * kMfmaCols + col;
 
     for (int q = threadIdx.x; q < kRoots; q += blockDim.x) {
@@ -263,8 +266,8 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
         lds_roots[q] = make_double2(cs, sn);
     }
     // B columns above nmax are never stored; keep them zero
-    for (int f = threadIdx.x; f < 2 * NW * Tile<NW>::bfrags; f += blockDim.x)
-        if (f % kMfmaCols > nmax) tile_bufs(f / (NW * Tile<NW>::bfrags)).bfr[f % (NW * Tile<NW>::bfrags)] = halfv_t{};
+    for (int f = threadIdx.x; f < 2 * NW * Tile<TA>::bfrags; f += blockDim.x)
+        if (f % kMfmaCols > nmax) tile_bufs(f / (NW * Tile<TA>::bfrags)).bfr[f % (NW * Tile<TA>::bfrags)] = halfv_t{};
 
     double acc[NW][4][4];
     float4_t sum[NW][4]; // products of the last Tile::acc_tiles tiles at most
@@ -281,17 +284,17 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
     int64_t a_end = a_begin + a.atoms_per_block;
     if (a_end > a.n_atoms) a_end = a.n_atoms;
     const int n_tiles =
-        a_end > a_begin ? (int)((a_end - a_begin + Tile<NW>::atoms - 1) / Tile<NW>::atoms) : 0;
+        a_end > a_begin ? (int)((a_end - a_begin + Tile<TA>::atoms - 1) / Tile<TA>::atoms) : 0;
 
-    // table task of this thread (blockDim >= TableShape<NW>::tasks) and its inputs,
+    // table task of this thread (blockDim >= TableShape<NW, TA>::tasks) and its inputs,
     // loaded one tile ahead of their use; the Z task also loads the weights
     const int task = threadIdx.x;
-    const bool builder = task < TableShape<NW>::tasks;
-    const int trem = task % (3 * Tile<NW>::atoms);
-    const int td = trem / Tile<NW>::atoms, tj = trem - td * Tile<NW>::atoms;
+    const bool builder = task < TableShape<NW, TA>::tasks;
+    const int trem = task % (3 * Tile<TA>::atoms);
+    const int td = trem / Tile<TA>::atoms, tj = trem - td * Tile<TA>::atoms;
     const bool weighted = NW > 1 && td == 2;
     auto load_in = [&](int it, float &x, float (&w)[NW]) -> bool {
-        const int64_t at = a_begin + (int64_t)it * Tile<NW>::atoms + tj;
+        const int64_t at = a_begin + (int64_t)it * Tile<TA>::atoms + tj;
         const bool live = builder && it < n_tiles && at < a_end;
         x = live ? a.pos[(int64_t)td * a.n_atoms + at] : 0.f;
 #pragma unroll
@@ -304,7 +307,7 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
     bool live_next = load_in(1, x_next, w_next);
     __syncthreads(); // roots and zero columns
     if (builder)
-        build_tile<NW>(tile_bufs(0), task, live_cur, x_cur, w_cur, a.inv_box, nmax, xrows, yrows,
+        build_tile<NW, TA>(tile_bufs(0), task, live_cur, x_cur, w_cur, a.inv_box, nmax, xrows, yrows,
                        lds_roots);
     __syncthreads();
 
@@ -314,7 +317,7 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
         if (builder && it + 1 < n_tiles) {
             float x_after, w_after[NW];
             const bool live_after = load_in(it + 2, x_after, w_after);
-            build_tile<NW>(tile_bufs((it + 1) & 1), task, live_next, x_next, w_next, a.inv_box,
+            build_tile<NW, TA>(tile_bufs((it + 1) & 1), task, live_next, x_next, w_next, a.inv_box,
                            nmax, xrows, yrows, lds_roots);
             x_next = x_after;
 #pragma unroll
@@ -326,7 +329,7 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
             const float4 *yrow = reinterpret_cast<const float4 *>(cur.taby + yoff);
             // all K-steps of the tile: the entries of atoms past the end are zero
 #pragma unroll
-            for (int ks = 0; ks < Tile<NW>::ksteps; ++ks) {
+            for (int ks = 0; ks < Tile<TA>::ksteps; ++ks) {
                 uint32_t wrh[kAtomsPerLane / 2], wrl[kAtomsPerLane / 2];
                 uint32_t wih[kAtomsPerLane / 2], wil[kAtomsPerLane / 2];
 #pragma unroll
@@ -369,7 +372,7 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
                 const halfv_t pil = __builtin_bit_cast(halfv_t, vil);
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
-                    const halfv_t *bl = cur.bfr + w * Tile<NW>::bfrags + boff;
+                    const halfv_t *bl = cur.bfr + w * Tile<TA>::bfrags + boff;
                     const halfv_t zrh = bl[bfrag_index(ks, 0, 0, 0)];
                     const halfv_t zrl = bl[bfrag_index(ks, 1, 0, 0)];
                     const halfv_t zih = bl[bfrag_index(ks, 2, 0, 0)];
@@ -390,7 +393,7 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
                     sw[3] = mfma(pil, zrh, sw[3]);
                 }
             }
-            if ((it + 1) % Tile<NW>::acc_tiles == 0 || it + 1 == n_tiles) {
+            if ((it + 1) % Tile<TA>::acc_tiles == 0 || it + 1 == n_tiles) {
 #pragma unroll
                 for (int w = 0; w < NW; ++w)
 #pragma unroll
@@ -427,22 +430,28 @@ template <int NW> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaA
     }
 }
 
-template <int NW> __global__ void rhok_mfma_kernel(RhokMfmaArgs a);
+template <int NW, int TA> __global__ void rhok_mfma_kernel(RhokMfmaArgs a);
 
 // One weight set: at most 120 registers, so that a SIMD holding three of its
 // waves (360 registers) keeps room for a wave of a flush kernel that runs
 // beside it on another stream.
 template <>
 __global__ __launch_bounds__(MfmaShape<1>::max_waves * 64) __attribute__((amdgpu_num_vgpr(60)))
-void rhok_mfma_kernel<1>(RhokMfmaArgs a)
+void rhok_mfma_kernel<1, 128>(RhokMfmaArgs a)
 {
-    rhok_mfma_body<1>(a);
+    rhok_mfma_body<1, 128>(a);
 }
 
 template <>
-__global__ __launch_bounds__(MfmaShape<3>::max_waves * 64) void rhok_mfma_kernel<3>(RhokMfmaArgs a)
+__global__ __launch_bounds__(MfmaShape<3>::max_waves * 64) void rhok_mfma_kernel<3, 64>(RhokMfmaArgs a)
 {
-    rhok_mfma_body<3>(a);
+    rhok_mfma_body<3, 64>(a);
+}
+
+template <>
+__global__ __launch_bounds__(MfmaShape<3>::max_waves * 64) void rhok_mfma_kernel<3, 128>(RhokMfmaArgs a)
+{
+    rhok_mfma_body<3, 128>(a);
 }
 
 // One wave per k-vector: sum the partials of its slot over the atom blocks in
@@ -503,25 +512,36 @@ __global__ __launch_bounds__(256) void rhok_mfma_final_kernel(RhokMfmaArgs a)
 int rhok_mfma_cols() { return kMfmaCols; }
 int rhok_mfma_max_nmax() { return kMfmaCols - 1; }
 
-template <int NW> static size_t lds_bytes(int table_rows)
+template <int NW, int TA> static size_t lds_bytes(int table_rows)
 {
     return (size_t)kRoots * sizeof(double2) +
-           2 * ((size_t)table_rows * Tile<NW>::stride * sizeof(float2) +
-                (size_t)NW * Tile<NW>::bfrags * sizeof(halfv_t));
+           2 * ((size_t)table_rows * Tile<TA>::stride * sizeof(float2) +
+                (size_t)NW * Tile<TA>::bfrags * sizeof(halfv_t));
+}
+
+// Atoms per tile for a k-set with table_rows X and Y rows.
+static int tile_atoms(int table_rows, int nw)
+{
+    return nw == 1 || lds_bytes<3, 128>(table_rows) <= kLdsBytes ? 128 : 64;
 }
 
 size_t rhok_mfma_lds_bytes(int table_rows, int nw)
 {
-    return nw == 1 ? lds_bytes<1>(table_rows) : lds_bytes<3>(table_rows);
+    if (nw == 1) return lds_bytes<1, 128>(table_rows);
+    return tile_atoms(table_rows, nw) == 128 ? lds_bytes<3, 128>(table_rows)
+                                             : lds_bytes<3, 64>(table_rows);
 }
 
 hipError_t rhok_mfma_prepare(int table_rows, int nw)
 {
     if (table_rows > 4 * kMfmaCols - 2 || (nw != 1 && nw != 3)) return hipErrorInvalidValue;
     const size_t lds = rhok_mfma_lds_bytes(table_rows, nw);
+    if (lds > kLdsBytes) return hipErrorInvalidValue;
     if (lds <= 64 * 1024) return hipSuccess;
-    const void *fn = nw == 1 ? reinterpret_cast<const void *>(&rhok_mfma_kernel<1>)
-                             : reinterpret_cast<const void *>(&rhok_mfma_kernel<3>);
+    const void *fn = nw == 1 ? reinterpret_cast<const void *>(&rhok_mfma_kernel<1, 128>)
+                     : tile_atoms(table_rows, nw) == 128
+                         ? reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 128>)
+                         : reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 64>);
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -531,15 +551,16 @@ int rhok_mfma_chunks(int n_mtiles, int nw)
     return (n_mtiles + maxw - 1) / maxw;
 }
 
-template <int NW> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t st)
+template <int NW, int TA> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t st)
 {
     // waves per block: the M tiles dealt evenly over the fewest blocks, at
     // least one thread per table task
     const int chunks = rhok_mfma_chunks(a.n_mtiles, NW);
     int waves = (a.n_mtiles + chunks - 1) / chunks;
-    if (waves < TableShape<NW>::min_waves) waves = TableShape<NW>::min_waves;
-    hipLaunchKernelGGL(rhok_mfma_kernel<NW>, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
-                       dim3(waves * 64), rhok_mfma_lds_bytes(a.x_rows + a.y_rows, NW), st, a);
+    if (waves < TableShape<NW, TA>::min_waves) waves = TableShape<NW, TA>::min_waves;
+    const size_t lds = lds_bytes<NW, TA>(a.x_rows + a.y_rows);
+    hipLaunchKernelGGL((rhok_mfma_kernel<NW, TA>), dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
+                       dim3(waves * 64), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rhok_mfma_final_kernel<NW>, dim3((unsigned)((a.nk + 3) / 4)), dim3(256), 0,
@@ -552,8 +573,10 @@ hipError_t launch_rhok_mfma(const RhokMfmaArgs &a, hipStream_t st)
     if (a.nmax > kMfmaCols - 1 || a.n_mtiles < 1 || a.x_rows < 1 || a.y_rows < 1 ||
         a.x_rows + a.y_rows > 4 * kMfmaCols - 2)
         return hipErrorInvalidValue;
-    if (a.nw == 1) return launch_nw<1>(a, st);
-    if (a.nw == 3) return launch_nw<3>(a, st);
+    const int rows = a.x_rows + a.y_rows;
+    if (a.nw == 1) return launch_nw<1, 128>(a, st);
+    if (a.nw == 3)
+        return tile_atoms(rows, 3) == 128 ? launch_nw<3, 128>(a, st) : launch_nw<3, 64>(a, st);
     return hipErrorInvalidValue;
 }
 
