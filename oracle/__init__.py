@@ -4,7 +4,8 @@ The oracle is the plain, slow, obviously-correct reference the GPU library is
 checked against: Algorithm 1 (update) and Algorithm 2 (readout) of the paper's
 Appendix D, applied per channel in double precision, plus the trapezoid
 Green-Kubo integral (Eqs. for viscosity and thermal conductivity, Section
-2.3) and the direct k-space density sum (Eq. k-density, Section "Currents").
+2.3), the direct k-space density sum (Eq. k-density, Section "Currents") and
+the partial momentum densities of the mass-flux correction (Section 2.3).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library
@@ -63,6 +64,8 @@ def lib():
         L.oracle_push_pair.restype = i32
         L.oracle_currents.argtypes = [vp, vp, i64, vp, i32, dbl, vp, vp]
         L.oracle_currents.restype = i32
+        L.oracle_partial_momentum.argtypes = [vp, vp, i64, vp, i32, dbl, vp]
+        L.oracle_partial_momentum.restype = i32
         _lib = L
     return _lib
 
@@ -200,6 +203,23 @@ def currents(pos_f32: np.ndarray, vel_f32: np.ndarray, kvec: np.ndarray, box: fl
     if rc != 0:
         raise ValueError("the zero k-vector has no direction")
     return (re + 1j * im).reshape(nk, 3)
+
+
+def partial_momentum(vel, species, masses, volume: float) -> np.ndarray:
+    """Partial momentum densities j_{I_s} = (1/V) sum_{i in I_s} m_i v_i of the
+    mass-flux correction (Section "Viscosity and thermal conductivity"; reading
+    R22 of the C source): [n_species * 3], component alpha of species s at
+    3 s + alpha, in FP64 from velocities [3][N] (any float dtype)."""
+    v = np.ascontiguousarray(vel, dtype=np.float64)
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    ms = np.ascontiguousarray(masses, dtype=np.float64)
+    assert v.ndim == 2 and v.shape[0] == 3 and sp.shape == (v.shape[1],)
+    out = np.zeros(3 * len(ms))
+    rc = lib().oracle_partial_momentum(_ptr(v), _ptr(sp), int(v.shape[1]), _ptr(ms), int(len(ms)),
+                                       float(volume), _ptr(out))
+    if rc != 0:
+        raise ValueError("species id out of range")
+    return out
 
 
 def current_basis(n) -> np.ndarray:

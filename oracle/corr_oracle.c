@@ -49,6 +49,11 @@
  *       normalised, e2 = khat x e1.  C_L is the correlation of the first,
  *       C_T the mean of the other two (for k along z these are the paper's
  *       z, and x, y components).
+ * The partial momentum density follows the mass-flux correction of Section
+ * "Viscosity and thermal conductivity" (the equation for j_{I_s}), with the
+ * reading
+ *   R22 every atom of species s has the mass m_s; V = L^3; the output holds
+ *       j_{I_s} for every species s, component alpha at 3 s + alpha.
  *
  * parity pins: see tests/test_oracle_*.py (brute-force Eq. (1) on block
  * averaged series, closed forms, invariants, hand-worked golden example).
@@ -493,6 +498,28 @@ int oracle_currents(const float *pos, const float *vel, int64_t n_atoms, const i
             }
             re[3 * q + c] = r;
             im[3 * q + c] = i;
+        }
+    }
+    return 0;
+}
+
+/* Partial momentum density of every species (Section "Viscosity and thermal
+ * conductivity", the mass-flux correction; reading R22):
+ * out[3 s + alpha] = (1/V) sum over atoms i with species[i] == s of
+ * m_s v_alpha(i), one plain double sum per species and component in atom
+ * order.  vel: [3][n_atoms]; species: [n_atoms] in [0, n_species).  Returns
+ * -1 (output untouched) when a species id is out of range. */
+int oracle_partial_momentum(const double *vel, const int32_t *species, int64_t n_atoms,
+                            const double *masses, int n_species, double volume, double *out)
+{
+    for (int64_t i = 0; i < n_atoms; ++i)
+        if (species[i] < 0 || species[i] >= n_species) return -1;
+    for (int s = 0; s < n_species; ++s) {
+        for (int d = 0; d < 3; ++d) {
+            double sum = 0.0;
+            for (int64_t i = 0; i < n_atoms; ++i)
+                if (species[i] == s) sum += masses[s] * vel[d * n_atoms + i];
+            out[3 * s + d] = sum / volume;
         }
     }
     return 0;

@@ -36,6 +36,8 @@ int oracle_push_pair(oracle_corr *o, const double *x_re, const double *x_im, con
                      const double *y_im);
 int oracle_currents(const float *pos, const float *vel, int64_t n_atoms, const int32_t *kvec,
                     int n_k, double box, double *re, double *im);
+int oracle_partial_momentum(const double *vel, const int32_t *species, int64_t n_atoms,
+                            const double *masses, int n_species, double volume, double *out);
 
 #ifdef __cplusplus
 }
