@@ -59,7 +59,7 @@ enum corr_accum { CORR_ACC_F64 = 1, CORR_ACC_KAHAN_F32 = 2, CORR_ACC_F32 = 3 };
 enum corr_source {
     CORR_SRC_SAMPLES = 0, /* caller provides n_channels samples per push        */
     CORR_SRC_RHOK = 1,    /* caller provides positions; channels = k-vectors     */
-    CORR_SRC_CURRENTS = 2 /* caller provides positions and velocities; three
+    CORR_SRC_CURRENTS = 2, /* caller provides positions and velocities; three
                              channels per k-vector: the longitudinal current
                              khat . j and the transverse current on the basis
                              vectors e1, e2 (Section "Currents", Eqs.
@@ -72,6 +72,18 @@ enum corr_source {
                              correlation of channel 3q, C_T the mean of
                              channels 3q+1 and 3q+2.  Components of n must
                              lie within +-15; n = 0 is rejected.          */
+    CORR_SRC_MOMENTUM = 3 /* caller provides velocities; channels = the
+                             partial momentum densities of the mass-flux
+                             correction of the thermal conductivity (Section
+                             "Viscosity and thermal conductivity"): channel
+                             3s + alpha = (1/V) sum over the atoms i of
+                             species s of m_s v_alpha(i), V = box^3, for
+                             every species s.  Input (the group's real
+                             dtype): velocities [3][n_atoms]; a pair group
+                             appends [n_channels] x samples (e.g. the heat
+                             flux component of each channel) and correlates
+                             C(L) = <x(s) j(s - L)>, the densities being y.
+                             The correlations are not divided by N.        */
 };
 
 /* corr_create flags. */
@@ -108,17 +120,27 @@ typedef struct corr_group_desc {
                                the x, y form of Algorithm 1 (Appendix D): both are
                                carried through the rings and the block means and
                                C(L) = <x(s) conj(y(s - L))>.  A push then brings
-                               [2][n_channels] samples (all x, then all y).
-                               CORR_SRC_SAMPLES only; such groups always take
+                               [2][n_channels] samples (all x, then all y);
+                               CORR_SRC_MOMENTUM: x from the caller, y the
+                               densities (see there).  CORR_SRC_SAMPLES and
+                               CORR_SRC_MOMENTUM only; such groups always take
                                the per-step (direct) form                        */
     double dt;              /* simulation time step; lag time = L m^k u dt        */
-    /* CORR_SRC_RHOK and CORR_SRC_CURRENTS only (ignored otherwise): */
+    /* CORR_SRC_RHOK and CORR_SRC_CURRENTS (kvec) and CORR_SRC_MOMENTUM
+       (n_atoms, box) only (ignored otherwise): */
     const int32_t *kvec;    /* host [n_k][3] integer n, k = 2 pi n / box, n_k =
                                n_channels (RHOK) or n_channels / 3 (CURRENTS);
                                copied during corr_create                          */
     int64_t n_atoms;        /* atoms per push: input float [3][n_atoms] positions,
-                               CURRENTS: then [3][n_atoms] velocities             */
-    double box;             /* cubic box edge L                                   */
+                               CURRENTS: then [3][n_atoms] velocities;
+                               MOMENTUM: [3][n_atoms] velocities (group dtype)    */
+    double box;             /* cubic box edge L (also MOMENTUM: V = L^3)          */
+    /* CORR_SRC_MOMENTUM only (ignored otherwise): */
+    const int32_t *species; /* host [n_atoms] species of every atom, in
+                               [0, n_species); copied during corr_create          */
+    const double *masses;   /* host [n_species] mass of the atoms of each species */
+    int32_t n_species;      /* 1..8; n_channels must be 3 n_species               */
+    int32_t reserved;       /* 0                                                  */
 } corr_group_desc;
 
 /* Launch shape.  Channels are stored in tiles of tile_channels consecutive

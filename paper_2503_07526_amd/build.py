@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libcorr_gfx950.so")
 HIPCC = "/opt/rocm/bin/hipcc"
 
 SOURCES = ["corr_push.hip", "corr_deferred.hip", "corr_rhok.hip", "corr_rhok_mfma.hip",
-           "corr_reduce.hip", "corr_window.hip", "corr_runtime.cpp", "corr_autotune.cpp"]
+           "corr_reduce.hip", "corr_window.hip", "corr_momentum.hip", "corr_runtime.cpp",
+           "corr_autotune.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-mcode-object-version=5", "-fPIC",

@@ -21,7 +21,7 @@ CORR_OK, CORR_E_INVALID, CORR_E_OOM, CORR_E_DEVICE, CORR_E_STATE, CORR_E_UNSUPPO
     0, -1, -2, -3, -4, -5
 DTYPES = {"f32": 1, "f64": 2, "cf32": 3, "cf64": 4}
 ACCUMS = {"f64": 1, "kahan": 2, "f32": 3}
-SOURCES = {"samples": 0, "rhok": 1, "currents": 2}
+SOURCES = {"samples": 0, "rhok": 1, "currents": 2, "momentum": 3}
 FLAG_GRAPH, FLAG_PER_GROUP, FLAG_TIMING, FLAG_DIRECT, FLAG_RHOK_VALU = 1, 2, 4, 8, 16
 _TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64, "cf32": torch.complex64,
                 "cf64": torch.complex128}
@@ -39,7 +39,10 @@ class _GroupDesc(ctypes.Structure):
                 ("accum", ctypes.c_int32), ("source", ctypes.c_int32),
                 ("update_every", ctypes.c_int32), ("pair", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("kvec", ctypes.POINTER(ctypes.c_int32)),
-                ("n_atoms", ctypes.c_int64), ("box", ctypes.c_double)]
+                ("n_atoms", ctypes.c_int64), ("box", ctypes.c_double),
+                ("species", ctypes.POINTER(ctypes.c_int32)),
+                ("masses", ctypes.POINTER(ctypes.c_double)), ("n_species", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -118,7 +121,11 @@ class GroupDesc:
     n_atoms: int = 0
     box: float = 0.0
     pair: bool = False  # correlate (x, y) per channel: samples [2][n_channels]
+    species: np.ndarray | None = None  # momentum: species id of every atom
+    masses: np.ndarray | None = None   # momentum: mass of each species
     _kbuf: object = field(default=None, repr=False)
+    _sbuf: object = field(default=None, repr=False)
+    _mbuf: object = field(default=None, repr=False)
 
     def to_c(self) -> _GroupDesc:
         d = _GroupDesc()
@@ -130,6 +137,13 @@ class GroupDesc:
             self._kbuf = np.ascontiguousarray(self.kvec, dtype=np.int32)
             d.kvec = self._kbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         d.n_atoms, d.box = int(self.n_atoms), float(self.box)
+        if self.species is not None:
+            self._sbuf = np.ascontiguousarray(self.species, dtype=np.int32)
+            d.species = self._sbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if self.masses is not None:
+            self._mbuf = np.ascontiguousarray(self.masses, dtype=np.float64)
+            d.masses = self._mbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.n_species = len(self._mbuf)
         return d
 
     @property

@@ -147,6 +147,23 @@ struct RhokArgs {
 // atoms of P(n_x, n_y) = X^{n_x} Y^{n_y} (rows: the distinct (n_x, n_y) pairs
 // of the k-set, padded to whole 16-row tiles) and Z^{|n_z|} (16 columns,
 // |n_z| = 0 .. 15); the sign of n_z selects how the sums combine.
+// Partial momentum densities of the mass-flux correction: channel 3s + a =
+// scale[s] * sum over the atoms of species s of v_a (scale = m_s / V).
+constexpr int kMomMaxSpecies = 8;
+struct MomentumArgs {
+    const void *vel;         // [3][n_atoms] velocities (float or double); pair: then
+                             // [n_ch] x samples of the same type
+    const int32_t *species;  // [n_atoms] species ids in [0, n_species)
+    int64_t n_atoms;
+    int32_t n_species;       // 1 .. kMomMaxSpecies
+    int32_t dbl;             // 1: double velocities and output
+    double scale[kMomMaxSpecies];
+    double *partial;         // [n_blocks][3 kMomMaxSpecies] block sums
+    int32_t n_blocks;
+    int32_t pair;            // 1: output [2][n_ch], x copied from the input
+    void *out;               // [n_ch] densities, or [2][n_ch] (x, then densities)
+};
+
 struct RhokMfmaArgs {
     const float *pos;        // [3][n_atoms] positions; currents: then [3][n_atoms] velocities
     int64_t n_atoms;

@@ -1,0 +1,117 @@
+// corr_momentum.hip -- partial momentum densities of the mass-flux correction
+// of the thermal conductivity (Section "Viscosity and thermal conductivity"):
+// j_s = (1/V) sum over the atoms i of species s of m_s v(i), for every species.
+//
+// HBM-bound reduction: per atom three velocity components (12 or 24 bytes)
+// and a 4-byte species id.  Each thread sums its atoms (grid-stride, fixed order) per
+// species and component in double, the block reduces its 3 x n_species sums
+// by wave shuffles and then across waves in a fixed order, and a final kernel
+// adds the block sums in block order and scales them by m_s / V, so the result
+// does not depend on timing.
+#include <hip/hip_runtime.h>
+
+#include "corr_kernels.h"
+
+namespace corr {
+
+namespace {
+
+constexpr int kMomThreads = 256;
+constexpr int kMomAtomsPerThread = 8; // atoms per thread before the grid is capped
+constexpr int kMomMaxBlocks = 1024;
+constexpr int kMomSums = 3 * kMomMaxSpecies;
+
+template <typename T> __global__ __launch_bounds__(kMomThreads) void momentum_partial_kernel(MomentumArgs a)
+{
+    const T *v = static_cast<const T *>(a.vel);
+    const int64_t n = a.n_atoms;
+    const int ns = a.n_species;
+    double acc[kMomSums];
+#pragma unroll
+    for (int q = 0; q < kMomSums; ++q) acc[q] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int sp = a.species[i];
+        const double vx = (double)v[i], vy = (double)v[n + i], vz = (double)v[2 * n + i];
+#pragma unroll
+        for (int s = 0; s < kMomMaxSpecies; ++s) {
+            if (s < ns) {
+                const bool hit = sp == s;
+                acc[3 * s + 0] += hit ? vx : 0.0;
+                acc[3 * s + 1] += hit ? vy : 0.0;
+                acc[3 * s + 2] += hit ? vz : 0.0;
+            }
+        }
+    }
+    // wave sums (lane 0 ends with the wave's sum), then waves in order
+    __shared__ double wsum[kMomThreads / 64][kMomSums];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kMomSums; ++q) {
+        if (q < 3 * ns) {
+            double x = acc[q];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
+            if (lane == 0) wsum[wave][q] = x;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 3 * ns) {
+        double x = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) x += wsum[w][threadIdx.x];
+        a.partial[(size_t)blockIdx.x * kMomSums + threadIdx.x] = x;
+    }
+}
+
+template <typename T> __global__ __launch_bounds__(64) void momentum_final_kernel(MomentumArgs a)
+{
+    const int q = threadIdx.x;
+    const int nch = 3 * a.n_species;
+    T *out = static_cast<T *>(a.out);
+    if (q < nch) {
+        double x = 0.0;
+        for (int b = 0; b < a.n_blocks; ++b) x += a.partial[(size_t)b * kMomSums + q];
+        const T j = (T)(x * a.scale[q / 3]);
+        if (a.pair) {
+            const T *xin = static_cast<const T *>(a.vel) + 3 * a.n_atoms;
+            out[q] = xin[q];
+            out[nch + q] = j;
+        } else {
+            out[q] = j;
+        }
+    }
+}
+
+} // namespace
+
+int momentum_blocks(int64_t n_atoms)
+{
+    const int64_t per_block = (int64_t)kMomThreads * kMomAtomsPerThread;
+    int64_t b = (n_atoms + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > kMomMaxBlocks) b = kMomMaxBlocks;
+    return (int)b;
+}
+
+hipError_t launch_momentum(const MomentumArgs &a, hipStream_t st)
+{
+    if (a.n_species < 1 || a.n_species > kMomMaxSpecies || a.n_atoms < 1 || a.n_blocks < 1 ||
+        a.n_blocks > kMomMaxBlocks)
+        return hipErrorInvalidValue;
+    if (a.dbl) {
+        hipLaunchKernelGGL(momentum_partial_kernel<double>, dim3((unsigned)a.n_blocks),
+                           dim3(kMomThreads), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(momentum_partial_kernel<float>, dim3((unsigned)a.n_blocks),
+                           dim3(kMomThreads), 0, st, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (a.dbl)
+        hipLaunchKernelGGL(momentum_final_kernel<double>, dim3(1), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL(momentum_final_kernel<float>, dim3(1), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+} // namespace corr

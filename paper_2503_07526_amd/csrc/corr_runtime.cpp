@@ -61,6 +61,12 @@ struct Group {
     int32_t *d_mtab = nullptr;    // pair_nx | pair_ny | slot_k | k_src
     double *d_basis = nullptr;    // currents: [nk][3][3] khat, e1, e2
     RhokMfmaArgs margs{};
+    // partial momentum density producer (output in rhok_out, block sums in
+    // d_partial)
+    bool mom = false;
+    int32_t *d_species = nullptr; // [n_atoms]
+    MomentumArgs mom_args{};
+    bool produced() const { return rhok || mom; } // samples come from a producer
 };
 
 } // namespace
@@ -174,12 +180,29 @@ int validate(const corr_group_desc &g, int idx)
     if (g.update_every < 1) return bad("update_every must be >= 1");
     if (g.dtype < CORR_F32 || g.dtype > CORR_CF64) return bad("unknown dtype");
     if (g.accum < CORR_ACC_F64 || g.accum > CORR_ACC_F32) return bad("unknown accumulator");
-    if (g.source != CORR_SRC_SAMPLES && g.source != CORR_SRC_RHOK && g.source != CORR_SRC_CURRENTS)
+    if (g.source != CORR_SRC_SAMPLES && g.source != CORR_SRC_RHOK &&
+        g.source != CORR_SRC_CURRENTS && g.source != CORR_SRC_MOMENTUM)
         return bad("unknown source");
     if ((g.dtype == CORR_F64 || g.dtype == CORR_CF64) && g.accum != CORR_ACC_F64)
         return bad("double samples need double accumulators");
     if (g.pair != 0 && g.pair != 1) return bad("pair must be 0 or 1");
-    if (g.pair && g.source != CORR_SRC_SAMPLES) return bad("pair groups take samples");
+    if (g.pair && g.source != CORR_SRC_SAMPLES && g.source != CORR_SRC_MOMENTUM)
+        return bad("pair groups take samples or momentum densities");
+    if (g.source == CORR_SRC_MOMENTUM) {
+        if (g.dtype != CORR_F32 && g.dtype != CORR_F64) return bad("momentum needs a real dtype");
+        if (g.n_species < 1 || g.n_species > kMomMaxSpecies)
+            return bad("momentum: n_species must be 1..8");
+        if (g.n_channels != 3 * (int64_t)g.n_species)
+            return bad("momentum: n_channels must be 3 x n_species");
+        if (!g.species || !g.masses) return bad("momentum group without species or masses");
+        if (g.n_atoms < 1) return bad("momentum group needs n_atoms >= 1");
+        if (!(g.box > 0.0)) return bad("momentum group needs box > 0");
+        for (int s = 0; s < g.n_species; ++s)
+            if (!std::isfinite(g.masses[s])) return bad("momentum: masses must be finite");
+        for (int64_t i = 0; i < g.n_atoms; ++i)
+            if (g.species[i] < 0 || g.species[i] >= g.n_species)
+                return bad("momentum: species id out of range");
+    }
     if (g.source == CORR_SRC_RHOK) {
         if (g.dtype != CORR_CF32 && g.dtype != CORR_CF64) return bad("k-density needs a complex dtype");
         if (!g.kvec) return bad("k-density group without k-vectors");
@@ -241,6 +264,7 @@ void free_group(Group &g)
     if (g.d_partial) (void)hipFree(g.d_partial);
     if (g.d_mtab) (void)hipFree(g.d_mtab);
     if (g.d_basis) (void)hipFree(g.d_basis);
+    if (g.d_species) (void)hipFree(g.d_species);
     if (g.d_flushed) (void)hipFree(g.d_flushed);
     g = Group{};
 }
@@ -454,7 +478,8 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
 {
     const size_t ng = c->groups.size();
     std::vector<const void *> resolved(ng);
-    for (size_t i = 0; i < ng; ++i) resolved[i] = c->groups[i].rhok ? c->groups[i].rhok_out : src[i];
+    for (size_t i = 0; i < ng; ++i)
+        resolved[i] = c->groups[i].produced() ? c->groups[i].rhok_out : src[i];
     // Events are only recorded on direct launches, never while capturing, on
     // one push in timing_stride.
     const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream &&
@@ -488,7 +513,11 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
             if (rc != CORR_OK) return rc;
             HIP_TRY(c, hipEventRecord(r0, pst));
         }
-        if (g.rhok_mfma) {
+        if (g.mom) {
+            MomentumArgs ma = g.mom_args;
+            ma.vel = src[i];
+            HIP_TRY(c, launch_momentum(ma, pst));
+        } else if (g.rhok_mfma) {
             RhokMfmaArgs ma = g.margs;
             ma.pos = static_cast<const float *>(src[i]);
             HIP_TRY(c, launch_rhok_mfma(ma, pst));
@@ -675,6 +704,8 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         Group &g = c->groups[(size_t)i];
         g.d = groups[i];
         g.d.kvec = nullptr;
+        g.d.species = nullptr;
+        g.d.masses = nullptr;
         g.kind = kind_of(g.d.dtype, g.d.accum);
         g.p = g.d.points;
         g.m = g.d.m;
@@ -892,6 +923,30 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 r.out = g.rhok_out;
                 r.out_double = g.d.dtype == CORR_CF64 ? 1 : 0;
             }
+        } else if (g.d.source == CORR_SRC_MOMENTUM) {
+            g.mom = true;
+            // velocities [3][N] in the group's dtype; pair: then the x samples
+            g.input_bytes = (size_t)(3 * g.d.n_atoms + (g.pair ? g.n_ch : 0)) * g.s_bytes;
+            CREATE_HIP(hipMalloc(&g.rhok_out, (size_t)(g.pair ? 2 : 1) * g.n_ch * g.s_bytes));
+            CREATE_HIP(hipMemsetAsync(g.rhok_out, 0, (size_t)(g.pair ? 2 : 1) * g.n_ch * g.s_bytes,
+                                      c->stream));
+            CREATE_HIP(hipMalloc(&g.d_species, (size_t)g.d.n_atoms * sizeof(int32_t)));
+            CREATE_HIP(hipMemcpy(g.d_species, groups[i].species,
+                                 (size_t)g.d.n_atoms * sizeof(int32_t), hipMemcpyHostToDevice));
+            MomentumArgs &ma = g.mom_args;
+            ma.vel = nullptr;
+            ma.species = g.d_species;
+            ma.n_atoms = g.d.n_atoms;
+            ma.n_species = g.d.n_species;
+            ma.dbl = g.d.dtype == CORR_F64 ? 1 : 0;
+            const double volume = g.d.box * g.d.box * g.d.box;
+            for (int s = 0; s < g.d.n_species; ++s) ma.scale[s] = groups[i].masses[s] / volume;
+            ma.n_blocks = momentum_blocks(g.d.n_atoms);
+            CREATE_HIP(hipMalloc(&g.d_partial,
+                                 (size_t)ma.n_blocks * 3 * kMomMaxSpecies * sizeof(double)));
+            ma.partial = g.d_partial;
+            ma.pair = g.pair ? 1 : 0;
+            ma.out = g.rhok_out;
         } else {
             g.input_bytes = (size_t)(g.pair ? 2 : 1) * (size_t)g.n_ch * g.s_bytes;
         }
@@ -927,7 +982,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     c->total_tiles = tile_first;
     for (int i = 0; i < n_groups; ++i) {
         const Group &g = c->groups[(size_t)i];
-        if (g.rhok)
+        if (g.produced())
             c->side_set.push_back(i);
         else if (!g.deferred)
             c->main_set.push_back(i);

@@ -119,3 +119,31 @@ def test_pair_descriptor_checks(corrmod):
     rc, msg = _create(corrmod, corrmod.GroupDesc(1, 4, 16, dtype="cf32", source="rhok", kvec=kv,
                                                  n_atoms=10, box=10.0, pair=True))
     assert rc == -1 and "pair" in msg
+
+
+def _mom(n_channels=6, n_atoms=10, box=10.0, dtype="f32", species=None, masses=(1.0, 2.0),
+         **kw):
+    sp = (np.zeros(n_atoms, np.int32) if species is None else
+          None if isinstance(species, str) else np.asarray(species, np.int32))
+    return dict(n_channels=n_channels, levels=4, points=16, dtype=dtype, source="momentum",
+                n_atoms=n_atoms, box=box, species=sp,
+                masses=None if masses is None else np.asarray(masses, np.float64), **kw)
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (_mom(dtype="cf32"), "real dtype"),
+    (_mom(n_channels=5), "3 x n_species"),
+    (_mom(n_channels=27, masses=[1.0] * 9), "n_species"),
+    (_mom(species="none"), "species or masses"),
+    (_mom(masses=None), "n_species"),
+    (_mom(n_atoms=0, species=np.zeros(1, np.int32)), "n_atoms"),
+    (_mom(box=0.0), "box"),
+    (_mom(species=[0] * 9 + [2]), "out of range"),
+    (_mom(species=[0] * 9 + [-1]), "out of range"),
+    (_mom(masses=[1.0, float("nan")]), "finite"),
+])
+def test_momentum_descriptor_checks(corrmod, kw, needle):
+    """Partial momentum density groups: a real dtype, 3 channels per species,
+    1..8 species with ids in range, finite masses, atoms and a box."""
+    rc, msg = _create(corrmod, corrmod.GroupDesc(**kw))
+    assert rc == -1 and needle in msg, (rc, msg)
