@@ -49,7 +49,7 @@ RHOK_FLOP_PER_ATOM_K = 14  # factorised phases: 2 complex multiplies + 1 complex
 # currents: the phase as for n(k) plus, per velocity component, a real x complex
 # multiply-add (4 flop)
 CURRENTS_FLOP_PER_ATOM_K = RHOK_FLOP_PER_ATOM_K + 3 * 4
-PRODUCER_KINDS = ("rhok", "currents")
+PRODUCER_KINDS = ("rhok", "currents", "momentum")
 
 
 def parse():
@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--config", default="batched",
-                    choices=["plain", "batched", "large", "rhok", "currents", "kgap", "precision"])
+                    choices=["plain", "batched", "large", "rhok", "currents", "kgap", "massflux",
+                             "precision"])
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the launch-shape autotuner (library defaults)")
     ap.add_argument("--precision-steps", type=int, default=1_000_000)
@@ -149,7 +150,48 @@ def workload(name):
                     dict(kind="rhok", n=2048, levels=1, points=10240, m=2, dtype="cf32",
                          accum="kahan", n_atoms=1_000_000, box=100.0, seed=6, stream=3, kvec=kv,
                          update_every=10, shares_positions=True)])
+    if name == "massflux":
+        return dict(
+            name=("massflux: partial momentum densities of 2 species (masses 6.941 and 18.998, "
+                  "half the atoms each) from 2e7 atoms with OU velocities in a box of 600, "
+                  "correlated with a 3-component heat-flux series (<q(s) j(s-L)>, 6 FP32 pair "
+                  "channels) + the heat-flux autocorrelation (3 FP32 channels), compensated, "
+                  "b=12 p=16 m=2"),
+            steps=4096, dominant="momentum",
+            groups=[dict(kind="ou", n=3, levels=12, points=16, m=2, dtype="f32", accum="kahan",
+                         comps=3, tau=(50, 50), sigma=1.0, seed=7, stream=2),
+                    dict(kind="momentum", n=6, levels=12, points=16, m=2, dtype="f32",
+                         accum="kahan", n_atoms=20_000_000, box=600.0, masses=(6.941, 18.998),
+                         seed=7, stream=5, vtau=(20, 200), pair_with=0)])
     raise ValueError(name)
+
+
+def momentum_species(g):
+    """Seeded species ids of a momentum workload (uniform over the species)."""
+    rng = np.random.default_rng([g["seed"], g["stream"]])
+    return rng.integers(0, len(g["masses"]), g["n_atoms"]).astype(np.int32)
+
+
+class MomentumInput:
+    """Velocities [3][N] (OU series, generated on the GPU) then, for a pair
+    group, the x samples: the heat-flux components of another group's input,
+    repeated for every species."""
+
+    def __init__(self, g, xbuf):
+        import synth
+        self.n = g["n_atoms"]
+        self.ns = len(g["masses"])
+        self.xbuf = xbuf
+        self.vel = synth.GpuOU(synth.OUSpec.make(g["seed"], g["stream"], 3 * self.n, comps=3,
+                                                 tau=g["vtau"][0], tau_hi=g["vtau"][1],
+                                                 sigma=1.0))
+
+    def fill(self, buf, n_steps):
+        self.vel.fill(buf[:, :3 * self.n], n_steps)
+        if self.xbuf is not None:
+            q = self.xbuf[:n_steps]
+            for s in range(self.ns):
+                buf[:n_steps, 3 * self.n + 3 * s:3 * self.n + 3 * s + 3].copy_(q)
 
 
 class CurrentsInput:
@@ -301,7 +343,10 @@ def window_push_cost(g):
 
 
 def producer_flop(g):
-    """Algorithmic flop of one producer launch (matrix-core forms)."""
+    """Algorithmic flop of one producer launch (matrix-core forms; the
+    momentum densities are an HBM-bound reduction and count no flop here)."""
+    if g["kind"] == "momentum":
+        return 0
     if g["kind"] == "currents":
         return CURRENTS_FLOP_PER_ATOM_K * (g["n"] // 3) * g["n_atoms"]
     return RHOK_FLOP_PER_ATOM_K * g["n"] * g["n_atoms"]
@@ -342,6 +387,8 @@ def cpu_baseline(wl):
     """The FP64 oracle on a bounded sample of the workload's largest group."""
     import oracle
     import synth
+    if wl.get("dominant") == "momentum":
+        return cpu_baseline_momentum(wl)
     if all(g["kind"] in PRODUCER_KINDS for g in wl["groups"]):
         return cpu_baseline_rhok(wl["groups"][0])
     g = max(wl["groups"], key=lambda x: x["n"])
@@ -388,6 +435,27 @@ def cpu_baseline_rhok(g):
                        f"single thread")}
 
 
+def cpu_baseline_momentum(wl):
+    """The oracle's partial momentum densities (plain double sums) over all
+    atoms of the workload for a few pushes; the correlator updates of the few
+    channels are negligible beside it."""
+    import oracle
+    g = next(x for x in wl["groups"] if x["kind"] == "momentum")
+    n_sample, reps = g["n_atoms"], 3
+    rng = np.random.default_rng(0)
+    vel = rng.standard_normal((3, n_sample)).astype(np.float32)
+    sp = momentum_species(dict(g, n_atoms=n_sample))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.partial_momentum(vel, sp, g["masses"], g["box"] ** 3)
+    dt = (time.perf_counter() - t0) / reps
+    per_push = dt * g["n_atoms"] / n_sample
+    n_total = sum(x["n"] for x in wl["groups"])
+    return {"value": n_total / per_push, "unit": "channel-samples/s", "cores": 1, "kind": "oracle",
+            "sample": (f"partial momentum densities of {len(g['masses'])} species over all "
+                       f"{n_sample} atoms, {reps} pushes, {dt:.2f} s each; single thread")}
+
+
 # -------------------------------------------------------------------- GPU leg
 def run(args):
     import torch
@@ -414,6 +482,15 @@ def run(args):
                                    update_every=g.get("update_every", 1)))
             gens.append(None)
             bufs.append(bufs[-1])
+        elif g["kind"] == "momentum":
+            pair = g.get("pair_with") is not None
+            descs.append(GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype=g["dtype"],
+                                   accum=g["accum"], source="momentum", n_atoms=g["n_atoms"],
+                                   box=g["box"], species=momentum_species(g),
+                                   masses=np.array(g["masses"]), pair=pair))
+            gens.append(MomentumInput(g, bufs[g["pair_with"]] if pair else None))
+            bufs.append(torch.empty((chunk, 3 * g["n_atoms"] + (g["n"] if pair else 0)),
+                                    dtype=torch.float32, device=dev))
         elif g["kind"] == "currents":
             descs.append(GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype=g["dtype"],
                                    accum=g["accum"], source="currents", kvec=g["kvec"],
@@ -513,7 +590,18 @@ def run(args):
                  and wl.get("dominant") not in ("push", "producer"))
     producer_dominant = wl.get("dominant") == "producer"
     push_dominant = wl.get("dominant") == "push"
-    if producer_dominant:
+    momentum_dominant = wl.get("dominant") == "momentum"
+    if momentum_dominant:
+        # the momentum density producers: per atom three velocity components
+        # and a one-byte species id, HIP events around the producer launches of
+        # a push
+        per_launch_bytes = sum(g["n_atoms"] * (3 * SB[g["dtype"]] + 1) for g in wl["groups"]
+                               if g["kind"] == "momentum")
+        per_launch_ms = rk_ms / kern_n
+        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+        kname = ("momentum density producer (HBM-bound reduction over the atoms), HIP events "
+                 "around its launches on its stream")
+    elif producer_dominant:
         # the producers of every k-space group, per push (HIP events on their
         # stream; several producer launches per push)
         flop_per = sum(producer_flop(g) for g in wl["groups"] if g["kind"] in PRODUCER_KINDS)
@@ -593,7 +681,7 @@ def run(args):
                                           "separate the push's kernels" % args.timing_stride)
     if rk_n:
         out["roofline"]["producer_ms_per_launch"] = rk_ms / rk_n
-        if not (rhok_only or producer_dominant):
+        if not (rhok_only or producer_dominant or momentum_dominant):
             # the producers beside the dominant kernel (forked, they may be the
             # longer branch of the step)
             pf = sum(producer_flop(g) for g in wl["groups"] if g["kind"] in PRODUCER_KINDS)

@@ -153,7 +153,7 @@ constexpr int kMomMaxSpecies = 8;
 struct MomentumArgs {
     const void *vel;         // [3][n_atoms] velocities (float or double); pair: then
                              // [n_ch] x samples of the same type
-    const int32_t *species;  // [n_atoms] species ids in [0, n_species)
+    const uint8_t *species;  // [n_atoms] species ids in [0, n_species)
     int64_t n_atoms;
     int32_t n_species;       // 1 .. kMomMaxSpecies
     int32_t dbl;             // 1: double velocities and output
@@ -161,6 +161,8 @@ struct MomentumArgs {
     double *partial;         // [n_blocks][3 kMomMaxSpecies] block sums
     int32_t n_blocks;
     int32_t pair;            // 1: output [2][n_ch], x copied from the input
+    int32_t vec4;            // 1: n_atoms % 4 == 0 and vel 16-byte aligned (4 atoms per load)
+    int32_t pad_;
     void *out;               // [n_ch] densities, or [2][n_ch] (x, then densities)
 };
 

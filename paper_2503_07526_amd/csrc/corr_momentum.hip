@@ -3,11 +3,11 @@
 // j_s = (1/V) sum over the atoms i of species s of m_s v(i), for every species.
 //
 // HBM-bound reduction: per atom three velocity components (12 or 24 bytes)
-// and a 4-byte species id.  Each thread sums its atoms (grid-stride, fixed order) per
+// and a one-byte species id (the ids are stored as bytes at create).  Each thread sums its atoms (grid-stride, fixed order) per
 // species and component in double, the block reduces its 3 x n_species sums
 // by wave shuffles and then across waves in a fixed order, and a final kernel
-// adds the block sums in block order and scales them by m_s / V, so the result
-// does not depend on timing.
+// (one wave per channel) adds the block sums in a fixed order and scales them
+// by m_s / V, so the result does not depend on timing.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
@@ -21,6 +21,41 @@ constexpr int kMomAtomsPerThread = 8; // atoms per thread before the grid is cap
 constexpr int kMomMaxBlocks = 1024;
 constexpr int kMomSums = 3 * kMomMaxSpecies;
 
+// Four consecutive values of a component (16-byte loads; the caller checks
+// the alignment).
+__device__ __forceinline__ void load4(const float *p, int64_t q, double (&o)[4])
+{
+    const float4 f = reinterpret_cast<const float4 *>(p)[q];
+    o[0] = f.x;
+    o[1] = f.y;
+    o[2] = f.z;
+    o[3] = f.w;
+}
+
+__device__ __forceinline__ void load4(const double *p, int64_t q, double (&o)[4])
+{
+    const double2 f = reinterpret_cast<const double2 *>(p)[2 * q];
+    const double2 g = reinterpret_cast<const double2 *>(p)[2 * q + 1];
+    o[0] = f.x;
+    o[1] = f.y;
+    o[2] = g.x;
+    o[3] = g.y;
+}
+
+__device__ __forceinline__ void add_atom(double (&acc)[kMomSums], int ns, int sp, double vx,
+                                         double vy, double vz)
+{
+#pragma unroll
+    for (int s = 0; s < kMomMaxSpecies; ++s) {
+        if (s < ns) {
+            const bool hit = sp == s;
+            acc[3 * s + 0] += hit ? vx : 0.0;
+            acc[3 * s + 1] += hit ? vy : 0.0;
+            acc[3 * s + 2] += hit ? vz : 0.0;
+        }
+    }
+}
+
 template <typename T> __global__ __launch_bounds__(kMomThreads) void momentum_partial_kernel(MomentumArgs a)
 {
     const T *v = static_cast<const T *>(a.vel);
@@ -30,18 +65,23 @@ template <typename T> __global__ __launch_bounds__(kMomThreads) void momentum_pa
 #pragma unroll
     for (int q = 0; q < kMomSums; ++q) acc[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int sp = a.species[i];
-        const double vx = (double)v[i], vy = (double)v[n + i], vz = (double)v[2 * n + i];
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a.vec4) {
+        // four consecutive atoms per step: n is a multiple of 4 and every
+        // component starts 16-byte aligned
+        const uint32_t *sp4 = reinterpret_cast<const uint32_t *>(a.species);
+        for (int64_t q = first; q < n / 4; q += stride) {
+            const uint32_t ids = sp4[q];
+            double x[4], y[4], z[4];
+            load4(v, q, x);
+            load4(v + n, q, y);
+            load4(v + 2 * n, q, z);
 #pragma unroll
-        for (int s = 0; s < kMomMaxSpecies; ++s) {
-            if (s < ns) {
-                const bool hit = sp == s;
-                acc[3 * s + 0] += hit ? vx : 0.0;
-                acc[3 * s + 1] += hit ? vy : 0.0;
-                acc[3 * s + 2] += hit ? vz : 0.0;
-            }
+            for (int e = 0; e < 4; ++e) add_atom(acc, ns, (int)((ids >> (8 * e)) & 0xffu), x[e], y[e], z[e]);
         }
+    } else {
+        for (int64_t i = first; i < n; i += stride)
+            add_atom(acc, ns, a.species[i], (double)v[i], (double)v[n + i], (double)v[2 * n + i]);
     }
     // wave sums (lane 0 ends with the wave's sum), then waves in order
     __shared__ double wsum[kMomThreads / 64][kMomSums];
@@ -63,22 +103,27 @@ template <typename T> __global__ __launch_bounds__(kMomThreads) void momentum_pa
     }
 }
 
+// One wave per channel (block q): lane l adds the block sums l, l + 64, ...
+// in order, then the wave adds its lanes by shuffles in a fixed order.
 template <typename T> __global__ __launch_bounds__(64) void momentum_final_kernel(MomentumArgs a)
 {
-    const int q = threadIdx.x;
+    const int q = blockIdx.x;
     const int nch = 3 * a.n_species;
+    const int lane = threadIdx.x;
+    double x = 0.0;
+#pragma unroll 4
+    for (int b = lane; b < a.n_blocks; b += 64) x += a.partial[(size_t)b * kMomSums + q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane != 0) return;
     T *out = static_cast<T *>(a.out);
-    if (q < nch) {
-        double x = 0.0;
-        for (int b = 0; b < a.n_blocks; ++b) x += a.partial[(size_t)b * kMomSums + q];
-        const T j = (T)(x * a.scale[q / 3]);
-        if (a.pair) {
-            const T *xin = static_cast<const T *>(a.vel) + 3 * a.n_atoms;
-            out[q] = xin[q];
-            out[nch + q] = j;
-        } else {
-            out[q] = j;
-        }
+    const T j = (T)(x * a.scale[q / 3]);
+    if (a.pair) {
+        const T *xin = static_cast<const T *>(a.vel) + 3 * a.n_atoms;
+        out[q] = xin[q];
+        out[nch + q] = j;
+    } else {
+        out[q] = j;
     }
 }
 
@@ -107,10 +152,11 @@ hipError_t launch_momentum(const MomentumArgs &a, hipStream_t st)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)(3 * a.n_species));
     if (a.dbl)
-        hipLaunchKernelGGL(momentum_final_kernel<double>, dim3(1), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(momentum_final_kernel<double>, grid, dim3(64), 0, st, a);
     else
-        hipLaunchKernelGGL(momentum_final_kernel<float>, dim3(1), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(momentum_final_kernel<float>, grid, dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -64,7 +64,7 @@ struct Group {
     // partial momentum density producer (output in rhok_out, block sums in
     // d_partial)
     bool mom = false;
-    int32_t *d_species = nullptr; // [n_atoms]
+    uint8_t *d_species = nullptr; // [n_atoms] (ids < 8 fit a byte)
     MomentumArgs mom_args{};
     bool produced() const { return rhok || mom; } // samples come from a producer
 };
@@ -516,6 +516,7 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
         if (g.mom) {
             MomentumArgs ma = g.mom_args;
             ma.vel = src[i];
+            ma.vec4 = g.d.n_atoms % 4 == 0 && reinterpret_cast<uintptr_t>(src[i]) % 16 == 0;
             HIP_TRY(c, launch_momentum(ma, pst));
         } else if (g.rhok_mfma) {
             RhokMfmaArgs ma = g.margs;
@@ -930,9 +931,12 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
             CREATE_HIP(hipMalloc(&g.rhok_out, (size_t)(g.pair ? 2 : 1) * g.n_ch * g.s_bytes));
             CREATE_HIP(hipMemsetAsync(g.rhok_out, 0, (size_t)(g.pair ? 2 : 1) * g.n_ch * g.s_bytes,
                                       c->stream));
-            CREATE_HIP(hipMalloc(&g.d_species, (size_t)g.d.n_atoms * sizeof(int32_t)));
-            CREATE_HIP(hipMemcpy(g.d_species, groups[i].species,
-                                 (size_t)g.d.n_atoms * sizeof(int32_t), hipMemcpyHostToDevice));
+            {
+                std::vector<uint8_t> ids((size_t)g.d.n_atoms);
+                for (int64_t a = 0; a < g.d.n_atoms; ++a) ids[(size_t)a] = (uint8_t)groups[i].species[a];
+                CREATE_HIP(hipMalloc(&g.d_species, ids.size()));
+                CREATE_HIP(hipMemcpy(g.d_species, ids.data(), ids.size(), hipMemcpyHostToDevice));
+            }
             MomentumArgs &ma = g.mom_args;
             ma.vel = nullptr;
             ma.species = g.d_species;

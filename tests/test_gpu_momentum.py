@@ -38,11 +38,12 @@ def _push_all(corr, xs):
 
 
 @pytest.mark.parametrize("dtype,accum", [("f32", "kahan"), ("f32", "f64"), ("f64", "f64")])
-@pytest.mark.parametrize("n_species,N", [(1, 1), (3, 5003), (8, 70001)])
+@pytest.mark.parametrize("n_species,N", [(1, 1), (3, 5003), (8, 70001), (2, 4), (5, 400_000)])
 def test_momentum_lag0_against_oracle(corrmod, dtype, accum, n_species, N):
     """One push: C(0) of channel 3s + a is j_{s,a}^2 (no 1/N), j from the
-    oracle's plain double sums; atom counts of one atom, a ragged count, and
-    several blocks of the reduction."""
+    oracle's plain double sums; atom counts of one atom, ragged counts (one
+    atom per load), multiples of 4 (four atoms per load) and several blocks
+    of the reduction."""
     box = 17.0
     say(f"[momentum lag 0] {dtype}/{accum} species={n_species} N={N}")
     sp, masses, vel = _system(31, N, n_species, 1, dtype)
