@@ -159,9 +159,13 @@ typedef struct corr_tuning {
     int32_t grid_blocks;      /* 0 = one block per tile                              */
     int32_t overlap_producers; /* 0: everything on the context's stream:
                                   staging, producers, per-step updates, flush;
-                                  1: producers (and their groups' updates) on a
-                                  forked stream, concurrently with the other
-                                  updates; 2: producers first, then the
+                                  1: producers on a forked stream, followed
+                                  there by the per-step updates of every
+                                  direct group when block-deferred groups are
+                                  present (concurrently with their staging and
+                                  flush), else by their own groups' updates
+                                  (concurrently with the other updates);
+                                  2: producers first, then the
                                   per-step updates on a forked stream,
                                   concurrently with the flush of the
                                   block-deferred groups                        */
