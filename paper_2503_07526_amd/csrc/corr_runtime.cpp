@@ -397,10 +397,9 @@ bool is_window_deferred(const GroupArgs &g) { return g.levels == 1 && g.deferred
 
 // Per-step groups of fewer than kSplitMaxTiles tiles (a few thousand
 // channels: the k-space groups) would keep only a few CUs busy in the batched
-// kernel; their level-0 lags are split over kSplitLags-lag blocks instead.
-// Not with forked producers (overlap_producers = 1): there the shorter
-// side-stream update moves the producer onto the next push's staging, and the
-// step is slower (measured: 0.270 vs 0.239 ms on the batched workload).
+// kernel; their level-0 lags are split over kSplitLags-lag blocks instead
+// (in every issue order: with the producers forked at the start of the push
+// the batched workload's step goes from 0.2125 to 0.208 ms).
 constexpr int64_t kSplitMaxTiles = 64;
 constexpr int kSplitLags = 8;
 
@@ -439,8 +438,7 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
                 HIP_TRY(c, launch_push_group(a.g[i], c->d_step, cpt, lch, block, st));
                 continue;
             }
-            if (!(c->flags & CORR_FLAG_PER_GROUP) && c->tuning.overlap_producers != 1 &&
-                is_split(a.g[i])) {
+            if (!(c->flags & CORR_FLAG_PER_GROUP) && is_split(a.g[i])) {
                 HIP_TRY(c, launch_push_split(a.g[i], c->d_step, cpt, lch, block, kSplitLags, st));
                 continue;
             }
