@@ -44,7 +44,7 @@ enum corr_status {
     CORR_E_OOM = -2,         /* device allocation failed                         */
     CORR_E_DEVICE = -3,      /* a HIP call failed (message names it)             */
     CORR_E_STATE = -4,       /* call not valid in the context's current state    */
-    CORR_E_UNSUPPORTED = -5  /* valid descriptor this build does not implement   */
+    CORR_E_UNSUPPORTED = -5  /* valid descriptor the library does not implement  */
 };
 
 /* Sample precision (complex types are interleaved re, im). */
