@@ -122,3 +122,46 @@ def test_momentum_pair_with_heat_flux_all_launch_modes(corrmod):
         o.push_pair(x[s].astype(np.float64), oracle.partial_momentum(vel[s], sp, masses, box ** 3))
     e = gate(out["serial"], o, TOL[("f32", "kahan")], slice_=(0, 3 * ns), label="momentum pair")
     say(f"  error {e:.2e}")
+
+
+def test_momentum_full_size_against_oracle(corrmod):
+    """The mass-flux workload's size (2 species, 2e7 atoms, the bench's
+    launch configuration with the pair form beside a sample-fed group): the
+    densities of three pushes against the oracle's, through C(0) and C(1) of
+    the autocorrelation and the pair group's C(0) = <q j>."""
+    N, box, S = 20_000_000, 600.0, 3
+    rng = np.random.default_rng(71)
+    sp = rng.integers(0, 2, N).astype(np.int32)
+    masses = np.array([6.941, 18.998])
+    vel = rng.standard_normal((S, 3, N)).astype(np.float32)
+    q = rng.standard_normal((S, 3)).astype(np.float32)
+    x = np.ascontiguousarray(np.tile(q, (1, 2)))
+    say(f"[momentum full size] N={N}")
+    inp = np.ascontiguousarray(np.concatenate([vel.reshape(S, -1), x], axis=1))
+    groups = [corrmod.GroupDesc(6, 4, 16, 2, dtype="f32", accum="kahan", source="momentum",
+                                n_atoms=N, box=box, species=sp, masses=masses),
+              corrmod.GroupDesc(6, 4, 16, 2, dtype="f32", accum="kahan", source="momentum",
+                                n_atoms=N, box=box, species=sp, masses=masses, pair=True),
+              corrmod.GroupDesc(3000, 4, 16, 2, dtype="f32", accum="kahan")]
+    xv = ou_inputs(71, 1, 3000, S, "f32")
+    dev = torch.device("cuda:0")
+    ti = torch.from_numpy(inp).to(dev)
+    tv = ti[:, :3 * N]
+    tx = torch.from_numpy(xv).to(dev)
+    with corrmod.Correlator(groups, tuning=dict(tile_channels=256, chans_per_thread=1,
+                                                lag_chunk=16, grid_blocks=0,
+                                                overlap_producers=1)) as c:
+        for s in range(S):
+            c.push([tv[s], ti[s], tx[s]])
+        torch.cuda.synchronize()
+        auto = c.finalize(0, slice_=(0, 6))
+        pair = c.finalize(1, slice_=(0, 6))
+    j = np.stack([oracle.partial_momentum(vel[s], sp, masses, box ** 3) for s in range(S)])
+    c0 = np.mean(j * j, axis=0)
+    c1 = np.mean(j[1:] * j[:-1], axis=0)
+    cq = np.mean(x * j, axis=0)
+    e0 = np.max(np.abs(auto["c_per_channel"][:, 0] - c0)) / np.max(np.abs(c0))
+    e1 = np.max(np.abs(auto["c_per_channel"][:, 1] - c1)) / np.max(np.abs(c0))
+    eq = np.max(np.abs(pair["c_per_channel"][:, 0] - cq)) / np.max(np.abs(cq))
+    say(f"  C(0) {e0:.2e}  C(1) {e1:.2e}  <q j> {eq:.2e}")
+    assert e0 < 1e-6 and e1 < 1e-6 and eq < 1e-6
