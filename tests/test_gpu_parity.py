@@ -638,6 +638,59 @@ def test_window_deferred_fed_by_producer_all_launch_modes(corrmod):
          label="window fed by rho(k)")
 
 
+def test_two_producer_groups_all_launch_modes(corrmod):
+    """Producer groups only (currents and n(k) of the same atoms, long windows
+    and a multi-level group): one stream, the forked order (which keeps
+    producer-only contexts on one stream), per-group launches and a graph give
+    bit-identical results, which match the oracle."""
+    S, N, box = 600, 1200, 30.0
+    kv = synth.kvectors(40)
+    x = _currents_inputs(45, N, box, S)  # [S][6][N]: positions, velocities
+    pos = np.ascontiguousarray(x[:, :3])
+    groups = [corrmod.GroupDesc(3 * len(kv), 1, 512, 2, dtype="cf32", accum="kahan",
+                                source="currents", kvec=kv, n_atoms=N, box=box),
+              corrmod.GroupDesc(len(kv), 1, 512, 2, dtype="cf32", accum="kahan", source="rhok",
+                                kvec=kv, n_atoms=N, box=box),
+              corrmod.GroupDesc(len(kv), 5, 16, 2, dtype="cf32", accum="f64", source="rhok",
+                                kvec=kv, n_atoms=N, box=box)]
+    base = dict(tile_channels=256, chans_per_thread=1, lag_chunk=8, grid_blocks=0)
+    dev = torch.device("cuda:0")
+    out = {}
+    for mode in ("serial", "forked", "per_group", "forked_graph"):
+        say(f"[two producers] mode={mode}")
+        ov = 1 if mode.startswith("forked") else 0
+        with corrmod.Correlator(groups, graph=(mode == "forked_graph"),
+                                per_group=(mode == "per_group"),
+                                tuning=dict(base, overlap_producers=ov)) as c:
+            ta, tb = torch.from_numpy(x).to(dev), torch.from_numpy(pos).to(dev)
+            if mode == "forked_graph":
+                ba, bb, bc = torch.empty_like(ta[0]), torch.empty_like(tb[0]), torch.empty_like(tb[0])
+                c.bind_input(0, ba); c.bind_input(1, bb); c.bind_input(2, bc)
+                for s in range(S):
+                    ba.copy_(ta[s]); bb.copy_(tb[s]); bc.copy_(tb[s])
+                    c.push()
+            else:
+                for s in range(S):
+                    c.push([ta[s], tb[s], tb[s]])
+            torch.cuda.synchronize()
+            out[mode] = [c.finalize(g, slice_=(0, 4)) for g in range(3)]
+    for mode in ("forked", "per_group", "forked_graph"):
+        for g in range(3):
+            assert np.array_equal(out[mode][g]["c_per_channel"], out["serial"][g]["c_per_channel"]), (mode, g)
+            assert np.array_equal(out[mode][g]["c"], out["serial"][g]["c"]), (mode, g)
+    oc = oracle.OracleCorrelator(3 * len(kv), 1, 512, 2, complex_=True)
+    orw = oracle.OracleCorrelator(len(kv), 1, 512, 2, complex_=True)
+    orl = oracle.OracleCorrelator(len(kv), 5, 16, 2, complex_=True)
+    for s in range(S):
+        oc.push(oracle.currents(x[s, :3], x[s, 3:], kv, box).reshape(-1))
+        r = oracle.rhok(x[s, :3], kv, box)
+        orw.push(r)
+        orl.push(r)
+    gate(out["serial"][0], oc, TOL[("cf32", "kahan")], scale=1.0 / N, slice_=(0, 4), label="currents")
+    gate(out["serial"][1], orw, TOL[("cf32", "kahan")], scale=1.0 / N, slice_=(0, 4), label="n(k) window")
+    gate(out["serial"][2], orl, TOL[("cf32", "f64")], scale=1.0 / N, slice_=(0, 4), label="n(k)")
+
+
 def _pair_inputs(seed, n, S, dtype):
     """x: OU series; y: 0.6 x + an independent OU series (cross-correlated)."""
     x = ou_inputs(seed, 11, n, S, dtype)
