@@ -3,11 +3,13 @@
 // j_s = (1/V) sum over the atoms i of species s of m_s v(i), for every species.
 //
 // HBM-bound reduction: per atom three velocity components (12 or 24 bytes)
-// and a one-byte species id (the ids are stored as bytes at create).  Each thread sums its atoms (grid-stride, fixed order) per
-// species and component in double, the block reduces its 3 x n_species sums
-// by wave shuffles and then across waves in a fixed order, and a final kernel
-// (one wave per channel) adds the block sums in a fixed order and scales them
-// by m_s / V, so the result does not depend on timing.
+// and a one-byte species id (the ids are stored as bytes at create).  Each
+// thread sums its atoms (grid-stride, fixed order; four consecutive atoms per
+// 16-byte load when the layout allows) per species and component in double,
+// the block reduces its 3 x n_species sums by wave shuffles and then across
+// waves in a fixed order, and a final kernel (one wave per channel) adds the
+// block sums in a fixed order and scales them by m_s / V, so the result does
+// not depend on timing.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
