@@ -686,7 +686,8 @@ def run(args):
                    "rhok_producer": "vector units" if args.rhok_valu else "matrix cores",
                    "push_calls": "one corr_push_steps per chunk" if args.replay else "one corr_push per step",
                    "producer_stream": {0: "the context's stream, before the other updates",
-                                       1: "forked, overlapping the other updates",
+                                       1: "forked at the start of the push (with the per-step "
+                                          "updates when block-deferred groups flush beside them)",
                                        2: "the context's stream; the per-step updates forked "
                                           "beside the flush"}[corr.tuning()["overlap_producers"]],
                    "tuning": corr.tuning(), "state_GB": round(state_gb, 2)},
