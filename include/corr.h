@@ -107,11 +107,13 @@ enum corr_flags {
 
 typedef struct corr_group_desc {
     int64_t n_channels;     /* channels; CORR_SRC_RHOK: the number of k-vectors;
-                               CORR_SRC_CURRENTS: 3 x the number of k-vectors */
+                               CORR_SRC_CURRENTS: 3 x the number of k-vectors;
+                               CORR_SRC_MOMENTUM: 3 x n_species                */
     int32_t levels;         /* b >= 1 blocks                                       */
     int32_t points;         /* p >= 2 values per block                             */
     int32_t m;              /* averaging factor, 2 <= m < p                        */
-    int32_t dtype;          /* enum corr_dtype (CORR_SRC_RHOK: CF32 or CF64)       */
+    int32_t dtype;          /* enum corr_dtype (CORR_SRC_RHOK, CURRENTS: CF32 or
+                               CF64; CORR_SRC_MOMENTUM: F32 or F64)              */
     int32_t accum;          /* enum corr_accum                                     */
     int32_t source;         /* enum corr_source                                    */
     int32_t update_every;   /* u >= 1: scales reported lag times only (Sec. 2.2)  */
@@ -137,8 +139,10 @@ typedef struct corr_group_desc {
     double box;             /* cubic box edge L (also MOMENTUM: V = L^3)          */
     /* CORR_SRC_MOMENTUM only (ignored otherwise): */
     const int32_t *species; /* host [n_atoms] species of every atom, in
-                               [0, n_species); copied during corr_create          */
-    const double *masses;   /* host [n_species] mass of the atoms of each species */
+                               [0, n_species) (else CORR_E_INVALID); copied
+                               during corr_create                                 */
+    const double *masses;   /* host [n_species] mass of the atoms of each species
+                               (finite; copied during corr_create)                */
     int32_t n_species;      /* 1..8; n_channels must be 3 n_species               */
     int32_t reserved;       /* 0                                                  */
 } corr_group_desc;
