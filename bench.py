@@ -750,7 +750,40 @@ def run(args):
     out["config"]["autotune_s"] = round(tune_s, 2)
     if max(wl["groups"], key=lambda x: x["n"])["kind"] == "ou":
         out["error_vs_fp64"] = spot_check(corr, wl, W + K)
+    tuned = corr.tuning()
     corr.close()
+    if fs_n and tuned["overlap_producers"] != 0 and not args.replay:
+        # the same flush kernel with nothing beside it: a short second context
+        # with every push on one stream, timed by the same device stamps
+        t0n = dict(tuned, overlap_producers=0)
+        c0 = Correlator(descs, per_group=(mode == "per_group"), tuning=t0n, timing=True,
+                        direct=args.direct, rhok_valu=args.rhok_valu)
+        c0.set_timing_stride(args.timing_stride)
+        n_alone = 256
+        for lead in (DEFER_T, n_alone):  # one block to fill the rings, then the timed pushes
+            if lead == n_alone:
+                c0.kernel_time(3, reset=True)
+            done = 0
+            while done < lead:
+                n = min(chunk, lead - done)
+                for gen, buf in zip(gens, bufs):
+                    if gen is not None:
+                        gen.fill(buf, n)
+                for j in range(n):
+                    c0.push([buf[j] for buf in bufs])
+                done += n
+        torch.cuda.synchronize()
+        a_ms, a_n = c0.kernel_time(3)
+        c0.close()
+        a_bytes = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
+                      for s in range(DEFER_T + 1, DEFER_T + n_alone + 1))
+        if a_n:
+            a_gbs = a_bytes / (a_ms * 1e-3) / 1e9
+            out["roofline"]["alone"] = {
+                "note": "the same flush kernel with every push on one stream (nothing beside "
+                        "it), %d pushes after one block, device stamps" % n_alone,
+                "kernel_ms_per_launch": a_ms / a_n, "achieved": a_gbs,
+                "frac": a_gbs / HBM_PEAK_GBS}
     if args.compare_plain:
         out["plain_form"] = compare_plain(wl, K, W, chunk, args.timing_stride)
         out["plain_form"]["speedup_of_this_form"] = value / out["plain_form"]["value"]
