@@ -700,6 +700,18 @@ def run(args):
                      "alg_bytes_per_step": (stage_bytes + fl_bytes) / kern_n,
                      "timed_pushes": kern_n, "timing_stride": args.timing_stride},
     }
+    if fs_n:
+        # context for the byte model of the per-step form (Algorithm 1 push by
+        # push): its algorithmic bytes for the same pushes of the same groups,
+        # over this form's wall time per push (an equivalent, not traffic)
+        eq = sum(step_bytes(g, s) for g in wl["groups"] if g["kind"] not in PRODUCER_KINDS
+                 for s in steps) / K
+        eq_gbs = eq / (wall / K) / 1e9
+        out["roofline"]["per_step_form_equivalent"] = {
+            "note": "the per-step form's algorithmic bytes for the same pushes of the sample-fed "
+                    "groups, divided by this form's wall time per push (a model figure, not HBM "
+                    "traffic)",
+            "bytes_per_push": eq, "GBs": eq_gbs, "x_peak": eq_gbs / HBM_PEAK_GBS}
     if fs_n and fl_n:
         out["roofline"]["kernel_ms_per_launch_events"] = fl_ms / fl_n
         out["roofline"]["events_note"] = ("HIP events on the timed pushes (one in %d); they "
