@@ -421,6 +421,35 @@ def _currents_inputs(seed, N, box, S):
     return np.ascontiguousarray(np.concatenate([pos, vel], axis=1))
 
 
+@pytest.mark.parametrize("source,valu", [("rhok", False), ("rhok", True), ("currents", False)])
+def test_producers_with_double_samples(corrmod, source, valu):
+    """Producer groups with complex-double samples (the producers' double
+    output path) and FP64 accumulators: C(0) and C(1) of two pushes against
+    the oracle's direct double sums; the producer's own precision (about 22
+    significant bits per product on the matrix cores) sets the bound."""
+    N, box = 4000, 40.0
+    kv = synth.kvectors(96)
+    say(f"[double samples] {source} valu={valu}")
+    x = _currents_inputs(46, N, box, 2)
+    nch = len(kv) * (3 if source == "currents" else 1)
+    g = corrmod.GroupDesc(nch, 3, 8, 2, dtype="cf64", accum="f64", source=source, kvec=kv,
+                          n_atoms=N, box=box)
+    inp = x if source == "currents" else np.ascontiguousarray(x[:, :3])
+    with corrmod.Correlator([g], rhok_valu=valu) as c:
+        _push_all(c, [inp])
+        res = c.finalize(0, slice_=(0, nch))
+    if source == "currents":
+        v = [oracle.currents(x[s, :3], x[s, 3:], kv, box).reshape(-1) for s in range(2)]
+    else:
+        v = [oracle.rhok(x[s, :3], kv, box) for s in range(2)]
+    c0 = (np.abs(v[0]) ** 2 + np.abs(v[1]) ** 2) / 2 / N
+    c1 = v[1] * np.conj(v[0]) / N
+    e0 = np.max(np.abs(res["c_per_channel"][:, 0] - c0)) / np.max(c0)
+    e1 = np.max(np.abs(res["c_per_channel"][:, 1] - c1)) / np.max(c0)
+    say(f"  C(0) {e0:.2e}  C(1) {e1:.2e}")
+    assert e0 < 2e-6 and e1 < 2e-6
+
+
 def test_currents_lag0_against_oracle(corrmod):
     """One push: C(0) of channel 3q+c = |J_c(k_q)|^2 / N with J from the
     oracle's direct double sums, for a k-set spanning |n| up to 15 and
