@@ -79,25 +79,26 @@ def test_momentum_correlator_parity(corrmod, dtype, accum):
     say(f"  error {e:.2e}")
 
 
-def test_momentum_pair_with_heat_flux_all_launch_modes(corrmod):
+@pytest.mark.parametrize("dtype,accum", [("f32", "kahan"), ("f64", "f64")])
+def test_momentum_pair_with_heat_flux_all_launch_modes(corrmod, dtype, accum):
     """Pair group: x = a heat-flux series q (component a for channel 3s + a),
     y = the densities, C(L) = <q(s) j(s - L)>, beside a block-deferred group:
     one stream, forked producers, forked updates and a graph give
     bit-identical results, which match the oracle's pair form."""
     N, S, box, ns = 2500, 400, 9.0, 2
-    sp, masses, vel = _system(33, N, ns, S, "f32")
-    q = ou_inputs(33, 9, 3, S, "f32")                 # [S][3]
+    sp, masses, vel = _system(33, N, ns, S, dtype)
+    q = ou_inputs(33, 9, 3, S, dtype)                 # [S][3]
     x = np.ascontiguousarray(np.tile(q, (1, ns)))     # [S][3 ns]
     inp = np.ascontiguousarray(np.concatenate([vel.reshape(S, -1), x], axis=1))
     xv = ou_inputs(33, 4, 3000, S, "f32")
-    groups = [corrmod.GroupDesc(3 * ns, 5, 16, 2, dtype="f32", accum="kahan", source="momentum",
+    groups = [corrmod.GroupDesc(3 * ns, 5, 16, 2, dtype=dtype, accum=accum, source="momentum",
                                 n_atoms=N, box=box, species=sp, masses=masses, pair=True),
               corrmod.GroupDesc(3000, 5, 16, 2, dtype="f32", accum="kahan")]
     base = dict(tile_channels=256, chans_per_thread=1, lag_chunk=8, grid_blocks=0)
     out = {}
     dev = torch.device("cuda:0")
     for mode in ("serial", "fork", "fork_updates", "graph"):
-        say(f"[momentum pair] {mode}")
+        say(f"[momentum pair] {dtype} {mode}")
         ov = {"serial": 0, "fork": 1, "fork_updates": 2, "graph": 1}[mode]
         with corrmod.Correlator(groups, graph=(mode == "graph"),
                                 tuning=dict(base, overlap_producers=ov)) as c:
@@ -120,7 +121,7 @@ def test_momentum_pair_with_heat_flux_all_launch_modes(corrmod):
     o = oracle.OracleCorrelator(3 * ns, 5, 16, 2)
     for s in range(S):
         o.push_pair(x[s].astype(np.float64), oracle.partial_momentum(vel[s], sp, masses, box ** 3))
-    e = gate(out["serial"], o, TOL[("f32", "kahan")], slice_=(0, 3 * ns), label="momentum pair")
+    e = gate(out["serial"], o, TOL[(dtype, accum)], slice_=(0, 3 * ns), label="momentum pair")
     say(f"  error {e:.2e}")
 
 
