@@ -565,6 +565,34 @@ def test_large_window(corrmod, dtype, accum, direct):
     say(f"  error {e:.2e}")
 
 
+def test_limits_of_the_descriptor(corrmod):
+    """The largest window (p = 16384, block-deferred window form, past the
+    ring's wrap) and the most levels (b = 40) against the oracle; one point
+    more of either is refused as unsupported."""
+    n, S, p = 8, 16600, 16384
+    say(f"[limits] window p={p} S={S}")
+    x = ou_inputs(32, 2, n, S, "f32", tau=300.0, tau_hi=None)
+    o = oracle_run(x, 1, p, 2)
+    with corrmod.Correlator([corrmod.GroupDesc(n, 1, p, 2, dtype="f32", accum="kahan")]) as c:
+        _push_all(c, [x])
+        res = c.finalize(0, slice_=(0, 3))
+    e = gate(res, o, TOL[("f32", "kahan")], slice_=(0, 3), label="p = 16384")
+    say(f"  window error {e:.2e}")
+    n, S, b = 300, 3000, 40
+    say(f"[limits] levels b={b} S={S}")
+    x = ou_inputs(33, 2, n, S, "f64", tau=50.0, tau_hi=None)
+    o = oracle_run(x, b, 16, 2)
+    with corrmod.Correlator([corrmod.GroupDesc(n, b, 16, 2, dtype="f64", accum="f64")]) as c:
+        _push_all(c, [x])
+        res = c.finalize(0, slice_=(0, 3))
+    e = gate(res, o, TOL[("f64", "f64")], slice_=(0, 3), label="b = 40")
+    say(f"  levels error {e:.2e}")
+    for kw in (dict(points=16385, levels=1), dict(points=16, levels=41)):
+        with pytest.raises(corrmod.CorrError) as ei:
+            corrmod.Correlator([corrmod.GroupDesc(8, kw["levels"], kw["points"], 2)])
+        assert ei.value.code == -5
+
+
 WINDOW_KINDS = [("cf32", "kahan"), ("cf32", "f64"), ("cf32", "f32"),
                 ("f32", "kahan"), ("f32", "f64"), ("f32", "f32")]
 
