@@ -147,3 +147,14 @@ def test_momentum_descriptor_checks(corrmod, kw, needle):
     1..8 species with ids in range, finite masses, atoms and a box."""
     rc, msg = _create(corrmod, corrmod.GroupDesc(**kw))
     assert rc == -1 and needle in msg, (rc, msg)
+
+
+def test_missing_library_fails_loudly(corrmod, monkeypatch, tmp_path):
+    """No fallback: without the built HIP library every entry point raises."""
+    import paper_2503_07526_amd.corr as c
+    monkeypatch.setattr(c, "_lib", None)
+    monkeypatch.setattr(c, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(ImportError):
+        c.lib()
+    with pytest.raises(ImportError):
+        c.Correlator([c.GroupDesc(8, 4, 16)])
