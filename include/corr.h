@@ -9,9 +9,13 @@
  * in groups; every channel of a group shares the correlator parameters
  * (b blocks/levels, p points per level, averaging factor m, update interval
  * u) and the sample / accumulator precision.  A group can instead be fed
- * with atom positions, in which case the library evaluates the k-space
- * density n(k) = sum_j exp(i k.r_j) (Section "Currents", Eq. k-density) for
- * each of its k-vectors on every push and correlates those.
+ * with atom data, in which case the library evaluates on every push, and
+ * correlates, the k-space density n(k) = sum_j exp(i k.r_j) of its
+ * k-vectors (Section "Currents", Eq. k-density), their longitudinal and
+ * transverse currents (Eqs. long-current, trans-current), or the partial
+ * momentum densities of the mass-flux correction (Section "Viscosity and
+ * thermal conductivity").  A group can also correlate pairs of observables
+ * (the x, y form of Algorithm 1).
  *
  * Conventions shared by every entry point:
  *  - every call returns int: CORR_OK (0) or a negative corr_status; no
