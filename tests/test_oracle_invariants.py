@@ -130,3 +130,44 @@ def test_green_kubo_prefactors(oracle_mod):
     assert eta == 10.0 / (2.0 * 5.0) * 6.0
     _, kap = oracle_mod.green_kubo_conductivity(t, c, volume=10.0, kB=2.0, temperature=5.0)
     assert np.isclose(kap, 10.0 / (3 * 2.0 * 25.0) * 3 * 6.0, rtol=1e-15)
+
+
+def test_conductivity_from_the_component_sum(oracle_mod):
+    """Reading R16 pinned independently of the oracle's prefactor: the heat
+    flux autocorrelation in Eq. (thermal conductivity) is the dot product
+    <q(t).q(0)> = sum over x, y, z of the component autocorrelations.  Here it
+    is formed directly from a 3-component series with numpy dot products (one
+    level, so every lag is Eq. (1) exactly), and from three one-channel oracle
+    readouts summed; its trapezoid integral (numpy) times V/(3 kB T^2) must
+    equal green_kubo_conductivity on the mean of the three channels."""
+    rng = np.random.default_rng(2503)
+    S, p = 600, 48
+    q = np.zeros((S, 3))
+    for s in range(1, S):  # correlated components of unequal variance
+        q[s] = 0.9 * q[s - 1] + rng.standard_normal(3) * np.array([1.0, 2.0, 0.5])
+    o = oracle_mod.OracleCorrelator(3, 1, p, 2)
+    o.push_series(q)
+    t, c_mean, n = o.readout()
+    lags = np.arange(len(t))
+    dot = np.array([np.einsum("ij,ij->", q[L:], q[:S - L]) / (S - L) for L in lags])
+    comp = np.zeros(len(t))
+    for a in range(3):
+        oa = oracle_mod.OracleCorrelator(1, 1, p, 2)
+        oa.push_series(q[:, a:a + 1])
+        comp += oa.readout()[1]
+    assert np.allclose(comp, dot, rtol=1e-12, atol=0)
+    V, kB, T = 27.0, 1.380649e-23, 300.0
+    integ = getattr(np, "trapezoid", None) or np.trapz
+    kappa_direct = V / (3 * kB * T * T) * float(integ(dot, t))
+    _, kappa = oracle_mod.green_kubo_conductivity(t, c_mean, volume=V, kB=kB, temperature=T)
+    assert np.isclose(kappa, kappa_direct, rtol=1e-12, atol=0), (kappa, kappa_direct)
+    # and with several levels: three one-channel readouts summed = 3 x the mean
+    o3 = oracle_mod.OracleCorrelator(3, 4, 16, 2)
+    o3.push_series(q)
+    t3, c3, _ = o3.readout()
+    s3 = np.zeros(len(t3))
+    for a in range(3):
+        oa = oracle_mod.OracleCorrelator(1, 4, 16, 2)
+        oa.push_series(q[:, a:a + 1])
+        s3 += oa.readout()[1]
+    assert np.allclose(s3, 3 * c3, rtol=1e-13, atol=1e-13 * abs(s3[0]))
