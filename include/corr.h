@@ -268,6 +268,26 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
                   double *t, double *c, int64_t *count, double *gk_running, double *gk_at_cut,
                   double *c_per_channel);
 
+/*
+ * corr_finalize for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, e.g. tight serving loops or harnesses that forbid
+ * it).  Same arguments, results and errors as corr_finalize, bit for bit; it
+ * allocates nothing: instead of the context's readout buffer (grown with
+ * hipMalloc on demand) it uses a fixed 16 MiB device array that the library
+ * holds once per GPU until the process ends.  Groups whose readout needs more
+ * than that fail with CORR_E_UNSUPPORTED and a message naming the size (the
+ * per-channel slice and, for direct-form groups, n_out x ceil(channels /
+ * 4096) partial sums must fit; block-deferred groups are reduced in several
+ * passes when their channels need more).  Every call on a GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (from several threads,
+ * or on contexts whose streams run concurrently) race and must be serialised
+ * by the caller.  Nothing in the array needs to start at zero; it keeps the
+ * last call's contents.
+ */
+int corr_finalize_noalloc(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts,
+                          int32_t *n_out, double *t, double *c, int64_t *count, double *gk_running,
+                          double *gk_at_cut, double *c_per_channel);
+
 /* Wait for all work issued by the context. */
 int corr_sync(corr_ctx *ctx);
 

@@ -63,9 +63,9 @@ class _ReadoutOpts(ctypes.Structure):
 
 
 EXPORTS = ["corr_create", "corr_input_buffer", "corr_bind_input", "corr_push", "corr_push_steps",
-           "corr_query",
-           "corr_finalize", "corr_sync", "corr_destroy", "corr_last_error", "corr_state_bytes",
-           "corr_get_tuning", "corr_kernel_time", "corr_set_timing_stride", "corr_autotune"]
+           "corr_query", "corr_finalize", "corr_finalize_noalloc", "corr_sync", "corr_destroy",
+           "corr_last_error", "corr_state_bytes", "corr_get_tuning", "corr_kernel_time",
+           "corr_set_timing_stride", "corr_autotune"]
 
 _lib = None
 
@@ -87,6 +87,7 @@ def lib():
         L.corr_query.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         L.corr_finalize.argtypes = [vp, i32, ctypes.POINTER(_ReadoutOpts), ctypes.POINTER(i32),
                                     vp, vp, vp, vp, vp, vp]
+        L.corr_finalize_noalloc.argtypes = L.corr_finalize.argtypes
         L.corr_sync.argtypes = [vp]
         L.corr_destroy.argtypes = [vp]
         L.corr_last_error.argtypes = [vp]
@@ -298,9 +299,10 @@ class Correlator:
         return t.as_dict()
 
     def finalize(self, g: int, ch=None, t_cut: float = 0.0, gk_kind: int = 0, volume=0.0,
-                 kB=0.0, temperature=0.0, slice_=None):
+                 kB=0.0, temperature=0.0, slice_=None, noalloc: bool = False):
         """Readout (Algorithm 2) of group g.  Returns a dict with t, c, count,
-        gk_running, gk_at_cut and, if slice_=(b, e) is given, c_per_channel."""
+        gk_running, gk_at_cut and, if slice_=(b, e) is given, c_per_channel.
+        noalloc=True calls corr_finalize_noalloc (no device allocation)."""
         gd = self.groups[g]
         nmax = gd.max_out
         cplx = gd.dtype in ("cf32", "cf64")
@@ -321,8 +323,9 @@ class Correlator:
             ns = o.slice_end - o.slice_begin
             per = np.zeros((ns, nmax, 2) if cplx else (ns, nmax))
         P = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
-        self._check(lib().corr_finalize(self._h, g, ctypes.byref(o), ctypes.byref(n_out), P(t),
-                                        P(c), P(cnt), P(run), ctypes.byref(at), P(per)))
+        fn = lib().corr_finalize_noalloc if noalloc else lib().corr_finalize
+        self._check(fn(self._h, g, ctypes.byref(o), ctypes.byref(n_out), P(t), P(c), P(cnt),
+                       P(run), ctypes.byref(at), P(per)))
         n = int(n_out.value)
         res = {"t": t[:n], "count": cnt[:n], "gk_running": run[:n], "gk_at_cut": float(at.value)}
         if cplx:

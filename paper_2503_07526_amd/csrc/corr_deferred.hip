@@ -178,7 +178,8 @@ __device__ __forceinline__ void fold_level(Ctx &cx, int k, const typename RK<K>:
                 // Fixed-order sum over the wave's 64 consecutive channels (a
                 // chunk aligned to 64 whatever the tile width).
                 const double s = wave_sum(cx.reduce_me ? v : 0.0);
-                if ((threadIdx.x & 63) == 0) a.chunk_partial[(size_t)(cx.ch >> 6) * a.ne + e] = s;
+                if ((threadIdx.x & 63) == 0)
+                    a.chunk_partial[(size_t)((cx.ch >> 6) - a.row_begin) * a.ne + e] = s;
             }
         }
     }
@@ -452,11 +453,13 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
     int64_t tile;
     if constexpr (READ) {
         // Readout (all tile groups caught up): fold the pushes after the
-        // last complete block without writing state.
+        // last complete block without writing state, for the tiles that hold
+        // the pass's chunk rows [row_begin, row_end).
         const int64_t S = *a.step;
         f = (S / kDeferT) * kDeferT;
         r = (int)(S - f);
-        tile = slot;
+        tile = (a.row_begin * 64) / g.tw + slot;
+        if (tile >= g.n_tiles) return;
     } else {
         // Flush of tile group j, block q: scheduled at push kDeferT q + j
         // (fixed_group < 0; the counter is advanced after this push) or
@@ -481,6 +484,11 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
         const int sub = part;
         // whole waves past the tile's end skip the pass (tw is a multiple of 64)
         if (sub * (int)blockDim.x + (int)(threadIdx.x & ~63u) >= g.tw) return;
+        if constexpr (READ) {
+            // and, in a readout, waves whose chunk row belongs to another pass
+            const int64_t row = (tile * g.tw + sub * (int64_t)blockDim.x + (threadIdx.x & ~63u)) >> 6;
+            if (row < a.row_begin || row >= a.row_end) return;
+        }
         Ctx cx;
         cx.a = &a;
         cx.f = f;
@@ -533,19 +541,22 @@ __global__ __launch_bounds__(kFoldThreads) void deferred_read_kernel(DeferredArg
 }
 
 // Column sums of rows [n_rows][ne] in a fixed order: groups of kColGroup rows
-// (grid.y), then the groups in order.
+// (grid.y: group group_begin + blockIdx.y, whose rows are held from row
+// row_begin on), then the groups in order.
 constexpr int kColGroup = 1024;
 
-__global__ void colsum_group_kernel(const double *rows, int64_t n_rows, int ne, double *groups)
+__global__ void colsum_group_kernel(const double *rows, int64_t row_begin, int64_t n_rows, int ne,
+                                    int64_t group_begin, double *groups)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
-    const int64_t r0 = (int64_t)blockIdx.y * kColGroup;
+    const int64_t grp = group_begin + blockIdx.y;
+    const int64_t r0 = grp * kColGroup;
     int64_t r1 = r0 + kColGroup;
     if (r1 > n_rows) r1 = n_rows;
     double s = 0.0;
-    for (int64_t r = r0; r < r1; ++r) s += rows[(size_t)r * ne + e];
-    groups[(size_t)blockIdx.y * ne + e] = s;
+    for (int64_t r = r0; r < r1; ++r) s += rows[(size_t)(r - row_begin) * ne + e];
+    groups[(size_t)grp * ne + e] = s;
 }
 
 __global__ void colsum_final_kernel(const double *groups, int64_t n_groups, int ne, double *out)
@@ -579,7 +590,9 @@ hipError_t launch_deferred_kp(const DeferredArgs &a, hipStream_t st)
 {
     const int block = a.g.tw < kFoldThreads ? a.g.tw : kFoldThreads;
     const int parts = (a.g.tw + block - 1) / block;
-    const int64_t grid = (READ ? a.g.n_tiles : a.tiles_per_group) * parts;
+    // readout: the tiles that hold chunk rows [row_begin, row_end)
+    const int64_t read_tiles = (a.row_end * 64 + a.g.tw - 1) / a.g.tw - (a.row_begin * 64) / a.g.tw;
+    const int64_t grid = (READ ? read_tiles : a.tiles_per_group) * parts;
     if (grid < 1) return hipSuccess;
     if constexpr (READ)
         hipLaunchKernelGGL((deferred_read_kernel<K, P, kDeferT>), dim3((unsigned)grid), dim3(block),
@@ -693,20 +706,30 @@ int64_t deferred_readout_groups(const GroupArgs &g)
     return (deferred_readout_rows(g) + kColGroup - 1) / kColGroup;
 }
 
-hipError_t launch_deferred_readout(const DeferredArgs &a, double *groups, double *sums,
-                                   hipStream_t st)
+int64_t deferred_readout_group_rows() { return kColGroup; }
+
+hipError_t launch_deferred_readout_pass(const DeferredArgs &a, double *groups, hipStream_t st)
 {
+    const int64_t n_rows = deferred_readout_rows(a.g);
+    if (a.row_begin < 0 || a.row_begin % kColGroup != 0 || a.row_end <= a.row_begin ||
+        (a.row_end != n_rows && a.row_end % kColGroup != 0) || a.row_end > n_rows)
+        return hipErrorInvalidValue; // a pass holds whole groups of rows
     hipError_t e = launch_deferred_t<true>(a, st);
     if (e != hipSuccess) return e;
-    const int64_t n_rows = deferred_readout_rows(a.g);
-    const int64_t n_groups = deferred_readout_groups(a.g);
+    const int64_t g0 = a.row_begin / kColGroup;
+    const int64_t g1 = (a.row_end + kColGroup - 1) / kColGroup;
     const unsigned ex = (unsigned)((a.ne + 63) / 64);
-    hipLaunchKernelGGL(colsum_group_kernel, dim3(ex, (unsigned)n_groups), dim3(64), 0, st,
-                       a.chunk_partial, n_rows, a.ne, groups);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_final_kernel, dim3(ex), dim3(64), 0, st, groups, n_groups, a.ne,
-                       sums);
+    hipLaunchKernelGGL(colsum_group_kernel, dim3(ex, (unsigned)(g1 - g0)), dim3(64), 0, st,
+                       a.chunk_partial, a.row_begin, n_rows, a.ne, g0, groups);
+    return hipGetLastError();
+}
+
+hipError_t launch_deferred_readout_final(const DeferredArgs &a, const double *groups, double *sums,
+                                         hipStream_t st)
+{
+    const unsigned ex = (unsigned)((a.ne + 63) / 64);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(ex), dim3(64), 0, st, groups,
+                       deferred_readout_groups(a.g), a.ne, sums);
     return hipGetLastError();
 }
 

@@ -87,7 +87,9 @@ struct DeferredArgs {
     int64_t fixed_block;
     int64_t ch_begin, ch_end;       // readout: channels reduced
     int64_t slice_begin, slice_end; // readout: channels written to slice_out
-    double *chunk_partial;  // readout: [n_tiles * tw / 64][ne] sums over 64-channel chunks
+    int64_t row_begin, row_end;     // readout: the 64-channel chunk rows of this pass
+    double *chunk_partial;  // readout: [row_end - row_begin][ne] sums over 64-channel chunks
+                            // (row r at r - row_begin)
     double *slice_out;      // readout: [(c - slice_begin) * ne + e]
     FoldStamps *stamps;     // scheduled flush with timing: block start / end stamps, else null
 };

@@ -35,8 +35,14 @@ hipError_t launch_flush_fold(const DeferredArgs &a, hipStream_t st);   // the fo
 hipError_t launch_flush_commit(const DeferredArgs &a, hipStream_t st); // flag update
 int64_t deferred_readout_rows(const GroupArgs &g);
 int64_t deferred_readout_groups(const GroupArgs &g);
-hipError_t launch_deferred_readout(const DeferredArgs &a, double *groups, double *sums,
-                                   hipStream_t st);
+int64_t deferred_readout_group_rows(); // chunk rows per fixed-order column group
+// Readout of the chunk rows [a.row_begin, a.row_end) (whole column groups, or
+// up to the last row): per-row sums into a.chunk_partial, then the column
+// groups of those rows into groups[group][ne].
+hipError_t launch_deferred_readout_pass(const DeferredArgs &a, double *groups, hipStream_t st);
+// Sum of every column group, in order, into sums[ne].
+hipError_t launch_deferred_readout_final(const DeferredArgs &a, const double *groups, double *sums,
+                                         hipStream_t st);
 hipError_t launch_gather(const ReduceArgs &a, hipStream_t st);
 bool window_deferred_supported(int kind);
 int window_lags_per_block(int p);

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,32 @@ using namespace corr;
 namespace {
 
 thread_local std::string g_create_error;
+
+// Readout scratch of corr_finalize_noalloc: a fixed device array, one copy per
+// GPU, held until the process ends.  Host code never uses the array's name as
+// an address: the device address of each GPU's copy is looked up once (in
+// corr_create, with that device current) and kept in g_noalloc_ptr.
+constexpr size_t kNoAllocBytes = (size_t)16 << 20;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocDevices] = {};
+
+// Device address of the current device's scratch array (looked up on first use).
+hipError_t noalloc_scratch(int device, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    *out = nullptr;
+    if (device < 0 || device >= kNoAllocDevices) return hipErrorInvalidDevice;
+    if (!g_noalloc_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_noalloc_ptr[device] = ptr;
+    }
+    *out = g_noalloc_ptr[device];
+    return hipSuccess;
+}
 
 // One-level groups with at least this many points take a window form: the
 // block-deferred window (corr_window.hip) where the kind allows, else the
@@ -105,9 +132,11 @@ struct corr_ctx {
         double ms = 0.0;
         int64_t n = 0;
     } pools[3];
-    // readout scratch
+    // readout scratch (corr_finalize; grown on demand)
     void *d_scratch = nullptr;
     size_t scratch_bytes = 0;
+    // this device's fixed readout scratch (corr_finalize_noalloc)
+    void *noalloc = nullptr;
     std::string err;
 };
 
@@ -1032,6 +1061,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     }
     CREATE_HIP(hipMalloc(&c->d_step, sizeof(int64_t)));
     CREATE_HIP(hipMemsetAsync(c->d_step, 0, sizeof(int64_t), c->stream));
+    CREATE_HIP(noalloc_scratch(device, &c->noalloc));
     if (flags & CORR_FLAG_TIMING) {
         int khz = 0;
         CREATE_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
@@ -1224,9 +1254,33 @@ int corr_destroy(corr_ctx *ctx)
     return CORR_OK;
 }
 
-int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, int32_t *n_out,
+} // extern "C"
+
+namespace {
+
+// Scratch of one readout: the context's own buffer (grown with hipMalloc) or,
+// for corr_finalize_noalloc, the device's fixed array.
+int readout_scratch(corr_ctx *ctx, bool noalloc, size_t bytes, char **out)
+{
+    if (noalloc) {
+        if (bytes > kNoAllocBytes)
+            return set_err(ctx, CORR_E_UNSUPPORTED,
+                           "readout needs %zu bytes of scratch; corr_finalize_noalloc has %zu",
+                           bytes, kNoAllocBytes);
+        *out = static_cast<char *>(ctx->noalloc);
+        return CORR_OK;
+    }
+    int rc = ensure_scratch(ctx, bytes);
+    if (rc != CORR_OK) return rc;
+    *out = static_cast<char *>(ctx->d_scratch);
+    return CORR_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int finalize_impl(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, int32_t *n_out,
                   double *t, double *c, int64_t *count, double *gk_running, double *gk_at_cut,
-                  double *c_per_channel)
+                  double *c_per_channel, bool noalloc)
 {
     if (!ctx) return CORR_E_INVALID;
     if (group < 0 || group >= (int)ctx->groups.size())
@@ -1294,18 +1348,37 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
         // Block-deferred group: fold pending complete blocks (the scheduled
         // flush would produce the same state), then fold the pushes after the
         // last block on the fly (no state is written) and reduce.
+        const GroupArgs &ga = ctx->pargs.g[(size_t)group];
+        // Per-chunk sums are reduced in passes over whole column groups of
+        // rows; corr_finalize takes all rows in one pass, the no-alloc
+        // readout as many groups per pass as its fixed scratch holds (the
+        // same sums in the same order either way).
+        const int64_t n_rows = deferred_readout_rows(ga);
+        const int64_t n_cg = deferred_readout_groups(ga);
+        const int64_t cg_rows = deferred_readout_group_rows();
+        const size_t gr_bytes = round256((size_t)n_cg * ne * sizeof(double));
+        const size_t s_bytes = round256((size_t)ne * sizeof(double));
+        const size_t sl_bytes = round256((size_t)std::max<int64_t>(n_slice, 1) * ne * sizeof(double));
+        const size_t fixed = gr_bytes + s_bytes + sl_bytes;
+        const size_t cg_bytes = (size_t)cg_rows * ne * sizeof(double);
+        int64_t cg_per_pass = n_cg;
+        if (noalloc) {
+            if (fixed + std::min<size_t>(cg_bytes, (size_t)n_rows * ne * sizeof(double)) > kNoAllocBytes)
+                return set_err(ctx, CORR_E_UNSUPPORTED,
+                               "readout needs more than the %zu bytes of scratch of "
+                               "corr_finalize_noalloc (%d entries, slice of %lld channels)",
+                               kNoAllocBytes, ne, (long long)n_slice);
+            cg_per_pass = std::max<int64_t>(1, std::min<int64_t>(n_cg, (int64_t)((kNoAllocBytes - fixed) / cg_bytes)));
+        }
+        const size_t tp_bytes =
+            round256((size_t)std::min<int64_t>(n_rows, cg_per_pass * cg_rows) * ne * sizeof(double));
+        char *sc = nullptr;
         {
-            int rc = catch_up_flushes(ctx, group);
+            int rc = readout_scratch(ctx, noalloc, tp_bytes + fixed, &sc);
+            if (rc != CORR_OK) return rc;
+            rc = catch_up_flushes(ctx, group);
             if (rc != CORR_OK) return rc;
         }
-        const GroupArgs &ga = ctx->pargs.g[(size_t)group];
-        const size_t tp_bytes = (size_t)deferred_readout_rows(ga) * ne * sizeof(double);
-        const size_t gr_bytes = (size_t)deferred_readout_groups(ga) * ne * sizeof(double);
-        const size_t s_bytes = (size_t)ne * sizeof(double);
-        const size_t sl_bytes = (size_t)std::max<int64_t>(n_slice, 1) * ne * sizeof(double);
-        int rc = ensure_scratch(ctx, tp_bytes + gr_bytes + s_bytes + sl_bytes);
-        if (rc != CORR_OK) return rc;
-        char *sc = static_cast<char *>(ctx->d_scratch);
         DeferredArgs da{};
         da.g = ctx->pargs.g[(size_t)group];
         da.step = ctx->d_step;
@@ -1318,9 +1391,16 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
         double *d_groups = reinterpret_cast<double *>(sc + tp_bytes);
         double *d_sums = reinterpret_cast<double *>(sc + tp_bytes + gr_bytes);
         da.slice_out = reinterpret_cast<double *>(sc + tp_bytes + gr_bytes + s_bytes);
-        HIP_TRY(ctx, launch_deferred_readout(da, d_groups, d_sums, ctx->stream));
+        for (int64_t g0 = 0; g0 < n_cg; g0 += cg_per_pass) {
+            const int64_t g1 = std::min(n_cg, g0 + cg_per_pass);
+            da.row_begin = g0 * cg_rows;
+            da.row_end = std::min(n_rows, g1 * cg_rows);
+            HIP_TRY(ctx, launch_deferred_readout_pass(da, d_groups, ctx->stream));
+        }
+        HIP_TRY(ctx, launch_deferred_readout_final(da, d_groups, d_sums, ctx->stream));
         std::vector<double> re((size_t)ne);
-        HIP_TRY(ctx, hipMemcpyAsync(re.data(), d_sums, s_bytes, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(re.data(), d_sums, (size_t)ne * sizeof(double),
+                                    hipMemcpyDeviceToHost, ctx->stream));
         std::vector<double> sl;
         if (want_slice) {
             sl.resize((size_t)n_slice * ne);
@@ -1344,11 +1424,11 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
     const size_t sum_bytes = (size_t)ne * 2 * sizeof(double);
     const size_t slice_bytes = (size_t)n_slice * ne * 2 * sizeof(double);
     const size_t total = off_bytes + part_bytes + sum_bytes + std::max(slice_bytes, (size_t)16);
+    char *sc = nullptr;
     {
-        int rc = ensure_scratch(ctx, total);
+        int rc = readout_scratch(ctx, noalloc, total, &sc);
         if (rc != CORR_OK) return rc;
     }
-    char *sc = static_cast<char *>(ctx->d_scratch);
     int64_t *d_off = reinterpret_cast<int64_t *>(sc);
     double *d_part = reinterpret_cast<double *>(sc + off_bytes);
     double *d_sum = reinterpret_cast<double *>(sc + off_bytes + part_bytes);
@@ -1455,6 +1535,26 @@ int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, i
     if (!cut_done) at_cut = acc;
     if (gk_at_cut) *gk_at_cut = at_cut * pref;
     return CORR_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int corr_finalize(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts, int32_t *n_out,
+                  double *t, double *c, int64_t *count, double *gk_running, double *gk_at_cut,
+                  double *c_per_channel)
+{
+    return finalize_impl(ctx, group, opts, n_out, t, c, count, gk_running, gk_at_cut,
+                         c_per_channel, false);
+}
+
+int corr_finalize_noalloc(corr_ctx *ctx, int32_t group, const corr_readout_opts *opts,
+                          int32_t *n_out, double *t, double *c, int64_t *count, double *gk_running,
+                          double *gk_at_cut, double *c_per_channel)
+{
+    return finalize_impl(ctx, group, opts, n_out, t, c, count, gk_running, gk_at_cut,
+                         c_per_channel, true);
 }
 
 } // extern "C"
