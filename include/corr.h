@@ -75,7 +75,13 @@ enum corr_source {
                              normalised, e2 = khat x e1.  C_L is the
                              correlation of channel 3q, C_T the mean of
                              channels 3q+1 and 3q+2.  Components of n must
-                             lie within +-15; n = 0 is rejected.          */
+                             lie within +-15; n = 0 is rejected.  Any finite
+                             velocities: each component is scaled by a
+                             power of two per block of about 1000 atoms
+                             before the fp16 split (see CORR_FLAG_RHOK_VALU),
+                             so products keep about 22 bits relative to
+                             the largest |v_alpha| of the block; J(k) must
+                             stay within the float range for CF32 groups.  */
     CORR_SRC_MOMENTUM = 3 /* caller provides velocities; channels = the
                              partial momentum densities of the mass-flux
                              correction of the thermal conductivity (Section
@@ -106,7 +112,12 @@ enum corr_flags {
                                  a matrix product on the matrix cores (fp16
                                  hi/lo operand split, about 22 significant
                                  bits per product, fp32 tile sums added in
-                                 fp64)                                          */
+                                 fp64).  On either unit the phases are float
+                                 (about 24 bits), so producer samples carry
+                                 about 22-24 significant bits per atom term
+                                 whatever the group dtype: a CF64 group gets
+                                 the double sums of those terms, not
+                                 double-precision phases                        */
 };
 
 typedef struct corr_group_desc {

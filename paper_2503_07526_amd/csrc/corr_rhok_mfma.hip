@@ -11,7 +11,11 @@
 // [0, 15] (one 16-column tile).  Per atom only one complex product P per pair
 // is formed on the vector units; z comes from a table.
 //
-// Precision: the operands are at most 1 in magnitude.  Each real operand v is
+// Precision: the operands are at most 1 in magnitude (the phases; for the
+// currents, the velocity components are first scaled by a power of two per
+// atom block, so that the largest magnitude of each component over the
+// block's atoms lies in [1/2, 1), and the block's double sums are scaled back
+// exactly when stored).  Each real operand v is
 // split into v_hi = fp16(v) and v_lo = fp16(v - v_hi) (about 22 significant
 // bits together) and a real product is a_hi b_hi + a_hi b_lo + a_lo b_hi (the
 // dropped a_lo b_lo is below 2^-22), i.e. three fp16 matrix products with
@@ -58,6 +62,9 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxWaves = 12;  // waves per block (one M tile each)
 constexpr int kMfmaCols = 16;      // |n_z| = 0 .. 15
 constexpr int kRoots = 64;         // e^{2 pi i q / kRoots} table for the base phase
+// LDS after the root table for the weight scales (three weight sets): the
+// waves' maxima [waves][NW] as floats, in double2 units
+template <int NW> struct ScaleSlots { static constexpr int n = NW == 1 ? 0 : 8; };
 // B fragments in LDS: [K-step][part: re hi, re lo, im hi, im lo][atom group][column]
 constexpr int kBParts = 4;
 // atoms whose products the fp32 matrix accumulators sum before they are added
@@ -166,8 +173,9 @@ struct TileBufs {
 // past the end (live == false) get zero entries, so they add nothing.
 template <int NW, int TA>
 __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool live, float x,
-                                           const float (&w)[NW], double inv_box, int nmax,
-                                           int2 xrows, int2 yrows, const double2 *roots)
+                                           const float (&w)[NW], const double (&wsc)[NW],
+                                           double inv_box, int nmax, int2 xrows, int2 yrows,
+                                           const double2 *roots)
 {
     const int hf = task / (3 * Tile<TA>::atoms);
     const int rem = task - hf * 3 * Tile<TA>::atoms;
@@ -203,7 +211,7 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
             if (n > 0) cmul(pr, pi, cs, sn);
 #pragma unroll
             for (int s = 0; s < NW; ++s) {
-                const double wd = NW == 1 ? 1.0 : (double)w[s];
+                const double wd = NW == 1 ? 1.0 : (double)w[s] * wsc[s];
                 float zr = (float)(pr * wd), zi = (float)(pi * wd);
                 // keep the float rounding step visible: otherwise double ->
                 // float -> half is folded into one double -> half conversion,
@@ -229,11 +237,11 @@ template <int NW> struct MfmaShape {
 
 template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaArgs &a)
 {
-    extern __shared__ double2 lds_roots[]; // [kRoots], then two tile buffers
+    extern __shared__ double2 lds_roots[]; // [kRoots], the scale slots, then two tile buffers
     const int nmax = a.nmax;
     const int2 xrows = make_int2(a.x_lo, a.x_rows), yrows = make_int2(a.y_lo, a.y_rows);
     // two tile buffers of buf_stride float2 each (a multiple of 2: 16-byte aligned)
-    float2 *const buf0 = reinterpret_cast<float2 *>(lds_roots + kRoots);
+    float2 *const buf0 = reinterpret_cast<float2 *>(lds_roots + kRoots + ScaleSlots<NW>::n);
     const int buf_stride =
         (a.x_rows + a.y_rows) * Tile<TA>::stride +
         NW * Tile<TA>::bfrags * (int)(sizeof(halfv_t) / sizeof(float2));
@@ -286,6 +294,42 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
     const int n_tiles =
         a_end > a_begin ? (int)((a_end - a_begin + Tile<TA>::atoms - 1) / Tile<TA>::atoms) : 0;
 
+    // Weight scales: 2^-e per weight set with e the binary exponent of the
+    // largest |w| over the block's atoms (frexp: max |w| 2^-e in [1/2, 1)),
+    // so that every split operand keeps its 22 bits relative to that maximum
+    // in any velocity units; wunsc = 2^e restores the double sums.
+    double wsc[NW], wunsc[NW];
+#pragma unroll
+    for (int s = 0; s < NW; ++s) wsc[s] = wunsc[s] = 1.0;
+    if constexpr (NW > 1) {
+        float *red = reinterpret_cast<float *>(lds_roots + kRoots); // [waves][NW]
+        float mx[NW];
+#pragma unroll
+        for (int s = 0; s < NW; ++s) mx[s] = 0.f;
+        for (int64_t at = a_begin + threadIdx.x; at < a_end; at += blockDim.x)
+#pragma unroll
+            for (int s = 0; s < NW; ++s) mx[s] = fmaxf(mx[s], fabsf(a.pos[(int64_t)(3 + s) * a.n_atoms + at]));
+#pragma unroll
+        for (int s = 0; s < NW; ++s)
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) mx[s] = fmaxf(mx[s], __shfl_xor(mx[s], off, 64));
+        if (lane == 0)
+#pragma unroll
+            for (int s = 0; s < NW; ++s) red[wave * NW + s] = mx[s];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NW; ++s) {
+            float m = 0.f;
+            for (int w2 = 0; w2 < waves; ++w2) m = fmaxf(m, red[w2 * NW + s]);
+            if (m > 0.f) {
+                int ex = 0;
+                (void)frexpf(m, &ex);
+                wsc[s] = ldexp(1.0, -ex);
+                wunsc[s] = ldexp(1.0, ex);
+            }
+        }
+    }
+
     // table task of this thread (blockDim >= TableShape<NW, TA>::tasks) and its inputs,
     // loaded one tile ahead of their use; the Z task also loads the weights
     const int task = threadIdx.x;
@@ -307,8 +351,8 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
     bool live_next = load_in(1, x_next, w_next);
     __syncthreads(); // roots and zero columns
     if (builder)
-        build_tile<NW, TA>(tile_bufs(0), task, live_cur, x_cur, w_cur, a.inv_box, nmax, xrows, yrows,
-                       lds_roots);
+        build_tile<NW, TA>(tile_bufs(0), task, live_cur, x_cur, w_cur, wsc, a.inv_box, nmax, xrows,
+                           yrows, lds_roots);
     __syncthreads();
 
     for (int it = 0; it < n_tiles; ++it) {
@@ -317,8 +361,8 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
         if (builder && it + 1 < n_tiles) {
             float x_after, w_after[NW];
             const bool live_after = load_in(it + 2, x_after, w_after);
-            build_tile<NW, TA>(tile_bufs((it + 1) & 1), task, live_next, x_next, w_next, a.inv_box,
-                           nmax, xrows, yrows, lds_roots);
+            build_tile<NW, TA>(tile_bufs((it + 1) & 1), task, live_next, x_next, w_next, wsc,
+                               a.inv_box, nmax, xrows, yrows, lds_roots);
             x_next = x_after;
 #pragma unroll
             for (int s = 0; s < NW; ++s) w_next[s] = w_after[s];
@@ -418,13 +462,13 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
         for (int w = 0; w < NW; ++w) {
             if (kp >= 0) {
                 double *dst = a.partial + (((size_t)kp * NW + w) * a.n_atom_blocks + blockIdx.y) * 2;
-                dst[0] = acc[w][0][v] - acc[w][1][v];
-                dst[1] = acc[w][2][v] + acc[w][3][v];
+                dst[0] = (acc[w][0][v] - acc[w][1][v]) * wunsc[w];
+                dst[1] = (acc[w][2][v] + acc[w][3][v]) * wunsc[w];
             }
             if (km >= 0) {
                 double *dst = a.partial + (((size_t)km * NW + w) * a.n_atom_blocks + blockIdx.y) * 2;
-                dst[0] = acc[w][0][v] + acc[w][1][v];
-                dst[1] = acc[w][3][v] - acc[w][2][v];
+                dst[0] = (acc[w][0][v] + acc[w][1][v]) * wunsc[w];
+                dst[1] = (acc[w][3][v] - acc[w][2][v]) * wunsc[w];
             }
         }
     }
@@ -514,7 +558,7 @@ int rhok_mfma_max_nmax() { return kMfmaCols - 1; }
 
 template <int NW, int TA> static size_t lds_bytes(int table_rows)
 {
-    return (size_t)kRoots * sizeof(double2) +
+    return (size_t)(kRoots + ScaleSlots<NW>::n) * sizeof(double2) +
            2 * ((size_t)table_rows * Tile<TA>::stride * sizeof(float2) +
                 (size_t)NW * Tile<TA>::bfrags * sizeof(halfv_t));
 }

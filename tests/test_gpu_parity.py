@@ -478,6 +478,33 @@ def test_currents_lag0_against_oracle(corrmod):
         assert np.max(np.abs(got1 - expect1)) / np.max(np.abs(expect1)) < 2e-6
 
 
+@pytest.mark.parametrize("scale", [(1e-3, 1e-3, 1e-3), (1e5, 1e5, 1e5), (1e-3, 1.0, 1e4)])
+def test_currents_in_any_velocity_units(corrmod, scale):
+    """Velocities far from unit size (e.g. Angstrom/fs, or large units) and
+    components of very different size: the producer scales each component by
+    a power of two per atom block before the fp16 split, so C(0) and C(1) of
+    two pushes keep the precision of unit velocities (against the oracle's
+    direct double sums of the same float inputs)."""
+    N, box = 2500, 40.0
+    kv = synth.kvectors(64)
+    say(f"[currents units] velocity scale per component {scale}")
+    x = _currents_inputs(31, N, box, 2)
+    x[:, 3:] *= np.array(scale, dtype=np.float32)[None, :, None]
+    g = corrmod.GroupDesc(3 * len(kv), 3, 8, 2, dtype="cf32", accum="f64", source="currents",
+                          kvec=kv, n_atoms=N, box=box)
+    with corrmod.Correlator([g]) as c:
+        _push_all(c, [x])
+        res = c.finalize(0, slice_=(0, 3 * len(kv)))
+    v = [oracle.currents(x[s, :3], x[s, 3:], kv, box).reshape(-1) for s in range(2)]
+    c0 = (np.abs(v[0]) ** 2 + np.abs(v[1]) ** 2) / 2 / N
+    c1 = v[1] * np.conj(v[0]) / N
+    assert np.all(np.isfinite(res["c_per_channel"]))
+    e0 = np.max(np.abs(res["c_per_channel"][:, 0] - c0)) / np.max(c0)
+    e1 = np.max(np.abs(res["c_per_channel"][:, 1] - c1)) / np.max(c0)
+    say(f"  C(0) {e0:.2e}  C(1) {e1:.2e}")
+    assert e0 < 2e-6 and e1 < 2e-6
+
+
 @pytest.mark.parametrize("accum", ["kahan", "f64"])
 def test_currents_correlator_parity(corrmod, accum):
     """S pushes of moving atoms: the currents group against the oracle
