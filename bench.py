@@ -73,8 +73,11 @@ def parse():
     ap.add_argument("--mode", default=None, choices=["batched", "per_group"],
                     help="launch form (default: per_group for plain, batched otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--compare-plain", action="store_true",
-                    help="also time the plain FP64 per-group form on the same velocity channels")
+    ap.add_argument("--no-compare-plain", action="store_true",
+                    help="skip the bounded leg that times the plain FP64 per-group form on the "
+                         "largest sample-fed group (run by default)")
+    ap.add_argument("--plain-steps", type=int, default=64,
+                    help="timed pushes of the plain-form leg (after %d fill pushes)" % 256)
     ap.add_argument("--tuning", default=None, help="JSON dict of corr_tuning fields")
     ap.add_argument("--timing-stride", type=int, default=7,
                     help="record the HIP timing events on one push in this many (each event pair "
@@ -408,7 +411,8 @@ def cpu_baseline(wl):
                       f"(b={g['levels']}, p={g['points']}, m={g['m']}), single thread, "
                       f"{dt:.1f} s")}
     # the same sample on every host core at once: one oracle per thread (its C
-    # calls release the interpreter lock), each pushing the same series
+    # calls release the interpreter lock), each pushing the same series; a GPU
+    # box gives one GPU a share of 16 host cores, whatever the affinity mask says
     import threading
     n_thr = min(16, len(os.sched_getaffinity(0)))
     if n_thr > 1:
@@ -426,10 +430,16 @@ def cpu_baseline(wl):
         for t in ths:
             t.join()
         dt2 = time.perf_counter() - t0
-        out["all_cores"] = {"value": n_thr * n_ch * S2 / dt2, "unit": "channel-samples/s",
-                            "cores": n_thr,
-                            "sample": (f"{n_thr} threads, each an oracle of {n_ch} channels "
-                                       f"pushed {S2} times, {dt2:.1f} s")}
+        # the reported baseline is the oracle on every core; the single-thread
+        # figure stays beside it
+        single = dict(out)
+        del single["kind"]
+        out = {"value": n_thr * n_ch * S2 / dt2, "unit": "channel-samples/s", "cores": n_thr,
+               "kind": "oracle",
+               "sample": (f"{n_thr} threads, each an oracle of {n_ch} channels of the "
+                          f"{g['dtype']} group (b={g['levels']}, p={g['points']}, m={g['m']}) "
+                          f"pushed {S2} times, {dt2:.1f} s"),
+               "single_thread": single}
     return out
 
 
@@ -568,15 +578,20 @@ def run(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    # warmup
+    # Fill, then the declared warm-up.  A block-deferred group folds its first
+    # block at push 256, so at least one whole block is pushed before the
+    # warm-up: the timed pushes then carry their scheduled folds whatever
+    # --warmup says (steady state).
+    direct = args.direct
+    fill = DEFER_T if any(deferred(g, direct) for g in wl["groups"]) else 0
     done = 0
-    while done < W:
-        n = min(chunk, W - done)
+    while done < fill + W:
+        n = min(chunk, fill + W - done)
         push_chunk(n)
         done += n
     for which in (0, 1, 2, 3):
         corr.kernel_time(which, reset=True)
-    s_first = W + 1
+    s_first = fill + W + 1
     wall = 0.0
     done = 0
     while done < K:
@@ -594,7 +609,6 @@ def run(args):
     has_rhok = any(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
     timed = [g for g in wl["groups"]
              if not (has_rhok and len(wl["groups"]) > 1 and g["kind"] in PRODUCER_KINDS)]
-    direct = args.direct
     # algorithmic bytes of the timed (sampled) pushes, to go with their event times
     stage_bytes = sum(push_bytes(g, s, direct) for g in timed for s in sampled)
     tw = corr.tuning()["tile_channels"]
@@ -657,6 +671,10 @@ def run(args):
     elif fs_n:
         # dominant kernel: the flush of the block-deferred groups, every timed push
         assert fs_n == K, (fs_n, K)
+        if fl_bytes_all <= 0:
+            raise RuntimeError("the timed pushes carried no fold work (pushes %d..%d): the "
+                               "block-deferred line would not measure its dominant kernel"
+                               % (s_first, s_first + K - 1))
         achieved = fl_bytes_all / (fs_ms * 1e-3) / 1e9
         kname = ("flush kernel (block-deferred fold of 256 pushes for 1/256 of the channels per "
                  "push), device stamps of every launch")
@@ -674,6 +692,7 @@ def run(args):
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
+        "fill_pushes": fill,
         "ms_per_step": wall / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -683,7 +702,11 @@ def run(args):
                 "timed chunk)",
         "config": {"workload": wl["name"], "channels": n_total, "launch": mode,
                    "update_form": "direct" if args.direct else "block-deferred where supported",
-                   "rhok_producer": "vector units" if args.rhok_valu else "matrix cores",
+                   "rhok_producer": ("vector units (fp32 phases, fp32 tile sums added in fp64)"
+                                     if args.rhok_valu else
+                                     "matrix cores (fp16 hi/lo operand split: about 22 "
+                                     "significant bits per product; fp32 tile sums added in "
+                                     "fp64)"),
                    "push_calls": "one corr_push_steps per chunk" if args.replay else "one corr_push per step",
                    "producer_stream": {0: "the context's stream, before the other updates",
                                        1: "forked at the start of the push (with the per-step "
@@ -707,7 +730,7 @@ def run(args):
         eq = sum(step_bytes(g, s) for g in wl["groups"] if g["kind"] not in PRODUCER_KINDS
                  for s in steps) / K
         eq_gbs = eq / (wall / K) / 1e9
-        out["roofline"]["per_step_form_equivalent"] = {
+        out["per_step_form_model"] = {
             "note": "the per-step form's algorithmic bytes for the same pushes of the sample-fed "
                     "groups, divided by this form's wall time per push (a model figure, not HBM "
                     "traffic)",
@@ -761,7 +784,7 @@ def run(args):
                 "pushes": rec["pushes"], "source": f"profiles/flush_traffic_{args.config}.md"}
     out["config"]["autotune_s"] = round(tune_s, 2)
     if max(wl["groups"], key=lambda x: x["n"])["kind"] == "ou":
-        out["error_vs_fp64"] = spot_check(corr, wl, W + K)
+        out["error_vs_fp64"] = spot_check(corr, wl, fill + W + K)
     tuned = corr.tuning()
     corr.close()
     if fs_n and tuned["overlap_producers"] != 0 and not args.replay:
@@ -796,8 +819,9 @@ def run(args):
                         "it), %d pushes after one block, device stamps" % n_alone,
                 "kernel_ms_per_launch": a_ms / a_n, "achieved": a_gbs,
                 "frac": a_gbs / HBM_PEAK_GBS}
-    if args.compare_plain:
-        out["plain_form"] = compare_plain(wl, K, W, chunk, args.timing_stride)
+    big = max(wl["groups"], key=lambda x: x["n"])
+    if not args.no_compare_plain and big["kind"] == "ou" and big["dtype"] == "f32":
+        out["plain_form"] = compare_plain(wl, args.plain_steps, chunk, args.timing_stride)
         out["plain_form"]["speedup_of_this_form"] = value / out["plain_form"]["value"]
     return out, wl
 
@@ -937,8 +961,10 @@ def precision(args):
             "runs": runs}
 
 
-def compare_plain(wl, K, W, chunk, stride):
-    """The velocity group alone in the plain form (FP64 sums, per-group launch)."""
+def compare_plain(wl, K, chunk, stride):
+    """The largest sample-fed group alone in the plain form (FP64 sums, per-step
+    update, per-group launch): one whole 256-push block to fill the level-0
+    window and the first levels, then K timed pushes."""
     import torch
 
     import synth
@@ -951,6 +977,7 @@ def compare_plain(wl, K, W, chunk, stride):
     corr = Correlator([GroupDesc(g["n"], g["levels"], g["points"], g["m"], dtype="f32",
                                  accum="f64")], per_group=True, timing=True, direct=True)
     corr.set_timing_stride(stride)
+    W = DEFER_T
     wall, done, reset = 0.0, 0, False
     while done < W + K:
         if done >= W and not reset:
@@ -975,7 +1002,7 @@ def compare_plain(wl, K, W, chunk, stride):
             "ms_per_step": wall / K * 1e3,
             "push_kernel_ms": kern_ms / kern_n if kern_n else None,
             "push_kernel_GBs": alg / (kern_ms / kern_n * 1e-3) / 1e9 if kern_n else None,
-            "channels": g["n"],
+            "channels": g["n"], "steps": K, "fill_pushes": W,
             "form": "the largest group alone: FP32 samples, FP64 sums, per-step update of every "
                     "channel, one launch per group and push"}
 
