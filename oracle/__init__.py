@@ -60,6 +60,8 @@ def lib():
         L.oracle_trapezoid.restype = dbl
         L.oracle_rhok.argtypes = [vp, i64, vp, i32, dbl, vp, vp]
         L.oracle_rhok.restype = None
+        L.oracle_push_rows.argtypes = [vp, i64, vp, vp]
+        L.oracle_push_rows.restype = i32
         L.oracle_push_pair.argtypes = [vp, vp, vp, vp, vp]
         L.oracle_push_pair.restype = i32
         L.oracle_currents.argtypes = [vp, vp, i64, vp, i32, dbl, vp, vp]
@@ -127,9 +129,19 @@ class OracleCorrelator:
             raise RuntimeError("oracle_push_pair failed (a record is auto or pair from its first push)")
 
     def push_series(self, xs) -> None:
-        """xs: [S][n_ch] -- push S steps in order."""
-        for row in xs:
-            self.push(row)
+        """xs: [S][n_ch] -- push S steps in order (one C call)."""
+        xs = np.asarray(xs)
+        if xs.ndim != 2 or xs.shape[1] != self.n_ch:
+            raise ValueError(f"expected [S][{self.n_ch}] samples, got {xs.shape}")
+        if self.complex:
+            xc = xs.astype(np.complex128)
+            re, im = np.ascontiguousarray(xc.real), np.ascontiguousarray(xc.imag)
+        else:
+            if np.iscomplexobj(xs):
+                raise TypeError("complex samples pushed into a real correlator")
+            re, im = np.ascontiguousarray(xs, dtype=np.float64), None
+        if lib().oracle_push_rows(self._h, xs.shape[0], _ptr(re), _ptr(im)) != 0:
+            raise RuntimeError("oracle_push_rows failed")
 
     @property
     def n_push(self) -> int:

@@ -272,6 +272,20 @@ int oracle_push(oracle_corr *o, const double *x_re, const double *x_im)
     return 0;
 }
 
+/* n_rows consecutive pushes: row r is x_re + r * n_ch (and x_im likewise),
+ * exactly n_rows calls of oracle_push in order. */
+int oracle_push_rows(oracle_corr *o, int64_t n_rows, const double *x_re, const double *x_im)
+{
+    if (!o || n_rows < 0)
+        return -1;
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int rc = oracle_push(o, x_re + r * o->n_ch, x_im ? x_im + r * o->n_ch : NULL);
+        if (rc != 0)
+            return rc;
+    }
+    return 0;
+}
+
 int64_t oracle_n_push(const oracle_corr *o) { return o ? o->n_push : -1; }
 
 int oracle_max_out(const oracle_corr *o)

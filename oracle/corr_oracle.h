@@ -19,6 +19,8 @@ oracle_corr *oracle_create(int64_t n_ch, int levels, int points, int m, int is_c
 void oracle_destroy(oracle_corr *o);
 /* One sample per channel (x_im only for complex correlators). */
 int oracle_push(oracle_corr *o, const double *x_re, const double *x_im);
+/* n_rows pushes of rows [n_rows][n_ch] (x_im likewise for complex records). */
+int oracle_push_rows(oracle_corr *o, int64_t n_rows, const double *x_re, const double *x_im);
 int64_t oracle_n_push(const oracle_corr *o);
 /* Upper bound on the number of readout points: p + (b-1)(p - floor(p/m)). */
 int oracle_max_out(const oracle_corr *o);

@@ -40,7 +40,8 @@ def test_plain_3e6_channels_1e4_steps():
     gen = synth.GpuOU(spec)
     chunk = 250
     buf = torch.empty((chunk, n), dtype=torch.float32, device="cuda")
-    with Correlator([GroupDesc(n, b, p, m, dtype="f32", accum="f64")], per_group=True) as c:
+    with Correlator([GroupDesc(n, b, p, m, dtype="f32", accum="f64")], per_group=True,
+                    direct=True) as c:
         for s0 in range(0, S, chunk):
             gen.fill(buf, chunk)
             for j in range(chunk):
@@ -63,17 +64,20 @@ def test_plain_3e6_channels_1e4_steps():
         assert abs(full["c"][0] - 1.0) < 0.01   # unit-variance OU: C(0) ~ 1
 
 
-def test_batched_config_full_size_short_run():
+def test_batched_config_full_size():
     """The batched workload at full size (3x10^7 compensated-FP32 velocity
     channels, k-space density of 2048 k-vectors from 10^6 atoms, 9 FP64 global
-    channels) for 300 pushes, so that the first 44 of the 256 channel subsets
-    have folded a block; sampled velocity channels (in folded and unfolded
-    subsets) and k-vectors against the oracle."""
+    channels) for its 10^4 pushes in the forked issue order: readouts at 300
+    pushes (44 of the 256 channel subsets have folded a block; the k-space
+    density against the oracle's direct sums), at the block boundaries 2560
+    and 5120 and at 10^4 (every level of the 10-level group holds values);
+    velocity channels sampled from the first, middle and last fold subsets and
+    the last tile, and the global channels, against the oracle."""
     from paper_2503_07526_amd import Correlator, GroupDesc
-    S = 300
+    S_end = 10_000
     nv, N, box = 30_000_000, 1_000_000, 100.0
     kv = synth.kvectors(2048)
-    say(f"[full size batched] nv={nv} N={N} S={S}")
+    say(f"[full size batched] nv={nv} N={N} S={S_end}")
     vspec = synth.OUSpec.make(seed=3, stream=1, n=nv, comps=3, tau=20, tau_hi=200)
     gspec = synth.OUSpec.make(seed=3, stream=2, n=9, tau=100, dtype=np.float64)
     pspec = synth.PositionSpec(seed=3, stream=3, n_atoms=N, box=box, sigma_d=0.1, tau_d=50)
@@ -81,37 +85,71 @@ def test_batched_config_full_size_short_run():
               GroupDesc(2048, 16, 32, 2, dtype="cf32", accum="kahan", source="rhok", kvec=kv,
                         n_atoms=N, box=box),
               GroupDesc(9, 20, 16, 2, dtype="f64", accum="f64")]
+    chunk = 100
     gv, gg, gp = synth.GpuOU(vspec), synth.GpuOU(gspec), synth.GpuPositions(pspec)
-    bv = torch.empty((S, nv), dtype=torch.float32, device="cuda")
-    bg = torch.empty((S, 9), dtype=torch.float64, device="cuda")
-    bp = torch.empty((S, 3, N), dtype=torch.float32, device="cuda")
-    gv.fill(bv, S)
-    gg.fill(bg, S)
-    gp.fill(bp, S)
-    with Correlator(groups) as c:
-        for s in range(S):
-            c.push([bv[s], bp[s], bg[s]])
-        torch.cuda.synchronize()
-        say("  pushes done")
-        _check_channels(c, 0, vspec, [(0, 3), (nv - 3, nv)], S, 10, 16, 2,
-                        TOL[("f32", "kahan")], "velocity")
-        del bv
-        # k-space density: oracle n(k) of 2 k-vectors per step from the same positions
-        res = c.finalize(1, slice_=(0, 2))
-        xp, _ = pspec.series(0, S)
-        o = oracle.OracleCorrelator(2, 16, 32, 2, complex_=True)
-        for s in range(S):
-            o.push(oracle.rhok(xp[s], kv[:2], box))
-        for i in range(2):
-            t, cc, n = o.readout(i, i + 1)
-            assert np.array_equal(res["t"], t) and np.array_equal(res["count"], n)
-            err = np.max(np.abs(res["c_per_channel"][i] - cc / N)) / abs(cc[0] / N)
-            assert err <= TOL[("cf32", "kahan")], f"rho(k) k={i}: {err:.3e}"
-        rg = c.finalize(2)
-        xg = bg.cpu().numpy()
-        og = oracle.OracleCorrelator(9, 20, 16, 2)
-        for row in xg:
-            og.push(row)
+    bv = torch.empty((chunk, nv), dtype=torch.float32, device="cuda")
+    bg = torch.empty((chunk, 9), dtype=torch.float64, device="cuda")
+    bp = torch.empty((chunk, 3, N), dtype=torch.float32, device="cuda")
+    checks = (300, 2560, 5120, S_end)
+    results = {}
+    with Correlator(groups, tuning=dict(tile_channels=256, chans_per_thread=1, lag_chunk=8,
+                                        grid_blocks=2048, overlap_producers=1)) as c:
+        tw = c.tuning()["tile_channels"]
+        n_tiles = -(-nv // tw)
+        tpg = -(-n_tiles // 256)
+        ranges = [(0, 3), (128 * tpg * tw + 7, 128 * tpg * tw + 10),
+                  (255 * tpg * tw, 255 * tpg * tw + 2), (nv - 3, nv)]
+        done = 0
+        for S in checks:
+            while done < S:
+                n = min(chunk, S - done)
+                gv.fill(bv, n)
+                gg.fill(bg, n)
+                gp.fill(bp, n)
+                for j in range(n):
+                    c.push([bv[j], bp[j], bg[j]])
+                done += n
+            torch.cuda.synchronize()
+            say(f"  {S} pushes")
+            results[S] = ([c.finalize(0, slice_=r) for r in ranges], c.finalize(2, slice_=(0, 9)),
+                          c.finalize(1, slice_=(0, 2)) if S == 300 else None, c.finalize(0))
+    del bv, bp
+    torch.cuda.empty_cache()
+    chans = np.concatenate([np.arange(lo, hi) for lo, hi in ranges])
+    x, _ = vspec.series(0, S_end, channels=chans)
+    xg, _ = gspec.series(0, S_end)
+    ov = oracle.OracleCorrelator(len(chans), 10, 16, 2)
+    og = oracle.OracleCorrelator(9, 20, 16, 2)
+    done = 0
+    for S in checks:
+        ov.push_series(x[done:S])
+        og.push_series(xg[done:S])
+        done = S
+        per, rg, rk, full = results[S]
+        worst, i = 0.0, 0
+        for r, (lo, hi) in zip(per, ranges):
+            for j in range(hi - lo):
+                t, cc, n = ov.readout(i, i + 1)
+                assert np.array_equal(r["t"], t) and np.array_equal(r["count"], n)
+                worst = max(worst, float(np.max(np.abs(r["c_per_channel"][j] - cc)) / abs(cc[0])))
+                i += 1
+        assert worst <= TOL[("f32", "kahan")], (S, worst)
         t, cg, n = og.readout()
         assert np.array_equal(rg["t"], t) and np.array_equal(rg["count"], n)
-        assert np.max(np.abs(rg["c"] - cg)) / abs(cg[0]) <= TOL[("f64", "f64")]
+        eg = float(np.max(np.abs(rg["c"] - cg)) / abs(cg[0]))
+        assert eg <= TOL[("f64", "f64")], (S, eg)
+        t, _, n = ov.readout()
+        assert np.array_equal(full["t"], t) and np.array_equal(full["count"], n)
+        say(f"  S={S}: velocity channels {worst:.2e}, global {eg:.2e}, {len(t)} lags")
+        if rk is not None:
+            # k-space density: oracle n(k) of 2 k-vectors per step from the same positions
+            xp, _ = pspec.series(0, S)
+            o = oracle.OracleCorrelator(2, 16, 32, 2, complex_=True)
+            for s in range(S):
+                o.push(oracle.rhok(xp[s], kv[:2], box))
+            for q in range(2):
+                t, cc, n = o.readout(q, q + 1)
+                assert np.array_equal(rk["t"], t) and np.array_equal(rk["count"], n)
+                err = np.max(np.abs(rk["c_per_channel"][q] - cc / N)) / abs(cc[0] / N)
+                assert err <= TOL[("cf32", "kahan")], f"rho(k) k={q}: {err:.3e}"
+    assert len(results[S_end][3]["t"]) == 16 + 9 * 8  # every level has counts at 10^4

@@ -863,9 +863,10 @@ def test_pair_group_in_all_launch_modes(corrmod):
 def test_push_steps_equals_single_pushes(corrmod):
     """corr_push_steps replays a stored history: the same state, bit for bit,
     as one push per step -- for block-deferred, per-step, pair, k-density and
-    long-window groups in one context, across flush boundaries, with a readout
-    between two replays."""
-    S, nv, N, box = 200, 3000, 800, 25.0
+    long-window groups in one context, across flush boundaries (three whole
+    256-push blocks inside one replay), with a readout between two replays --
+    and both against the oracle fed the same series."""
+    S, nv, N, box = 900, 3000, 800, 25.0
     kv = synth.kvectors(24)
     xv = ou_inputs(51, 1, nv, S, "f32")
     xg = ou_inputs(51, 2, 9, S, "f64")
@@ -889,12 +890,26 @@ def test_push_steps_equals_single_pushes(corrmod):
         b.push_steps([h[77:] for h in hs])
         torch.cuda.synchronize()
         assert a.n_pushes() == b.n_pushes() == S
+        res = []
         for g in range(5):
             ra, rb = a.finalize(g, slice_=(0, 3)), b.finalize(g, slice_=(0, 3))
             assert np.array_equal(ra["c"], rb["c"]), g
             assert np.array_equal(ra["c_per_channel"], rb["c_per_channel"]), g
+            res.append(rb)
         assert len(mid[0]["t"]) > 0
         short = torch.zeros((2, 10), dtype=torch.float32, device=dev)  # rows below 3N floats
         with pytest.raises(corrmod.CorrError):
             b.push_steps([hs[0][:2], hs[1][:2], hs[2][:2], short, hs[4][:2]])
         assert b.n_pushes() == S  # rejected before anything was issued
+    # the replayed state against the oracle
+    gate(res[0], oracle_run(xv, 6, 16, 2), TOL[("f32", "kahan")], slice_=(0, 3), label="deferred")
+    gate(res[1], oracle_run(xg, 8, 16, 2), TOL[("f64", "f64")], slice_=(0, 3), label="FP64")
+    o = oracle.OracleCorrelator(300, 5, 16, 2)
+    for s in range(S):
+        o.push_pair(x[s], y[s])
+    gate(res[2], o, TOL[("f32", "kahan")], slice_=(0, 3), label="pair")
+    o = oracle.OracleCorrelator(len(kv), 4, 16, 2, complex_=True)
+    for s in range(S):
+        o.push(oracle.rhok(pos[s], kv, box))
+    gate(res[3], o, TOL[("cf32", "kahan")], scale=1.0 / N, slice_=(0, 3), label="n(k)")
+    gate(res[4], oracle_run(xw, 1, 640, 2), TOL[("cf32", "kahan")], slice_=(0, 3), label="window")
