@@ -66,7 +66,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy 8 times (reference for "
                          "the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--chunk", type=int, default=128, help="pushes per generated input chunk")
+    ap.add_argument("--chunk", type=int, default=None,
+                    help="pushes per generated input chunk (default 128; with --replay 256, one "
+                         "fold block)")
     ap.add_argument("--replay", action="store_true",
                     help="push each generated chunk with one corr_push_steps call (a stored "
                          "history replayed) instead of one corr_push per step")
@@ -76,6 +78,12 @@ def parse():
     ap.add_argument("--no-compare-plain", action="store_true",
                     help="skip the bounded leg that times the plain FP64 per-group form on the "
                          "largest sample-fed group (run by default)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time block-deferred workloads eagerly (one corr_push per step) instead "
+                         "of as captured HIP graphs per chunk of pushes")
+    ap.add_argument("--no-mode-leg", action="store_true",
+                    help="skip the leg that times the other issue form (eager beside a graph "
+                         "headline, graphs beside an eager one)")
     ap.add_argument("--plain-steps", type=int, default=64,
                     help="timed pushes of the plain-form leg (after %d fill pushes)" % 256)
     ap.add_argument("--tuning", default=None, help="JSON dict of corr_tuning fields")
@@ -278,37 +286,60 @@ AB = {("f32", "f64"): 8, ("f32", "kahan"): 8, ("f32", "f32"): 4, ("f64", "f64"):
       ("cf32", "f64"): 16, ("cf32", "kahan"): 16, ("cf32", "f32"): 8, ("cf64", "f64"): 16}
 
 
-DEFER_T = 256   # pushes per block of the block-deferred form
+DEFER_T = 256   # pushes per block of the block-deferred form (the library's default T)
 WINDOW_T = 64   # pushes per block of the block-deferred window
 
 
 def deferred(g, direct=False):
-    """Groups the library runs in the block-deferred form."""
+    """Groups the library runs in the block-deferred form (as it reports them
+    once the context exists: corr_group_form)."""
+    if "form" in g:
+        return g["form"] == 1
     return (not direct and g["kind"] == "ou" and g["dtype"] == "f32" and g["points"] == 16
             and g["m"] == 2)
 
 
-def flush_bytes(g, s):
-    """Algorithmic HBM bytes of the flush at push s (s a multiple of 256) for one
-    block-deferred group: level 0 reads the 256 new and 15 older ring values and
-    reads+writes its 16 accumulators; every level k that receives n_k > 0 new
-    values reads its 15 older ring values, writes min(n_k, 16) slots and
-    reads+writes its 8 accumulators."""
+def block_of(g):
+    return g.get("T", DEFER_T)
+
+
+def fold_bytes(g, s, level0_new):
+    """Algorithmic HBM bytes per channel of folding the block of T pushes that
+    ends at push s (s a multiple of T): level 0 moves level0_new bytes for the
+    T new values and reads+writes its 16 accumulators; every level k that
+    receives n_k > 0 new values reads its 15 older ring values, writes
+    min(n_k, 16) slots and reads+writes its 8 accumulators."""
     sb, ab = SB[g["dtype"]], AB[(g["dtype"], g["accum"])]
-    p, b, T = g["points"], g["levels"], DEFER_T
-    B = (p - 1 + T) * sb + 2 * p * ab
+    p, b, T = g["points"], g["levels"], block_of(g)
+    B = level0_new + 2 * p * ab
     for k in range(1, b):
         nk = s // 2 ** k - (s - T) // 2 ** k
         if nk <= 0:
             break
         B += (p - 1) * sb + min(nk, p) * sb + 2 * (p - p // 2) * ab
-    return B * g["n"]
+    return B
+
+
+def flush_bytes(g, s):
+    """Algorithmic HBM bytes of the flush at push s (s a multiple of T) for one
+    block-deferred group: level 0 reads the T new and 15 older values from the
+    ring (the staging wrote them there), then the levels as in fold_bytes."""
+    sb, p, T = SB[g["dtype"]], g["points"], block_of(g)
+    return fold_bytes(g, s, (p - 1 + T) * sb) * g["n"]
+
+
+def history_fold_bytes(g, s):
+    """The same block folded straight from a stored history (corr_push_steps):
+    level 0 reads the T new values from the history and the 15 older ones from
+    the ring, and writes the block's last 15 values to the ring."""
+    sb, p, T = SB[g["dtype"]], g["points"], block_of(g)
+    return fold_bytes(g, s, (T + 2 * (p - 1)) * sb) * g["n"]
 
 
 def group_channels(g, tw, j):
-    """Channels of tile group j (256 groups of contiguous tiles) of a block-deferred group."""
+    """Channels of tile group j (T groups of contiguous tiles) of a block-deferred group."""
     n_tiles = -(-g["n"] // tw)
-    tpg = -(-n_tiles // DEFER_T)
+    tpg = -(-n_tiles // block_of(g))
     t0, t1 = j * tpg, min((j + 1) * tpg, n_tiles)
     if t0 >= t1:
         return 0
@@ -316,12 +347,13 @@ def group_channels(g, tw, j):
 
 
 def staggered_flush_bytes(g, s, tw):
-    """Bytes of the flush issued with push s: tile group s mod 256 folds block
-    s // 256 (pushes (256 (q-1), 256 q])."""
-    j, q = s % DEFER_T, s // DEFER_T
+    """Bytes of the flush issued with push s: tile group s mod T folds block
+    s // T (pushes (T (q-1), T q])."""
+    T = block_of(g)
+    j, q = s % T, s // T
     if q < 1:
         return 0
-    per_channel = flush_bytes(dict(g, n=1), q * DEFER_T)
+    per_channel = flush_bytes(dict(g, n=1), q * T)
     return per_channel * group_channels(g, tw, j)
 
 
@@ -491,22 +523,14 @@ def cpu_baseline_momentum(wl):
 
 
 # -------------------------------------------------------------------- GPU leg
-def run(args):
+def make_inputs(wl, chunk, dev):
+    """Group descriptors, device input generators and chunk buffers ([chunk]
+    rows of one push's input each) of a workload."""
     import torch
 
     import synth
-    from paper_2503_07526_amd import Correlator, GroupDesc, autotune
-
-    wl = workload(args.config)
-    K = args.steps if args.steps is not None else wl["steps"]
-    W = args.warmup if args.warmup is not None else wl.get("warmup", 256)
-    mode = args.mode or ("per_group" if args.config == "plain" else "batched")
-    args.direct = args.direct or wl.get("direct", False)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(0)
-
+    from paper_2503_07526_amd import GroupDesc
     descs, gens, bufs = [], [], []
-    chunk = max(1, min(args.chunk, K))
     for g in wl["groups"]:
         if g.get("shares_positions"):
             # positions are the first [3][N] floats of the previous group's input
@@ -550,6 +574,28 @@ def run(args):
             gens.append(synth.GpuOU(spec))
             tdt = torch.float32 if real == np.float32 else torch.float64
             bufs.append(torch.empty((chunk, g["n"]), dtype=tdt, device=dev))
+    return descs, gens, bufs
+
+
+def run(args):
+    import torch
+
+    import synth
+    from paper_2503_07526_amd import Correlator, GroupDesc, autotune
+
+    wl = workload(args.config)
+    K = args.steps if args.steps is not None else wl["steps"]
+    W = args.warmup if args.warmup is not None else wl.get("warmup", 256)
+    mode = args.mode or ("per_group" if args.config == "plain" else "batched")
+    args.direct = args.direct or wl.get("direct", False)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(0)
+
+    if args.replay:
+        chunk = args.chunk or DEFER_T
+    else:
+        chunk = max(1, min(args.chunk or 128, K))
+    descs, gens, bufs = make_inputs(wl, chunk, dev)
     tuning = json.loads(args.tuning) if args.tuning else None
     tune_s = 0.0
     if tuning is None and not args.no_autotune:
@@ -559,10 +605,24 @@ def run(args):
         tune_s = time.perf_counter() - t0
     if args.overlap is not None:
         tuning = dict(tuning or {}, overlap_producers=args.overlap)
+    # Block-deferred workloads are timed as captured HIP graphs (one graph per
+    # chunk of pushes, corr_push_steps on a CORR_FLAG_GRAPH context), the
+    # eager form beside them; the others eagerly, one corr_push per step.
+    use_graph = (not args.eager and not args.replay and not args.direct and mode != "per_group"
+                 and any(deferred(g) for g in wl["groups"]))
     corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuning, timing=True,
-                      direct=args.direct, rhok_valu=args.rhok_valu)
+                      direct=args.direct, rhok_valu=args.rhok_valu, graph=use_graph)
     state_gb = sum(corr.state_bytes(i) for i in range(len(descs))) / 1e9
-    corr.set_timing_stride(args.timing_stride)
+    if not use_graph:
+        corr.set_timing_stride(args.timing_stride)
+    # the update form and fold block the library chose for each group
+    wl = dict(wl, groups=[dict(g) for g in wl["groups"]])
+    for i, g in enumerate(wl["groups"]):
+        g["form"], blk = corr.group_form(i)
+        if g["form"] == 1:
+            g["T"] = blk
+    if args.replay:
+        return run_replay(args, wl, corr, descs, gens, bufs, K, W, mode, state_gb, tune_s)
 
     def push_chunk(n):
         for gen, buf in zip(gens, bufs):
@@ -570,7 +630,7 @@ def run(args):
                 gen.fill(buf, n)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if args.replay:
+        if use_graph:
             corr.push_steps([buf[:n] for buf in bufs])
         else:
             for j in range(n):
@@ -579,17 +639,24 @@ def run(args):
         return time.perf_counter() - t0
 
     # Fill, then the declared warm-up.  A block-deferred group folds its first
-    # block at push 256, so at least one whole block is pushed before the
+    # block at push T (256), so at least one whole block is pushed before the
     # warm-up: the timed pushes then carry their scheduled folds whatever
-    # --warmup says (steady state).
+    # --warmup says (steady state).  In graph mode the fill also captures the
+    # graph of every chunk length the timed pushes use.
     direct = args.direct
-    fill = DEFER_T if any(deferred(g, direct) for g in wl["groups"]) else 0
+    fill = max([block_of(g) for g in wl["groups"] if deferred(g, direct)], default=0)
+    lead = [min(chunk, fill - d) for d in range(0, fill, chunk)]
+    if use_graph:
+        lead += [n for n in {chunk, K % chunk} if n and n not in lead]
+    fill = sum(lead)
+    for n in lead:
+        push_chunk(n)
     done = 0
-    while done < fill + W:
-        n = min(chunk, fill + W - done)
+    while done < W:
+        n = min(chunk, W - done)
         push_chunk(n)
         done += n
-    for which in (0, 1, 2, 3):
+    for which in (0, 1, 2, 3, 4):
         corr.kernel_time(which, reset=True)
     s_first = fill + W + 1
     wall = 0.0
@@ -598,55 +665,52 @@ def run(args):
         n = min(chunk, K - done)
         wall += push_chunk(n)
         done += n
-    kern_ms, kern_n = corr.kernel_time(0)
-    # the library times push s (1-based) when s - 1 is a multiple of the stride
     steps = range(s_first, s_first + K)
-    sampled = [s for s in steps if (s - 1) % args.timing_stride == 0]
-    assert kern_n == len(sampled), (kern_n, len(sampled))
-    # The timed launch: with k-density groups next to other groups, those run
-    # (producer + own push) on a forked side stream and the events bracket the
-    # push launch of the other groups only.
-    has_rhok = any(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
-    timed = [g for g in wl["groups"]
-             if not (has_rhok and len(wl["groups"]) > 1 and g["kind"] in PRODUCER_KINDS)]
-    # algorithmic bytes of the timed (sampled) pushes, to go with their event times
-    stage_bytes = sum(push_bytes(g, s, direct) for g in timed for s in sampled)
-    tw = corr.tuning()["tile_channels"]
-    fl_bytes = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
-                   for s in sampled)
-    fl_ms, fl_n = corr.kernel_time(which=1)
-    rk_ms, rk_n = corr.kernel_time(which=2)
-    # the fold kernels timed by their own device stamps on every timed push (no
-    # event between the kernels of a push, which would shift a forked producer
-    # against the fold); the sampled events above stay for comparison
-    fs_ms, fs_n = corr.kernel_time(which=3)
-    fl_bytes_all = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
-                       for s in steps)
     n_total = sum(g["n"] for g in wl["groups"])
     value = n_total * K / wall
+    tw = corr.tuning()["tile_channels"]
+    has_rhok = any(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
+    # the groups whose update the push events bracket (a forked producer
+    # branch runs beside them)
+    timed = [g for g in wl["groups"]
+             if not (has_rhok and len(wl["groups"]) > 1 and g["kind"] in PRODUCER_KINDS)]
+    # device stamps of every push: the folds (3) and the producers (4)
+    fs_ms, fs_n = corr.kernel_time(which=3)
+    ps_ms, ps_n = corr.kernel_time(which=4)
+    fl_bytes_all = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
+                       for s in steps)
+    # HIP events (eager pushes only): one push in timing_stride
+    kern_ms, kern_n = corr.kernel_time(0)
+    fl_ms, fl_n = corr.kernel_time(which=1)
+    rk_ms, rk_n = corr.kernel_time(which=2)
+    sampled = [s for s in steps if (s - 1) % args.timing_stride == 0]
+    if not use_graph:
+        assert kern_n == len(sampled), (kern_n, len(sampled))
+    stage_bytes = sum(push_bytes(g, s, direct) for g in timed for s in sampled)
+    fl_bytes = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
+                   for s in sampled)
     rhok_only = (all(g["kind"] in PRODUCER_KINDS for g in wl["groups"])
                  and wl.get("dominant") not in ("push", "producer"))
     producer_dominant = wl.get("dominant") == "producer"
     push_dominant = wl.get("dominant") == "push"
     momentum_dominant = wl.get("dominant") == "momentum"
+    flop_per = None
     if momentum_dominant:
         # the momentum density producers: per atom three velocity components
-        # and a one-byte species id, HIP events around the producer launches of
-        # a push
+        # and a one-byte species id; device stamps of every push's producers
         per_launch_bytes = sum(g["n_atoms"] * (3 * SB[g["dtype"]] + 1) for g in wl["groups"]
                                if g["kind"] == "momentum")
-        per_launch_ms = rk_ms / kern_n
+        per_launch_ms = ps_ms / ps_n
         achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-        kname = ("momentum density producer (HBM-bound reduction over the atoms), HIP events "
-                 "around its launches on its stream")
+        kname = ("momentum density producer (HBM-bound reduction over the atoms), device stamps "
+                 "of every push")
     elif producer_dominant:
-        # the producers of every k-space group, per push (HIP events on their
-        # stream; several producer launches per push)
+        # the producers of every k-space group, per push
         flop_per = sum(producer_flop(g) for g in wl["groups"] if g["kind"] in PRODUCER_KINDS)
-        per_launch_ms = rk_ms / kern_n
+        per_launch_ms = ps_ms / ps_n
         achieved = flop_per / (per_launch_ms * 1e-3) / 1e12
-        kname = ("k-space producers (matrix cores), HIP events around the %d producer launches of "
-                 "a push" % (rk_n // kern_n))
+        kname = ("k-space producers (matrix cores), device stamps spanning the producer launches "
+                 "of every push")
         per_launch_bytes = None
     elif push_dominant:
         # the per-step correlator update of every group (direct form): the
@@ -661,13 +725,13 @@ def run(args):
         g0 = wl["groups"][0]
         if g0["kind"] == "currents":
             flop_per = CURRENTS_FLOP_PER_ATOM_K * (g0["n"] // 3) * g0["n_atoms"]
-            kname = "current producer (matrix cores), HIP events per launch on its stream"
+            kname = "current producer (matrix cores), device stamps of every launch"
         else:
             flop_per = RHOK_FLOP_PER_ATOM_K * g0["n"] * g0["n_atoms"]
-            kname = ("k-density producer (%s), HIP events per launch on its stream"
+            kname = ("k-density producer (%s), device stamps of every launch"
                      % ("vector units" if args.rhok_valu else "matrix cores"))
-        achieved = flop_per / (rk_ms / rk_n * 1e-3) / 1e12
-        per_launch_ms, per_launch_bytes = rk_ms / rk_n, None
+        achieved = flop_per / (ps_ms / ps_n * 1e-3) / 1e12
+        per_launch_ms, per_launch_bytes = ps_ms / ps_n, None
     elif fs_n:
         # dominant kernel: the flush of the block-deferred groups, every timed push
         assert fs_n == K, (fs_n, K)
@@ -676,15 +740,15 @@ def run(args):
                                "block-deferred line would not measure its dominant kernel"
                                % (s_first, s_first + K - 1))
         achieved = fl_bytes_all / (fs_ms * 1e-3) / 1e9
-        kname = ("flush kernel (block-deferred fold of 256 pushes for 1/256 of the channels per "
-                 "push), device stamps of every launch")
+        T0 = max(block_of(g) for g in timed if deferred(g, direct))
+        kname = ("flush kernel (block-deferred fold of %d pushes for 1/%d of the channels per "
+                 "push), device stamps of every launch" % (T0, T0))
         per_launch_ms, per_launch_bytes = fs_ms / fs_n, fl_bytes_all / fs_n
     else:
         achieved = (stage_bytes + fl_bytes) / (kern_ms * 1e-3) / 1e9
         kname = ("push kernel (correlator update of %d of %d groups), HIP events per launch"
                  % (len(timed), len(wl["groups"])))
         per_launch_ms, per_launch_bytes = kern_ms / kern_n, (stage_bytes + fl_bytes) / kern_n
-    update_gbs = (stage_bytes + fl_bytes) / (kern_ms * 1e-3) / 1e9
     out = {
         "metric": "channel-samples/sec into correlators",
         "value": value,
@@ -707,7 +771,10 @@ def run(args):
                                      "matrix cores (fp16 hi/lo operand split: about 22 "
                                      "significant bits per product; fp32 tile sums added in "
                                      "fp64)"),
-                   "push_calls": "one corr_push_steps per chunk" if args.replay else "one corr_push per step",
+                   "push_calls": ("one captured HIP graph per chunk of %d pushes (corr_push_steps "
+                                  "with CORR_FLAG_GRAPH)" % chunk if use_graph
+                                  else "one corr_push per step"),
+                   "fold_block": {str(i): g["T"] for i, g in enumerate(wl["groups"]) if "T" in g},
                    "producer_stream": {0: "the context's stream, before the other updates",
                                        1: "forked at the start of the push (with the per-step "
                                           "updates when block-deferred groups flush beside them)",
@@ -717,12 +784,14 @@ def run(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
                      "kernel_ms_per_launch": per_launch_ms,
-                     "alg_bytes_per_launch": per_launch_bytes,
-                     "update_kernels_GBs": update_gbs,
-                     "update_ms_per_step": kern_ms / kern_n,
-                     "alg_bytes_per_step": (stage_bytes + fl_bytes) / kern_n,
-                     "timed_pushes": kern_n, "timing_stride": args.timing_stride},
+                     "alg_bytes_per_launch": per_launch_bytes},
     }
+    r = out["roofline"]
+    if kern_n:
+        r.update({"update_kernels_GBs": (stage_bytes + fl_bytes) / (kern_ms * 1e-3) / 1e9,
+                  "update_ms_per_step": kern_ms / kern_n,
+                  "alg_bytes_per_step": (stage_bytes + fl_bytes) / kern_n,
+                  "timed_pushes": kern_n, "timing_stride": args.timing_stride})
     if fs_n:
         # context for the byte model of the per-step form (Algorithm 1 push by
         # push): its algorithmic bytes for the same pushes of the same groups,
@@ -736,24 +805,26 @@ def run(args):
                     "traffic)",
             "bytes_per_push": eq, "GBs": eq_gbs, "x_peak": eq_gbs / HBM_PEAK_GBS}
     if fs_n and fl_n:
-        out["roofline"]["kernel_ms_per_launch_events"] = fl_ms / fl_n
-        out["roofline"]["events_note"] = ("HIP events on the timed pushes (one in %d); they "
-                                          "separate the push's kernels" % args.timing_stride)
-    if rk_n:
-        out["roofline"]["producer_ms_per_launch"] = rk_ms / rk_n
+        r["kernel_ms_per_launch_events"] = fl_ms / fl_n
+        r["events_note"] = ("HIP events on the timed pushes (one in %d); they separate the "
+                            "push's kernels" % args.timing_stride)
+    if ps_n:
+        r["producer_ms_per_push"] = ps_ms / ps_n
         if not (rhok_only or producer_dominant or momentum_dominant):
             # the producers beside the dominant kernel (forked, they may be the
             # longer branch of the step)
             pf = sum(producer_flop(g) for g in wl["groups"] if g["kind"] in PRODUCER_KINDS)
-            pms = rk_ms / kern_n
+            pms = ps_ms / ps_n
             out["producers"] = {
                 "ms_per_push": pms, "alg_flop_per_push": pf,
                 "TFLOPs": pf / (pms * 1e-3) / 1e12,
                 "frac_of_fp16_matrix_peak": pf / (pms * 1e-3) / 1e12 / MFMA_F16_PEAK_TFS,
+                "timing": "device stamps from the first producer block's start to the end of "
+                          "its final reduction, every push",
                 "stream": "forked beside the other updates"
                           if corr.tuning()["overlap_producers"] == 1 else "the context's stream"}
     wins = [g for g in wl["groups"] if window_deferred(g, direct)]
-    if wins and len(wins) == len(wl["groups"]):
+    if wins and len(wins) == len(wl["groups"]) and kern_n:
         # the correlator update of the block-deferred windows: the push events
         # less the producer launches they contain
         wb = sum(window_push_cost(g)[0] for g in wins)
@@ -766,7 +837,6 @@ def run(args):
             "TFLOPs": wf / (wms * 1e-3) / 1e12,
             "alu_frac": wf / (wms * 1e-3) / 1e12 / VALU_F32_PEAK_TFS}
     if rhok_only or producer_dominant:
-        r = out["roofline"]
         bound, peak = ("alu", VALU_F32_PEAK_TFS) if args.rhok_valu else ("mfma", MFMA_F16_PEAK_TFS)
         r.update({"bound": bound, "unit": "TFLOP/s", "peak": peak, "frac": achieved / peak,
                   "alg_flop_per_launch": flop_per})
@@ -776,8 +846,8 @@ def run(args):
         rec = traffic_record(args.config)
         if rec is not None:
             tb = float(rec["read_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
-            out["roofline"]["traffic"] = tb
-            out["roofline"]["traffic_detail"] = {
+            r["traffic"] = tb
+            r["traffic_detail"] = {
                 "hbm_bytes_per_launch": tb,
                 "alg_bytes_per_launch_same_pushes": float(rec["alg_bytes_per_launch"]),
                 "ratio": tb / float(rec["alg_bytes_per_launch"]),
@@ -787,20 +857,20 @@ def run(args):
         out["error_vs_fp64"] = spot_check(corr, wl, fill + W + K)
     tuned = corr.tuning()
     corr.close()
-    if fs_n and tuned["overlap_producers"] != 0 and not args.replay:
+    if fs_n and tuned["overlap_producers"] != 0:
         # the same flush kernel with nothing beside it: a short second context
         # with every push on one stream, timed by the same device stamps
         t0n = dict(tuned, overlap_producers=0)
         c0 = Correlator(descs, per_group=(mode == "per_group"), tuning=t0n, timing=True,
                         direct=args.direct, rhok_valu=args.rhok_valu)
-        c0.set_timing_stride(args.timing_stride)
         n_alone = 256
-        for lead in (DEFER_T, n_alone):  # one block to fill the rings, then the timed pushes
-            if lead == n_alone:
+        T0 = max(block_of(g) for g in timed if deferred(g, direct))
+        for lead_n in (T0, n_alone):  # one block to fill the rings, then the timed pushes
+            if lead_n == n_alone:
                 c0.kernel_time(3, reset=True)
             done = 0
-            while done < lead:
-                n = min(chunk, lead - done)
+            while done < lead_n:
+                n = min(chunk, lead_n - done)
                 for gen, buf in zip(gens, bufs):
                     if gen is not None:
                         gen.fill(buf, n)
@@ -811,18 +881,130 @@ def run(args):
         a_ms, a_n = c0.kernel_time(3)
         c0.close()
         a_bytes = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
-                      for s in range(DEFER_T + 1, DEFER_T + n_alone + 1))
+                      for s in range(T0 + 1, T0 + n_alone + 1))
         if a_n:
             a_gbs = a_bytes / (a_ms * 1e-3) / 1e9
-            out["roofline"]["alone"] = {
+            r["alone"] = {
                 "note": "the same flush kernel with every push on one stream (nothing beside "
                         "it), %d pushes after one block, device stamps" % n_alone,
                 "kernel_ms_per_launch": a_ms / a_n, "achieved": a_gbs,
                 "frac": a_gbs / HBM_PEAK_GBS}
+    if use_graph and not args.no_mode_leg:
+        out["eager"] = mode_leg(args, wl, descs, gens, bufs, tuned, mode, chunk, False, value)
+    elif fs_n and not args.no_mode_leg and mode != "per_group":
+        out["graph"] = mode_leg(args, wl, descs, gens, bufs, tuned, mode, chunk, True, value)
     big = max(wl["groups"], key=lambda x: x["n"])
     if not args.no_compare_plain and big["kind"] == "ou" and big["dtype"] == "f32":
         out["plain_form"] = compare_plain(wl, args.plain_steps, chunk, args.timing_stride)
         out["plain_form"]["speedup_of_this_form"] = value / out["plain_form"]["value"]
+    return out, wl
+
+
+def mode_leg(args, wl, descs, gens, bufs, tuned, mode, chunk, graph, headline_value):
+    """The same workload in the other issue form, timed like the headline
+    beside it: graph=True replays every chunk of pushes as one captured HIP
+    graph (corr_push_steps with CORR_FLAG_GRAPH), graph=False issues one
+    corr_push per step (eager)."""
+    import torch
+
+    from paper_2503_07526_amd import Correlator
+    n_total = sum(g["n"] for g in wl["groups"])
+    corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuned, graph=graph,
+                      direct=args.direct, rhok_valu=args.rhok_valu)
+    T0 = max([block_of(g) for g in wl["groups"] if deferred(g, args.direct)], default=0)
+
+    def chunk_run(n):
+        for gen, buf in zip(gens, bufs):
+            if gen is not None:
+                gen.fill(buf, n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if graph:
+            corr.push_steps([buf[:n] for buf in bufs])
+        else:
+            for j in range(n):
+                corr.push([buf[j] for buf in bufs])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    lead = [min(chunk, T0 - d) for d in range(0, T0, chunk)] + [chunk]
+    for n in lead:  # one fold block, then a chunk (which captures the timed graph)
+        chunk_run(n)
+    steps = max(256, chunk) // chunk * chunk
+    wall = sum(chunk_run(chunk) for _ in range(steps // chunk))
+    corr.close()
+    v = n_total * steps / wall
+    return {"note": ("the same pushes as one captured HIP graph per chunk of %d (corr_push_steps "
+                     "with CORR_FLAG_GRAPH)" % chunk) if graph else
+                    "the same pushes issued eagerly, one corr_push per step",
+            "fill_pushes": sum(lead), "steps": steps, "ms_per_step": wall / steps * 1e3,
+            "value": v, "ratio_to_headline": v / headline_value}
+
+
+def run_replay(args, wl, corr, descs, gens, bufs, K, W, mode, state_gb, tune_s):
+    """Replay of stored histories (corr_push_steps without a graph): every
+    chunk of pushes is handed over at once, block-aligned, so the
+    block-deferred groups fold each whole block straight from the history; the
+    other groups are pushed row by row.  The dominant kernel is that history
+    fold, timed by its own device stamps."""
+    import torch
+    chunk = bufs[0].shape[0]
+    Ts = [block_of(g) for g in wl["groups"] if deferred(g, args.direct)]
+    T = max(Ts, default=DEFER_T)
+    if chunk % T:
+        raise SystemExit(f"--replay needs --chunk a multiple of the fold block ({T})")
+    W = -(-W // T) * T          # block-aligned warm-up
+    K = max(chunk, -(-K // chunk) * chunk)
+    n_total = sum(g["n"] for g in wl["groups"])
+
+    def chunk_run(n):
+        for gen, buf in zip(gens, bufs):
+            if gen is not None:
+                gen.fill(buf, n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        corr.push_steps([buf[:n] for buf in bufs])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    done = 0
+    while done < W:
+        n = min(chunk, W - done)
+        chunk_run(n)
+        done += n
+    corr.kernel_time(3, reset=True)
+    wall = sum(chunk_run(chunk) for _ in range(K // chunk))
+    fs_ms, fs_n = corr.kernel_time(3)
+    blocks = [s for s in range(W + T, W + K + 1, T)]
+    fold_b = sum(history_fold_bytes(g, s) for g in wl["groups"] if deferred(g, args.direct)
+                 for s in blocks)
+    achieved = fold_b / (fs_ms * 1e-3) / 1e9 if fs_n else 0.0
+    value = n_total * K / wall
+    out = {
+        "metric": "channel-samples/sec into correlators (replay of stored histories)",
+        "value": value, "unit": "channel-samples/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+kahan" if any(g["accum"] == "kahan" for g in wl["groups"]) else "f32+f64",
+        "data": "synthetic (seeded OU series and atom positions generated in HBM before each "
+                "timed chunk)",
+        "config": {"workload": wl["name"], "channels": n_total, "launch": mode,
+                   "push_calls": "one corr_push_steps per chunk of %d stored pushes" % chunk,
+                   "fold_block": T, "tuning": corr.tuning(), "state_GB": round(state_gb, 2),
+                   "autotune_s": round(tune_s, 2)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "history fold (a whole block of %d pushes of every channel read "
+                               "straight from the stored history), device stamps" % T,
+                     "kernel_ms_per_launch": fs_ms / fs_n if fs_n else None,
+                     "alg_bytes_per_launch": fold_b / max(fs_n, 1),
+                     "alg_bytes_per_channel_step": fold_b / max(len(blocks), 1) / T /
+                     sum(g["n"] for g in wl["groups"] if deferred(g, args.direct)),
+                     "launches": fs_n},
+    }
+    if max(wl["groups"], key=lambda x: x["n"])["kind"] == "ou":
+        out["error_vs_fp64"] = spot_check(corr, wl, W + K)
+    corr.close()
     return out, wl
 
 

@@ -188,6 +188,13 @@ typedef struct corr_tuning {
                                   per-step updates on a forked stream,
                                   concurrently with the flush of the
                                   block-deferred groups                        */
+    int32_t fold_block;        /* pushes per fold block T of block-deferred
+                                  groups: 256 or 128; 0 = 256, or 128 when the
+                                  state of 256 would not fit in the device's
+                                  free memory (and the per-step form when
+                                  neither fits)                                 */
+    int32_t fold_threads;      /* threads per block of the scheduled fold
+                                  kernel: 64, 128 or 256 (0 = 128)              */
 } corr_tuning;
 
 /*
@@ -230,17 +237,34 @@ int corr_bind_input(corr_ctx *ctx, int32_t group, void *dev_ptr, size_t bytes);
 int corr_push(corr_ctx *ctx, const void *const *samples);
 
 /* Replay of a stored history (the paper's comparison of on-the-fly analysis
- * with replaying saved trajectories, Section "Benchmarks and Trade-offs"): n_steps
- * consecutive pushes in one call.  samples[g] is group g's device history; row r (the input of push r)
- * starts at samples[g] + r * strides[g] bytes (strides NULL: rows packed,
- * stride = the group's per-push input size, see corr_input_buffer).  Exactly
- * equivalent to n_steps corr_push calls with those pointers, in order (same
- * kernels, same results bit for bit); a captured graph is not used.  Every
- * group needs a history (CORR_E_INVALID otherwise, or for a stride below the
- * push size).  Work is issued on the context's stream; the rows must stay
- * valid until it has run. */
+ * with replaying saved trajectories, Section "Benchmarks and Trade-offs"):
+ * n_steps consecutive pushes in one call.  samples[g] is group g's device
+ * history; row r (the input of push r) starts at samples[g] + r * strides[g]
+ * bytes (strides NULL: rows packed, stride = the group's per-push input size,
+ * see corr_input_buffer).  Equivalent to n_steps corr_push calls with those
+ * pointers, in order, with the same results bit for bit.  Every group needs a
+ * history (CORR_E_INVALID otherwise, or for a stride below the push size).
+ * Work is issued on the context's stream; the rows must stay valid until it
+ * has run.
+ *  - Without CORR_FLAG_GRAPH, the block-deferred groups fold every whole
+ *    block of T pushes that the history holds (after the pushes up to the
+ *    next block boundary, which are single pushes) in one pass per block,
+ *    reading the block's samples from the history instead of staging them
+ *    (the fold's products, block means and sums are the same); the other
+ *    groups are pushed row by row.
+ *  - With CORR_FLAG_GRAPH, the n_steps single pushes are captured once as a
+ *    graph and replayed; the few most recent (histories, strides, n_steps)
+ *    keep their graphs, so repeated replays of the same buffers launch once.
+ *    No timing events are recorded in these replays (the fold kernels' device
+ *    stamps are kept). */
 int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
                     const int64_t *strides);
+
+/* The update form of a group (chosen at corr_create): *form = 0 per-step
+ * form (Algorithm 1 push by push), 1 block-deferred form, 2 block-deferred
+ * one-level window, 3 per-step one-level window; *block = pushes per fold
+ * block (T for form 1, 64 for form 2, else 0).  Either pointer may be NULL. */
+int corr_group_form(const corr_ctx *ctx, int32_t group, int32_t *form, int32_t *block);
 
 /* Number of pushes so far and the maximum number of readout points of a
  * group, p + (b - 1)(p - floor(p/m)) (Algorithm 2). */
@@ -327,9 +351,12 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
  * launches.  which = 3: the scheduled fold kernels of block-deferred groups
  * timed by the kernels themselves on every push (the earliest block start to
  * the latest block end, device wall clock), so that no event sits between
- * the kernels of a push; *n = pushes with a fold launch.  In graph mode the
- * which = 0 events bracket the whole graph replay and the which = 3 stamps
- * are kept; no other times are recorded.  reset != 0 clears the counters of
+ * the kernels of a push; *n = pushes with a fold launch.  which = 4: the
+ * producers of a push timed the same way (first block start of the producer
+ * kernel to the last end of its final reduction; several producer groups in
+ * one span); *n = pushes with a producer.  In graph mode the which = 0
+ * events bracket the whole graph replay and the which = 3 and 4 stamps are
+ * kept; no other times are recorded.  reset != 0 clears the counters of
  * `which` after reading.  CORR_E_STATE without the flag.
  *
  * Block-deferred form: for groups of single-precision samples with p = 16 and

@@ -48,7 +48,8 @@ class _GroupDesc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_channels", ctypes.c_int32), ("chans_per_thread", ctypes.c_int32),
                 ("lag_chunk", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("overlap_producers", ctypes.c_int32)]
+                ("overlap_producers", ctypes.c_int32), ("fold_block", ctypes.c_int32),
+                ("fold_threads", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -65,7 +66,7 @@ class _ReadoutOpts(ctypes.Structure):
 EXPORTS = ["corr_create", "corr_input_buffer", "corr_bind_input", "corr_push", "corr_push_steps",
            "corr_query", "corr_finalize", "corr_finalize_noalloc", "corr_sync", "corr_destroy",
            "corr_last_error", "corr_state_bytes", "corr_get_tuning", "corr_kernel_time",
-           "corr_set_timing_stride", "corr_autotune"]
+           "corr_set_timing_stride", "corr_autotune", "corr_group_form"]
 
 _lib = None
 
@@ -97,6 +98,7 @@ def lib():
         L.corr_kernel_time.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i64), i32]
         L.corr_set_timing_stride.argtypes = [vp, i32]
+        L.corr_group_form.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.corr_autotune.argtypes = [ctypes.POINTER(_GroupDesc), i32, i32, vp, ctypes.c_uint32,
                                     ctypes.c_char_p, i64, i32, ctypes.POINTER(Tuning)]
         for name in EXPORTS:
@@ -292,6 +294,14 @@ class Correlator:
     def set_timing_stride(self, stride: int) -> None:
         """Record the timing events on one push in `stride` only."""
         self._check(lib().corr_set_timing_stride(self._h, int(stride)))
+
+    def group_form(self, g: int):
+        """(form, block): 0 per-step, 1 block-deferred (block = T pushes), 2
+        block-deferred window (block 64), 3 per-step window."""
+        f = ctypes.c_int32()
+        b = ctypes.c_int32()
+        self._check(lib().corr_group_form(self._h, g, ctypes.byref(f), ctypes.byref(b)))
+        return int(f.value), int(b.value)
 
     def tuning(self) -> dict:
         t = Tuning()

@@ -1,12 +1,13 @@
 // corr_autotune.cpp -- launch-shape autotuner with a persistent cache.
 //
 // The launch shape (tile width, channels per thread, lag batch, persistent
-// grid size) changes neither results nor state semantics, only speed, and the
-// best choice depends on the mix of groups.  corr_autotune times trial
-// contexts over whole flush periods for a fixed list of candidates and caches
-// the winner per (device architecture, flags, group descriptors) in a text
-// file of JSON lines; corr_create consults the cache when the caller passes no
-// tuning.
+// grid size, issue order, the fold kernel's block length and threads per
+// block) changes neither results beyond rounding nor state semantics, only
+// speed, and the best choice depends on the mix of groups.  corr_autotune
+// times trial contexts over whole flush periods for a fixed list of
+// candidates and caches the winner per (device architecture, flags, group
+// descriptors) in a text file of JSON lines; corr_create consults the cache
+// when the caller passes no tuning.
 #include <hip/hip_runtime.h>
 
 #include <sys/stat.h>
@@ -83,6 +84,8 @@ bool tune_cache_lookup(const std::string &path, const std::string &key, corr_tun
             parse_int(line, "lag_chunk", &c.lag_chunk) &&
             parse_int(line, "grid_blocks", &c.grid_blocks)) {
             if (!parse_int(line, "overlap_producers", &c.overlap_producers)) c.overlap_producers = 0;
+            if (!parse_int(line, "fold_block", &c.fold_block)) c.fold_block = 0;
+            if (!parse_int(line, "fold_threads", &c.fold_threads)) c.fold_threads = 0;
             t = c; // the last entry for a key wins
             found = true;
         }
@@ -100,6 +103,7 @@ static void tune_cache_store(const std::string &path, const std::string &key, co
     f << "{\"key\":\"" << key << "\",\"tile_channels\":" << t.tile_channels
       << ",\"chans_per_thread\":" << t.chans_per_thread << ",\"lag_chunk\":" << t.lag_chunk
       << ",\"grid_blocks\":" << t.grid_blocks << ",\"overlap_producers\":" << t.overlap_producers
+      << ",\"fold_block\":" << t.fold_block << ",\"fold_threads\":" << t.fold_threads
       << ",\"ms_per_push\":" << ms_per_push << "}\n";
 }
 
@@ -173,22 +177,27 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
     // by one factor (groups up to kOrderTrialChannels channels run at full
     // size).  The trial timing covers every stream (the events bracket whole
     // pushes).
-    bool producer = false, sampled = false;
+    bool producer = false, sampled = false, folded = false;
     int64_t n_max = 0;
     for (int i = 0; i < n_groups; ++i) {
         (groups[i].source == CORR_SRC_SAMPLES ? sampled : producer) = true;
         if (groups[i].source == CORR_SRC_SAMPLES) n_max = std::max<int64_t>(n_max, groups[i].n_channels);
+        // groups the library folds in blocks (single-precision real samples,
+        // p = 16, m = 2, not pairs)
+        if (!(flags & CORR_FLAG_DIRECT) && groups[i].source == CORR_SRC_SAMPLES && !groups[i].pair &&
+            groups[i].dtype == CORR_F32 && groups[i].points == 16 && groups[i].m == 2)
+            folded = true;
+    }
+    const double scale = n_max > kOrderTrialChannels ? (double)kOrderTrialChannels / (double)n_max : 1.0;
+    std::vector<corr_group_desc> order(groups, groups + n_groups);
+    for (auto &g : order) {
+        if (g.source != CORR_SRC_SAMPLES)
+            g.n_atoms = std::max<int64_t>(std::min<int64_t>(g.n_atoms, 1024),
+                                          (int64_t)(scale * (double)g.n_atoms));
+        else
+            g.n_channels = std::max<int64_t>(1, (int64_t)(scale * (double)g.n_channels));
     }
     if (best < 1e300 && n_groups >= 2) {
-        const double scale = n_max > kOrderTrialChannels ? (double)kOrderTrialChannels / (double)n_max : 1.0;
-        std::vector<corr_group_desc> order(groups, groups + n_groups);
-        for (auto &g : order) {
-            if (g.source != CORR_SRC_SAMPLES)
-                g.n_atoms = std::max<int64_t>(std::min<int64_t>(g.n_atoms, 1024),
-                                              (int64_t)(scale * (double)g.n_atoms));
-            else
-                g.n_channels = std::max<int64_t>(1, (int64_t)(scale * (double)g.n_channels));
-        }
         double best_o = 1e300;
         corr_tuning best_o_t = best_t;
         for (int mode = 0; mode <= 2; ++mode) {
@@ -202,6 +211,47 @@ extern "C" int corr_autotune(const corr_group_desc *groups, int32_t n_groups, in
             }
         }
         if (best_o < 1e300) best_t = best_o_t;
+    }
+    // Then the fold kernel of the block-deferred groups, in the chosen issue
+    // order: threads per block, and the shorter block (more bytes per push, a
+    // smaller ring).  How the fold shares the chip with what that order runs
+    // beside it does not scale down with the channel count (on scaled trials
+    // 64-thread folds won and were slower at full size), so these trials run
+    // the groups at full size when that fits, else on the balanced trials;
+    // another shape replaces the default (256-push blocks, 128 threads) only
+    // when it is at least 2% faster.
+    if (best < 1e300 && folded) {
+        static const int32_t fold_shapes[][2] = {{256, 128}, {256, 64}, {256, 256},
+                                                 {128, 128}, {128, 64}, {128, 256}};
+        std::vector<corr_group_desc> full(groups, groups + n_groups);
+        double best_f = 1e300, base_f = -1.0;
+        corr_tuning best_f_t = best_t;
+        const std::vector<corr_group_desc> *fdescs = &full;
+        for (const auto &fs : fold_shapes) {
+            corr_tuning ft = best_t;
+            ft.fold_block = fs[0];
+            ft.fold_threads = fs[1];
+            double ms = trial_ms_on(*fdescs, ft);
+            if (ms < 0.0 && fdescs == &full && base_f < 0.0) { // full size does not fit
+                fdescs = &order;
+                ms = trial_ms_on(*fdescs, ft);
+            }
+            if (fs[0] == kDeferT && fs[1] == kFoldThreadsDefault) base_f = ms;
+            if (ms >= 0.0 && ms < best_f) {
+                best_f = ms;
+                best_f_t = ft;
+            }
+        }
+        if (best_f < 1e300) {
+            if (base_f >= 0.0 && best_f > 0.98 * base_f) {
+                best_f_t.fold_block = kDeferT;
+                best_f_t.fold_threads = kFoldThreadsDefault;
+            }
+            // the block length only when the full-size state fits with it
+            // (corr_create falls back to the shorter block by itself)
+            if (best_f_t.fold_block == kDeferT) best_f_t.fold_block = 0;
+            best_t = best_f_t;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -32,11 +32,18 @@
 // over chunks in a fixed order (the group mean does not depend on the tile
 // width).
 //
-// Supported here: single-precision real samples, m = 2, p = 16, T = kDeferT
-// (256).  Levels 0 and 1 are folded together, streamed through chunks of 64
-// pushes (levels01); from level 2 on the cascade takes the T / 4 level-2
-// values at once.  Levels k <= 8 receive T / 2^k new values per flush
-// (compile-time counts); deeper levels receive at most one.
+// Replay of a stored history: when whole blocks of pushes are given at once,
+// every tile group folds a block in one pass with the level-0 values of the
+// block read straight from the caller's history (no staging write and read);
+// only the block's last p - 1 values are written to the ring, the ones later
+// folds and readouts look back to.  The products, block means and sums are
+// those of the staged fold, in the same order.
+//
+// Supported here: single-precision real samples, m = 2, p = 16, T = 256 or
+// 128 (the group's defer_t).  Levels 0 and 1 are folded together, streamed
+// through chunks of 64 pushes (levels01); from level 2 on the cascade takes
+// the T / 4 level-2 values at once.  Levels k <= log2 T receive T / 2^k new
+// values per flush (compile-time counts); deeper levels receive at most one.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
@@ -86,7 +93,7 @@ __device__ __forceinline__ double wave_sum(double v)
 
 struct Ctx {
     const DeferredArgs *a;
-    int64_t f;       // pushes already folded (multiple of kDeferT)
+    int64_t f;       // pushes already folded (multiple of T)
     int r;           // pushes folded by this pass
     char *tb;        // tile base
     int lane;        // channel within the tile
@@ -190,10 +197,6 @@ __device__ __forceinline__ void fold_level(Ctx &cx, int k, const typename RK<K>:
 // taken in chunks of kL0Chunk with a sliding window of the P - 1 values
 // before each chunk, so that only P - 1 + kL0Chunk ring values are live.
 constexpr int kL0Chunk = 64;
-// Threads per block of the fold kernels (at most): a tile wider than this is
-// split over several blocks, so that a flush of 1/kFlushGroups of the
-// channels still spreads over every CU (and the per-block LDS stays small).
-constexpr int kFoldThreads = 128;
 
 template <int K, int P, int T, bool READ>
 __device__ __forceinline__ void level0(Ctx &cx, typename RK<K>::S (&out)[T / 2])
@@ -257,7 +260,7 @@ __device__ __forceinline__ void level0(Ctx &cx, typename RK<K>::S (&out)[T / 2])
 // (in registers they would crowd out the windows).  Only the last P level-1
 // values of the block are written to the level-1 ring (the earlier ones would
 // be overwritten).
-template <int K, int P, int T, bool READ>
+template <int K, int P, int T, bool READ, bool HIST>
 __device__ __forceinline__ void levels01(Ctx &cx, typename RK<K>::S *out)
 {
     using S = typename RK<K>::S;
@@ -284,6 +287,15 @@ __device__ __forceinline__ void levels01(Ctx &cx, typename RK<K>::S *out)
         if (slot >= P0) slot -= P0;
         return __builtin_nontemporal_load(&ring0[(size_t)slot * tw + cx.lane]);
     };
+    // value i (0-based) of the block: staged in the ring, or from the history
+    auto newval = [&](int i) -> S {
+        if constexpr (HIST) {
+            const S *row = reinterpret_cast<const S *>(a.hist + (int64_t)i * a.hist_stride);
+            return cx.valid ? __builtin_nontemporal_load(&row[cx.ch]) : S(0);
+        } else {
+            return row0(P - 1 + i);
+        }
+    };
     S W0[P - 1 + C], W1[P - 1 + C1];
 #pragma unroll
     for (int i = 0; i < P - 1; ++i) W0[i] = row0(i);
@@ -302,7 +314,7 @@ __device__ __forceinline__ void levels01(Ctx &cx, typename RK<K>::S *out)
 #pragma unroll 1
     for (int c0 = 0; c0 < T; c0 += C) {
 #pragma unroll
-        for (int q = 0; q < C; ++q) W0[P - 1 + q] = c0 + q < r ? row0(P - 1 + c0 + q) : S(0);
+        for (int q = 0; q < C; ++q) W0[P - 1 + q] = c0 + q < r ? newval(c0 + q) : S(0);
 #pragma unroll
         for (int q = 0; q < C; ++q) {
             if (c0 + q < r) {
@@ -345,6 +357,18 @@ __device__ __forceinline__ void levels01(Ctx &cx, typename RK<K>::S *out)
         for (int i = 0; i < P - 1; ++i) {
             W0[i] = W0[i + C];
             W1[i] = W1[i + C1];
+        }
+    }
+    if constexpr (HIST && !READ) {
+        // the block's last P - 1 values (now W0[0 .. P-2]) go to their ring
+        // slots: the next block's folds and the readouts look back to them
+        S *ring0w = reinterpret_cast<S *>(cx.tb);
+        const int slot_w = (int)((f + T - (P - 1)) % P0); // value f + T - P + 2
+#pragma unroll
+        for (int i = 0; i < P - 1; ++i) {
+            int slot = slot_w + i;
+            if (slot >= P0) slot -= P0;
+            __builtin_nontemporal_store(W0[i], &ring0w[(size_t)slot * tw + cx.lane]);
         }
     }
     fold_level<K, P, P, READ>(cx, 0, part0, r > 0);
@@ -440,7 +464,7 @@ __device__ __forceinline__ void cascade(Ctx &cx, int k, const typename RK<K>::S 
     }
 }
 
-template <int K, int P, int T, bool READ>
+template <int K, int P, int T, int NT, bool READ, bool HIST>
 __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
 {
     const GroupArgs &g = a.g;
@@ -456,29 +480,38 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
         // last complete block without writing state, for the tiles that hold
         // the pass's chunk rows [row_begin, row_end).
         const int64_t S = *a.step;
-        f = (S / kDeferT) * kDeferT;
+        f = (S / T) * T;
         r = (int)(S - f);
         tile = (a.row_begin * 64) / g.tw + slot;
         if (tile >= g.n_tiles) return;
     } else {
-        // Flush of tile group j, block q: scheduled at push kDeferT q + j
-        // (fixed_group < 0; the counter is advanced after this push) or
-        // requested explicitly.  Skipped when that block is already folded.
+        // Flush of tile group j, block q: scheduled at push T q + j
+        // (fixed_group -1; the counter is advanced after this push), requested
+        // for one tile group (fixed_group >= 0) or for every tile group
+        // (fixed_group -2: the grid spans all tiles).  Skipped when that block
+        // is already folded.
         int j;
         int64_t q;
-        if (a.fixed_group >= 0) {
-            j = a.fixed_group;
+        if (a.fixed_group == -2) {
             q = a.fixed_block;
+            tile = slot;
+            if (tile >= g.n_tiles) return;
+            j = (int)(tile / a.tiles_per_group);
         } else {
-            const int64_t S = *a.step + 1;
-            j = (int)(S % kDeferT);
-            q = S / kDeferT;
+            if (a.fixed_group >= 0) {
+                j = a.fixed_group;
+                q = a.fixed_block;
+            } else {
+                const int64_t S = *a.step + 1;
+                j = (int)(S % T);
+                q = S / T;
+            }
+            tile = (int64_t)j * a.tiles_per_group + slot;
+            if (tile >= g.n_tiles || slot >= a.tiles_per_group) return;
         }
         if (q < 1 || a.flushed[j] >= q) return;
-        tile = (int64_t)j * a.tiles_per_group + slot;
-        if (tile >= g.n_tiles || slot >= a.tiles_per_group) return;
-        f = (q - 1) * kDeferT;
-        r = kDeferT;
+        f = (q - 1) * T;
+        r = T;
     }
     {
         const int sub = part;
@@ -503,13 +536,14 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
             // level 2 (f is a multiple of T, so level-1 pairs align); each
             // thread reads back only its own column of l2s
             using S = typename RK<K>::S;
-            __shared__ S l2s[(T / 4) * kFoldThreads];
-            levels01<K, P, T, READ>(cx, l2s);
+            __shared__ S l2s[(T / 4) * NT];
+            levels01<K, P, T, READ, HIST>(cx, l2s);
             S l2[T / 4];
 #pragma unroll
             for (int q = 0; q < T / 4; ++q) l2[q] = l2s[(size_t)q * blockDim.x + threadIdx.x];
             cascade<K, P, T / 4, READ>(cx, 2, l2, (r / 2) / 2);
         } else {
+            static_assert(!HIST, "history folds take blocks of more than kL0Chunk pushes");
             typename RK<K>::S l1[T / 2];
             level0<K, P, T, READ>(cx, l1);
             cascade<K, P, T / 2, READ>(cx, 1, l1, r / 2);
@@ -517,27 +551,28 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
     }
 }
 
-// The scheduled (or requested) flush: at most two waves per SIMD, so that the
-// register budget covers the whole block of pushes without spilling.
-template <int K, int P, int T>
-__global__ __launch_bounds__(kFoldThreads) __attribute__((amdgpu_waves_per_eu(2))) void deferred_kernel(DeferredArgs a)
+// The scheduled (or requested) flush, NT threads per block: at most two waves
+// per SIMD, so that the register budget covers the whole block of pushes
+// without spilling.  HIST: level 0 from a stored history.
+template <int K, int P, int T, int NT, bool HIST>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void deferred_kernel(DeferredArgs a)
 {
     // with timing: earliest block start and latest block end of the push's
     // folds (device wall clock; no event between kernels)
     FoldStamps *st = a.stamps;
-    if (st && threadIdx.x == 0) atomicMin(&st->start, (unsigned long long)wall_clock64());
-    deferred_pass<K, P, T, false>(a);
+    if (st && threadIdx.x == 0) stamp_start(st, blockIdx.x);
+    deferred_pass<K, P, T, NT, false, HIST>(a);
     if (st) {
         __syncthreads();
-        if (threadIdx.x == 0) atomicMax(&st->end, (unsigned long long)wall_clock64());
+        if (threadIdx.x == 0) stamp_end(st, blockIdx.x);
     }
 }
 
 // The readout pass (no state written).
 template <int K, int P, int T>
-__global__ __launch_bounds__(kFoldThreads) void deferred_read_kernel(DeferredArgs a)
+__global__ __launch_bounds__(kFoldThreadsDefault) void deferred_read_kernel(DeferredArgs a)
 {
-    deferred_pass<K, P, T, true>(a);
+    deferred_pass<K, P, T, kFoldThreadsDefault, true, false>(a);
 }
 
 // Column sums of rows [n_rows][ne] in a fixed order: groups of kColGroup rows
@@ -572,6 +607,7 @@ __global__ void colsum_final_kernel(const double *groups, int64_t n_groups, int 
 __global__ void flush_commit_kernel(DeferredArgs a)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int T = a.g.defer_t;
     int j;
     int64_t q;
     if (a.fixed_group >= 0) {
@@ -579,38 +615,67 @@ __global__ void flush_commit_kernel(DeferredArgs a)
         q = a.fixed_block;
     } else {
         const int64_t S = *a.step + 1;
-        j = (int)(S % kDeferT);
-        q = S / kDeferT;
+        j = (int)(S % T);
+        q = S / T;
     }
     if (q >= 1 && a.flushed[j] < q) a.flushed[j] = q;
 }
 
-template <int K, int P, bool READ>
-hipError_t launch_deferred_kp(const DeferredArgs &a, hipStream_t st)
+template <int K, int P, int T, int NT, bool READ, bool HIST>
+hipError_t launch_deferred_kpt(const DeferredArgs &a, hipStream_t st)
 {
-    const int block = a.g.tw < kFoldThreads ? a.g.tw : kFoldThreads;
+    const int block = a.g.tw < NT ? a.g.tw : NT;
     const int parts = (a.g.tw + block - 1) / block;
-    // readout: the tiles that hold chunk rows [row_begin, row_end)
+    // readout: the tiles that hold chunk rows [row_begin, row_end); every
+    // tile group: all tiles; otherwise the tiles of one tile group
     const int64_t read_tiles = (a.row_end * 64 + a.g.tw - 1) / a.g.tw - (a.row_begin * 64) / a.g.tw;
-    const int64_t grid = (READ ? read_tiles : a.tiles_per_group) * parts;
+    const int64_t tiles = READ ? read_tiles : a.fixed_group == -2 ? a.g.n_tiles : a.tiles_per_group;
+    const int64_t grid = tiles * parts;
     if (grid < 1) return hipSuccess;
     if constexpr (READ)
-        hipLaunchKernelGGL((deferred_read_kernel<K, P, kDeferT>), dim3((unsigned)grid), dim3(block),
-                           0, st, a);
+        hipLaunchKernelGGL((deferred_read_kernel<K, P, T>), dim3((unsigned)grid), dim3(block), 0, st,
+                           a);
     else
-        hipLaunchKernelGGL((deferred_kernel<K, P, kDeferT>), dim3((unsigned)grid), dim3(block), 0,
-                           st, a);
+        hipLaunchKernelGGL((deferred_kernel<K, P, T, NT, HIST>), dim3((unsigned)grid), dim3(block),
+                           0, st, a);
     return hipGetLastError();
 }
 
-template <bool READ>
+// Instantiated block shapes: the staged fold with 64, 128 or 256 threads per
+// block; the readout and the history fold with the default 128.
+template <int K, int P, int T, bool READ, bool HIST>
+hipError_t launch_deferred_nt(const DeferredArgs &a, hipStream_t st)
+{
+    if constexpr (READ || HIST) {
+        return launch_deferred_kpt<K, P, T, kFoldThreadsDefault, READ, HIST>(a, st);
+    } else {
+        switch (a.threads) {
+        case 64: return launch_deferred_kpt<K, P, T, 64, false, false>(a, st);
+        case 256: return launch_deferred_kpt<K, P, T, 256, false, false>(a, st);
+        default: return launch_deferred_kpt<K, P, T, 128, false, false>(a, st);
+        }
+    }
+}
+
+template <int K, bool READ, bool HIST>
+hipError_t launch_deferred_k(const DeferredArgs &a, hipStream_t st)
+{
+    switch (a.g.defer_t) {
+    case kDeferT: return launch_deferred_nt<K, 16, kDeferT, READ, HIST>(a, st);
+    case kDeferTMin: return launch_deferred_nt<K, 16, kDeferTMin, READ, HIST>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool READ, bool HIST = false>
 hipError_t launch_deferred_t(const DeferredArgs &a, hipStream_t st)
 {
     if (a.g.p != 16) return hipErrorInvalidValue;
+    if (HIST && (!a.hist || a.fixed_group != -2)) return hipErrorInvalidValue;
     switch (a.g.kind) {
-    case K_F32_F64: return launch_deferred_kp<K_F32_F64, 16, READ>(a, st);
-    case K_F32_KAHAN: return launch_deferred_kp<K_F32_KAHAN, 16, READ>(a, st);
-    case K_F32_F32: return launch_deferred_kp<K_F32_F32, 16, READ>(a, st);
+    case K_F32_F64: return launch_deferred_k<K_F32_F64, READ, HIST>(a, st);
+    case K_F32_KAHAN: return launch_deferred_k<K_F32_KAHAN, READ, HIST>(a, st);
+    case K_F32_F32: return launch_deferred_k<K_F32_F32, READ, HIST>(a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -684,6 +749,11 @@ bool deferred_supported(int kind, int p, int m)
 hipError_t launch_flush_fold(const DeferredArgs &a, hipStream_t st)
 {
     return launch_deferred_t<false>(a, st);
+}
+
+hipError_t launch_history_fold(const DeferredArgs &a, hipStream_t st)
+{
+    return launch_deferred_t<false, true>(a, st);
 }
 
 hipError_t launch_flush_commit(const DeferredArgs &a, hipStream_t st)

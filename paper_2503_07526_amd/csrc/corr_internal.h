@@ -50,30 +50,61 @@ struct GroupArgs {
     int32_t s_bytes;     // bytes per sample
     int32_t a_bytes;     // bytes per accumulator plane element
     int32_t deferred;    // 1: block-deferred form (pushes only stage samples)
-    int32_t p0;          // ring rows of level 0 (p; 2 kDeferT + p when block-deferred;
+    int32_t p0;          // ring rows of level 0 (p; 2 T + p when block-deferred;
                          // 2 kWindowT + p for a block-deferred window)
     int32_t pair;        // 1: channels correlate (x, y): samples [2][n_ch], and each
                          // level holds the lagged y ring, then an x ring
-    int32_t pad_;
+    int32_t defer_t;     // block-deferred form: pushes per fold block T, else 0
 };
 
-// Pushes staged between two flushes of a block-deferred group.
+// Pushes staged between two flushes of a block-deferred group: T = kDeferT by
+// default, kDeferTMin when the state of the longer block would not fit.
 constexpr int kDeferT = 256;
+constexpr int kDeferTMin = 128;
 // Pushes per block of the block-deferred one-level window (corr_window.hip).
 constexpr int kWindowT = 64;
-// Tile groups of a block-deferred group: tile group j folds block q (pushes
-// (kDeferT (q-1), kDeferT q]) at push kDeferT q + j, so every push flushes one
-// group; the level-0 ring keeps 2 kDeferT + p slots.
+// Tile groups of a block-deferred group: T of them; tile group j folds block
+// q (pushes (T (q-1), T q]) at push T q + j, so every push flushes one group;
+// the level-0 ring keeps 2 T + p slots.  Arrays of tile groups hold
+// kFlushGroups (the largest T) entries.
 constexpr int kFlushGroups = kDeferT;
+// Threads per block of the fold kernels (the scheduled flush takes 64, 128 or
+// 256; a tile wider than a block is split over several blocks).
+constexpr int kFoldThreadsDefault = 128;
 
-// Device timestamps of the scheduled fold kernels of a push (timing only):
-// the earliest block start and the latest block end of this push's folds, in
-// wall-clock ticks, and their running sum over pushes (the push's end kernel
-// adds and resets them).
-struct FoldStamps {
+// Device timestamps of a class of kernels of a push (timing only: record 0
+// the scheduled folds, record 1 the producers): the earliest block start and
+// the latest block end of this push's kernels of that class, in wall-clock
+// ticks, and their running sum over pushes (the push's end kernel reduces the
+// slots, adds the span and resets them).  Blocks record into one of
+// kStampSlots slots, each on its own 128-byte line, so that the stamps of a
+// few thousand blocks do not queue on one address (on one line they delayed
+// the end of the fold kernel by about 15 us).
+constexpr int kStampSlots = 64;
+struct StampSlot {
     unsigned long long start, end;
-    unsigned long long total, count;
+    unsigned long long pad_[14];
 };
+struct FoldStamps {
+    StampSlot slot[kStampSlots];
+    unsigned long long total, count;
+    unsigned long long pad_[14];
+};
+
+// Record a block's start (or end) in its slot.
+#if defined(__HIPCC__)
+} // namespace corr
+#include <hip/hip_runtime.h>
+namespace corr {
+__device__ __forceinline__ void stamp_start(FoldStamps *st, unsigned block)
+{
+    atomicMin(&st->slot[block % kStampSlots].start, (unsigned long long)wall_clock64());
+}
+__device__ __forceinline__ void stamp_end(FoldStamps *st, unsigned block)
+{
+    atomicMax(&st->slot[block % kStampSlots].end, (unsigned long long)wall_clock64());
+}
+#endif
 
 // Flush / readout of a block-deferred group.
 struct DeferredArgs {
@@ -82,7 +113,9 @@ struct DeferredArgs {
                             // the increment of its push, a readout after it)
     int64_t *flushed;       // [kFlushGroups] last block folded per tile group
     int64_t tiles_per_group;
-    int32_t fixed_group;    // >= 0: fold block fixed_block of this tile group
+    int32_t fixed_group;    // >= 0: fold block fixed_block of this tile group; -2: of
+                            // every tile group that has not folded it; -1: the
+                            // flush scheduled for the push being issued
     int32_t ne;             // readout: number of (level, lag) entries
     int64_t fixed_block;
     int64_t ch_begin, ch_end;       // readout: channels reduced
@@ -92,6 +125,13 @@ struct DeferredArgs {
                             // (row r at r - row_begin)
     double *slice_out;      // readout: [(c - slice_begin) * ne + e]
     FoldStamps *stamps;     // scheduled flush with timing: block start / end stamps, else null
+    // Fold straight from a stored history (fixed_group -2): row i (push
+    // T (fixed_block - 1) + 1 + i) of the block holds the n_ch samples at
+    // hist + i hist_stride bytes; null: the level-0 ring
+    const char *hist;
+    int64_t hist_stride;
+    int32_t threads;        // threads per block of the fold kernel (64, 128 or 256)
+    int32_t pad_;
 };
 
 struct PushArgs {
@@ -143,6 +183,7 @@ struct RhokArgs {
     void *out;               // [nk] complex samples (float2 or double2)
     int32_t out_double;      // 1: double2 output
     int32_t pad_;
+    FoldStamps *stamps;      // timing: the push's producer stamps, else null
 };
 
 // k-density producer on the matrix cores: n(k) from real products over the
@@ -166,6 +207,7 @@ struct MomentumArgs {
     int32_t vec4;            // 1: n_atoms % 4 == 0 and vel 16-byte aligned (4 atoms per load)
     int32_t pad_;
     void *out;               // [n_ch] densities, or [2][n_ch] (x, then densities)
+    FoldStamps *stamps;      // timing: the push's producer stamps, else null
 };
 
 struct RhokMfmaArgs {
@@ -190,16 +232,22 @@ struct RhokMfmaArgs {
     int32_t nw;              // weight sets: 1 = n(k), 3 = current components
     int32_t pad_;
     const double *basis;     // nw == 3: [nk][3][3] rows khat, e1, e2
+    FoldStamps *stamps;      // timing: the push's producer stamps, else null
 };
 
 // End of a push: record the scheduled flush of each block-deferred group,
-// then advance the device push counter.
+// then advance the device push counter by `advance` (1 for a push).  With
+// commit_block >= 1 the record is instead that every tile group of those
+// groups has folded block commit_block (after folds of all tile groups).
 struct PushEndArgs {
     int64_t *step;
     int32_t n_flushed;                 // block-deferred groups
-    int32_t pad_;
+    int32_t advance;                   // pushes counted
     int64_t *flushed[kMaxGroups];      // their [kFlushGroups] last-folded arrays
-    FoldStamps *stamps;                // timing: the push's fold stamps, else null
+    int32_t defer_t[kMaxGroups];       // their blocks T
+    int64_t commit_block;
+    FoldStamps *stamps;                // timing: the push's [2] stamp records (folds,
+                                       // producers), else null
 };
 
 // Readout reduction arguments.

@@ -32,6 +32,9 @@ bool deferred_supported(int kind, int p, int m);
 hipError_t launch_stage(const GroupArgs &g, const int64_t *step, hipStream_t st);
 hipError_t launch_flush(const DeferredArgs &a, hipStream_t st);        // fold + commit
 hipError_t launch_flush_fold(const DeferredArgs &a, hipStream_t st);   // the fold kernel
+// Fold of block a.fixed_block for every tile group (a.fixed_group == -2) with
+// level 0 read from the history a.hist (a.hist_stride bytes per push).
+hipError_t launch_history_fold(const DeferredArgs &a, hipStream_t st);
 hipError_t launch_flush_commit(const DeferredArgs &a, hipStream_t st); // flag update
 int64_t deferred_readout_rows(const GroupArgs &g);
 int64_t deferred_readout_groups(const GroupArgs &g);

@@ -60,6 +60,7 @@ __device__ __forceinline__ void add_atom(double (&acc)[kMomSums], int ns, int sp
 
 template <typename T> __global__ __launch_bounds__(kMomThreads) void momentum_partial_kernel(MomentumArgs a)
 {
+    if (a.stamps && threadIdx.x == 0) stamp_start(a.stamps, blockIdx.x);
     const T *v = static_cast<const T *>(a.vel);
     const int64_t n = a.n_atoms;
     const int ns = a.n_species;
@@ -118,6 +119,7 @@ template <typename T> __global__ __launch_bounds__(64) void momentum_final_kerne
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
     if (lane != 0) return;
+    if (a.stamps) stamp_end(a.stamps, (unsigned)q);
     T *out = static_cast<T *>(a.out);
     const T j = (T)(x * a.scale[q / 3]);
     if (a.pair) {

@@ -431,27 +431,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
         lag_loop<K, CPT, LCH>(x, y, ring, hi, lo, slot, p, l_begin, l_end, 0, tw, lane_off);
 }
 
-// Last kernel of a push S = *step + 1: tile group S mod kDeferT of every
-// block-deferred group has folded block S / kDeferT (its flush ran earlier
-// in this push), then the counter advances.
+// Last kernel of a push S = *step + 1: tile group S mod T of every
+// block-deferred group has folded block S / T (its flush ran earlier in this
+// push), then the counter advances.  After the folds of every tile group
+// (a catch-up, or a block folded from a stored history) the record is that
+// block for all tile groups, and the counter advances by the pushes the
+// launch stands for (a whole history block when no group needs per-push
+// work, else 0: those pushes ended with their own end kernels).
 __global__ void push_end_kernel(PushEndArgs a)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int64_t S = *a.step + 1;
-    const int j = (int)(S % kDeferT);
-    const int64_t q = S / kDeferT;
-    for (int i = 0; i < a.n_flushed; ++i)
-        if (q >= 1 && a.flushed[i][j] < q) a.flushed[i][j] = q;
+    if (blockIdx.x != 0) return;
     if (a.stamps) {
-        FoldStamps &st = *a.stamps;
-        if (st.end > st.start) {
-            st.total += st.end - st.start;
-            st.count += 1;
+        // each lane takes one slot of both stamp records; the wave's earliest
+        // start and latest end give the push's span of each class
+        __shared__ unsigned long long lo[kStampSlots], hi[kStampSlots];
+        for (int r = 0; r < 2; ++r) {
+            FoldStamps &st = a.stamps[r];
+            const int l = threadIdx.x;
+            if (l < kStampSlots) {
+                lo[l] = st.slot[l].start;
+                hi[l] = st.slot[l].end;
+                st.slot[l].start = ~0ull;
+                st.slot[l].end = 0;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                unsigned long long s0 = ~0ull, e0 = 0;
+                for (int q = 0; q < kStampSlots; ++q) {
+                    s0 = lo[q] < s0 ? lo[q] : s0;
+                    e0 = hi[q] > e0 ? hi[q] : e0;
+                }
+                if (e0 > s0) {
+                    st.total += e0 - s0;
+                    st.count += 1;
+                }
+            }
+            __syncthreads();
         }
-        st.start = ~0ull;
-        st.end = 0;
     }
-    *a.step = S;
+    if (threadIdx.x != 0) return;
+    const int64_t S = *a.step + 1;
+    for (int i = 0; i < a.n_flushed; ++i) {
+        const int T = a.defer_t[i];
+        if (a.commit_block >= 1) {
+            // every tile group folded block commit_block
+            for (int j = 0; j < T; ++j)
+                if (a.flushed[i][j] < a.commit_block) a.flushed[i][j] = a.commit_block;
+        } else {
+            const int j = (int)(S % T);
+            const int64_t q = S / T;
+            if (q >= 1 && a.flushed[i][j] < q) a.flushed[i][j] = q;
+        }
+    }
+    *a.step += a.advance;
 }
 
 // ------------------------------------------------------------ host launchers

@@ -35,6 +35,7 @@ __host__ __device__ inline int tab_atom(int nmax) { return tab_x(nmax) + 2 * tab
 
 __global__ __launch_bounds__(1024) void rhok_partial_kernel(RhokArgs a, int tile_atoms)
 {
+    if (a.stamps && threadIdx.x == 0) stamp_start(a.stamps, blockIdx.x + gridDim.x * blockIdx.y);
     extern __shared__ float2 tab[]; // [tile_atoms][tab_atom]
     const int nmax = a.nmax;
     const int TX = tab_x(nmax), TYZ = tab_yz(nmax), TA = tab_atom(nmax);
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(256) void rhok_final_kernel(RhokArgs a)
         si += __shfl_down(si, off, 64);
     }
     if (lane != 0) return;
+    if (a.stamps) stamp_end(a.stamps, (unsigned)q);
     if (a.out_double)
         static_cast<double2 *>(a.out)[o] = make_double2(sr, si);
     else

@@ -237,6 +237,7 @@ template <int NW> struct MfmaShape {
 
 template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaArgs &a)
 {
+    if (a.stamps && threadIdx.x == 0) stamp_start(a.stamps, blockIdx.x + gridDim.x * blockIdx.y);
     extern __shared__ double2 lds_roots[]; // [kRoots], the scale slots, then two tile buffers
     const int nmax = a.nmax;
     const int2 xrows = make_int2(a.x_lo, a.x_rows), yrows = make_int2(a.y_lo, a.y_rows);
@@ -528,6 +529,7 @@ __global__ __launch_bounds__(256) void rhok_mfma_final_kernel(RhokMfmaArgs a)
         si[w] = i;
     }
     if (lane != 0) return;
+    if (a.stamps) stamp_end(a.stamps, (unsigned)k);
     if constexpr (NW == 1) {
         if (a.out_double)
             static_cast<double2 *>(a.out)[k] = make_double2(sr[0], si[0]);

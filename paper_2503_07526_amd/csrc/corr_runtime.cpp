@@ -65,11 +65,12 @@ struct Group {
     int p = 0, m = 0, b = 0, lag0 = 0, nlk = 0;
     int s_bytes = 0, a_bytes = 0, np = 1;
     bool deferred = false; // block-deferred form (stage per push, staggered flushes)
+    int T = 0;             // block-deferred form: pushes per fold block
     bool wdef = false;     // one-level window in the block-deferred form (staged per
                            // push, one lag block folded per push)
     int p0 = 0;            // ring rows of level 0
     bool pair = false;     // channels correlate (x, y) pairs
-    int64_t *d_flushed = nullptr;                // [kFlushGroups] blocks folded per tile group
+    int64_t *d_flushed = nullptr;                // [kFlushGroups] blocks folded per tile group (T used)
     std::vector<int64_t> flushed;                // host mirror of d_flushed
     int64_t tiles_per_group = 0;
     int64_t n_ch = 0, n_tiles = 0, tile_bytes = 0, lvl0_bytes = 0, lvlk_bytes = 0;
@@ -106,6 +107,8 @@ struct corr_ctx {
     std::vector<Group> groups;
     int64_t *d_step = nullptr;
     int64_t n_push = 0;
+    int32_t defer_t = 0;       // pushes per fold block of the block-deferred groups
+    int32_t fold_threads = kFoldThreadsDefault;
     int32_t timing_stride = 1; // CORR_FLAG_TIMING: events on pushes with n_push % stride == 0
     FoldStamps *d_stamps = nullptr; // CORR_FLAG_TIMING: device stamps of the scheduled folds
     double stamp_khz = 0.0;         // wall-clock rate of the stamps
@@ -123,6 +126,16 @@ struct corr_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // graph mode: captured replays of corr_push_steps (n pushes from given
+    // histories), most recent last
+    struct StepsGraph {
+        int32_t n = 0;
+        std::vector<const void *> src;
+        std::vector<int64_t> stride;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<StepsGraph> steps_graphs;
     std::vector<int> deferred_set; // context group indices in the block-deferred form
     // kernel timing (CORR_FLAG_TIMING): pool 0 per push, pool 1 per flush
     // fold, pool 2 per k-density producer launch
@@ -281,6 +294,11 @@ int validate_tuning(const corr_tuning &t)
     if (t.grid_blocks < 0) return set_err(nullptr, CORR_E_INVALID, "tuning: grid_blocks < 0");
     if (t.overlap_producers < 0 || t.overlap_producers > 2)
         return set_err(nullptr, CORR_E_INVALID, "tuning: overlap_producers must be 0, 1 or 2");
+    if (t.fold_block != 0 && t.fold_block != kDeferT && t.fold_block != kDeferTMin)
+        return set_err(nullptr, CORR_E_INVALID, "tuning: fold_block must be 0, %d or %d", kDeferTMin,
+                       kDeferT);
+    if (t.fold_threads != 0 && t.fold_threads != 64 && t.fold_threads != 128 && t.fold_threads != 256)
+        return set_err(nullptr, CORR_E_INVALID, "tuning: fold_threads must be 0, 64, 128 or 256");
     return CORR_OK;
 }
 
@@ -305,6 +323,10 @@ void free_ctx(corr_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto &sg : c->steps_graphs) {
+        if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+        if (sg.graph) (void)hipGraphDestroy(sg.graph);
+    }
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
@@ -370,6 +392,7 @@ DeferredArgs deferred_args(const corr_ctx *c, int i)
     da.flushed = g.d_flushed;
     da.tiles_per_group = g.tiles_per_group;
     da.fixed_group = -1;
+    da.threads = c->fold_threads;
     return da;
 }
 
@@ -392,21 +415,21 @@ int launch_flushes(corr_ctx *c, hipStream_t st, hipEvent_t f0, hipEvent_t f1)
 // Host mirror of the scheduled flush of push S (after it was issued).
 void mirror_flushes(corr_ctx *c, int64_t S)
 {
-    const int j = (int)(S % kDeferT);
-    const int64_t q = S / kDeferT;
     for (int i : c->deferred_set) {
         Group &g = c->groups[(size_t)i];
+        const int j = (int)(S % g.T);
+        const int64_t q = S / g.T;
         if (q >= 1 && g.flushed[(size_t)j] < q) g.flushed[(size_t)j] = q;
     }
 }
 
 // Before a readout: fold every complete block a tile group has not folded yet
-// (at most one per group: a block is scheduled within kDeferT - 1 pushes).
+// (at most one per group: a block is scheduled within T - 1 pushes).
 int catch_up_flushes(corr_ctx *c, int gi)
 {
     Group &g = c->groups[(size_t)gi];
-    const int64_t qn = c->n_push / kDeferT;
-    for (int j = 0; j < kFlushGroups; ++j) {
+    const int64_t qn = c->n_push / g.T;
+    for (int j = 0; j < g.T; ++j) {
         while (g.flushed[(size_t)j] < qn) {
             DeferredArgs da = deferred_args(c, gi);
             da.fixed_group = j;
@@ -504,8 +527,14 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
 // by the push of the producers' groups only (the sample-fed groups then run on
 // the main stream beside them); 2 keeps the producers on the main stream and
 // forks the per-step pushes, which then run beside the flush.
-int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_flush)
+int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_flush,
+               bool skip_deferred = false)
 {
+    // skip_deferred: the block-deferred groups take no part in this push (a
+    // replay folds their block straight from the history instead)
+    static const std::vector<int> none;
+    const std::vector<int> &dset = skip_deferred ? none : c->deferred_set;
+    if (skip_deferred) with_flush = false;
     const size_t ng = c->groups.size();
     std::vector<const void *> resolved(ng);
     for (size_t i = 0; i < ng; ++i)
@@ -515,9 +544,8 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
     const bool timed = (c->flags & CORR_FLAG_TIMING) && st == c->stream &&
                        c->n_push % c->timing_stride == 0;
     const bool fork = c->tuning.overlap_producers == 1 && !c->side_set.empty() &&
-                      (!c->main_set.empty() || !c->deferred_set.empty());
-    const bool fork_updates = c->tuning.overlap_producers == 2 && with_flush &&
-                              !c->deferred_set.empty() &&
+                      (!c->main_set.empty() || !dset.empty());
+    const bool fork_updates = c->tuning.overlap_producers == 2 && with_flush && !dset.empty() &&
                               (!c->main_set.empty() || !c->side_set.empty());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -533,7 +561,7 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
         HIP_TRY(c, hipEventRecord(c->ev_fork, st));
         HIP_TRY(c, hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
     }
-    for (int i : c->deferred_set) {
+    for (int i : dset) {
         GroupArgs ga = c->pargs.g[(size_t)i];
         ga.samples = resolved[(size_t)i];
         HIP_TRY(c, launch_stage(ga, c->d_step, st));
@@ -547,23 +575,27 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
             if (rc != CORR_OK) return rc;
             HIP_TRY(c, hipEventRecord(r0, pst));
         }
+        FoldStamps *pst_stamps = c->d_stamps ? c->d_stamps + 1 : nullptr;
         if (g.mom) {
             MomentumArgs ma = g.mom_args;
             ma.vel = src[i];
             ma.vec4 = g.d.n_atoms % 4 == 0 && reinterpret_cast<uintptr_t>(src[i]) % 16 == 0;
+            ma.stamps = pst_stamps;
             HIP_TRY(c, launch_momentum(ma, pst));
         } else if (g.rhok_mfma) {
             RhokMfmaArgs ma = g.margs;
             ma.pos = static_cast<const float *>(src[i]);
+            ma.stamps = pst_stamps;
             HIP_TRY(c, launch_rhok_mfma(ma, pst));
         } else {
             RhokArgs ra = g.rargs;
             ra.pos = static_cast<const float *>(src[i]);
+            ra.stamps = pst_stamps;
             HIP_TRY(c, launch_rhok(ra, pst));
         }
         if (timed) HIP_TRY(c, hipEventRecord(r1, pst));
     }
-    if (fork && !c->deferred_set.empty()) {
+    if (fork && !dset.empty()) {
         // the per-step push of every direct group, sample-fed ones included,
         // in one launch after the producers: the main stream keeps only the
         // staging and the flush of the block-deferred groups
@@ -594,7 +626,7 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
             if (fork_updates) HIP_TRY(c, hipEventRecord(c->ev_join, ust));
         }
     }
-    if (with_flush && !c->deferred_set.empty()) {
+    if (with_flush && !dset.empty()) {
         hipEvent_t f0 = nullptr, f1 = nullptr;
         if (timed) {
             int rc = next_events(c, 1, &f0, &f1);
@@ -608,9 +640,13 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
     if (fork) HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
     PushEndArgs pe{};
     pe.step = c->d_step;
+    pe.advance = 1;
     if (with_flush)
-        for (int i : c->deferred_set) pe.flushed[pe.n_flushed++] = c->groups[(size_t)i].d_flushed;
-    if (with_flush && !c->deferred_set.empty()) pe.stamps = c->d_stamps;
+        for (int i : dset) {
+            pe.defer_t[pe.n_flushed] = c->groups[(size_t)i].T;
+            pe.flushed[pe.n_flushed++] = c->groups[(size_t)i].d_flushed;
+        }
+    pe.stamps = c->d_stamps; // timing: adds this push's fold and producer spans
     HIP_TRY(c, launch_push_end(pe, st));
     return CORR_OK;
 }
@@ -694,10 +730,11 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     // Default launch shape: 512-channel tiles, 2 channels per thread (256-thread
     // blocks), 8 lags per load batch, a persistent grid of 8 blocks per CU,
     // producers on the context's stream.
-    corr_tuning tn{512, 2, 8, 2048, 0};
+    corr_tuning tn{512, 2, 8, 2048, 0, 0, 0};
     const bool given = tuning && (tuning->tile_channels || tuning->chans_per_thread ||
                                   tuning->lag_chunk || tuning->grid_blocks ||
-                                  tuning->overlap_producers);
+                                  tuning->overlap_producers || tuning->fold_block ||
+                                  tuning->fold_threads);
     if (!given) {
         // the autotuner's cached choice for these groups, if any
         corr_tuning cached{};
@@ -727,6 +764,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     c->stream = static_cast<hipStream_t>(stream);
     c->flags = flags;
     c->tuning = tn;
+    c->fold_threads = tn.fold_threads ? tn.fold_threads : kFoldThreadsDefault;
     DeviceGuard dg(device);
 
     auto fail = [&](int rc) {
@@ -741,6 +779,55 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     } while (0)
 
     const int tw = tn.tile_channels;
+    // Block length of the block-deferred groups: the tuning's, else the
+    // longest whose state fits in the device's free memory (each step down
+    // shortens the level-0 ring of 2 T + p rows), else the per-step form.
+    bool fold_ok = !(flags & CORR_FLAG_DIRECT);
+    {
+        auto folds = [&](const corr_group_desc &d) {
+            return d.source == CORR_SRC_SAMPLES && !d.pair &&
+                   deferred_supported(kind_of(d.dtype, d.accum), d.points, d.m);
+        };
+        // device bytes of the context's groups with fold block T (0: the
+        // per-step form for the foldable groups)
+        auto ctx_bytes = [&](int T) {
+            double total = 0.0;
+            for (int i = 0; i < n_groups; ++i) {
+                const corr_group_desc &d = groups[i];
+                const int kind = kind_of(d.dtype, d.accum);
+                const int64_t n_tiles = (d.n_channels + tw - 1) / tw;
+                const int64_t rowS = (int64_t)tw * kind_sample_bytes(kind);
+                const int64_t rowA = (int64_t)tw * kind_acc_bytes(kind);
+                const int np = acc_planes(kind), nlk = d.points - d.points / d.m;
+                const bool def = T > 0 && folds(d);
+                const bool win = !def && d.levels == 1 && d.points >= kWindowMinP && !d.pair &&
+                                 !(flags & CORR_FLAG_DIRECT) && window_deferred_supported(kind);
+                const int64_t p0 = def ? 2 * T + d.points : win ? 2 * kWindowT + d.points : d.points;
+                const int rings = d.pair ? 2 : 1;
+                const int64_t tile = rings * p0 * rowS + np * (int64_t)d.points * rowA +
+                                     (int64_t)(d.levels - 1) * (rings * d.points * rowS + np * nlk * rowA);
+                total += (double)n_tiles * (double)tile;
+                total += (double)(d.pair ? 2 : 1) * (double)d.n_channels * kind_sample_bytes(kind);
+            }
+            return total;
+        };
+        bool any_fold = false;
+        for (int i = 0; i < n_groups; ++i) any_fold = any_fold || folds(groups[i]);
+        c->defer_t = tn.fold_block ? tn.fold_block : kDeferT;
+        if (fold_ok && any_fold && tn.fold_block == 0) {
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && total_b > 0) {
+                // keep a margin for the runtime and the caller's next buffers
+                const double avail = (double)free_b - std::max(1.0 * (1 << 30), 0.01 * (double)total_b);
+                if (ctx_bytes(kDeferT) > avail) {
+                    if (ctx_bytes(kDeferTMin) <= avail)
+                        c->defer_t = kDeferTMin;
+                    else if (ctx_bytes(0) <= avail)
+                        fold_ok = false; // only the per-step form fits
+                }
+            }
+        }
+    }
     c->groups.resize((size_t)n_groups);
     int64_t tile_first = 0;
     for (int i = 0; i < n_groups; ++i) {
@@ -763,11 +850,12 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         const int64_t rowS = (int64_t)tw * g.s_bytes;
         const int64_t rowA = (int64_t)tw * g.a_bytes;
         g.pair = g.d.pair != 0;
-        g.deferred = !(flags & CORR_FLAG_DIRECT) && g.d.source == CORR_SRC_SAMPLES && !g.pair &&
+        g.deferred = fold_ok && g.d.source == CORR_SRC_SAMPLES && !g.pair &&
                      deferred_supported(g.kind, g.p, g.m);
+        g.T = g.deferred ? c->defer_t : 0;
         g.wdef = !(flags & CORR_FLAG_DIRECT) && !g.deferred && !g.pair && g.b == 1 &&
                  g.p >= kWindowMinP && window_deferred_supported(g.kind);
-        g.p0 = g.deferred ? 2 * kDeferT + g.p : g.wdef ? 2 * kWindowT + g.p : g.p;
+        g.p0 = g.deferred ? 2 * g.T + g.p : g.wdef ? 2 * kWindowT + g.p : g.p;
         // pair groups: each level holds the lagged y ring, then an x ring
         const int rings = g.pair ? 2 : 1;
         g.lvl0_bytes = rings * g.p0 * rowS + (int64_t)g.np * g.p * rowA;
@@ -777,8 +865,8 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         CREATE_HIP(hipMalloc(&g.state, state_bytes));
         CREATE_HIP(hipMemsetAsync(g.state, 0, state_bytes, c->stream));
         if (g.deferred) {
-            g.tiles_per_group = (g.n_tiles + kFlushGroups - 1) / kFlushGroups;
-            g.flushed.assign(kFlushGroups, 0);
+            g.tiles_per_group = (g.n_tiles + g.T - 1) / g.T;
+            g.flushed.assign((size_t)g.T, 0);
             CREATE_HIP(hipMalloc(&g.d_flushed, kFlushGroups * sizeof(int64_t)));
             CREATE_HIP(hipMemsetAsync(g.d_flushed, 0, kFlushGroups * sizeof(int64_t), c->stream));
         }
@@ -1020,6 +1108,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         ga.deferred = (g.deferred || g.wdef) ? 1 : 0;
         ga.p0 = g.p0;
         ga.pair = g.pair ? 1 : 0;
+        ga.defer_t = g.T;
         if (g.deferred) c->deferred_set.push_back(i);
         tile_first += g.n_tiles;
     }
@@ -1066,9 +1155,13 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         int khz = 0;
         CREATE_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
         c->stamp_khz = khz > 0 ? (double)khz : 0.0;
-        const FoldStamps init{~0ull, 0ull, 0ull, 0ull};
-        CREATE_HIP(hipMalloc(&c->d_stamps, sizeof(FoldStamps)));
-        CREATE_HIP(hipMemcpy(c->d_stamps, &init, sizeof(FoldStamps), hipMemcpyHostToDevice));
+        std::vector<FoldStamps> init(2);
+        for (auto &r : init) {
+            r = FoldStamps{};
+            for (auto &sl : r.slot) sl.start = ~0ull;
+        }
+        CREATE_HIP(hipMalloc(&c->d_stamps, 2 * sizeof(FoldStamps)));
+        CREATE_HIP(hipMemcpy(c->d_stamps, init.data(), 2 * sizeof(FoldStamps), hipMemcpyHostToDevice));
     }
     c->pargs.step = c->d_step;
     c->pa_main.step = c->d_step;
@@ -1160,14 +1253,158 @@ int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
     }
     const bool with_flush = !ctx->deferred_set.empty();
     std::vector<const void *> src(ng);
-    for (int32_t r = 0; r < n_steps; ++r) {
+    auto row = [&](int32_t r) {
         for (size_t i = 0; i < ng; ++i)
             src[i] = static_cast<const char *>(samples[i]) + (int64_t)r * stride[i];
+    };
+    auto one_push = [&](int32_t r) -> int {
+        row(r);
         int rc = issue_push(ctx, src.data(), ctx->stream, with_flush);
         if (rc != CORR_OK) return rc;
         ctx->n_push += 1;
         mirror_flushes(ctx, ctx->n_push);
+        return CORR_OK;
+    };
+    if (n_steps == 0) return CORR_OK;
+
+    if (ctx->flags & CORR_FLAG_GRAPH) {
+        // Graph mode: the n pushes as one captured graph (the same kernels as
+        // single pushes; they take their schedule from the device counter, so
+        // a graph replays correctly at any push count), kept for the next call
+        // with the same histories and length.
+        std::vector<const void *> base(samples, samples + ng);
+        auto &cache = ctx->steps_graphs;
+        size_t hit = cache.size();
+        for (size_t k = 0; k < cache.size(); ++k)
+            if (cache[k].n == n_steps && cache[k].src == base && cache[k].stride == stride) hit = k;
+        if (hit == cache.size()) {
+            corr_ctx::StepsGraph sg;
+            sg.n = n_steps;
+            sg.src = base;
+            sg.stride = stride;
+            HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = CORR_OK;
+            for (int32_t r = 0; r < n_steps && rc == CORR_OK; ++r) {
+                row(r);
+                rc = issue_push(ctx, src.data(), ctx->cap_stream, with_flush);
+            }
+            const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &sg.graph);
+            if (rc != CORR_OK || ec != hipSuccess) {
+                if (sg.graph) (void)hipGraphDestroy(sg.graph);
+                return rc != CORR_OK ? rc : hip_err(ctx, ec, "hipStreamEndCapture");
+            }
+            const hipError_t ei = hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                (void)hipGraphDestroy(sg.graph);
+                return hip_err(ctx, ei, "hipGraphInstantiate");
+            }
+            if (cache.size() >= 4) { // keep the most recent few
+                (void)hipGraphExecDestroy(cache.front().exec);
+                (void)hipGraphDestroy(cache.front().graph);
+                cache.erase(cache.begin());
+            }
+            cache.push_back(std::move(sg));
+            hit = cache.size() - 1;
+        }
+        HIP_TRY(ctx, hipGraphLaunch(cache[hit].exec, ctx->stream));
+        for (int32_t r = 0; r < n_steps; ++r) {
+            ctx->n_push += 1;
+            mirror_flushes(ctx, ctx->n_push);
+        }
+        return CORR_OK;
     }
+
+    int32_t r = 0;
+    const int T = ctx->defer_t;
+    if (!ctx->deferred_set.empty() && n_steps >= T) {
+        // Block-deferred groups fold whole blocks of the history directly.
+        // Up to the next block boundary the pushes are single pushes.
+        while (r < n_steps && ctx->n_push % T != 0) {
+            int rc = one_push(r++);
+            if (rc != CORR_OK) return rc;
+        }
+        const bool others = !ctx->main_set.empty() || !ctx->side_set.empty();
+        int64_t q = ctx->n_push / T; // blocks that end at or before the current push
+        bool behind = false;          // some tile group has not folded block q yet
+        for (int i : ctx->deferred_set)
+            for (int64_t f : ctx->groups[(size_t)i].flushed) behind = behind || f < q;
+        if (n_steps - r >= T && q >= 1 && behind) {
+            // every tile group folds block q now (their scheduled folds would
+            // come during the next T - 1 pushes)
+            for (int i : ctx->deferred_set) {
+                DeferredArgs da = deferred_args(ctx, i);
+                da.fixed_group = -2;
+                da.fixed_block = q;
+                HIP_TRY(ctx, launch_flush_fold(da, ctx->stream));
+            }
+            PushEndArgs pe{};
+            pe.step = ctx->d_step;
+            pe.advance = 0;
+            pe.commit_block = q;
+            for (int i : ctx->deferred_set) {
+                pe.defer_t[pe.n_flushed] = ctx->groups[(size_t)i].T;
+                pe.flushed[pe.n_flushed++] = ctx->groups[(size_t)i].d_flushed;
+            }
+            HIP_TRY(ctx, launch_push_end(pe, ctx->stream));
+            for (int i : ctx->deferred_set) {
+                Group &g = ctx->groups[(size_t)i];
+                for (int j = 0; j < g.T; ++j) g.flushed[(size_t)j] = std::max(g.flushed[(size_t)j], q);
+            }
+        }
+        while (n_steps - r >= T) {
+            // the other groups' pushes of the block, one by one
+            if (others)
+                for (int k = 0; k < T; ++k) {
+                    row(r + k);
+                    int rc = issue_push(ctx, src.data(), ctx->stream, false, true);
+                    if (rc != CORR_OK) return rc;
+                    ctx->n_push += 1;
+                }
+            // block q + 1 of every block-deferred group, read from the history
+            for (int i : ctx->deferred_set) {
+                DeferredArgs da = deferred_args(ctx, i);
+                da.fixed_group = -2;
+                da.fixed_block = q + 1;
+                da.hist = static_cast<const char *>(samples[(size_t)i]) + (int64_t)r * stride[(size_t)i];
+                da.hist_stride = stride[(size_t)i];
+                da.stamps = ctx->d_stamps;
+                HIP_TRY(ctx, launch_history_fold(da, ctx->stream));
+            }
+            PushEndArgs pe{};
+            pe.step = ctx->d_step;
+            pe.advance = others ? 0 : T; // the other groups' pushes advanced the counter
+            pe.commit_block = q + 1;
+            pe.stamps = ctx->d_stamps;
+            for (int i : ctx->deferred_set) {
+                pe.defer_t[pe.n_flushed] = ctx->groups[(size_t)i].T;
+                pe.flushed[pe.n_flushed++] = ctx->groups[(size_t)i].d_flushed;
+            }
+            HIP_TRY(ctx, launch_push_end(pe, ctx->stream));
+            q += 1;
+            r += T;
+            if (!others) ctx->n_push += T;
+            for (int i : ctx->deferred_set) {
+                Group &g = ctx->groups[(size_t)i];
+                for (int j = 0; j < g.T; ++j) g.flushed[(size_t)j] = std::max(g.flushed[(size_t)j], q);
+            }
+        }
+    }
+    while (r < n_steps) {
+        int rc = one_push(r++);
+        if (rc != CORR_OK) return rc;
+    }
+    return CORR_OK;
+}
+
+int corr_group_form(const corr_ctx *ctx, int32_t group, int32_t *form, int32_t *block)
+{
+    if (!ctx) return CORR_E_INVALID;
+    if (group < 0 || group >= (int)ctx->groups.size()) return CORR_E_INVALID;
+    const Group &g = ctx->groups[(size_t)group];
+    const bool win = g.b == 1 && g.p >= kWindowMinP;
+    const int f = g.deferred ? 1 : g.wdef ? 2 : win ? 3 : 0;
+    if (form) *form = f;
+    if (block) *block = g.deferred ? g.T : g.wdef ? kWindowT : 0;
     return CORR_OK;
 }
 
@@ -1193,20 +1430,21 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes)
 int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n, int32_t reset)
 {
     if (!ctx) return CORR_E_INVALID;
-    if (which < 0 || which > 3) return set_err(ctx, CORR_E_INVALID, "which must be 0, 1, 2 or 3");
+    if (which < 0 || which > 4) return set_err(ctx, CORR_E_INVALID, "which must be 0 .. 4");
     if (!(ctx->flags & CORR_FLAG_TIMING))
         return set_err(ctx, CORR_E_STATE, "context created without CORR_FLAG_TIMING");
     DeviceGuard dg(ctx->device);
-    if (which == 3) {
-        // device stamps of the scheduled folds, every push
+    if (which >= 3) {
+        // device stamps of the folds (3) or the producers (4), every push
+        FoldStamps *rec = ctx->d_stamps + (which - 3);
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-        FoldStamps h{};
-        HIP_TRY(ctx, hipMemcpy(&h, ctx->d_stamps, sizeof(FoldStamps), hipMemcpyDeviceToHost));
-        if (ms_total) *ms_total = ctx->stamp_khz > 0 ? (double)h.total / ctx->stamp_khz : 0.0;
-        if (n) *n = (int64_t)h.count;
+        unsigned long long tc[2] = {0, 0}; // total, count
+        HIP_TRY(ctx, hipMemcpy(tc, &rec->total, sizeof(tc), hipMemcpyDeviceToHost));
+        if (ms_total) *ms_total = ctx->stamp_khz > 0 ? (double)tc[0] / ctx->stamp_khz : 0.0;
+        if (n) *n = (int64_t)tc[1];
         if (reset) {
-            const FoldStamps init{~0ull, 0ull, 0ull, 0ull};
-            HIP_TRY(ctx, hipMemcpy(ctx->d_stamps, &init, sizeof(FoldStamps), hipMemcpyHostToDevice));
+            const unsigned long long zero[2] = {0, 0};
+            HIP_TRY(ctx, hipMemcpy(&rec->total, zero, sizeof(zero), hipMemcpyHostToDevice));
         }
         return CORR_OK;
     }

@@ -385,17 +385,20 @@ def test_kernel_time_pools(corrmod):
                                 kvec=kv, n_atoms=N, box=box)]
     with corrmod.Correlator(groups, timing=True) as c:
         _push_all(c, [xv, xp])
-        for which in (0, 1, 2, 3):
+        for which in (0, 1, 2, 3, 4):
             ms, n = c.kernel_time(which)
             assert n == S and ms > 0.0, (which, n, ms)
-        # the device stamps of the fold span its events' interval at most
+        # the device stamps of the fold and of the producer span their events'
+        # intervals at most
         assert c.kernel_time(3)[0] <= c.kernel_time(1)[0] * 1.05 + 0.01
+        assert c.kernel_time(4)[0] <= c.kernel_time(2)[0] * 1.05 + 0.01
         ms, n = c.kernel_time(2, reset=True)
         assert c.kernel_time(2) == (0.0, 0)
-        c.kernel_time(3, reset=True)
-        assert c.kernel_time(3) == (0.0, 0)
+        for which in (3, 4):
+            c.kernel_time(which, reset=True)
+            assert c.kernel_time(which) == (0.0, 0)
         with pytest.raises(corrmod.CorrError):
-            c.kernel_time(4)
+            c.kernel_time(5)
     # one push in 8 timed (pushes 0, 8, ..., 64 of 70): same state as every push timed
     with corrmod.Correlator(groups, timing=True) as c, corrmod.Correlator(groups) as ref:
         c.set_timing_stride(8)
@@ -406,7 +409,7 @@ def test_kernel_time_pools(corrmod):
         for which in (0, 1, 2):
             ms, n = c.kernel_time(which)
             assert n == 9 and ms > 0.0, (which, n, ms)
-        assert c.kernel_time(3)[1] == S  # device stamps on every push
+        assert c.kernel_time(3)[1] == S and c.kernel_time(4)[1] == S  # stamps on every push
         assert np.array_equal(c.finalize(0, slice_=(0, 3))["c_per_channel"],
                               ref.finalize(0, slice_=(0, 3))["c_per_channel"])
         with pytest.raises(corrmod.CorrError):
@@ -913,3 +916,127 @@ def test_push_steps_equals_single_pushes(corrmod):
         o.push(oracle.rhok(pos[s], kv, box))
     gate(res[3], o, TOL[("cf32", "kahan")], scale=1.0 / N, slice_=(0, 3), label="n(k)")
     gate(res[4], oracle_run(xw, 1, 640, 2), TOL[("cf32", "kahan")], slice_=(0, 3), label="window")
+
+
+@pytest.mark.parametrize("fold_block", [128, 256])
+def test_fold_block_lengths_against_oracle(corrmod, fold_block):
+    """The block-deferred form with 128- and 256-push blocks (tuning
+    fold_block): compensated and FP64 sums against the oracle at readouts on
+    both sides of block boundaries, and a replay that folds whole blocks from
+    the history bit for bit equal to single pushes."""
+    S, n = 3 * fold_block + 37, 2500
+    x = ou_inputs(61, 1, n, S, "f32")
+    dev = torch.device("cuda:0")
+    hx = torch.from_numpy(x).to(dev)
+    say(f"[fold block {fold_block}] n={n} S={S}")
+    tn = dict(tile_channels=256, chans_per_thread=1, lag_chunk=8, grid_blocks=0,
+              fold_block=fold_block)
+    groups = [corrmod.GroupDesc(n, 7, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(n, 7, 16, 2, dtype="f32", accum="f64")]
+    o = oracle.OracleCorrelator(n, 7, 16, 2)
+    with corrmod.Correlator(groups, tuning=tn) as a, corrmod.Correlator(groups, tuning=tn) as b:
+        assert a.group_form(0) == (1, fold_block)
+        done = 0
+        for stop in (fold_block - 1, fold_block, fold_block + 1, 2 * fold_block + 5, S):
+            for s in range(done, stop):
+                a.push([hx[s], hx[s]])
+            o.push_series(x[done:stop])
+            done = stop
+            for g, accum in ((0, "kahan"), (1, "f64")):
+                gate(a.finalize(g, slice_=(0, 3)), o, TOL[("f32", accum)], slice_=(0, 3),
+                     label=f"T={fold_block} {accum} at {stop}")
+        b.push_steps([hx[:29], hx[:29]])
+        b.push_steps([hx[29:], hx[29:]])  # crosses whole blocks: folded from the history
+        torch.cuda.synchronize()
+        for g in (0, 1):
+            ra, rb = a.finalize(g, slice_=(n - 3, n)), b.finalize(g, slice_=(n - 3, n))
+            assert np.array_equal(ra["c"], rb["c"]) and np.array_equal(ra["c_per_channel"],
+                                                                        rb["c_per_channel"])
+
+
+def test_fold_threads_bitwise(corrmod):
+    """Threads per block of the scheduled fold (64, 128, 256) change only the
+    launch shape: identical results bit for bit."""
+    S, n = 600, 3000
+    x = ou_inputs(62, 1, n, S, "f32")
+    out = {}
+    for nt in (64, 128, 256):
+        tn = dict(tile_channels=512, chans_per_thread=2, lag_chunk=8, grid_blocks=0,
+                  fold_threads=nt)
+        with corrmod.Correlator([corrmod.GroupDesc(n, 6, 16, 2, dtype="f32", accum="kahan")],
+                                tuning=tn) as c:
+            assert c.tuning()["fold_threads"] == nt
+            _push_all(c, [x])
+            out[nt] = c.finalize(0, slice_=(0, n))["c_per_channel"]
+    assert np.array_equal(out[64], out[128]) and np.array_equal(out[256], out[128])
+
+
+def test_graph_replay_equals_single_pushes(corrmod):
+    """Graph mode: corr_push_steps captures its pushes once and replays the
+    graph for later calls with the same histories -- the same state bit for
+    bit as single pushes, for block-deferred, FP64, n(k) and window groups,
+    with readouts between replays."""
+    S, nv, N, box, chunk = 4 * 150, 3000, 600, 20.0, 150
+    kv = synth.kvectors(16)
+    xv = ou_inputs(63, 1, nv, S, "f32")
+    xg = ou_inputs(63, 2, 9, S, "f64")
+    pos, _ = synth.PositionSpec(63, 3, N, box).series(0, S)
+    xw = ou_inputs(63, 4, 100, S, "f32")
+    groups = [corrmod.GroupDesc(nv, 6, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(9, 8, 16, 2, dtype="f64", accum="f64"),
+              corrmod.GroupDesc(len(kv), 4, 16, 2, dtype="cf32", accum="kahan", source="rhok",
+                                kvec=kv, n_atoms=N, box=box),
+              corrmod.GroupDesc(100, 1, 600, 2, dtype="f32", accum="f64")]
+    dev = torch.device("cuda:0")
+    hs = [torch.from_numpy(a).to(dev) for a in (xv, xg, pos, xw)]
+    bufs = [torch.empty((chunk,) + tuple(h.shape[1:]), dtype=h.dtype, device=dev) for h in hs]
+    with corrmod.Correlator(groups) as a, corrmod.Correlator(groups, graph=True) as b:
+        for s0 in range(0, S, chunk):
+            for buf, h in zip(bufs, hs):
+                buf.copy_(h[s0:s0 + chunk])  # the same buffers every call: one capture
+            for s in range(s0, s0 + chunk):
+                a.push([h[s] for h in hs])
+            b.push_steps(bufs)
+            torch.cuda.synchronize()
+            for g in range(4):
+                ra, rb = a.finalize(g, slice_=(0, 3)), b.finalize(g, slice_=(0, 3))
+                assert np.array_equal(ra["c_per_channel"], rb["c_per_channel"]), (s0, g)
+        assert a.n_pushes() == b.n_pushes() == S
+    gate(rb, oracle_run(xw, 1, 600, 2), TOL[("f32", "f64")], slice_=(0, 3), label="window")
+
+
+def test_state_that_fits_only_with_the_shorter_block(corrmod):
+    """A block-deferred group too large for 256-push blocks in the device's
+    free memory (3648 B per channel) but not for 128-push blocks (2624 B): the
+    library takes T = 128 by itself; sampled channels against the oracle."""
+    free, total = torch.cuda.mem_get_info()
+    n = int(0.80 * free / 2624) // 1024 * 1024
+    assert n * 3648 > free  # the longer block could not fit
+    S, chunk = 300, 20
+    say(f"[fit] free {free / 1e9:.1f} GB: {n} channels, b=12, compensated")
+    spec = synth.OUSpec.make(seed=64, stream=1, n=n, comps=3, tau=20, tau_hi=200)
+    gen = synth.GpuOU(spec)
+    buf = torch.empty((chunk, n), dtype=torch.float32, device="cuda")
+    with corrmod.Correlator([corrmod.GroupDesc(n, 12, 16, 2, dtype="f32", accum="kahan")]) as c:
+        assert c.group_form(0) == (1, 128)
+        say(f"  state {c.state_bytes(0) / 1e9:.1f} GB")
+        for _ in range(0, S, chunk):
+            gen.fill(buf, chunk)
+            c.push_steps([buf])
+        torch.cuda.synchronize()
+        ranges = [(0, 2), (n // 2, n // 2 + 2), (n - 2, n)]
+        res = [c.finalize(0, slice_=r) for r in ranges]
+    del buf
+    torch.cuda.empty_cache()
+    chans = np.concatenate([np.arange(lo, hi) for lo, hi in ranges])
+    xs, _ = spec.series(0, S, channels=chans)
+    o = oracle.OracleCorrelator(len(chans), 12, 16, 2)
+    o.push_series(xs)
+    i = 0
+    for r, (lo, hi) in zip(res, ranges):
+        for j in range(hi - lo):
+            t, cc, cnt = o.readout(i, i + 1)
+            assert np.array_equal(r["t"], t) and np.array_equal(r["count"], cnt)
+            err = np.max(np.abs(r["c_per_channel"][j] - cc)) / abs(cc[0])
+            assert err <= TOL[("f32", "kahan")], (lo + j, err)
+            i += 1
