@@ -21,7 +21,7 @@
 // dropped a_lo b_lo is below 2^-22), i.e. three fp16 matrix products with
 // fp32 accumulation per sum, twelve per K-step.  The fp32 accumulators are
 // added to double accumulators after every kAccAtoms atoms (an fp32 partial
-// sum of at most 128 terms of magnitude <= 1 each) and the blocks write double
+// sum of at most 256 terms of magnitude <= 1 each) and the blocks write double
 // partials, reduced over the atom blocks in a fixed order as in the
 // vector-unit producer (corr_rhok.hip), so the result is reproducible.  The tables start from e^{2 pi i x / L} in double (a 64-entry
 // root table times a short Taylor series) and take the powers by a double
@@ -68,8 +68,9 @@ template <int NW> struct ScaleSlots { static constexpr int n = NW == 1 ? 0 : 8; 
 // B fragments in LDS: [K-step][part: re hi, re lo, im hi, im lo][atom group][column]
 constexpr int kBParts = 4;
 // atoms whose products the fp32 matrix accumulators sum before they are added
-// to the double accumulators
-constexpr int kAccAtoms = 128;
+// to the double accumulators (256: the promotion's 16 conversions and double
+// adds per 128-atom tile halve; C(0) of 2048 k at 10^6 atoms moves by 2e-7)
+constexpr int kAccAtoms = 256;
 
 // The LDS tile of TA atoms: K-steps, table row stride (float2; TA + 2 shifts
 // consecutive rows by 4 banks) and B fragments per weight set.  128-atom tiles
@@ -212,13 +213,15 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
 #pragma unroll
             for (int s = 0; s < NW; ++s) {
                 const double wd = NW == 1 ? 1.0 : (double)w[s] * wsc[s];
-                float zr = (float)(pr * wd), zi = (float)(pi * wd);
-                // keep the float rounding step visible: otherwise double ->
-                // float -> half is folded into one double -> half conversion,
-                // which has no instruction and is expanded into integer code
-                asm volatile("" : "+v"(zr), "+v"(zi));
-                const _Float16 rh = (_Float16)zr, ih = (_Float16)zi;
-                const _Float16 rl = (_Float16)(zr - (float)rh), il = (_Float16)(zi - (float)ih);
+                const float zr = (float)(pr * wd), zi = (float)(pi * wd);
+                // hi of both parts in one packed conversion, lo by one
+                // mixed-precision fma each (as for P in the contraction)
+                const uint32_t hh = pack_half2(zr, zi);
+                uint32_t ll;
+                lo_half2(ll, hh, zr, zi);
+                typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+                const h2v H = __builtin_bit_cast(h2v, hh), L = __builtin_bit_cast(h2v, ll);
+                const _Float16 rh = H[0], ih = H[1], rl = L[0], il = L[1];
                 _Float16 *bs = bh + (size_t)s * Tile<TA>::bfrags * kAtomsPerLane;
                 bs[bfrag_index(ks, 0, g, n) * kAtomsPerLane + h] = rh;
                 bs[bfrag_index(ks, 1, g, n) * kAtomsPerLane + h] = rl;
