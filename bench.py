@@ -79,8 +79,11 @@ def parse():
                     help="skip the bounded leg that times the plain FP64 per-group form on the "
                          "largest sample-fed group (run by default)")
     ap.add_argument("--eager", action="store_true",
-                    help="time block-deferred workloads eagerly (one corr_push per step) instead "
-                         "of as captured HIP graphs per chunk of pushes")
+                    help="time every workload eagerly (one corr_push per step); by default "
+                         "block-deferred workloads whose pushes fork onto a side stream are timed "
+                         "as captured HIP graphs per chunk of pushes")
+    ap.add_argument("--graph", action="store_true",
+                    help="time block-deferred workloads as captured HIP graphs even on one stream")
     ap.add_argument("--no-mode-leg", action="store_true",
                     help="skip the leg that times the other issue form (eager beside a graph "
                          "headline, graphs beside an eager one)")
@@ -605,11 +608,17 @@ def run(args):
         tune_s = time.perf_counter() - t0
     if args.overlap is not None:
         tuning = dict(tuning or {}, overlap_producers=args.overlap)
-    # Block-deferred workloads are timed as captured HIP graphs (one graph per
-    # chunk of pushes, corr_push_steps on a CORR_FLAG_GRAPH context), the
-    # eager form beside them; the others eagerly, one corr_push per step.
+    # Block-deferred workloads whose issue order forks onto a side stream are
+    # timed as captured HIP graphs (one graph per chunk of pushes,
+    # corr_push_steps on a CORR_FLAG_GRAPH context), the eager form beside
+    # them: there the graph's edges replace the per-push fork and join (1.7 to
+    # 4% faster on the batched line).  On one stream eager in-order launches
+    # were faster than graph replays (large 0.247 against 0.259 ms per push),
+    # so those lines are timed eagerly with the graph form beside them.
+    tn_order = (tuning or {}).get("overlap_producers", 0)
     use_graph = (not args.eager and not args.replay and not args.direct and mode != "per_group"
-                 and any(deferred(g) for g in wl["groups"]))
+                 and any(deferred(g) for g in wl["groups"])
+                 and (args.graph or (tn_order != 0 and len(wl["groups"]) > 1)))
     corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuning, timing=True,
                       direct=args.direct, rhok_valu=args.rhok_valu, graph=use_graph)
     state_gb = sum(corr.state_bytes(i) for i in range(len(descs))) / 1e9

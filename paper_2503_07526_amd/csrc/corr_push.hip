@@ -442,22 +442,28 @@ __global__ void push_end_kernel(PushEndArgs a)
 {
     if (blockIdx.x != 0) return;
     if (a.stamps) {
-        // each lane takes one slot of both stamp records; the wave's earliest
-        // start and latest end give the push's span of each class
-        __shared__ unsigned long long lo[kStampSlots], hi[kStampSlots];
+        // the lanes take the slots of both stamp records in turn; the earliest
+        // start and the latest end give the push's span of each class
+        __shared__ unsigned long long lo[64], hi[64];
         for (int r = 0; r < 2; ++r) {
             FoldStamps &st = a.stamps[r];
             const int l = threadIdx.x;
-            if (l < kStampSlots) {
-                lo[l] = st.slot[l].start;
-                hi[l] = st.slot[l].end;
-                st.slot[l].start = ~0ull;
-                st.slot[l].end = 0;
+            if (l < 64) {
+                unsigned long long s0 = ~0ull, e0 = 0;
+                for (int q = l; q < kStampSlots; q += 64) {
+                    const unsigned long long a0 = st.slot[q].start, b0 = st.slot[q].end;
+                    s0 = a0 < s0 ? a0 : s0;
+                    e0 = b0 > e0 ? b0 : e0;
+                    st.slot[q].start = ~0ull;
+                    st.slot[q].end = 0;
+                }
+                lo[l] = s0;
+                hi[l] = e0;
             }
             __syncthreads();
             if (threadIdx.x == 0) {
                 unsigned long long s0 = ~0ull, e0 = 0;
-                for (int q = 0; q < kStampSlots; ++q) {
+                for (int q = 0; q < 64; ++q) {
                     s0 = lo[q] < s0 ? lo[q] : s0;
                     e0 = hi[q] > e0 ? hi[q] : e0;
                 }
