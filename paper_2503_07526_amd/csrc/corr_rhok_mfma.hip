@@ -32,15 +32,20 @@
 // and receives D[4(l/16)+v][l%16] for v < 4.  Only the pairing of A and B
 // along K matters for the sum, and it is the same for both operands.
 //
-// Work split: block (chunk, atom block); each wave of a block owns one M tile
-// and all waves share the tile's LDS tables: X and Y powers as float2
+// Work split: block (chunk, atom block); each contraction wave of a block
+// owns one M tile and all waves share the tile's LDS tables: X and Y powers as float2
 // [rows][Tile::stride] (a row per power that a pair of the k-set uses: n_x in
 // [x_lo, x_lo + x_rows), n_y likewise; atoms along the row, so a lane's
 // atoms are 16-byte reads; the row stride is padded so that the 16 rows a
 // K-step reads start in different banks) and the split |n_z| powers already
-// in B-fragment order.  The tables are double-buffered: the first waves build
-// the next tile's tables while every wave contracts the current one, one
-// barrier per tile, and the positions are loaded a tile ahead.
+// in B-fragment order.  The tables are double-buffered: builder waves build
+// the next tile's tables while the contraction waves contract the current
+// one, one barrier per tile, and the positions are loaded a tile ahead.  With
+// one weight set a block has two more waves than M tiles: they build the Z
+// fragments and contract nothing, waves 0..3 build X and Y besides their own
+// M tile.  Waves w and w + 4 of a block share a SIMD, so with ten M tiles the
+// two Z waves (10, 11) join the SIMDs of waves 2, 6 and 3, 7, which hold two
+// M tiles, not three.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
@@ -59,7 +64,8 @@ constexpr int kKStep = 4 * kAtomsPerLane; // atoms per K-step
 typedef _Float16 halfv_t __attribute__((ext_vector_type(kAtomsPerLane)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaMaxWaves = 12;  // waves per block (one M tile each)
+constexpr int kMfmaMaxWaves = 12;  // waves per block
+constexpr int kZWaves = 2;         // one weight set: waves per block that only build Z
 constexpr int kMfmaCols = 16;      // |n_z| = 0 .. 15
 constexpr int kRoots = 64;         // e^{2 pi i q / kRoots} table for the base phase
 // LDS after the root table for the weight scales (three weight sets): the
@@ -165,7 +171,9 @@ struct TileBufs {
     halfv_t *bfr;   // [NW][Tile::bfrags]
 };
 
-// Build the tables of one tile.  Task (power part hf, axis d, atom j): with
+// Build the tables of one tile.  Task (power part hf, axis d, atom j), the
+// task of lane `lane` of task wave `twave` (uniform over the wave, which
+// fixes hf and d: 64 divides the tile, so all control flow is uniform): with
 // two parts, part 0 takes n = 0 .. n1 and part 1 takes n = n1+1 .. nmax
 // starting from its own e^{2 pi i n1 x / L} (both from unit_phase).  Powers
 // by a double recurrence, each rounded once; X and Y rows for both signs, and
@@ -173,25 +181,24 @@ struct TileBufs {
 // fragments (NW = 1: w = 1; NW = 3: the atom's velocity components).  Atoms
 // past the end (live == false) get zero entries, so they add nothing.
 template <int NW, int TA>
-__device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool live, float x,
+__device__ __forceinline__ void build_tile(const TileBufs &tb, int twave, int lane, bool live, float x,
                                            const float (&w)[NW], const double (&wsc)[NW],
                                            double inv_box, int nmax, int2 xrows, int2 yrows,
                                            const double2 *roots)
 {
-    const int hf = task / (3 * Tile<TA>::atoms);
-    const int rem = task - hf * 3 * Tile<TA>::atoms;
-    const int d = rem / Tile<TA>::atoms, j = rem - d * Tile<TA>::atoms;
+    const int hf = twave * 64 / (3 * Tile<TA>::atoms);
+    const int rem = twave * 64 - hf * 3 * Tile<TA>::atoms;
+    const int d = rem / Tile<TA>::atoms, j = rem - d * Tile<TA>::atoms + lane;
     const int n1 = TableShape<NW, TA>::parts == 1 ? nmax : (nmax + 1) / 2;
     const int n_begin = hf == 0 ? 0 : n1 + 1, n_end = hf == 0 ? n1 : nmax;
     const double f = (double)x * inv_box;
-    double cs = 0.0, sn = 0.0, pr = 0.0, pi = 0.0;
-    if (live) {
-        unit_phase(f, roots, cs, sn);
-        if (hf == 0) {
-            pr = 1.0;
-        } else {
-            unit_phase(f * n1, roots, pr, pi); // e^{i n1 theta}; n1 f is exact to 1 ulp
-        }
+    // every lane evaluates (x = 0 past the end); a dead lane's powers are zero
+    double cs, sn, pr = live ? 1.0 : 0.0, pi = 0.0;
+    unit_phase(f, roots, cs, sn);
+    if (hf != 0) {
+        unit_phase(f * n1, roots, pr, pi); // e^{i n1 theta}; n1 f is exact to 1 ulp
+        pr = live ? pr : 0.0;
+        pi = live ? pi : 0.0;
     }
     if (d < 2) {
         // rows lo .. hi of this axis; row of power m at zero + m * stride
@@ -208,8 +215,7 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
     } else {
         const int ks = j / kKStep, g = (j % kKStep) / kAtomsPerLane, h = j % kAtomsPerLane;
         _Float16 *bh = reinterpret_cast<_Float16 *>(tb.bfr);
-        for (int n = n_begin; n <= n_end; ++n) {
-            if (n > 0) cmul(pr, pi, cs, sn);
+        auto store_z = [&](int n) {
 #pragma unroll
             for (int s = 0; s < NW; ++s) {
                 const double wd = NW == 1 ? 1.0 : (double)w[s] * wsc[s];
@@ -228,6 +234,11 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int task, bool li
                 bs[bfrag_index(ks, 2, g, n) * kAtomsPerLane + h] = ih;
                 bs[bfrag_index(ks, 3, g, n) * kAtomsPerLane + h] = il;
             }
+        };
+        if (n_begin == 0) store_z(0);
+        for (int n = n_begin > 0 ? n_begin : 1; n <= n_end; ++n) {
+            cmul(pr, pi, cs, sn);
+            store_z(n);
         }
     }
 }
@@ -257,13 +268,16 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
         return t;
     };
 
+    // One weight set: the last kZWaves waves of a block only build Z.
+    constexpr bool kZBuilders = NW == 1 && TA == 128;
     const int waves = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15; // A row / B column within the tile
     const int grp = lane >> 4; // atom group of the K-step
-    const int mt = blockIdx.x * waves + wave;
-    const bool active = mt < a.n_mtiles; // wave-uniform
+    const int cwaves = kZBuilders ? waves - kZWaves : waves; // contraction waves
+    const int mt = blockIdx.x * cwaves + wave;
+    const bool active = wave < cwaves && mt < a.n_mtiles; // wave-uniform
     const int pm_row = mt * 16 + col;
     const int ax = active ? a.pair_nx[pm_row] - a.x_lo : 0; // table rows
     const int ay = active ? a.pair_ny[pm_row] - a.y_lo : 0;
@@ -334,10 +348,18 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
         }
     }
 
-    // table task of this thread (blockDim >= TableShape<NW, TA>::tasks) and its inputs,
-    // loaded one tile ahead of their use; the Z task also loads the weights
-    const int task = threadIdx.x;
-    const bool builder = task < TableShape<NW, TA>::tasks;
+    // table task of this thread and its inputs, loaded one tile ahead of their
+    // use; the Z task also loads the weights.  Task wave t holds tasks 64 t ..
+    // 64 t + 63.  One weight set: X and Y tasks on waves 0..3, Z on the last
+    // two waves (a block has at least six); otherwise task wave = wave.
+    // (the wave index as a wave-uniform value: the build's loops and branches
+    // then stay scalar; `wave` itself stays a vector value, which measured
+    // 6% faster in the contraction)
+    const int wv_u = __builtin_amdgcn_readfirstlane(wave);
+    const int twave = __builtin_amdgcn_readfirstlane(
+        kZBuilders && wv_u >= 4 ? (wv_u >= waves - kZWaves ? 4 + wv_u - (waves - kZWaves) : 6 + wv_u) : wv_u);
+    const int task = twave * 64 + lane;
+    const bool builder = twave * 64 < TableShape<NW, TA>::tasks; // wave-uniform
     const int trem = task % (3 * Tile<TA>::atoms);
     const int td = trem / Tile<TA>::atoms, tj = trem - td * Tile<TA>::atoms;
     const bool weighted = NW > 1 && td == 2;
@@ -355,8 +377,8 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
     bool live_next = load_in(1, x_next, w_next);
     __syncthreads(); // roots and zero columns
     if (builder)
-        build_tile<NW, TA>(tile_bufs(0), task, live_cur, x_cur, w_cur, wsc, a.inv_box, nmax, xrows,
-                           yrows, lds_roots);
+        build_tile<NW, TA>(tile_bufs(0), twave, lane, live_cur, x_cur, w_cur, wsc, a.inv_box, nmax,
+                           xrows, yrows, lds_roots);
     __syncthreads();
 
     for (int it = 0; it < n_tiles; ++it) {
@@ -365,8 +387,8 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
         if (builder && it + 1 < n_tiles) {
             float x_after, w_after[NW];
             const bool live_after = load_in(it + 2, x_after, w_after);
-            build_tile<NW, TA>(tile_bufs((it + 1) & 1), task, live_next, x_next, w_next, wsc,
-                               a.inv_box, nmax, xrows, yrows, lds_roots);
+            build_tile<NW, TA>(tile_bufs((it + 1) & 1), twave, lane, live_next, x_next, w_next,
+                               wsc, a.inv_box, nmax, xrows, yrows, lds_roots);
             x_next = x_after;
 #pragma unroll
             for (int s = 0; s < NW; ++s) w_next[s] = w_after[s];
@@ -596,16 +618,18 @@ hipError_t rhok_mfma_prepare(int table_rows, int nw)
 
 int rhok_mfma_chunks(int n_mtiles, int nw)
 {
-    const int maxw = nw == 3 ? MfmaShape<3>::max_waves : MfmaShape<1>::max_waves;
-    return (n_mtiles + maxw - 1) / maxw;
+    // M tiles per block (one weight set: two of the block's waves build Z)
+    const int maxt = nw == 3 ? MfmaShape<3>::max_waves : MfmaShape<1>::max_waves - kZWaves;
+    return (n_mtiles + maxt - 1) / maxt;
 }
 
 template <int NW, int TA> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t st)
 {
-    // waves per block: the M tiles dealt evenly over the fewest blocks, at
-    // least one thread per table task
+    // waves per block: the M tiles dealt evenly over the fewest blocks (one
+    // weight set: and the two Z waves), at least one thread per table task
     const int chunks = rhok_mfma_chunks(a.n_mtiles, NW);
     int waves = (a.n_mtiles + chunks - 1) / chunks;
+    if (NW == 1 && TA == 128) waves += kZWaves;
     if (waves < TableShape<NW, TA>::min_waves) waves = TableShape<NW, TA>::min_waves;
     const size_t lds = lds_bytes<NW, TA>(a.x_rows + a.y_rows);
     hipLaunchKernelGGL((rhok_mfma_kernel<NW, TA>), dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
