@@ -199,7 +199,12 @@ typedef struct corr_tuning {
 
 /*
  * Create a context for n_groups channel groups on HIP device `device`, whose
- * work is issued on `stream`.  Validates every descriptor (CORR_E_INVALID on
+ * work is issued on `stream`.  A group is a set of correlators of one shape
+ * (b blocks, p points, averaging m; section "Correlation functions at
+ * runtime" and the appendix on general correlations: one correlator per
+ * observable, each with its shift arrays, accumulators and correlation sums
+ * per block); corr_create allocates that state for every channel, all of
+ * it on the device.  Validates every descriptor (CORR_E_INVALID on
  * b < 1, p < 2, m < 2, m >= p, n_channels < 1, u < 1, an unknown dtype /
  * accumulator / source, a compensated or FP32 accumulator with a double
  * dtype, a k-density group without k-vectors, positions or a positive box),
@@ -211,8 +216,11 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 uint32_t flags, const corr_tuning *tuning, corr_ctx **out);
 
 /* Device buffer the library reads a group's samples from when corr_push is
- * given NULL for that group: n_channels elements of the group dtype, or for
- * CORR_SRC_RHOK float positions [3][n_atoms].  The pointer is stable for the
+ * given NULL for that group: the newly observed values that Algorithm 1
+ * (appendix on general correlations) feeds to each correlator of the group,
+ * n_channels elements of the group dtype, or for CORR_SRC_RHOK float
+ * positions [3][n_atoms] (the atoms of Eq. k-density, section "Currents").
+ * The library owns the buffer; *bytes receives its size.  The pointer is stable for the
  * life of the context (required by graph mode). */
 int corr_input_buffer(corr_ctx *ctx, int32_t group, void **dev_ptr, size_t *bytes);
 
