@@ -80,10 +80,8 @@ def parse():
                          "largest sample-fed group (run by default)")
     ap.add_argument("--eager", action="store_true",
                     help="time every workload eagerly (one corr_push per step); by default "
-                         "block-deferred workloads whose pushes fork onto a side stream are timed "
-                         "as captured HIP graphs per chunk of pushes")
-    ap.add_argument("--graph", action="store_true",
-                    help="time block-deferred workloads as captured HIP graphs even on one stream")
+                         "block-deferred workloads are timed as captured HIP graphs per chunk of "
+                         "pushes")
     ap.add_argument("--no-mode-leg", action="store_true",
                     help="skip the leg that times the other issue form (eager beside a graph "
                          "headline, graphs beside an eager one)")
@@ -233,7 +231,7 @@ TRAFFIC_SOURCE = "paper_2503_07526_amd/csrc/corr_deferred.hip"
 TRAFFIC_HEADER = "paper_2503_07526_amd/csrc/corr_internal.h"
 TRAFFIC_HEADER_PARTS = ("enum Kind", "struct GroupArgs", "struct DeferredArgs", "kDeferT",
                         "kFlushGroups", "acc_planes", "kind_complex", "kind_sample_bytes",
-                        "kind_acc_bytes")
+                        "kind_acc_bytes", "struct FoldStamps", "kStampSlots", "stamp_")
 
 
 def _strip_comments(src):
@@ -608,22 +606,19 @@ def run(args):
         tune_s = time.perf_counter() - t0
     if args.overlap is not None:
         tuning = dict(tuning or {}, overlap_producers=args.overlap)
-    # Block-deferred workloads whose issue order forks onto a side stream are
-    # timed as captured HIP graphs (one graph per chunk of pushes,
-    # corr_push_steps on a CORR_FLAG_GRAPH context), the eager form beside
-    # them: there the graph's edges replace the per-push fork and join (1.7 to
-    # 4% faster on the batched line).  On one stream eager in-order launches
-    # were faster than graph replays (large 0.247 against 0.259 ms per push),
-    # so those lines are timed eagerly with the graph form beside them.
-    tn_order = (tuning or {}).get("overlap_producers", 0)
+    # Block-deferred workloads are timed as captured HIP graphs (one graph per
+    # chunk of pushes, corr_push_steps on a CORR_FLAG_GRAPH context), the eager
+    # form beside them (1.5 to 6% slower on every such line once the timing
+    # stamps sample one push in timing_stride); the others eagerly, one
+    # corr_push per step.
     use_graph = (not args.eager and not args.replay and not args.direct and mode != "per_group"
-                 and any(deferred(g) for g in wl["groups"])
-                 and (args.graph or (tn_order != 0 and len(wl["groups"]) > 1)))
+                 and any(deferred(g) for g in wl["groups"]))
     corr = Correlator(descs, per_group=(mode == "per_group"), tuning=tuning, timing=True,
                       direct=args.direct, rhok_valu=args.rhok_valu, graph=use_graph)
     state_gb = sum(corr.state_bytes(i) for i in range(len(descs))) / 1e9
-    if not use_graph:
-        corr.set_timing_stride(args.timing_stride)
+    # events and device stamps on one push in timing_stride (a stored-history
+    # replay stamps every block fold: there are few of them)
+    corr.set_timing_stride(1 if args.replay else args.timing_stride)
     # the update form and fold block the library chose for each group
     wl = dict(wl, groups=[dict(g) for g in wl["groups"]])
     for i, g in enumerate(wl["groups"]):
@@ -683,12 +678,12 @@ def run(args):
     # branch runs beside them)
     timed = [g for g in wl["groups"]
              if not (has_rhok and len(wl["groups"]) > 1 and g["kind"] in PRODUCER_KINDS)]
-    # device stamps of every push: the folds (3) and the producers (4)
+    # device stamps of one push in timing_stride: the folds (3) and the producers (4)
     fs_ms, fs_n = corr.kernel_time(which=3)
     ps_ms, ps_n = corr.kernel_time(which=4)
     fl_bytes_all = sum(staggered_flush_bytes(g, s, tw) for g in timed if deferred(g, direct)
                        for s in steps)
-    # HIP events (eager pushes only): one push in timing_stride
+    # HIP events (eager pushes only), like the stamps on one push in timing_stride
     kern_ms, kern_n = corr.kernel_time(0)
     fl_ms, fl_n = corr.kernel_time(which=1)
     rk_ms, rk_n = corr.kernel_time(which=2)
@@ -706,20 +701,20 @@ def run(args):
     flop_per = None
     if momentum_dominant:
         # the momentum density producers: per atom three velocity components
-        # and a one-byte species id; device stamps of every push's producers
+        # and a one-byte species id; device stamps of the sampled pushes' producers
         per_launch_bytes = sum(g["n_atoms"] * (3 * SB[g["dtype"]] + 1) for g in wl["groups"]
                                if g["kind"] == "momentum")
         per_launch_ms = ps_ms / ps_n
         achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
         kname = ("momentum density producer (HBM-bound reduction over the atoms), device stamps "
-                 "of every push")
+                 "of one push in %d" % args.timing_stride)
     elif producer_dominant:
         # the producers of every k-space group, per push
         flop_per = sum(producer_flop(g) for g in wl["groups"] if g["kind"] in PRODUCER_KINDS)
         per_launch_ms = ps_ms / ps_n
         achieved = flop_per / (per_launch_ms * 1e-3) / 1e12
         kname = ("k-space producers (matrix cores), device stamps spanning the producer launches "
-                 "of every push")
+                 "of one push in %d" % args.timing_stride)
         per_launch_bytes = None
     elif push_dominant:
         # the per-step correlator update of every group (direct form): the
@@ -734,25 +729,27 @@ def run(args):
         g0 = wl["groups"][0]
         if g0["kind"] == "currents":
             flop_per = CURRENTS_FLOP_PER_ATOM_K * (g0["n"] // 3) * g0["n_atoms"]
-            kname = "current producer (matrix cores), device stamps of every launch"
+            kname = ("current producer (matrix cores), device stamps of one launch in %d"
+                     % args.timing_stride)
         else:
             flop_per = RHOK_FLOP_PER_ATOM_K * g0["n"] * g0["n_atoms"]
-            kname = ("k-density producer (%s), device stamps of every launch"
-                     % ("vector units" if args.rhok_valu else "matrix cores"))
+            kname = ("k-density producer (%s), device stamps of one launch in %d"
+                     % ("vector units" if args.rhok_valu else "matrix cores", args.timing_stride))
         achieved = flop_per / (ps_ms / ps_n * 1e-3) / 1e12
         per_launch_ms, per_launch_bytes = ps_ms / ps_n, None
     elif fs_n:
-        # dominant kernel: the flush of the block-deferred groups, every timed push
-        assert fs_n == K, (fs_n, K)
+        # dominant kernel: the flush of the block-deferred groups, stamped on the
+        # sampled pushes
+        assert fs_n == len(sampled), (fs_n, len(sampled))
         if fl_bytes_all <= 0:
             raise RuntimeError("the timed pushes carried no fold work (pushes %d..%d): the "
                                "block-deferred line would not measure its dominant kernel"
                                % (s_first, s_first + K - 1))
-        achieved = fl_bytes_all / (fs_ms * 1e-3) / 1e9
+        achieved = fl_bytes / (fs_ms * 1e-3) / 1e9
         T0 = max(block_of(g) for g in timed if deferred(g, direct))
         kname = ("flush kernel (block-deferred fold of %d pushes for 1/%d of the channels per "
-                 "push), device stamps of every launch" % (T0, T0))
-        per_launch_ms, per_launch_bytes = fs_ms / fs_n, fl_bytes_all / fs_n
+                 "push), device stamps of one launch in %d" % (T0, T0, args.timing_stride))
+        per_launch_ms, per_launch_bytes = fs_ms / fs_n, fl_bytes / fs_n
     else:
         achieved = (stage_bytes + fl_bytes) / (kern_ms * 1e-3) / 1e9
         kname = ("push kernel (correlator update of %d of %d groups), HIP events per launch"

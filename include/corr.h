@@ -387,13 +387,19 @@ int corr_state_bytes(const corr_ctx *ctx, int32_t group, int64_t *bytes);
  * splits the lag range over the grid. */
 int corr_kernel_time(corr_ctx *ctx, int32_t which, double *ms_total, int64_t *n, int32_t reset);
 
-/* With CORR_FLAG_TIMING: record the timing events (all three kinds of
- * corr_kernel_time) only on pushes whose index n (pushes completed before it)
- * satisfies n % stride == 0, so that the events themselves (each one a
- * completion signal between two kernels) slow the other pushes down by
- * nothing; the times and counts of corr_kernel_time then cover those pushes
- * only.  stride >= 1 (default 1: every push); CORR_E_INVALID otherwise,
- * CORR_E_STATE without the flag.  Takes effect from the next push. */
+/* With CORR_FLAG_TIMING: record the timing events (the three event kinds of
+ * corr_kernel_time) and the device stamps (the two stamp kinds) only on pushes
+ * whose index n (pushes completed before it) satisfies n % stride == 0, so
+ * that the events (each one a completion signal between two kernels) and the
+ * stamps (atomics of every block, reduced by the push's last kernel) slow the
+ * other pushes down by nothing; the times and counts of corr_kernel_time then
+ * cover those pushes only.  The stamps take the push index from the device
+ * counter, so captured graphs and stored-history replays follow the stride
+ * too (a block folded from a stored history is stamped when the counter at
+ * its launch is a multiple of the stride).
+ * stride >= 1 (default 1: every push); CORR_E_INVALID otherwise, CORR_E_STATE
+ * without the flag.  Takes effect from the next push (synchronises the
+ * context's stream). */
 int corr_set_timing_stride(corr_ctx *ctx, int32_t stride);
 
 /* Launch shape in use. */

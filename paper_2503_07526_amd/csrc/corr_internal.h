@@ -76,7 +76,10 @@ constexpr int kFoldThreadsDefault = 128;
 // the scheduled folds, record 1 the producers): the earliest block start and
 // the latest block end of this push's kernels of that class, in wall-clock
 // ticks, and their running sum over pushes (the push's end kernel reduces the
-// slots, adds the span and resets them).  Blocks record into one of
+// slots, adds the span and resets them).  Only the pushes whose index n
+// (pushes completed before them: the device counter `step`) satisfies
+// n % stride == 0 are stamped, so that one push in `stride` carries the cost
+// of the stamps.  Blocks record into one of
 // kStampSlots slots, each on its own 128-byte line, so that the stamps of a
 // few thousand blocks do not queue on one address (on one line they delayed
 // the end of the fold kernel by about 15 us, on 64 lines still by 4 us).
@@ -88,7 +91,9 @@ struct StampSlot {
 struct FoldStamps {
     StampSlot slot[kStampSlots];
     unsigned long long total, count;
-    unsigned long long pad_[14];
+    const int64_t *step; // the context's device push counter
+    long long stride;    // stamp the pushes with *step % stride == 0
+    unsigned long long pad_[12];
 };
 
 // Record a block's start (or end) in its slot.
@@ -96,13 +101,19 @@ struct FoldStamps {
 } // namespace corr
 #include <hip/hip_runtime.h>
 namespace corr {
+__device__ __forceinline__ bool stamp_sampled(const FoldStamps *st)
+{
+    return *st->step % st->stride == 0;
+}
 __device__ __forceinline__ void stamp_start(FoldStamps *st, unsigned block)
 {
-    atomicMin(&st->slot[block % kStampSlots].start, (unsigned long long)wall_clock64());
+    if (stamp_sampled(st))
+        atomicMin(&st->slot[block % kStampSlots].start, (unsigned long long)wall_clock64());
 }
 __device__ __forceinline__ void stamp_end(FoldStamps *st, unsigned block)
 {
-    atomicMax(&st->slot[block % kStampSlots].end, (unsigned long long)wall_clock64());
+    if (stamp_sampled(st))
+        atomicMax(&st->slot[block % kStampSlots].end, (unsigned long long)wall_clock64());
 }
 #endif
 

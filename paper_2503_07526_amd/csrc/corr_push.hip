@@ -441,7 +441,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
 __global__ void push_end_kernel(PushEndArgs a)
 {
     if (blockIdx.x != 0) return;
-    if (a.stamps) {
+    if (a.stamps && stamp_sampled(a.stamps)) {
         // the lanes take the slots of both stamp records in turn; the earliest
         // start and the latest end give the push's span of each class
         __shared__ unsigned long long lo[64], hi[64];

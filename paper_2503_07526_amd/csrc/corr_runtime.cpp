@@ -1159,6 +1159,8 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         for (auto &r : init) {
             r = FoldStamps{};
             for (auto &sl : r.slot) sl.start = ~0ull;
+            r.step = c->d_step;
+            r.stride = 1;
         }
         CREATE_HIP(hipMalloc(&c->d_stamps, 2 * sizeof(FoldStamps)));
         CREATE_HIP(hipMemcpy(c->d_stamps, init.data(), 2 * sizeof(FoldStamps), hipMemcpyHostToDevice));
@@ -1466,6 +1468,13 @@ int corr_set_timing_stride(corr_ctx *ctx, int32_t stride)
     if (stride < 1) return set_err(ctx, CORR_E_INVALID, "timing stride must be >= 1");
     if (!(ctx->flags & CORR_FLAG_TIMING))
         return set_err(ctx, CORR_E_STATE, "timing stride without CORR_FLAG_TIMING");
+    // the device stamps read their stride next to the push counter (so that
+    // captured graphs follow it too), ordered after the pushes already issued
+    const long long st = stride;
+    for (int r = 0; r < 2; ++r)
+        HIP_TRY(ctx, hipMemcpyAsync(&ctx->d_stamps[r].stride, &st, sizeof(st), hipMemcpyHostToDevice,
+                                    ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     ctx->timing_stride = stride;
     return CORR_OK;
 }

@@ -409,11 +409,24 @@ def test_kernel_time_pools(corrmod):
         for which in (0, 1, 2):
             ms, n = c.kernel_time(which)
             assert n == 9 and ms > 0.0, (which, n, ms)
-        assert c.kernel_time(3)[1] == S and c.kernel_time(4)[1] == S  # stamps on every push
+        # the device stamps follow the stride too (the device push counter)
+        assert c.kernel_time(3)[1] == 9 and c.kernel_time(4)[1] == 9
         assert np.array_equal(c.finalize(0, slice_=(0, 3))["c_per_channel"],
                               ref.finalize(0, slice_=(0, 3))["c_per_channel"])
         with pytest.raises(corrmod.CorrError):
             ref.set_timing_stride(4)  # no CORR_FLAG_TIMING
+    # captured graphs: stamps on pushes 0, 8, ..., 64 whatever the chunks, same state
+    with corrmod.Correlator(groups, timing=True, graph=True) as c, \
+            corrmod.Correlator(groups) as ref:
+        c.set_timing_stride(8)
+        xv_d = torch.as_tensor(xv, device="cuda")
+        xp_d = torch.as_tensor(xp, device="cuda")
+        for a, b in ((0, 13), (13, 45), (45, S)):
+            c.push_steps([xv_d[a:b], xp_d[a:b]])
+        _push_all(ref, [xv, xp])
+        assert c.kernel_time(3)[1] == 9 and c.kernel_time(4)[1] == 9
+        assert np.array_equal(c.finalize(0, slice_=(0, 3))["c_per_channel"],
+                              ref.finalize(0, slice_=(0, 3))["c_per_channel"])
 
 
 def _currents_inputs(seed, N, box, S):
