@@ -557,14 +557,16 @@ __device__ __forceinline__ void deferred_pass(const DeferredArgs &a)
 template <int K, int P, int T, int NT, bool HIST>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void deferred_kernel(DeferredArgs a)
 {
-    // with timing: earliest block start and latest block end of the push's
-    // folds (device wall clock; no event between kernels)
+    // with timing, on the sampled pushes: earliest block start and latest
+    // block end of the push's folds (device wall clock; no event between
+    // kernels); the other pushes skip the closing barrier as well
     FoldStamps *st = a.stamps;
-    if (st && threadIdx.x == 0) stamp_start(st, blockIdx.x);
+    const bool stamped = st && stamp_sampled(st);
+    if (stamped && threadIdx.x == 0) stamp_start_now(st, blockIdx.x);
     deferred_pass<K, P, T, NT, false, HIST>(a);
-    if (st) {
+    if (stamped) {
         __syncthreads();
-        if (threadIdx.x == 0) stamp_end(st, blockIdx.x);
+        if (threadIdx.x == 0) stamp_end_now(st, blockIdx.x);
     }
 }
 

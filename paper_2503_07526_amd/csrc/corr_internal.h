@@ -105,15 +105,22 @@ __device__ __forceinline__ bool stamp_sampled(const FoldStamps *st)
 {
     return *st->step % st->stride == 0;
 }
+// The stamps themselves, for a caller that has checked stamp_sampled.
+__device__ __forceinline__ void stamp_start_now(FoldStamps *st, unsigned block)
+{
+    atomicMin(&st->slot[block % kStampSlots].start, (unsigned long long)wall_clock64());
+}
+__device__ __forceinline__ void stamp_end_now(FoldStamps *st, unsigned block)
+{
+    atomicMax(&st->slot[block % kStampSlots].end, (unsigned long long)wall_clock64());
+}
 __device__ __forceinline__ void stamp_start(FoldStamps *st, unsigned block)
 {
-    if (stamp_sampled(st))
-        atomicMin(&st->slot[block % kStampSlots].start, (unsigned long long)wall_clock64());
+    if (stamp_sampled(st)) stamp_start_now(st, block);
 }
 __device__ __forceinline__ void stamp_end(FoldStamps *st, unsigned block)
 {
-    if (stamp_sampled(st))
-        atomicMax(&st->slot[block % kStampSlots].end, (unsigned long long)wall_clock64());
+    if (stamp_sampled(st)) stamp_end_now(st, block);
 }
 #endif
 
