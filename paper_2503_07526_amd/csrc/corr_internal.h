@@ -231,15 +231,18 @@ struct MomentumArgs {
 struct RhokMfmaArgs {
     const float *pos;        // [3][n_atoms] positions; currents: then [3][n_atoms] velocities
     int64_t n_atoms;
-    const int32_t *pair_nx;  // [n_mtiles * 16], padding pairs (x_lo, y_lo)
-    const int32_t *pair_ny;  // [n_mtiles * 16]
-    const int32_t *slot_k;   // [n_mtiles * 16][16 |n_z|][2 sign (n_z < 0)]: k index
+    // Rows.  nw == 3: the (n_x, n_y) pairs, 16 per M tile; nw == 1: the
+    // couples (n_x, |n_y|), 4 per M tile.  Padding rows (x_lo, y_lo).
+    const int32_t *pair_nx;  // [n_mtiles * 16 | 4]
+    const int32_t *pair_ny;  // [n_mtiles * 16 | 4]
+    const int32_t *slot_k;   // nw == 3: [pair][16 |n_z|][n_z < 0]; nw == 1:
+                             // [couple][16 |n_z|][n_y < 0][n_z < 0]: k index
                              // stored for the slot, or -1
     const int32_t *k_src;    // [nk]: partial row that holds k's sum
     int32_t n_mtiles;
     int32_t nmax;            // max |n component|, at most 15
-    int32_t x_lo, x_rows;    // table rows: n_x in [x_lo, x_lo + x_rows) over the pairs
-    int32_t y_lo, y_rows;    // n_y likewise
+    int32_t x_lo, x_rows;    // table rows: n_x in [x_lo, x_lo + x_rows) over the rows
+    int32_t y_lo, y_rows;    // n_y likewise (nw == 1: |n_y|, y_lo = 0)
     double inv_box;          // 1 / L
     double *partial;         // [nk][nw][n_atom_blocks][2] FP64 partial sums
     int32_t n_atom_blocks;

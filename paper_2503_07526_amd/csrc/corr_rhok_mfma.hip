@@ -40,12 +40,12 @@
 // K-step reads start in different banks) and the split |n_z| powers already
 // in B-fragment order.  The tables are double-buffered: builder waves build
 // the next tile's tables while the contraction waves contract the current
-// one, one barrier per tile, and the positions are loaded a tile ahead.  With
-// one weight set a block has two more waves than M tiles: they build the Z
-// fragments and contract nothing, waves 0..3 build X and Y besides their own
-// M tile.  Waves w and w + 4 of a block share a SIMD, so with ten M tiles the
-// two Z waves (10, 11) join the SIMDs of waves 2, 6 and 3, 7, which hold two
-// M tiles, not three.
+// one, one barrier per tile, and the positions are loaded a tile ahead.
+//
+// That is the form of the current producer (three weight sets).  n(k) (one
+// weight set) takes the couple form below (rhok_couple_kernel): rows of the
+// products that a pair (n_x, n_y) and its mirror (n_x, -n_y) share, which
+// forms fewer products per pair on the vector units.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
@@ -65,7 +65,6 @@ typedef _Float16 halfv_t __attribute__((ext_vector_type(kAtomsPerLane)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaMaxWaves = 12;  // waves per block
-constexpr int kZWaves = 2;         // one weight set: waves per block that only build Z
 constexpr int kMfmaCols = 16;      // |n_z| = 0 .. 15
 constexpr int kRoots = 64;         // e^{2 pi i q / kRoots} table for the base phase
 // LDS after the root table for the weight scales (three weight sets): the
@@ -111,7 +110,8 @@ __device__ __forceinline__ float4_t mfma(half8_t a, half8_t b, float4_t c)
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float4_t mfma(half4_t a, half4_t b, float4_t c)
+// (the K = 16 form, for kWideK = false)
+[[maybe_unused]] __device__ __forceinline__ float4_t mfma(half4_t a, half4_t b, float4_t c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
@@ -268,16 +268,13 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
         return t;
     };
 
-    // One weight set: the last kZWaves waves of a block only build Z.
-    constexpr bool kZBuilders = NW == 1 && TA == 128;
     const int waves = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15; // A row / B column within the tile
     const int grp = lane >> 4; // atom group of the K-step
-    const int cwaves = kZBuilders ? waves - kZWaves : waves; // contraction waves
-    const int mt = blockIdx.x * cwaves + wave;
-    const bool active = wave < cwaves && mt < a.n_mtiles; // wave-uniform
+    const int mt = blockIdx.x * waves + wave;
+    const bool active = mt < a.n_mtiles; // wave-uniform
     const int pm_row = mt * 16 + col;
     const int ax = active ? a.pair_nx[pm_row] - a.x_lo : 0; // table rows
     const int ay = active ? a.pair_ny[pm_row] - a.y_lo : 0;
@@ -349,15 +346,11 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
     }
 
     // table task of this thread and its inputs, loaded one tile ahead of their
-    // use; the Z task also loads the weights.  Task wave t holds tasks 64 t ..
-    // 64 t + 63.  One weight set: X and Y tasks on waves 0..3, Z on the last
-    // two waves (a block has at least six); otherwise task wave = wave.
-    // (the wave index as a wave-uniform value: the build's loops and branches
-    // then stay scalar; `wave` itself stays a vector value, which measured
-    // 6% faster in the contraction)
-    const int wv_u = __builtin_amdgcn_readfirstlane(wave);
-    const int twave = __builtin_amdgcn_readfirstlane(
-        kZBuilders && wv_u >= 4 ? (wv_u >= waves - kZWaves ? 4 + wv_u - (waves - kZWaves) : 6 + wv_u) : wv_u);
+    // use; the Z task also loads the weights.  Task wave t = wave holds tasks
+    // 64 t .. 64 t + 63 (taken as a wave-uniform value: the build's loops and
+    // branches then stay scalar; `wave` itself stays a vector value, which
+    // measured 6% faster in the contraction).
+    const int twave = __builtin_amdgcn_readfirstlane(wave);
     const int task = twave * 64 + lane;
     const bool builder = twave * 64 < TableShape<NW, TA>::tasks; // wave-uniform
     const int trem = task % (3 * Tile<TA>::atoms);
@@ -502,15 +495,6 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
 
 template <int NW, int TA> __global__ void rhok_mfma_kernel(RhokMfmaArgs a);
 
-// One weight set: at most 120 registers, so that a SIMD holding three of its
-// waves (360 registers) keeps room for a wave of a flush kernel that runs
-// beside it on another stream.
-template <>
-__global__ __launch_bounds__(MfmaShape<1>::max_waves * 64) __attribute__((amdgpu_num_vgpr(60)))
-void rhok_mfma_kernel<1, 128>(RhokMfmaArgs a)
-{
-    rhok_mfma_body<1, 128>(a);
-}
 
 template <>
 __global__ __launch_bounds__(MfmaShape<3>::max_waves * 64) void rhok_mfma_kernel<3, 64>(RhokMfmaArgs a)
@@ -522,6 +506,327 @@ template <>
 __global__ __launch_bounds__(MfmaShape<3>::max_waves * 64) void rhok_mfma_kernel<3, 128>(RhokMfmaArgs a)
 {
     rhok_mfma_body<3, 128>(a);
+}
+
+// ---- One weight set (n(k)): rows of couples ------------------------------
+//
+// The k-set's (n_x, n_y) pairs come in couples (a, +|b|), (a, -|b|) that share
+// X = X^a and Y = Y^|b| (Y^{-|b|} = conj Y^|b|).  With the four real products
+//     u = Xr Yr,  v = Xi Yi,  w = Xi Yr,  t = Xr Yi
+// per atom, P(a, +|b|) = (u - v) + i (t + w) and P(a, -|b|) = (u + v) + i (w - t).
+// The contraction's rows are (couple, component): a tile of 16 rows holds 4
+// couples, row 4c + q the component q (u, v, w, t) of couple c, and each row
+// is summed against Re z and Im z (two sums, three split products each).
+// Every sign combination of (n_y, n_z) follows at the end from these eight
+// sums of a couple by additions in double (the sums are linear in the
+// products).  Per row and atom: one product and its split (2.5 vector
+// instructions) instead of a complex product and the split of both parts for
+// each pair (7 per pair; 5 per pair here).  A lane's four accumulator values
+// of a tile are the four components of one couple at one |n_z| (D row 4g + v),
+// so the combination needs no data from other lanes.
+//
+// Tables: X and Y as separate real and imaginary planes of float
+// [2][rows][kPlaneStride] (X: n_x in [x_lo, x_lo + x_rows); Y: |n_y| in
+// [0, y_rows)), Z split in B-fragment order as for the pairs.  Waves: each
+// contraction wave takes kCpTilesPerWave tiles; waves 0, 1 build the X planes
+// and 2, 3 the Y planes besides their tiles; the block's last wave builds the
+// Z fragments, two atoms per lane (two interleaved recurrences).
+constexpr int kCpTilesPerWave = 2;
+constexpr int kCpMaxCWaves = kMfmaMaxWaves - 1;
+constexpr int kCpMinCWaves = 4;               // waves 0 .. 3 build X and Y
+constexpr int kPlaneStride = 128 + 4;         // floats per plane row (128-atom tiles); +4 banks per row
+// B fragments of the couple kernel: the pair kernels' layout with a padded
+// atom-group row (17 halfv) and K-step (+8 halfv), so that the Z builder's
+// 2-byte writes of 64 atoms spread over 32 banks instead of 4.
+constexpr int kCpGrpStride = kMfmaCols + 1;
+constexpr int kCpKsStride = kBParts * 4 * kCpGrpStride + 8;
+constexpr int kCpBfrags = Tile<128>::ksteps * kCpKsStride; // halfv per buffer
+__device__ __forceinline__ int cp_bfrag_index(int ks, int part, int grp, int col)
+{
+    return ks * kCpKsStride + (part * 4 + grp) * kCpGrpStride + col; // in halfv_t units
+}
+
+struct CpBufs {
+    float *xp;      // [2][x_rows][kPlaneStride]: real plane, then imaginary plane
+    float *yp;      // [2][y_rows][kPlaneStride]
+    halfv_t *bfr;   // [kCpBfrags] (cp_bfrag_index)
+};
+
+// X (d = 0) or Y (d = 1) planes of atom j of the tile: powers n in
+// [lo, lo + rows) by a double recurrence from e^{2 pi i x / L}, each rounded
+// once to float; a dead lane (past the atoms) writes zeros.  lo, rows and d
+// are uniform over the wave, so the loop and its conditions are scalar.
+// (Shorter dependency chains, e^{n+4} = e^n e^4 four at a time, measured no
+// faster.)
+__device__ __forceinline__ void cp_build_planes(float *plane0, int rows, int lo, int j, bool live,
+                                                float x, double inv_box, const double2 *roots)
+{
+    double cs, sn, pr = live ? 1.0 : 0.0, pi = 0.0;
+    unit_phase((double)x * inv_box, roots, cs, sn);
+    float *re = plane0 + j - lo * kPlaneStride; // power m at re + m * kPlaneStride
+    float *im = re + rows * kPlaneStride;
+    const int hi = lo + rows - 1;
+    if (lo <= 0 && hi >= 0) {
+        re[0] = (float)pr;
+        im[0] = 0.f;
+    }
+    const int n_last = max(-lo, hi);
+    for (int n = 1; n <= n_last; ++n) {
+        cmul(pr, pi, cs, sn);
+        const float fr = (float)pr, fi = (float)pi;
+        if (n >= lo && n <= hi) {
+            re[n * kPlaneStride] = fr;
+            im[n * kPlaneStride] = fi;
+        }
+        if (-n >= lo && -n <= hi) {
+            re[-n * kPlaneStride] = fr;
+            im[-n * kPlaneStride] = -fi;
+        }
+    }
+}
+
+// Z fragments of atoms 2 lane and 2 lane + 1 of the tile (|n_z| = 0 .. nmax):
+// the two atoms are neighbours in a B fragment, so each part of a power is
+// one 4-byte write of both atoms' halves.
+__device__ __forceinline__ void cp_build_z(halfv_t *bfr, int lane, const bool (&live)[2],
+                                           const float (&z)[2], double inv_box, int nmax,
+                                           const double2 *roots)
+{
+    double cs[2], sn[2], pr[2], pi[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        unit_phase((double)z[e] * inv_box, roots, cs[e], sn[e]);
+        pr[e] = live[e] ? 1.0 : 0.0;
+        pi[e] = 0.0;
+    }
+    const int j = 2 * lane;
+    const int ks = j / kKStep, g = (j % kKStep) / kAtomsPerLane, h = j % kAtomsPerLane;
+    // dword of the pair in part 0 of power 0; parts kPart dwords apart
+    uint32_t *const b0 = reinterpret_cast<uint32_t *>(bfr) + cp_bfrag_index(ks, 0, g, 0) * (kAtomsPerLane / 2) + h / 2;
+    constexpr int kPart = 4 * kCpGrpStride * (kAtomsPerLane / 2);
+    auto store = [&](int n) {
+        const float r0 = (float)pr[0], r1 = (float)pr[1], i0 = (float)pi[0], i1 = (float)pi[1];
+        const uint32_t rh = pack_half2(r0, r1), ih = pack_half2(i0, i1);
+        uint32_t rl, il;
+        lo_half2(rl, rh, r0, r1);
+        lo_half2(il, ih, i0, i1);
+        uint32_t *b = b0 + n * (kAtomsPerLane / 2);
+        b[0] = rh;
+        b[kPart] = rl;
+        b[2 * kPart] = ih;
+        b[3 * kPart] = il;
+    };
+    store(0);
+    for (int n = 1; n <= nmax; ++n) {
+        cmul(pr[0], pi[0], cs[0], sn[0]);
+        cmul(pr[1], pi[1], cs[1], sn[1]);
+        store(n);
+    }
+}
+
+__device__ __forceinline__ void rhok_couple_body(const RhokMfmaArgs &a)
+{
+    constexpr int TA = 128;
+    if (a.stamps && threadIdx.x == 0) stamp_start(a.stamps, blockIdx.x + gridDim.x * blockIdx.y);
+    extern __shared__ double2 lds_roots[]; // [kRoots], then two tile buffers
+    const int nmax = a.nmax;
+    const int plane_rows = 2 * (a.x_rows + a.y_rows);
+    // buffer: X planes, Y planes, B fragments (float units; 16-byte aligned)
+    const int buf_floats = plane_rows * kPlaneStride + kCpBfrags * (int)(sizeof(halfv_t) / sizeof(float));
+    float *const buf0 = reinterpret_cast<float *>(lds_roots + kRoots);
+    auto bufs = [&](int b) {
+        CpBufs t;
+        t.xp = buf0 + b * buf_floats;
+        t.yp = t.xp + 2 * a.x_rows * kPlaneStride;
+        t.bfr = reinterpret_cast<halfv_t *>(t.yp + 2 * a.y_rows * kPlaneStride);
+        return t;
+    };
+    const int waves = blockDim.x >> 6;
+    const int cwaves = waves - 1; // the last wave builds Z
+    const int wave = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15; // A row / B column within the tile
+    const int grp = lane >> 4; // atom group of the K-step; couple of the lane's D rows
+    const int cq = col & 3;    // the lane's A row: component cq of couple col / 4
+    int tile[kCpTilesPerWave];
+    bool act[kCpTilesPerWave]; // wave-uniform
+    int xoff[kCpTilesPerWave], yoff[kCpTilesPerWave];
+#pragma unroll
+    for (int t = 0; t < kCpTilesPerWave; ++t) {
+        tile[t] = (blockIdx.x * cwaves + wave) * kCpTilesPerWave + t;
+        act[t] = wave < cwaves && tile[t] < a.n_mtiles;
+        const int gc = act[t] ? tile[t] * 4 + (col >> 2) : 0; // the lane's A-row couple
+        const int ax = act[t] ? a.pair_nx[gc] - a.x_lo : 0;
+        const int ay = act[t] ? a.pair_ny[gc] - a.y_lo : 0;
+        // u = Xr Yr, v = Xi Yi, w = Xi Yr, t = Xr Yi
+        const int xpl = cq == 0 || cq == 3 ? 0 : 1, ypl = cq == 0 || cq == 2 ? 0 : 1;
+        xoff[t] = (xpl * a.x_rows + ax) * kPlaneStride + grp * kAtomsPerLane;
+        yoff[t] = (ypl * a.y_rows + ay) * kPlaneStride + grp * kAtomsPerLane;
+    }
+    const int boff = grp * kCpGrpStride + col;
+
+    for (int q = threadIdx.x; q < kRoots; q += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * q / kRoots, &sn, &cs);
+        lds_roots[q] = make_double2(cs, sn);
+    }
+    // B columns above nmax are never stored; keep them zero
+    for (int f = threadIdx.x; f < 2 * Tile<TA>::ksteps * kBParts * 4 * kMfmaCols; f += blockDim.x) {
+        const int c = f % kMfmaCols, r = f / kMfmaCols; // r: (buffer, K-step, part, group)
+        const int gq = r % 4, part = (r / 4) % kBParts, ks = (r / (4 * kBParts)) % Tile<TA>::ksteps;
+        if (c > nmax) bufs(r / (4 * kBParts * Tile<TA>::ksteps)).bfr[cp_bfrag_index(ks, part, gq, c)] = halfv_t{};
+    }
+
+    double acc[kCpTilesPerWave][2][4];
+    float4_t sum[kCpTilesPerWave][2];
+#pragma unroll
+    for (int t = 0; t < kCpTilesPerWave; ++t)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][s][v] = 0.0;
+            sum[t][s] = float4_t{0.f, 0.f, 0.f, 0.f};
+        }
+
+    const int64_t a_begin = (int64_t)blockIdx.y * a.atoms_per_block;
+    int64_t a_end = a_begin + a.atoms_per_block;
+    if (a_end > a.n_atoms) a_end = a.n_atoms;
+    const int n_tiles =
+        a_end > a_begin ? (int)((a_end - a_begin + Tile<TA>::atoms - 1) / Tile<TA>::atoms) : 0;
+
+    // builders: waves 0, 1 the X planes, 2, 3 the Y planes (atom 64 (w & 1) +
+    // lane), the last wave the Z fragments (atoms 2 lane, 2 lane + 1)
+    const bool zb = wv == waves - 1;
+    const bool xyb = wv < 4;
+    const int bd = wv >> 1;                 // X/Y builder: axis
+    const int bj = (wv & 1) * 64 + lane;    // X/Y builder: atom of the tile
+    auto load_in = [&](int it, float (&in)[2], bool (&lv)[2]) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int j = zb ? 2 * lane + e : bj;
+            const int64_t at = a_begin + (int64_t)it * TA + j;
+            lv[e] = (zb || (xyb && e == 0)) && it < n_tiles && at < a_end;
+            in[e] = lv[e] ? a.pos[(int64_t)(zb ? 2 : bd) * a.n_atoms + at] : 0.f;
+        }
+    };
+    auto build = [&](const CpBufs &tb, const float (&in)[2], const bool (&lv)[2]) {
+        if (zb)
+            cp_build_z(tb.bfr, lane, lv, in, a.inv_box, nmax, lds_roots);
+        else if (xyb)
+            cp_build_planes(bd == 0 ? tb.xp : tb.yp, bd == 0 ? a.x_rows : a.y_rows,
+                            bd == 0 ? a.x_lo : a.y_lo, bj, lv[0], in[0], a.inv_box, lds_roots);
+    };
+    float in_cur[2], in_next[2];
+    bool lv_cur[2], lv_next[2];
+    load_in(0, in_cur, lv_cur);
+    load_in(1, in_next, lv_next);
+    __syncthreads(); // roots and zero columns
+    build(bufs(0), in_cur, lv_cur);
+    __syncthreads();
+
+    for (int it = 0; it < n_tiles; ++it) {
+        const CpBufs cur = bufs(it & 1);
+        // tables of the next tile into the other buffer
+        if ((zb || xyb) && it + 1 < n_tiles) {
+            float in_after[2];
+            bool lv_after[2];
+            load_in(it + 2, in_after, lv_after);
+            build(bufs((it + 1) & 1), in_next, lv_next);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                in_next[e] = in_after[e];
+                lv_next[e] = lv_after[e];
+            }
+        }
+        if (act[0]) {
+            const halfv_t *bl = cur.bfr + boff;
+            // all K-steps of the tile: the entries of atoms past the end are zero
+#pragma unroll
+            for (int ks = 0; ks < Tile<TA>::ksteps; ++ks) {
+                const halfv_t zrh = bl[cp_bfrag_index(ks, 0, 0, 0)];
+                const halfv_t zrl = bl[cp_bfrag_index(ks, 1, 0, 0)];
+                const halfv_t zih = bl[cp_bfrag_index(ks, 2, 0, 0)];
+                const halfv_t zil = bl[cp_bfrag_index(ks, 3, 0, 0)];
+#pragma unroll
+                for (int t = 0; t < kCpTilesPerWave; ++t) {
+                    if (!act[t]) continue;
+                    const float4 *xr = reinterpret_cast<const float4 *>(cur.xp + xoff[t] + ks * kKStep);
+                    const float4 *yr = reinterpret_cast<const float4 *>(cur.yp + yoff[t] + ks * kKStep);
+                    typedef uint32_t wv_t __attribute__((ext_vector_type(kAtomsPerLane / 2)));
+                    wv_t vh, vl;
+#pragma unroll
+                    for (int q4 = 0; q4 < kAtomsPerLane / 4; ++q4) {
+                        const float4 x = xr[q4], y = yr[q4];
+                        const float c0 = x.x * y.x, c1 = x.y * y.y, c2 = x.z * y.z, c3 = x.w * y.w;
+                        // hi = fp16(v) two atoms per packed conversion, lo = fp16(v - hi)
+                        const uint32_t h01 = pack_half2(c0, c1), h23 = pack_half2(c2, c3);
+                        uint32_t l01, l23;
+                        lo_half2(l01, h01, c0, c1);
+                        lo_half2(l23, h23, c2, c3);
+                        vh[2 * q4] = h01;
+                        vh[2 * q4 + 1] = h23;
+                        vl[2 * q4] = l01;
+                        vl[2 * q4 + 1] = l23;
+                    }
+                    const halfv_t ch = __builtin_bit_cast(halfv_t, vh);
+                    const halfv_t cl = __builtin_bit_cast(halfv_t, vl);
+                    float4_t *sw = sum[t];
+                    sw[0] = mfma(ch, zrh, sw[0]);
+                    sw[1] = mfma(ch, zih, sw[1]);
+                    sw[0] = mfma(ch, zrl, sw[0]);
+                    sw[1] = mfma(ch, zil, sw[1]);
+                    sw[0] = mfma(cl, zrh, sw[0]);
+                    sw[1] = mfma(cl, zih, sw[1]);
+                }
+            }
+            if ((it + 1) % Tile<TA>::acc_tiles == 0 || it + 1 == n_tiles) {
+#pragma unroll
+                for (int t = 0; t < kCpTilesPerWave; ++t)
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[t][s][v] += (double)sum[t][s][v];
+                        sum[t][s] = float4_t{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+        }
+        __syncthreads(); // next buffer complete; this one free for the tile after
+    }
+    // The lane's accumulator values v = 0..3 are the components u, v, w, t of
+    // couple grp of the tile at |n_z| = col, against Re z (s = 0) and Im z (s
+    // = 1).  Slots [couple][|n_z|][n_y < 0][n_z < 0] that are k-vectors of the
+    // group are stored in partial[k][atom block].
+#pragma unroll
+    for (int t = 0; t < kCpTilesPerWave; ++t) {
+        if (!act[t]) continue;
+        const int gc = tile[t] * 4 + grp;
+        const double ur = acc[t][0][0], vr = acc[t][0][1], wr = acc[t][0][2], tr = acc[t][0][3];
+        const double ui = acc[t][1][0], vi = acc[t][1][1], wi = acc[t][1][2], ti = acc[t][1][3];
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb) {
+            // P = (u -+ v) + i (t + w  |  w - t): sums against Re z (R) and Im z (I)
+            const double prR = sb ? ur + vr : ur - vr, prI = sb ? ui + vi : ui - vi;
+            const double piR = sb ? wr - tr : tr + wr, piI = sb ? wi - ti : ti + wi;
+#pragma unroll
+            for (int sz = 0; sz < 2; ++sz) {
+                const int k = a.slot_k[(((size_t)gc * kMfmaCols + col) * 2 + sb) * 2 + sz];
+                if (k < 0) continue;
+                double *dst = a.partial + ((size_t)k * a.n_atom_blocks + blockIdx.y) * 2;
+                dst[0] = sz ? prR + piI : prR - piI; // Re P z or Re P conj(z)
+                dst[1] = sz ? piR - prI : prI + piR; // Im
+            }
+        }
+    }
+}
+
+// One weight set: at most 120 registers, so that a SIMD holding three of its
+// waves (360 registers) keeps room for a wave of a flush kernel that runs
+// beside it on another stream.
+__global__ __launch_bounds__(kMfmaMaxWaves * 64) __attribute__((amdgpu_num_vgpr(60)))
+void rhok_couple_kernel(RhokMfmaArgs a)
+{
+    rhok_couple_body(a);
 }
 
 // One wave per k-vector: sum the partials of its slot over the atom blocks in
@@ -596,9 +901,17 @@ static int tile_atoms(int table_rows, int nw)
     return nw == 1 || lds_bytes<3, 128>(table_rows) <= kLdsBytes ? 128 : 64;
 }
 
+// One weight set: the root table and two buffers of X and Y planes (table_rows
+// rows of both parts) and B fragments.
+static size_t couple_lds_bytes(int table_rows)
+{
+    return (size_t)kRoots * sizeof(double2) +
+           2 * ((size_t)2 * table_rows * kPlaneStride * sizeof(float) + (size_t)kCpBfrags * sizeof(halfv_t));
+}
+
 size_t rhok_mfma_lds_bytes(int table_rows, int nw)
 {
-    if (nw == 1) return lds_bytes<1, 128>(table_rows);
+    if (nw == 1) return couple_lds_bytes(table_rows);
     return tile_atoms(table_rows, nw) == 128 ? lds_bytes<3, 128>(table_rows)
                                              : lds_bytes<3, 64>(table_rows);
 }
@@ -609,7 +922,7 @@ hipError_t rhok_mfma_prepare(int table_rows, int nw)
     const size_t lds = rhok_mfma_lds_bytes(table_rows, nw);
     if (lds > kLdsBytes) return hipErrorInvalidValue;
     if (lds <= 64 * 1024) return hipSuccess;
-    const void *fn = nw == 1 ? reinterpret_cast<const void *>(&rhok_mfma_kernel<1, 128>)
+    const void *fn = nw == 1 ? reinterpret_cast<const void *>(&rhok_couple_kernel)
                      : tile_atoms(table_rows, nw) == 128
                          ? reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 128>)
                          : reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 64>);
@@ -618,18 +931,34 @@ hipError_t rhok_mfma_prepare(int table_rows, int nw)
 
 int rhok_mfma_chunks(int n_mtiles, int nw)
 {
-    // M tiles per block (one weight set: two of the block's waves build Z)
-    const int maxt = nw == 3 ? MfmaShape<3>::max_waves : MfmaShape<1>::max_waves - kZWaves;
+    // M tiles per block (one weight set: couple tiles, kCpTilesPerWave per
+    // contraction wave, one more wave builds Z)
+    const int maxt = nw == 3 ? MfmaShape<3>::max_waves : kCpMaxCWaves * kCpTilesPerWave;
     return (n_mtiles + maxt - 1) / maxt;
+}
+
+static hipError_t launch_couples(const RhokMfmaArgs &a, hipStream_t st)
+{
+    const int chunks = rhok_mfma_chunks(a.n_mtiles, 1);
+    const int per_chunk = (a.n_mtiles + chunks - 1) / chunks;
+    int cwaves = (per_chunk + kCpTilesPerWave - 1) / kCpTilesPerWave;
+    if (cwaves < kCpMinCWaves) cwaves = kCpMinCWaves;
+    const size_t lds = couple_lds_bytes(a.x_rows + a.y_rows);
+    hipLaunchKernelGGL(rhok_couple_kernel, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
+                       dim3((cwaves + 1) * 64), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(rhok_mfma_final_kernel<1>, dim3((unsigned)((a.nk + 3) / 4)), dim3(256), 0, st,
+                       a);
+    return hipGetLastError();
 }
 
 template <int NW, int TA> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t st)
 {
-    // waves per block: the M tiles dealt evenly over the fewest blocks (one
-    // weight set: and the two Z waves), at least one thread per table task
+    // waves per block: the M tiles dealt evenly over the fewest blocks, at
+    // least one thread per table task
     const int chunks = rhok_mfma_chunks(a.n_mtiles, NW);
     int waves = (a.n_mtiles + chunks - 1) / chunks;
-    if (NW == 1 && TA == 128) waves += kZWaves;
     if (waves < TableShape<NW, TA>::min_waves) waves = TableShape<NW, TA>::min_waves;
     const size_t lds = lds_bytes<NW, TA>(a.x_rows + a.y_rows);
     hipLaunchKernelGGL((rhok_mfma_kernel<NW, TA>), dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
@@ -647,7 +976,7 @@ hipError_t launch_rhok_mfma(const RhokMfmaArgs &a, hipStream_t st)
         a.x_rows + a.y_rows > 4 * kMfmaCols - 2)
         return hipErrorInvalidValue;
     const int rows = a.x_rows + a.y_rows;
-    if (a.nw == 1) return launch_nw<1, 128>(a, st);
+    if (a.nw == 1) return launch_couples(a, st);
     if (a.nw == 3)
         return tile_atoms(rows, 3) == 128 ? launch_nw<3, 128>(a, st) : launch_nw<3, 64>(a, st);
     return hipErrorInvalidValue;

@@ -892,11 +892,21 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
             // producer takes up to 512.
             int n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(512, g.d.n_atoms / 1024));
             if (g.rhok_mfma) {
+                // Rows of the contraction.  Currents: the distinct (n_x, n_y)
+                // pairs, 16 per M tile, slots [pair][|n_z|][n_z < 0].  n(k):
+                // the couples (n_x, |n_y|), 4 per M tile (one row per
+                // component of the products they share), slots
+                // [couple][|n_z|][n_y < 0][n_z < 0].
+                const bool couples = g.nw == 1;
+                const int per_tile = couples ? 4 : 16;
+                const int n_signs = couples ? 4 : 2;
                 std::map<std::pair<int, int>, int> pair_ix;
-                for (int q = 0; q < nk; ++q)
-                    pair_ix.emplace(std::make_pair(kv[3 * q], kv[3 * q + 1]), 0);
+                auto row_key = [&](int q) {
+                    return std::make_pair(kv[3 * q], couples ? std::abs(kv[3 * q + 1]) : kv[3 * q + 1]);
+                };
+                for (int q = 0; q < nk; ++q) pair_ix.emplace(row_key(q), 0);
                 const int n_pairs = (int)pair_ix.size();
-                const int n_mtiles = (n_pairs + 15) / 16;
+                const int n_mtiles = (n_pairs + per_tile - 1) / per_tile;
                 // The matrix-core producer runs fastest with one block per
                 // compute unit (its double-buffered LDS tables and one wave
                 // per M tile fill a CU): CUs / M-tile chunks atom blocks.
@@ -906,16 +916,17 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 n_ab = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(512, per_cu),
                                                                    g.d.n_atoms / 1024));
                 const int ncol = rhok_mfma_cols();
-                // table rows: the n_x and n_y ranges of the pairs (padding
-                // pairs take the first row of each)
-                int x_lo = kv[0], x_hi = kv[0], y_lo = kv[1], y_hi = kv[1];
+                // table rows: the n_x and n_y (couples: |n_y|) ranges of the
+                // rows (padding rows take the first row of each)
+                int x_lo = kv[0], x_hi = kv[0], y_lo = row_key(0).second, y_hi = y_lo;
                 for (int q = 0; q < nk; ++q) {
                     x_lo = std::min(x_lo, kv[3 * q]);
                     x_hi = std::max(x_hi, kv[3 * q]);
-                    y_lo = std::min(y_lo, kv[3 * q + 1]);
-                    y_hi = std::max(y_hi, kv[3 * q + 1]);
+                    y_lo = std::min(y_lo, row_key(q).second);
+                    y_hi = std::max(y_hi, row_key(q).second);
                 }
-                std::vector<int32_t> pnx((size_t)n_mtiles * 16, x_lo), pny((size_t)n_mtiles * 16, y_lo);
+                if (couples) y_lo = 0; // Y planes hold |n_y| = 0 .. y_hi
+                std::vector<int32_t> pnx((size_t)n_mtiles * per_tile, x_lo), pny((size_t)n_mtiles * per_tile, y_lo);
                 int u = 0;
                 for (auto &e : pair_ix) {
                     e.second = u;
@@ -923,11 +934,13 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                     pny[(size_t)u] = e.first.second;
                     ++u;
                 }
-                std::vector<int32_t> slot_k((size_t)n_mtiles * 16 * ncol * 2, -1), k_src((size_t)nk);
+                std::vector<int32_t> slot_k((size_t)n_mtiles * per_tile * ncol * n_signs, -1),
+                    k_src((size_t)nk);
                 for (int q = 0; q < nk; ++q) {
-                    const int pm = pair_ix[std::make_pair(kv[3 * q], kv[3 * q + 1])];
+                    const int pm = pair_ix[row_key(q)];
                     const int nz = kv[3 * q + 2];
-                    const size_t slot = ((size_t)pm * ncol + std::abs(nz)) * 2 + (nz < 0 ? 1 : 0);
+                    const int sign = couples ? (kv[3 * q + 1] < 0 ? 2 : 0) + (nz < 0 ? 1 : 0) : (nz < 0 ? 1 : 0);
+                    const size_t slot = ((size_t)pm * ncol + std::abs(nz)) * n_signs + sign;
                     if (slot_k[slot] < 0) slot_k[slot] = q; // first listing of a k-vector
                     k_src[(size_t)q] = slot_k[slot];
                 }
