@@ -25,7 +25,7 @@ int rhok_mfma_cols();        // |n_z| columns of the matrix-core producer
 int rhok_mfma_max_nmax();    // largest |n component| it takes
 hipError_t launch_momentum(const MomentumArgs &a, hipStream_t st); // partial + final kernels
 int momentum_blocks(int64_t n_atoms); // blocks of the partial kernel (size of the partial buffer)
-hipError_t rhok_mfma_prepare(int table_rows, int nw); // once per context, before the first launch
+hipError_t rhok_mfma_prepare(int table_rows, int nw, int nmax); // once per context, before the first launch
 int rhok_mfma_chunks(int n_mtiles, int nw); // blocks along the M tiles (grid.x)
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 bool deferred_supported(int kind, int p, int m);

@@ -171,7 +171,10 @@ struct TileBufs {
     halfv_t *bfr;   // [NW][Tile::bfrags]
 };
 
-// Build the tables of one tile.  Task (power part hf, axis d, atom j), the
+// Build the tables of one tile.  The B fragments of the NW weight sets are
+// packed by column: column s (nmax + 1) + n of B tile (column / 16) holds
+// w_s Z^n (NB = ceil(NW (nmax + 1) / 16) tiles instead of NW).
+// Task (power part hf, axis d, atom j), the
 // task of lane `lane` of task wave `twave` (uniform over the wave, which
 // fixes hf and d: 64 divides the tile, so all control flow is uniform): with
 // two parts, part 0 takes n = 0 .. n1 and part 1 takes n = n1+1 .. nmax
@@ -228,11 +231,13 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int twave, int la
                 typedef _Float16 h2v __attribute__((ext_vector_type(2)));
                 const h2v H = __builtin_bit_cast(h2v, hh), L = __builtin_bit_cast(h2v, ll);
                 const _Float16 rh = H[0], ih = H[1], rl = L[0], il = L[1];
-                _Float16 *bs = bh + (size_t)s * Tile<TA>::bfrags * kAtomsPerLane;
-                bs[bfrag_index(ks, 0, g, n) * kAtomsPerLane + h] = rh;
-                bs[bfrag_index(ks, 1, g, n) * kAtomsPerLane + h] = rl;
-                bs[bfrag_index(ks, 2, g, n) * kAtomsPerLane + h] = ih;
-                bs[bfrag_index(ks, 3, g, n) * kAtomsPerLane + h] = il;
+                // column s (nmax + 1) + n of the packed B tiles
+                const int gc = s * (nmax + 1) + n, bt = gc / kMfmaCols, c = gc % kMfmaCols;
+                _Float16 *bs = bh + (size_t)bt * Tile<TA>::bfrags * kAtomsPerLane;
+                bs[bfrag_index(ks, 0, g, c) * kAtomsPerLane + h] = rh;
+                bs[bfrag_index(ks, 1, g, c) * kAtomsPerLane + h] = rl;
+                bs[bfrag_index(ks, 2, g, c) * kAtomsPerLane + h] = ih;
+                bs[bfrag_index(ks, 3, g, c) * kAtomsPerLane + h] = il;
             }
         };
         if (n_begin == 0) store_z(0);
@@ -249,7 +254,7 @@ template <int NW> struct MfmaShape {
     static constexpr int max_waves = NW == 1 ? kMfmaMaxWaves : 8;
 };
 
-template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaArgs &a)
+template <int NW, int TA, int NB> __device__ __forceinline__ void rhok_mfma_body(const RhokMfmaArgs &a)
 {
     if (a.stamps && threadIdx.x == 0) stamp_start(a.stamps, blockIdx.x + gridDim.x * blockIdx.y);
     extern __shared__ double2 lds_roots[]; // [kRoots], the scale slots, then two tile buffers
@@ -259,7 +264,7 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
     float2 *const buf0 = reinterpret_cast<float2 *>(lds_roots + kRoots + ScaleSlots<NW>::n);
     const int buf_stride =
         (a.x_rows + a.y_rows) * Tile<TA>::stride +
-        NW * Tile<TA>::bfrags * (int)(sizeof(halfv_t) / sizeof(float2));
+        NB * Tile<TA>::bfrags * (int)(sizeof(halfv_t) / sizeof(float2));
     auto tile_bufs = [&](int b) {
         TileBufs t;
         t.tabx = buf0 + b * buf_stride;
@@ -288,14 +293,16 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
         sincospi(2.0 * q / kRoots, &sn, &cs);
         lds_roots[q] = make_double2(cs, sn);
     }
-    // B columns above nmax are never stored; keep them zero
-    for (int f = threadIdx.x; f < 2 * NW * Tile<TA>::bfrags; f += blockDim.x)
-        if (f % kMfmaCols > nmax) tile_bufs(f / (NW * Tile<TA>::bfrags)).bfr[f % (NW * Tile<TA>::bfrags)] = halfv_t{};
+    // packed B columns past NW (nmax + 1) are never stored; keep them zero
+    const int ncols = NW * (nmax + 1);
+    for (int f = threadIdx.x; f < 2 * NB * Tile<TA>::bfrags; f += blockDim.x)
+        if (((f / Tile<TA>::bfrags) % NB) * kMfmaCols + f % kMfmaCols >= ncols)
+            tile_bufs(f / (NB * Tile<TA>::bfrags)).bfr[f % (NB * Tile<TA>::bfrags)] = halfv_t{};
 
-    double acc[NW][4][4];
-    float4_t sum[NW][4]; // products of the last Tile::acc_tiles tiles at most
+    double acc[NB][4][4];
+    float4_t sum[NB][4]; // products of the last Tile::acc_tiles tiles at most
 #pragma unroll
-    for (int w = 0; w < NW; ++w)
+    for (int w = 0; w < NB; ++w)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
 #pragma unroll
@@ -434,7 +441,7 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
                 const halfv_t pih = __builtin_bit_cast(halfv_t, vih);
                 const halfv_t pil = __builtin_bit_cast(halfv_t, vil);
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
+                for (int w = 0; w < NB; ++w) {
                     const halfv_t *bl = cur.bfr + w * Tile<TA>::bfrags + boff;
                     const halfv_t zrh = bl[bfrag_index(ks, 0, 0, 0)];
                     const halfv_t zrl = bl[bfrag_index(ks, 1, 0, 0)];
@@ -458,7 +465,7 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
             }
             if ((it + 1) % Tile<TA>::acc_tiles == 0 || it + 1 == n_tiles) {
 #pragma unroll
-                for (int w = 0; w < NW; ++w)
+                for (int w = 0; w < NB; ++w)
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
 #pragma unroll
@@ -470,43 +477,54 @@ template <int NW, int TA> __device__ __forceinline__ void rhok_mfma_body(const R
         __syncthreads(); // next buffer complete; this one free for the tile after
     }
     if (!active) return;
-    // Row pm = pair, column col = |n_z|: only slots that are k-vectors of the
-    // group are stored, in partial[k][weight set][atom block].
+    // Row pm = pair; the lane's column of B tile w is packed column
+    // 16 w + col = s (nmax + 1) + |n_z| of weight set s.  Only slots that are
+    // k-vectors of the group are stored, in partial[k][weight set][atom block].
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int pm = mt * 16 + grp * 4 + v;
-        const int32_t *sk = a.slot_k + ((size_t)pm * kMfmaCols + col) * 2;
-        const int kp = sk[0], km = sk[1];
+    for (int w = 0; w < NB; ++w) {
+        const int gc = w * kMfmaCols + col;
+        if (gc >= ncols) continue;
+        const int s = gc / (nmax + 1), nz = gc - s * (nmax + 1);
+        double un = wunsc[0]; // the set's scale back (a select: no indexed private array)
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
+        for (int q = 1; q < NW; ++q) un = s == q ? wunsc[q] : un;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int pm = mt * 16 + grp * 4 + v;
+            const int32_t *sk = a.slot_k + ((size_t)pm * kMfmaCols + nz) * 2;
+            const int kp = sk[0], km = sk[1];
             if (kp >= 0) {
-                double *dst = a.partial + (((size_t)kp * NW + w) * a.n_atom_blocks + blockIdx.y) * 2;
-                dst[0] = (acc[w][0][v] - acc[w][1][v]) * wunsc[w];
-                dst[1] = (acc[w][2][v] + acc[w][3][v]) * wunsc[w];
+                double *dst = a.partial + (((size_t)kp * NW + s) * a.n_atom_blocks + blockIdx.y) * 2;
+                dst[0] = (acc[w][0][v] - acc[w][1][v]) * un;
+                dst[1] = (acc[w][2][v] + acc[w][3][v]) * un;
             }
             if (km >= 0) {
-                double *dst = a.partial + (((size_t)km * NW + w) * a.n_atom_blocks + blockIdx.y) * 2;
-                dst[0] = (acc[w][0][v] + acc[w][1][v]) * wunsc[w];
-                dst[1] = (acc[w][3][v] - acc[w][2][v]) * wunsc[w];
+                double *dst = a.partial + (((size_t)km * NW + s) * a.n_atom_blocks + blockIdx.y) * 2;
+                dst[0] = (acc[w][0][v] + acc[w][1][v]) * un;
+                dst[1] = (acc[w][3][v] - acc[w][2][v]) * un;
             }
         }
     }
 }
 
-template <int NW, int TA> __global__ void rhok_mfma_kernel(RhokMfmaArgs a);
+template <int NW, int TA, int NB> __global__ void rhok_mfma_kernel(RhokMfmaArgs a);
 
 
-template <>
-__global__ __launch_bounds__(MfmaShape<3>::max_waves * 64) void rhok_mfma_kernel<3, 64>(RhokMfmaArgs a)
-{
-    rhok_mfma_body<3, 64>(a);
-}
-
-template <>
-__global__ __launch_bounds__(MfmaShape<3>::max_waves * 64) void rhok_mfma_kernel<3, 128>(RhokMfmaArgs a)
-{
-    rhok_mfma_body<3, 128>(a);
-}
+// Three weight sets (currents), NB packed B tiles.
+#define CORR_CURRENT_KERNEL(TA, NB)                                                               \
+    template <>                                                                                   \
+    __global__ __launch_bounds__(MfmaShape<3>::max_waves * 64) void rhok_mfma_kernel<3, TA, NB>( \
+        RhokMfmaArgs a)                                                                           \
+    {                                                                                             \
+        rhok_mfma_body<3, TA, NB>(a);                                                             \
+    }
+CORR_CURRENT_KERNEL(64, 1)
+CORR_CURRENT_KERNEL(64, 2)
+CORR_CURRENT_KERNEL(64, 3)
+CORR_CURRENT_KERNEL(128, 1)
+CORR_CURRENT_KERNEL(128, 2)
+CORR_CURRENT_KERNEL(128, 3)
+#undef CORR_CURRENT_KERNEL
 
 // ---- One weight set (n(k)): rows of couples ------------------------------
 //
@@ -888,17 +906,20 @@ __global__ __launch_bounds__(256) void rhok_mfma_final_kernel(RhokMfmaArgs a)
 int rhok_mfma_cols() { return kMfmaCols; }
 int rhok_mfma_max_nmax() { return kMfmaCols - 1; }
 
-template <int NW, int TA> static size_t lds_bytes(int table_rows)
+// Three weight sets: packed B tiles for components up to nmax.
+static int current_btiles(int nmax) { return (3 * (nmax + 1) + kMfmaCols - 1) / kMfmaCols; }
+
+template <int TA> static size_t lds_bytes(int table_rows, int nb)
 {
-    return (size_t)(kRoots + ScaleSlots<NW>::n) * sizeof(double2) +
+    return (size_t)(kRoots + ScaleSlots<3>::n) * sizeof(double2) +
            2 * ((size_t)table_rows * Tile<TA>::stride * sizeof(float2) +
-                (size_t)NW * Tile<TA>::bfrags * sizeof(halfv_t));
+                (size_t)nb * Tile<TA>::bfrags * sizeof(halfv_t));
 }
 
-// Atoms per tile for a k-set with table_rows X and Y rows.
-static int tile_atoms(int table_rows, int nw)
+// Atoms per tile for a current k-set with table_rows X and Y rows.
+static int tile_atoms(int table_rows, int nb)
 {
-    return nw == 1 || lds_bytes<3, 128>(table_rows) <= kLdsBytes ? 128 : 64;
+    return lds_bytes<128>(table_rows, nb) <= kLdsBytes ? 128 : 64;
 }
 
 // One weight set: the root table and two buffers of X and Y planes (table_rows
@@ -909,23 +930,35 @@ static size_t couple_lds_bytes(int table_rows)
            2 * ((size_t)2 * table_rows * kPlaneStride * sizeof(float) + (size_t)kCpBfrags * sizeof(halfv_t));
 }
 
-size_t rhok_mfma_lds_bytes(int table_rows, int nw)
+size_t rhok_mfma_lds_bytes(int table_rows, int nw, int nmax)
 {
     if (nw == 1) return couple_lds_bytes(table_rows);
-    return tile_atoms(table_rows, nw) == 128 ? lds_bytes<3, 128>(table_rows)
-                                             : lds_bytes<3, 64>(table_rows);
+    const int nb = current_btiles(nmax);
+    return tile_atoms(table_rows, nb) == 128 ? lds_bytes<128>(table_rows, nb)
+                                             : lds_bytes<64>(table_rows, nb);
 }
 
-hipError_t rhok_mfma_prepare(int table_rows, int nw)
+static const void *current_kernel(int ta, int nb)
 {
-    if (table_rows > 4 * kMfmaCols - 2 || (nw != 1 && nw != 3)) return hipErrorInvalidValue;
-    const size_t lds = rhok_mfma_lds_bytes(table_rows, nw);
+    if (ta == 128)
+        return nb == 1 ? reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 128, 1>)
+               : nb == 2 ? reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 128, 2>)
+                         : reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 128, 3>);
+    return nb == 1 ? reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 64, 1>)
+           : nb == 2 ? reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 64, 2>)
+                     : reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 64, 3>);
+}
+
+hipError_t rhok_mfma_prepare(int table_rows, int nw, int nmax)
+{
+    if (table_rows > 4 * kMfmaCols - 2 || (nw != 1 && nw != 3) || nmax > kMfmaCols - 1)
+        return hipErrorInvalidValue;
+    const size_t lds = rhok_mfma_lds_bytes(table_rows, nw, nmax);
     if (lds > kLdsBytes) return hipErrorInvalidValue;
     if (lds <= 64 * 1024) return hipSuccess;
     const void *fn = nw == 1 ? reinterpret_cast<const void *>(&rhok_couple_kernel)
-                     : tile_atoms(table_rows, nw) == 128
-                         ? reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 128>)
-                         : reinterpret_cast<const void *>(&rhok_mfma_kernel<3, 64>);
+                             : current_kernel(tile_atoms(table_rows, current_btiles(nmax)),
+                                              current_btiles(nmax));
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -953,19 +986,19 @@ static hipError_t launch_couples(const RhokMfmaArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int NW, int TA> static hipError_t launch_nw(const RhokMfmaArgs &a, hipStream_t st)
+template <int TA, int NB> static hipError_t launch_currents(const RhokMfmaArgs &a, hipStream_t st)
 {
     // waves per block: the M tiles dealt evenly over the fewest blocks, at
     // least one thread per table task
-    const int chunks = rhok_mfma_chunks(a.n_mtiles, NW);
+    const int chunks = rhok_mfma_chunks(a.n_mtiles, 3);
     int waves = (a.n_mtiles + chunks - 1) / chunks;
-    if (waves < TableShape<NW, TA>::min_waves) waves = TableShape<NW, TA>::min_waves;
-    const size_t lds = lds_bytes<NW, TA>(a.x_rows + a.y_rows);
-    hipLaunchKernelGGL((rhok_mfma_kernel<NW, TA>), dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
+    if (waves < TableShape<3, TA>::min_waves) waves = TableShape<3, TA>::min_waves;
+    const size_t lds = lds_bytes<TA>(a.x_rows + a.y_rows, NB);
+    hipLaunchKernelGGL((rhok_mfma_kernel<3, TA, NB>), dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
                        dim3(waves * 64), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(rhok_mfma_final_kernel<NW>, dim3((unsigned)((a.nk + 3) / 4)), dim3(256), 0,
+    hipLaunchKernelGGL(rhok_mfma_final_kernel<3>, dim3((unsigned)((a.nk + 3) / 4)), dim3(256), 0,
                        st, a);
     return hipGetLastError();
 }
@@ -977,9 +1010,13 @@ hipError_t launch_rhok_mfma(const RhokMfmaArgs &a, hipStream_t st)
         return hipErrorInvalidValue;
     const int rows = a.x_rows + a.y_rows;
     if (a.nw == 1) return launch_couples(a, st);
-    if (a.nw == 3)
-        return tile_atoms(rows, 3) == 128 ? launch_nw<3, 128>(a, st) : launch_nw<3, 64>(a, st);
-    return hipErrorInvalidValue;
+    if (a.nw != 3) return hipErrorInvalidValue;
+    const int nb = current_btiles(a.nmax);
+    if (tile_atoms(rows, nb) == 128)
+        return nb == 1 ? launch_currents<128, 1>(a, st)
+               : nb == 2 ? launch_currents<128, 2>(a, st) : launch_currents<128, 3>(a, st);
+    return nb == 1 ? launch_currents<64, 1>(a, st)
+           : nb == 2 ? launch_currents<64, 2>(a, st) : launch_currents<64, 3>(a, st);
 }
 
 } // namespace corr

@@ -953,7 +953,7 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
                 CREATE_HIP(hipMemcpy(g.d_mtab, packed.data(), packed.size() * sizeof(int32_t),
                                      hipMemcpyHostToDevice));
                 CREATE_HIP(hipMalloc(&g.d_partial, (size_t)n_ab * nk * g.nw * 2 * sizeof(double)));
-                CREATE_HIP(rhok_mfma_prepare((x_hi - x_lo + 1) + (y_hi - y_lo + 1), g.nw));
+                CREATE_HIP(rhok_mfma_prepare((x_hi - x_lo + 1) + (y_hi - y_lo + 1), g.nw, nmax));
                 if (g.nw == 3) {
                     // basis of each k-vector: khat, then e1 = the Cartesian axis
                     // least aligned with khat, made orthogonal to it and
