@@ -70,8 +70,15 @@ constexpr int kRoots = 64;         // e^{2 pi i q / kRoots} table for the base p
 // LDS after the root table for the weight scales (three weight sets): the
 // waves' maxima [waves][NW] as floats, in double2 units
 template <int NW> struct ScaleSlots { static constexpr int n = NW == 1 ? 0 : 8; };
-// B fragments in LDS: [K-step][part: re hi, re lo, im hi, im lo][atom group][column]
+// B fragments in LDS: [K-step][part: re hi, re lo, im hi, im lo][atom group][column],
+// each atom group's row of 16 columns padded by one fragment and each K-step
+// by four, so that a Z builder wave's 2-byte writes of 64 consecutive atoms
+// (two K-steps, four atom groups, eight atoms each) fall in 32 different
+// banks (16 ks + 4 grp + h / 2 modulo 32) instead of four
 constexpr int kBParts = 4;
+constexpr int kBGrpStride = 16 + 1;                          // halfv per atom-group row
+constexpr int kBPartStride = 4 * kBGrpStride;                // halfv per part
+constexpr int kBKsStride = kBParts * kBPartStride + 4;       // halfv per K-step
 // atoms whose products the fp32 matrix accumulators sum before they are added
 // to the double accumulators (256: the promotion's 16 conversions and double
 // adds per 128-atom tile halve; C(0) of 2048 k at 10^6 atoms moves by 2e-7)
@@ -87,20 +94,36 @@ template <int TA> struct Tile {
     static constexpr int atoms = TA;
     static constexpr int ksteps = atoms / kKStep;
     static constexpr int stride = atoms + 2;
-    static constexpr int bfrags = ksteps * kBParts * 4 * kMfmaCols;
+    static constexpr int bfrags = ksteps * kBKsStride; // halfv per B tile
     static constexpr int acc_tiles = kAccAtoms / atoms;
 };
 constexpr size_t kLdsBytes = 160 * 1024; // LDS of a CU (and most one block may take)
 
-// Table tasks per tile: (power part, axis, atom).  With three weight sets the
-// Z task carries three times the work, so with 64-atom tiles every axis's
-// powers are split in two parts on separate threads; otherwise one part per
-// axis (128-atom tiles already give every thread of six waves a task).
+// Table tasks per tile: (axis, power part, atom), ordered X parts, Y parts, Z
+// parts.  With three weight sets the Z task carries about three times the work
+// of an X or Y task (three products and splits per power), so its powers are
+// split in two parts on separate threads; with 64-atom tiles the X and Y
+// powers are split as well, so that six waves still have a task per thread.
+// (128-atom tiles: X, Y and Z in one part each made the two Z waves the
+// critical path, 7000 cycles of build per tile against 2200-2500.)
 template <int NW, int TA> struct TableShape {
-    static constexpr int parts = NW == 1 || TA == 128 ? 1 : 2;
-    static constexpr int tasks = parts * 3 * TA;
+    static constexpr int xy_parts = NW == 3 && TA == 64 ? 2 : 1;
+    static constexpr int z_parts = NW == 3 ? 2 : 1;
+    static constexpr int tasks = (2 * xy_parts + z_parts) * TA;
     static constexpr int min_waves = tasks / 64; // every task has its own thread
 };
+
+// Axis d, power part hf and atom j of table task `task` (d and hf are uniform
+// over a wave: 64 divides the tile).
+template <int NW, int TA>
+__device__ __forceinline__ void table_task(int task, int &d, int &hf, int &j)
+{
+    constexpr int xyp = TableShape<NW, TA>::xy_parts;
+    const int u = task / TA;
+    j = task - u * TA;
+    d = u < 2 * xyp ? u / xyp : 2;
+    hf = u < 2 * xyp ? u - d * xyp : u - 2 * xyp;
+}
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
@@ -118,7 +141,7 @@ __device__ __forceinline__ float4_t mfma(half8_t a, half8_t b, float4_t c)
 
 __device__ __forceinline__ int bfrag_index(int ks, int part, int grp, int col)
 {
-    return ((ks * kBParts + part) * 4 + grp) * kMfmaCols + col; // in halfv_t units
+    return ks * kBKsStride + part * kBPartStride + grp * kBGrpStride + col; // in halfv_t units
 }
 
 // Two floats to two fp16 (round to nearest even), packed low | high.
@@ -174,11 +197,12 @@ struct TileBufs {
 // Build the tables of one tile.  The B fragments of the NW weight sets are
 // packed by column: column s (nmax + 1) + n of B tile (column / 16) holds
 // w_s Z^n (NB = ceil(NW (nmax + 1) / 16) tiles instead of NW).
-// Task (power part hf, axis d, atom j), the
+// Task (axis d, power part hf, atom j), the
 // task of lane `lane` of task wave `twave` (uniform over the wave, which
 // fixes hf and d: 64 divides the tile, so all control flow is uniform): with
 // two parts, part 0 takes n = 0 .. n1 and part 1 takes n = n1+1 .. nmax
-// starting from its own e^{2 pi i n1 x / L} (both from unit_phase).  Powers
+// (n1 = nmax / 2) starting from its own e^{2 pi i n1 x / L} (both from
+// unit_phase).  Powers
 // by a double recurrence, each rounded once; X and Y rows for both signs, and
 // for each weight set w the products w * Z^n split into fp16 hi/lo B
 // fragments (NW = 1: w = 1; NW = 3: the atom's velocity components).  Atoms
@@ -189,10 +213,11 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int twave, int la
                                            double inv_box, int nmax, int2 xrows, int2 yrows,
                                            const double2 *roots)
 {
-    const int hf = twave * 64 / (3 * Tile<TA>::atoms);
-    const int rem = twave * 64 - hf * 3 * Tile<TA>::atoms;
-    const int d = rem / Tile<TA>::atoms, j = rem - d * Tile<TA>::atoms + lane;
-    const int n1 = TableShape<NW, TA>::parts == 1 ? nmax : (nmax + 1) / 2;
+    int d, hf, j;
+    table_task<NW, TA>(twave * 64, d, hf, j);
+    j += lane;
+    const int parts = d < 2 ? TableShape<NW, TA>::xy_parts : TableShape<NW, TA>::z_parts;
+    const int n1 = parts == 1 ? nmax : nmax / 2;
     const int n_begin = hf == 0 ? 0 : n1 + 1, n_end = hf == 0 ? n1 : nmax;
     const double f = (double)x * inv_box;
     // every lane evaluates (x = 0 past the end); a dead lane's powers are zero
@@ -217,7 +242,10 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int twave, int la
         }
     } else {
         const int ks = j / kKStep, g = (j % kKStep) / kAtomsPerLane, h = j % kAtomsPerLane;
-        _Float16 *bh = reinterpret_cast<_Float16 *>(tb.bfr);
+        // the lane's entry of column 0, part 0 of B tile 0; columns and B
+        // tiles add a uniform offset, the parts a constant one
+        _Float16 *const lane_b =
+            reinterpret_cast<_Float16 *>(tb.bfr) + bfrag_index(ks, 0, g, 0) * kAtomsPerLane + h;
         auto store_z = [&](int n) {
 #pragma unroll
             for (int s = 0; s < NW; ++s) {
@@ -233,11 +261,11 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int twave, int la
                 const _Float16 rh = H[0], ih = H[1], rl = L[0], il = L[1];
                 // column s (nmax + 1) + n of the packed B tiles
                 const int gc = s * (nmax + 1) + n, bt = gc / kMfmaCols, c = gc % kMfmaCols;
-                _Float16 *bs = bh + (size_t)bt * Tile<TA>::bfrags * kAtomsPerLane;
-                bs[bfrag_index(ks, 0, g, c) * kAtomsPerLane + h] = rh;
-                bs[bfrag_index(ks, 1, g, c) * kAtomsPerLane + h] = rl;
-                bs[bfrag_index(ks, 2, g, c) * kAtomsPerLane + h] = ih;
-                bs[bfrag_index(ks, 3, g, c) * kAtomsPerLane + h] = il;
+                _Float16 *const e = lane_b + (bt * Tile<TA>::bfrags + c) * kAtomsPerLane;
+                e[0] = rh;
+                e[kBPartStride * kAtomsPerLane] = rl;
+                e[2 * kBPartStride * kAtomsPerLane] = ih;
+                e[3 * kBPartStride * kAtomsPerLane] = il;
             }
         };
         if (n_begin == 0) store_z(0);
@@ -278,15 +306,18 @@ template <int NW, int TA, int NB> __device__ __forceinline__ void rhok_mfma_body
     const int lane = threadIdx.x & 63;
     const int col = lane & 15; // A row / B column within the tile
     const int grp = lane >> 4; // atom group of the K-step
-    const int mt = blockIdx.x * waves + wave;
-    const bool active = mt < a.n_mtiles; // wave-uniform
+    // the M tiles dealt evenly over the chunks (gridDim.x), one per wave from
+    // wave 0; the waves past them only build tables
+    const int per_chunk = (a.n_mtiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int mt = blockIdx.x * per_chunk + wave;
+    const bool active = wave < per_chunk && mt < a.n_mtiles; // wave-uniform
     const int pm_row = mt * 16 + col;
     const int ax = active ? a.pair_nx[pm_row] - a.x_lo : 0; // table rows
     const int ay = active ? a.pair_ny[pm_row] - a.y_lo : 0;
     // the lane's X and Y rows at its first atom (16-byte aligned) per buffer
     const int xoff = ax * Tile<TA>::stride + grp * kAtomsPerLane;
     const int yoff = ay * Tile<TA>::stride + grp * kAtomsPerLane;
-    const int boff = grp * kMfmaCols + col;
+    const int boff = bfrag_index(0, 0, grp, col);
 
     for (int q = threadIdx.x; q < kRoots; q += blockDim.x) {
         double sn, cs;
@@ -294,10 +325,16 @@ template <int NW, int TA, int NB> __device__ __forceinline__ void rhok_mfma_body
         lds_roots[q] = make_double2(cs, sn);
     }
     // packed B columns past NW (nmax + 1) are never stored; keep them zero
+    // (f runs over (buffer, B tile, K-step, part, group, column))
     const int ncols = NW * (nmax + 1);
-    for (int f = threadIdx.x; f < 2 * NB * Tile<TA>::bfrags; f += blockDim.x)
-        if (((f / Tile<TA>::bfrags) % NB) * kMfmaCols + f % kMfmaCols >= ncols)
-            tile_bufs(f / (NB * Tile<TA>::bfrags)).bfr[f % (NB * Tile<TA>::bfrags)] = halfv_t{};
+    constexpr int kRowsPerTile = Tile<TA>::ksteps * kBParts * 4;
+    for (int f = threadIdx.x; f < 2 * NB * kRowsPerTile * kMfmaCols; f += blockDim.x) {
+        const int c = f % kMfmaCols, r = f / kMfmaCols;
+        const int gq = r % 4, part = (r / 4) % kBParts, ks = (r / (4 * kBParts)) % Tile<TA>::ksteps;
+        const int bt = (r / kRowsPerTile) % NB, b = r / (kRowsPerTile * NB);
+        if (bt * kMfmaCols + c >= ncols)
+            tile_bufs(b).bfr[bt * Tile<TA>::bfrags + bfrag_index(ks, part, gq, c)] = halfv_t{};
+    }
 
     double acc[NB][4][4];
     float4_t sum[NB][4]; // products of the last Tile::acc_tiles tiles at most
@@ -360,8 +397,9 @@ template <int NW, int TA, int NB> __device__ __forceinline__ void rhok_mfma_body
     const int twave = __builtin_amdgcn_readfirstlane(wave);
     const int task = twave * 64 + lane;
     const bool builder = twave * 64 < TableShape<NW, TA>::tasks; // wave-uniform
-    const int trem = task % (3 * Tile<TA>::atoms);
-    const int td = trem / Tile<TA>::atoms, tj = trem - td * Tile<TA>::atoms;
+    int td, thf, tj;
+    table_task<NW, TA>(task, td, thf, tj);
+    (void)thf; // both Z parts load the same atom's inputs
     const bool weighted = NW > 1 && td == 2;
     auto load_in = [&](int it, float &x, float (&w)[NW]) -> bool {
         const int64_t at = a_begin + (int64_t)it * Tile<TA>::atoms + tj;
@@ -383,16 +421,21 @@ template <int NW, int TA, int NB> __device__ __forceinline__ void rhok_mfma_body
 
     for (int it = 0; it < n_tiles; ++it) {
         const TileBufs cur = tile_bufs(it & 1);
-        // tables of the next tile into the other buffer
-        if (builder && it + 1 < n_tiles) {
-            float x_after, w_after[NW];
-            const bool live_after = load_in(it + 2, x_after, w_after);
+        // tables of the next tile into the other buffer; the inputs of the
+        // tile after that are loaded after the build and moved up after this
+        // tile's contraction, so that no wave waits for them: loaded before
+        // the build, or moved up right after it, they cost every builder wave
+        // a memory latency per tile (the loads are conditional, so a wait
+        // for older ones waits for them too)
+        const bool building = builder && it + 1 < n_tiles;
+        float x_after = 0.f, w_after[NW];
+        bool live_after = false;
+#pragma unroll
+        for (int s = 0; s < NW; ++s) w_after[s] = 1.f;
+        if (building) {
             build_tile<NW, TA>(tile_bufs((it + 1) & 1), twave, lane, live_next, x_next, w_next,
                                wsc, a.inv_box, nmax, xrows, yrows, lds_roots);
-            x_next = x_after;
-#pragma unroll
-            for (int s = 0; s < NW; ++s) w_next[s] = w_after[s];
-            live_next = live_after;
+            live_after = load_in(it + 2, x_after, w_after);
         }
         if (active) {
             const float4 *xrow = reinterpret_cast<const float4 *>(cur.tabx + xoff);
@@ -473,6 +516,12 @@ template <int NW, int TA, int NB> __device__ __forceinline__ void rhok_mfma_body
                         sum[w][s] = float4_t{0.f, 0.f, 0.f, 0.f};
                     }
             }
+        }
+        if (building) {
+            x_next = x_after;
+#pragma unroll
+            for (int s = 0; s < NW; ++s) w_next[s] = w_after[s];
+            live_next = live_after;
         }
         __syncthreads(); // next buffer complete; this one free for the tile after
     }

@@ -153,3 +153,37 @@ def test_batched_config_full_size():
                 err = np.max(np.abs(rk["c_per_channel"][q] - cc / N)) / abs(cc[0] / N)
                 assert err <= TOL[("cf32", "kahan")], f"rho(k) k={q}: {err:.3e}"
     assert len(results[S_end][3]["t"]) == 16 + 9 * 8  # every level has counts at 10^4
+
+
+def test_currents_2048k_1e6_atoms():
+    """The current producer in the benchmark's launch configuration: 2048
+    k-vectors (|n| <= 12 half-space) from 10^6 atoms in a box of 100, i.e.
+    128-atom tiles, two packed B tiles and two M-tile chunks of 256 atom
+    blocks in all.  C(0) and C(1) of two pushes on 48 sampled k-vectors
+    (the first, middle and last 16) against the oracle's direct double sums of
+    the same float inputs, at the producer's precision (2e-6 of the largest
+    C(0) of the sample)."""
+    from paper_2503_07526_amd import Correlator, GroupDesc
+    N, box, S = 1_000_000, 100.0, 2
+    kv = synth.kvectors(2048)
+    say(f"[full size currents] N={N} nk={len(kv)}")
+    pos, _ = synth.PositionSpec(5, 3, N, box).series(0, S)
+    vel = np.random.default_rng(12).standard_normal((S, 3, N)).astype(np.float32)
+    x = torch.from_numpy(np.ascontiguousarray(np.concatenate([pos, vel], axis=1))).to("cuda")
+    g = GroupDesc(3 * len(kv), 3, 8, 2, dtype="cf32", accum="f64", source="currents", kvec=kv,
+                  n_atoms=N, box=box)
+    ranges = [(0, 16), (1016, 1032), (2032, 2048)]
+    with Correlator([g]) as c:
+        for s in range(S):
+            c.push([x[s]])
+        torch.cuda.synchronize()
+        got = [c.finalize(0, slice_=(3 * lo, 3 * hi))["c_per_channel"] for lo, hi in ranges]
+    got = np.concatenate(got)
+    ks = np.concatenate([kv[lo:hi] for lo, hi in ranges])
+    j = [oracle.currents(pos[s], vel[s], ks, box).reshape(-1) for s in range(S)]
+    c0 = (np.abs(j[0]) ** 2 + np.abs(j[1]) ** 2) / 2 / N
+    c1 = j[1] * np.conj(j[0]) / N
+    e0 = np.max(np.abs(got[:, 0] - c0)) / np.max(c0)
+    e1 = np.max(np.abs(got[:, 1] - c1)) / np.max(c0)
+    say(f"  C(0) {e0:.2e}  C(1) {e1:.2e}")
+    assert e0 < 2e-6 and e1 < 2e-6
