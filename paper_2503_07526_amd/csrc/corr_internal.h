@@ -262,13 +262,16 @@ struct RhokMfmaArgs {
 // groups has folded block commit_block (after folds of all tile groups).
 struct PushEndArgs {
     int64_t *step;
+    int64_t *step2;                    // a second counter advanced with step (the
+                                       // producer chain's), or null
     int32_t n_flushed;                 // block-deferred groups
     int32_t advance;                   // pushes counted
     int64_t *flushed[kMaxGroups];      // their [kFlushGroups] last-folded arrays
     int32_t defer_t[kMaxGroups];       // their blocks T
     int64_t commit_block;
-    FoldStamps *stamps;                // timing: the push's [2] stamp records (folds,
+    FoldStamps *stamps;                // timing: the push's stamp records (folds, then
                                        // producers), else null
+    int32_t n_stamps;                  // records reduced from stamps (1 or 2)
 };
 
 // Readout reduction arguments.

@@ -445,7 +445,7 @@ __global__ void push_end_kernel(PushEndArgs a)
         // the lanes take the slots of both stamp records in turn; the earliest
         // start and the latest end give the push's span of each class
         __shared__ unsigned long long lo[64], hi[64];
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < a.n_stamps; ++r) {
             FoldStamps &st = a.stamps[r];
             const int l = threadIdx.x;
             if (l < 64) {
@@ -490,6 +490,7 @@ __global__ void push_end_kernel(PushEndArgs a)
         }
     }
     *a.step += a.advance;
+    if (a.step2) *a.step2 += a.advance;
 }
 
 // ------------------------------------------------------------ host launchers
@@ -623,7 +624,8 @@ hipError_t launch_push_window(const GroupArgs &g, const int64_t *step, int cpt, 
 
 hipError_t launch_push_end(const PushEndArgs &a, hipStream_t st)
 {
-    if (a.n_flushed < 0 || a.n_flushed > kMaxGroups) return hipErrorInvalidValue;
+    if (a.n_flushed < 0 || a.n_flushed > kMaxGroups || a.n_stamps < 0 || a.n_stamps > 2)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(push_end_kernel, dim3(1), dim3(64), 0, st, a);
     return hipGetLastError();
 }

@@ -105,7 +105,13 @@ struct corr_ctx {
     uint32_t flags = 0;
     corr_tuning tuning{};
     std::vector<Group> groups;
+    // push counters: d_step[0] for the main stream's kernels, d_step[1]
+    // (d_step_side) for the kernels that run on the side stream when the
+    // producers are forked (their per-step pushes); equal after every push,
+    // except inside a captured run of pushes whose two chains are joined only
+    // at its end
     int64_t *d_step = nullptr;
+    int64_t *d_step_side = nullptr;
     int64_t n_push = 0;
     int32_t defer_t = 0;       // pushes per fold block of the block-deferred groups
     int32_t fold_threads = kFoldThreadsDefault;
@@ -116,8 +122,10 @@ struct corr_ctx {
     int64_t total_tiles = 0;
     hipStream_t cap_stream = nullptr;
     // k-density groups run on a side stream (producer, then their own push
-    // launch) forked from and joined to the main stream on every push, so the
-    // ALU-bound producer overlaps the HBM-bound push of the other groups.
+    // launch) forked from and joined to the main stream on every push (in a
+    // captured corr_push_steps beside block-deferred groups: once per
+    // capture), so the ALU-bound producer overlaps the HBM-bound push of the
+    // other groups.
     // main_set: per-step (direct) groups fed with samples; side_set: k-density
     // groups; deferred_set (below): block-deferred groups (staged per push).
     std::vector<int> main_set, side_set; // context group indices
@@ -463,7 +471,7 @@ bool is_split(const GroupArgs &g)
 
 // Push kernel launch(es) for the groups of one set (batched: one launch;
 // per-group form: one launch per group; long one-level windows: one window
-// launch each).
+// launch each), all reading the push counter of the set's arguments.
 int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
                const std::vector<const void *> &resolved, hipStream_t st)
 {
@@ -478,20 +486,20 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
         int64_t tf = 0;
         for (int i = 0; i < a.n_groups; ++i) {
             if (is_window_deferred(a.g[i])) {
-                HIP_TRY(c, launch_push_group(a.g[i], c->d_step, cpt, lch, block, st));
-                HIP_TRY(c, launch_window_fold(a.g[i], c->d_step, st));
+                HIP_TRY(c, launch_push_group(a.g[i], base.step, cpt, lch, block, st));
+                HIP_TRY(c, launch_window_fold(a.g[i], base.step, st));
                 continue;
             }
             if (is_window(a.g[i])) {
-                HIP_TRY(c, launch_push_window(a.g[i], c->d_step, cpt, lch, block, kWindowLags, st));
+                HIP_TRY(c, launch_push_window(a.g[i], base.step, cpt, lch, block, kWindowLags, st));
                 continue;
             }
             if (a.g[i].pair) { // pair groups have their own kernels
-                HIP_TRY(c, launch_push_group(a.g[i], c->d_step, cpt, lch, block, st));
+                HIP_TRY(c, launch_push_group(a.g[i], base.step, cpt, lch, block, st));
                 continue;
             }
             if (!(c->flags & CORR_FLAG_PER_GROUP) && is_split(a.g[i])) {
-                HIP_TRY(c, launch_push_split(a.g[i], c->d_step, cpt, lch, block, kSplitLags, st));
+                HIP_TRY(c, launch_push_split(a.g[i], base.step, cpt, lch, block, kSplitLags, st));
                 continue;
             }
             rest.g[n] = a.g[i];
@@ -506,7 +514,7 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
     }
     if (c->flags & CORR_FLAG_PER_GROUP) {
         for (int i = 0; i < a.n_groups; ++i)
-            HIP_TRY(c, launch_push_group(a.g[i], c->d_step, cpt, lch, block, st));
+            HIP_TRY(c, launch_push_group(a.g[i], base.step, cpt, lch, block, st));
     } else {
         int64_t grid = c->tuning.grid_blocks > 0 ? c->tuning.grid_blocks : a.total_tiles;
         grid = std::min<int64_t>(grid, a.total_tiles);
@@ -527,8 +535,17 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
 // by the push of the producers' groups only (the sample-fed groups then run on
 // the main stream beside them); 2 keeps the producers on the main stream and
 // forks the per-step pushes, which then run beside the flush.
+//
+// chained: a push inside a captured run whose two chains are forked and
+// joined once around the whole run (the caller does both; it requires the
+// producers forked beside block-deferred groups).  Each chain then ends the
+// push with its own end kernel and counter: the main stream staging, flush and
+// end (d_step, flush records, fold stamps), the side stream the producers,
+// the per-step pushes and an end (d_step_side, producer stamps).  No push
+// waits for the other stream's work of the push before (the per-push fork
+// and join each left the chip idle for a few microseconds).
 int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_flush,
-               bool skip_deferred = false)
+               bool skip_deferred = false, bool chained = false)
 {
     // skip_deferred: the block-deferred groups take no part in this push (a
     // replay folds their block straight from the history instead)
@@ -553,7 +570,9 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
         if (rc != CORR_OK) return rc;
         HIP_TRY(c, hipEventRecord(e0, st));
     }
-    if (fork) {
+    if (chained && !(fork && with_flush && !dset.empty() && !timed))
+        return set_err(c, CORR_E_STATE, "chained push without forked producers beside a flush");
+    if (fork && !chained) {
         // forked before the staging: the producers start at once and hold
         // their CUs before the staging and the flush fill the rest (forked
         // after the staging, the flush's small blocks took the chip first and
@@ -603,7 +622,16 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
         idx.insert(idx.end(), c->side_set.begin(), c->side_set.end());
         int rc = launch_set(c, c->pa_direct, idx, resolved, pst);
         if (rc != CORR_OK) return rc;
-        HIP_TRY(c, hipEventRecord(c->ev_join, pst));
+        if (chained) {
+            PushEndArgs se{};
+            se.step = c->d_step_side;
+            se.advance = 1;
+            se.stamps = c->d_stamps ? c->d_stamps + 1 : nullptr;
+            se.n_stamps = 1;
+            HIP_TRY(c, launch_push_end(se, pst));
+        } else {
+            HIP_TRY(c, hipEventRecord(c->ev_join, pst));
+        }
     } else if (fork) {
         // no flush to overlap: the sample-fed groups run beside the producers
         int rc = launch_set(c, c->pa_side, c->side_set, resolved, pst);
@@ -637,16 +665,18 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
     }
     if (fork_updates) HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
     if (timed) HIP_TRY(c, hipEventRecord(e1, st));
-    if (fork) HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
+    if (fork && !chained) HIP_TRY(c, hipStreamWaitEvent(st, c->ev_join, 0));
     PushEndArgs pe{};
     pe.step = c->d_step;
+    pe.step2 = chained ? nullptr : c->d_step_side;
     pe.advance = 1;
     if (with_flush)
         for (int i : dset) {
             pe.defer_t[pe.n_flushed] = c->groups[(size_t)i].T;
             pe.flushed[pe.n_flushed++] = c->groups[(size_t)i].d_flushed;
         }
-    pe.stamps = c->d_stamps; // timing: adds this push's fold and producer spans
+    pe.stamps = c->d_stamps; // timing: adds this push's fold (and producer) spans
+    pe.n_stamps = chained ? 1 : 2;
     HIP_TRY(c, launch_push_end(pe, st));
     return CORR_OK;
 }
@@ -1161,18 +1191,20 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
         CREATE_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         CREATE_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     }
-    CREATE_HIP(hipMalloc(&c->d_step, sizeof(int64_t)));
-    CREATE_HIP(hipMemsetAsync(c->d_step, 0, sizeof(int64_t), c->stream));
+    CREATE_HIP(hipMalloc(&c->d_step, 2 * sizeof(int64_t)));
+    CREATE_HIP(hipMemsetAsync(c->d_step, 0, 2 * sizeof(int64_t), c->stream));
+    c->d_step_side = c->d_step + 1;
     CREATE_HIP(noalloc_scratch(device, &c->noalloc));
     if (flags & CORR_FLAG_TIMING) {
         int khz = 0;
         CREATE_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
         c->stamp_khz = khz > 0 ? (double)khz : 0.0;
         std::vector<FoldStamps> init(2);
-        for (auto &r : init) {
+        for (size_t k = 0; k < init.size(); ++k) {
+            FoldStamps &r = init[k];
             r = FoldStamps{};
             for (auto &sl : r.slot) sl.start = ~0ull;
-            r.step = c->d_step;
+            r.step = k == 0 ? c->d_step : c->d_step_side; // folds / producers
             r.stride = 1;
         }
         CREATE_HIP(hipMalloc(&c->d_stamps, 2 * sizeof(FoldStamps)));
@@ -1180,8 +1212,8 @@ int corr_create(const corr_group_desc *groups, int32_t n_groups, int32_t device,
     }
     c->pargs.step = c->d_step;
     c->pa_main.step = c->d_step;
-    c->pa_side.step = c->d_step;
-    c->pa_direct.step = c->d_step;
+    c->pa_side.step = c->d_step_side; // the sets that run on the side stream
+    c->pa_direct.step = c->d_step_side;
     CREATE_HIP(hipStreamSynchronize(c->stream));
 
     if (flags & CORR_FLAG_GRAPH) {
@@ -1284,9 +1316,11 @@ int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
 
     if (ctx->flags & CORR_FLAG_GRAPH) {
         // Graph mode: the n pushes as one captured graph (the same kernels as
-        // single pushes; they take their schedule from the device counter, so
-        // a graph replays correctly at any push count), kept for the next call
-        // with the same histories and length.
+        // single pushes; they take their schedule from the device counters,
+        // so a graph replays correctly at any push count), kept for the next
+        // call with the same histories and length.  With the producers forked
+        // beside block-deferred groups the two streams form two chains forked
+        // and joined once around the run (chained pushes).
         std::vector<const void *> base(samples, samples + ng);
         auto &cache = ctx->steps_graphs;
         size_t hit = cache.size();
@@ -1297,11 +1331,29 @@ int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
             sg.n = n_steps;
             sg.src = base;
             sg.stride = stride;
+            const bool chained = ctx->tuning.overlap_producers == 1 && !ctx->side_set.empty() &&
+                                 with_flush;
             HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
             int rc = CORR_OK;
+            auto cap = [&](hipError_t e, const char *what) {
+                if (rc == CORR_OK && e != hipSuccess) rc = hip_err(ctx, e, what);
+            };
+            if (chained) {
+                cap(hipEventRecord(ctx->ev_fork, ctx->cap_stream), "hipEventRecord");
+                cap(hipStreamWaitEvent(ctx->side_stream, ctx->ev_fork, 0), "hipStreamWaitEvent");
+            }
             for (int32_t r = 0; r < n_steps && rc == CORR_OK; ++r) {
                 row(r);
-                rc = issue_push(ctx, src.data(), ctx->cap_stream, with_flush);
+                rc = issue_push(ctx, src.data(), ctx->cap_stream, with_flush, false, chained);
+            }
+            if (chained) {
+                // joined even after an error: the capture must end with the
+                // side stream back in the main one
+                const int rc0 = rc;
+                rc = CORR_OK;
+                cap(hipEventRecord(ctx->ev_join, ctx->side_stream), "hipEventRecord");
+                cap(hipStreamWaitEvent(ctx->cap_stream, ctx->ev_join, 0), "hipStreamWaitEvent");
+                if (rc0 != CORR_OK) rc = rc0;
             }
             const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &sg.graph);
             if (rc != CORR_OK || ec != hipSuccess) {
@@ -1354,6 +1406,7 @@ int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
             }
             PushEndArgs pe{};
             pe.step = ctx->d_step;
+            pe.step2 = ctx->d_step_side;
             pe.advance = 0;
             pe.commit_block = q;
             for (int i : ctx->deferred_set) {
@@ -1387,9 +1440,11 @@ int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
             }
             PushEndArgs pe{};
             pe.step = ctx->d_step;
+            pe.step2 = ctx->d_step_side;
             pe.advance = others ? 0 : T; // the other groups' pushes advanced the counter
             pe.commit_block = q + 1;
             pe.stamps = ctx->d_stamps;
+            pe.n_stamps = 2;
             for (int i : ctx->deferred_set) {
                 pe.defer_t[pe.n_flushed] = ctx->groups[(size_t)i].T;
                 pe.flushed[pe.n_flushed++] = ctx->groups[(size_t)i].d_flushed;

@@ -205,7 +205,10 @@ def test_batched_mixed_groups_and_modes(corrmod, rhok_valu):
     k-space density, FP64 global channels): parity with the oracle, and
     bit-identical state from the batched launch, the per-group launches, the
     HIP graph replay and both forked issue orders (producers forked; per-step
-    updates forked beside the flush), with either k-density producer."""
+    updates forked beside the flush), with either k-density producer, and from
+    captured runs of 100 pushes with the producers forked (corr_push_steps:
+    two chains forked and joined once per run, one capture replayed four
+    times across the first fold block)."""
     S, nv, N, box = 400, 2500, 3000, 100.0
     kv = synth.kvectors(200)
     say(f"[batched] S={S} nv={nv} N={N} nk={len(kv)}")
@@ -224,20 +227,28 @@ def test_batched_mixed_groups_and_modes(corrmod, rhok_valu):
         orh.push(oracle.rhok(xp[s], kv, box))
     results = {}
     modes = ("batched", "per_group", "graph", "overlap", "overlap_graph", "overlap2",
-             "overlap2_graph")
+             "overlap2_graph", "overlap_steps")
     for mode in modes:
         say(f"  mode {mode}")
         tuning = None
         if mode.startswith("overlap"):
             tuning = {"overlap_producers": 2 if mode.startswith("overlap2") else 1}
-        with corrmod.Correlator(groups, graph=mode.endswith("graph"),
+        with corrmod.Correlator(groups, graph=mode.endswith(("graph", "steps")),
                                 per_group=(mode == "per_group"), rhok_valu=rhok_valu,
                                 tuning=tuning) as c:
             dev = torch.device("cuda:0")
             tv = torch.from_numpy(xv).to(dev)
             tg = torch.from_numpy(xg).to(dev)
             tp = torch.from_numpy(xp).to(dev)
-            if mode.endswith("graph"):
+            if mode.endswith("steps"):
+                ch = 100
+                bufs = [torch.empty((ch,) + tuple(t.shape[1:]), dtype=t.dtype, device=dev)
+                        for t in (tv, tp, tg)]
+                for s0 in range(0, S, ch):
+                    for b, t in zip(bufs, (tv, tp, tg)):
+                        b.copy_(t[s0:s0 + ch])  # the same buffers every call: one capture
+                    c.push_steps(bufs)
+            elif mode.endswith("graph"):
                 bv = torch.empty_like(tv[0]); bp = torch.empty_like(tp[0]); bg = torch.empty_like(tg[0])
                 c.bind_input(0, bv); c.bind_input(1, bp); c.bind_input(2, bg)
                 for s in range(S):
@@ -416,17 +427,21 @@ def test_kernel_time_pools(corrmod):
         with pytest.raises(corrmod.CorrError):
             ref.set_timing_stride(4)  # no CORR_FLAG_TIMING
     # captured graphs: stamps on pushes 0, 8, ..., 64 whatever the chunks, same state
-    with corrmod.Correlator(groups, timing=True, graph=True) as c, \
-            corrmod.Correlator(groups) as ref:
-        c.set_timing_stride(8)
-        xv_d = torch.as_tensor(xv, device="cuda")
-        xp_d = torch.as_tensor(xp, device="cuda")
-        for a, b in ((0, 13), (13, 45), (45, S)):
-            c.push_steps([xv_d[a:b], xp_d[a:b]])
-        _push_all(ref, [xv, xp])
-        assert c.kernel_time(3)[1] == 9 and c.kernel_time(4)[1] == 9
-        assert np.array_equal(c.finalize(0, slice_=(0, 3))["c_per_channel"],
-                              ref.finalize(0, slice_=(0, 3))["c_per_channel"])
+    # (also with the producers forked, where each captured run forks and joins
+    # the two streams once and each stream ends its pushes with its own counter)
+    for tuning in (None, {"overlap_producers": 1}):
+        with corrmod.Correlator(groups, timing=True, graph=True, tuning=tuning) as c, \
+                corrmod.Correlator(groups) as ref:
+            c.set_timing_stride(8)
+            xv_d = torch.as_tensor(xv, device="cuda")
+            xp_d = torch.as_tensor(xp, device="cuda")
+            for a, b in ((0, 13), (13, 45), (45, S)):
+                c.push_steps([xv_d[a:b], xp_d[a:b]])
+            _push_all(ref, [xv, xp])
+            assert c.kernel_time(3)[1] == 9 and c.kernel_time(4)[1] == 9, tuning
+            for g in range(2):
+                assert np.array_equal(c.finalize(g, slice_=(0, 3))["c_per_channel"],
+                                      ref.finalize(g, slice_=(0, 3))["c_per_channel"]), tuning
 
 
 def _currents_inputs(seed, N, box, S):
