@@ -782,8 +782,14 @@ def run(args):
                                   else "one corr_push per step"),
                    "fold_block": {str(i): g["T"] for i, g in enumerate(wl["groups"]) if "T" in g},
                    "producer_stream": {0: "the context's stream, before the other updates",
-                                       1: "forked at the start of the push (with the per-step "
-                                          "updates when block-deferred groups flush beside them)",
+                                       1: ("a side stream with the per-step updates, forked and "
+                                           "joined once per captured chunk (each stream ends its "
+                                           "pushes with its own counter)"
+                                           if use_graph and any(deferred(g, args.direct)
+                                                                for g in wl["groups"]) else
+                                           "forked at the start of the push (with the per-step "
+                                           "updates when block-deferred groups flush beside "
+                                           "them)"),
                                        2: "the context's stream; the per-step updates forked "
                                           "beside the flush"}[corr.tuning()["overlap_producers"]],
                    "tuning": corr.tuning(), "state_GB": round(state_gb, 2)},
