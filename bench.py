@@ -783,8 +783,8 @@ def run(args):
                    "fold_block": {str(i): g["T"] for i, g in enumerate(wl["groups"]) if "T" in g},
                    "producer_stream": {0: "the context's stream, before the other updates",
                                        1: ("a side stream with the per-step updates, forked and "
-                                           "joined once per captured chunk (each stream ends its "
-                                           "pushes with its own counter)"
+                                           "joined every 4 pushes of a captured chunk (each "
+                                           "stream ends its pushes with its own counter)"
                                            if use_graph and any(deferred(g, args.direct)
                                                                 for g in wl["groups"]) else
                                            "forked at the start of the push (with the per-step "

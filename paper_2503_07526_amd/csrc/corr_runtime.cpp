@@ -123,9 +123,9 @@ struct corr_ctx {
     hipStream_t cap_stream = nullptr;
     // k-density groups run on a side stream (producer, then their own push
     // launch) forked from and joined to the main stream on every push (in a
-    // captured corr_push_steps beside block-deferred groups: once per
-    // capture), so the ALU-bound producer overlaps the HBM-bound push of the
-    // other groups.
+    // captured corr_push_steps beside block-deferred groups: every
+    // kChainSync pushes), so the ALU-bound producer overlaps the HBM-bound
+    // push of the other groups.
     // main_set: per-step (direct) groups fed with samples; side_set: k-density
     // groups; deferred_set (below): block-deferred groups (staged per push).
     std::vector<int> main_set, side_set; // context group indices
@@ -537,7 +537,7 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
 // forks the per-step pushes, which then run beside the flush.
 //
 // chained: a push inside a captured run whose two chains are forked and
-// joined once around the whole run (the caller does both; it requires the
+// joined around a few pushes at a time (the caller does both; it requires the
 // producers forked beside block-deferred groups).  Each chain then ends the
 // push with its own end kernel and counter: the main stream staging, flush and
 // end (d_step, flush records, fold stamps), the side stream the producers,
@@ -1284,6 +1284,14 @@ int corr_push(corr_ctx *ctx, const void *const *samples)
     return CORR_OK;
 }
 
+// Chained pushes of a captured run meet (join and fork again) after every
+// kChainSync pushes.  Unprofiled, meeting every 4 to 32 pushes or only at the
+// end of the run gave the same batched step within 2% (0.175-0.179 ms); under
+// kernel tracing, where the graph's kernels are submitted more slowly and
+// stream by stream, long chains ran one after the other (0.250 ms, the fold
+// 80 us alone) and chains of 4 pushes still overlapped (0.187 ms).
+constexpr int32_t kChainSync = 4;
+
 int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
                     const int64_t *strides)
 {
@@ -1320,7 +1328,7 @@ int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
         // so a graph replays correctly at any push count), kept for the next
         // call with the same histories and length.  With the producers forked
         // beside block-deferred groups the two streams form two chains forked
-        // and joined once around the run (chained pushes).
+        // and joined around every kChainSync pushes (chained pushes).
         std::vector<const void *> base(samples, samples + ng);
         auto &cache = ctx->steps_graphs;
         size_t hit = cache.size();
@@ -1345,6 +1353,12 @@ int corr_push_steps(corr_ctx *ctx, int32_t n_steps, const void *const *samples,
             for (int32_t r = 0; r < n_steps && rc == CORR_OK; ++r) {
                 row(r);
                 rc = issue_push(ctx, src.data(), ctx->cap_stream, with_flush, false, chained);
+                if (chained && rc == CORR_OK && (r + 1) % kChainSync == 0 && r + 1 < n_steps) {
+                    cap(hipEventRecord(ctx->ev_join, ctx->side_stream), "hipEventRecord");
+                    cap(hipStreamWaitEvent(ctx->cap_stream, ctx->ev_join, 0), "hipStreamWaitEvent");
+                    cap(hipEventRecord(ctx->ev_fork, ctx->cap_stream), "hipEventRecord");
+                    cap(hipStreamWaitEvent(ctx->side_stream, ctx->ev_fork, 0), "hipStreamWaitEvent");
+                }
             }
             if (chained) {
                 // joined even after an error: the capture must end with the

@@ -207,7 +207,7 @@ def test_batched_mixed_groups_and_modes(corrmod, rhok_valu):
     HIP graph replay and both forked issue orders (producers forked; per-step
     updates forked beside the flush), with either k-density producer, and from
     captured runs of 100 pushes with the producers forked (corr_push_steps:
-    two chains forked and joined once per run, one capture replayed four
+    two chains joined every 4 pushes, one capture replayed four
     times across the first fold block)."""
     S, nv, N, box = 400, 2500, 3000, 100.0
     kv = synth.kvectors(200)
@@ -427,8 +427,9 @@ def test_kernel_time_pools(corrmod):
         with pytest.raises(corrmod.CorrError):
             ref.set_timing_stride(4)  # no CORR_FLAG_TIMING
     # captured graphs: stamps on pushes 0, 8, ..., 64 whatever the chunks, same state
-    # (also with the producers forked, where each captured run forks and joins
-    # the two streams once and each stream ends its pushes with its own counter)
+    # (also with the producers forked, where a captured run joins the two
+    # streams every few pushes and each stream ends its pushes with its own
+    # counter; the runs of 13, 32 and 25 pushes end between joins)
     for tuning in (None, {"overlap_producers": 1}):
         with corrmod.Correlator(groups, timing=True, graph=True, tuning=tuning) as c, \
                 corrmod.Correlator(groups) as ref:
