@@ -104,25 +104,54 @@ constexpr size_t kLdsBytes = 160 * 1024; // LDS of a CU (and most one block may 
 // of an X or Y task (three products and splits per power), so its powers are
 // split in two parts on separate threads; with 64-atom tiles the X and Y
 // powers are split as well, so that six waves still have a task per thread.
-// (128-atom tiles: X, Y and Z in one part each made the two Z waves the
-// critical path, 7000 cycles of build per tile against 2200-2500.)
+// With 128-atom tiles (z_pairs) the Z tasks take two neighbouring atoms per
+// lane instead (table_role): a Z wave's build is bound by the latency of its
+// dependent double operations, not by their issue, so two interleaved atoms
+// cost far less than two waves, and the two waves this frees let one SIMD
+// carry two contraction waves and no build.
 template <int NW, int TA> struct TableShape {
     static constexpr int xy_parts = NW == 3 && TA == 64 ? 2 : 1;
     static constexpr int z_parts = NW == 3 ? 2 : 1;
+    static constexpr bool z_pairs = NW == 3 && TA == 128;
     static constexpr int tasks = (2 * xy_parts + z_parts) * TA;
-    static constexpr int min_waves = tasks / 64; // every task has its own thread
+    static constexpr int min_waves = z_pairs ? 8 : tasks / 64; // every task has its own thread
 };
 
-// Axis d, power part hf and atom j of table task `task` (d and hf are uniform
-// over a wave: 64 divides the tile).
-template <int NW, int TA>
-__device__ __forceinline__ void table_task(int task, int &d, int &hf, int &j)
+// The table role of wave `twave` (uniform over the wave): axis d, power part
+// hf, and the atom of lane 0 (a lane builds atom j0 + lane, or with pairs the
+// atoms j0 + 2 lane and j0 + 2 lane + 1).
+struct TableRole {
+    bool builder;
+    bool pairs;
+    int d, hf, j0;
+};
+
+template <int NW, int TA> __device__ __forceinline__ TableRole table_role(int twave)
 {
-    constexpr int xyp = TableShape<NW, TA>::xy_parts;
-    const int u = task / TA;
-    j = task - u * TA;
-    d = u < 2 * xyp ? u / xyp : 2;
-    hf = u < 2 * xyp ? u - d * xyp : u - 2 * xyp;
+    TableRole r{false, false, 0, 0, 0};
+    if constexpr (TableShape<NW, TA>::z_pairs) {
+        // waves w and w + 4 share a SIMD: waves 0 and 4 only contract; X on
+        // 1, 2 and Y on 3, 7 (64 atoms each), the Z powers' halves on 5, 6
+        switch (twave) {
+        case 1: r = TableRole{true, false, 0, 0, 0}; break;
+        case 2: r = TableRole{true, false, 0, 0, 64}; break;
+        case 3: r = TableRole{true, false, 1, 0, 0}; break;
+        case 7: r = TableRole{true, false, 1, 0, 64}; break;
+        case 5: r = TableRole{true, true, 2, 0, 0}; break;
+        case 6: r = TableRole{true, true, 2, 1, 0}; break;
+        default: break;
+        }
+    } else {
+        // task t = 64 twave + lane: unit u = t / TA of X parts, Y parts, Z parts
+        constexpr int xyp = TableShape<NW, TA>::xy_parts;
+        const int t = twave * 64;
+        const int u = t / TA;
+        r.builder = t < TableShape<NW, TA>::tasks;
+        r.j0 = t - u * TA;
+        r.d = u < 2 * xyp ? u / xyp : 2;
+        r.hf = u < 2 * xyp ? u - r.d * xyp : u - 2 * xyp;
+    }
+    return r;
 }
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
@@ -197,25 +226,20 @@ struct TileBufs {
 // Build the tables of one tile.  The B fragments of the NW weight sets are
 // packed by column: column s (nmax + 1) + n of B tile (column / 16) holds
 // w_s Z^n (NB = ceil(NW (nmax + 1) / 16) tiles instead of NW).
-// Task (axis d, power part hf, atom j), the
-// task of lane `lane` of task wave `twave` (uniform over the wave, which
-// fixes hf and d: 64 divides the tile, so all control flow is uniform): with
-// two parts, part 0 takes n = 0 .. n1 and part 1 takes n = n1+1 .. nmax
-// (n1 = nmax / 2) starting from its own e^{2 pi i n1 x / L} (both from
-// unit_phase).  Powers
+// Task (axis d, power part hf, atom j) of a lane (d and hf uniform over the
+// wave, so all control flow is uniform): with two parts, part 0 takes n = 0
+// .. n1 and part 1 takes n = n1+1 .. nmax (n1 = nmax / 2) starting from its
+// own e^{2 pi i n1 x / L} (both from unit_phase).  Powers
 // by a double recurrence, each rounded once; X and Y rows for both signs, and
 // for each weight set w the products w * Z^n split into fp16 hi/lo B
 // fragments (NW = 1: w = 1; NW = 3: the atom's velocity components).  Atoms
 // past the end (live == false) get zero entries, so they add nothing.
 template <int NW, int TA>
-__device__ __forceinline__ void build_tile(const TileBufs &tb, int twave, int lane, bool live, float x,
+__device__ __forceinline__ void build_tile(const TileBufs &tb, int d, int hf, int j, bool live, float x,
                                            const float (&w)[NW], const double (&wsc)[NW],
                                            double inv_box, int nmax, int2 xrows, int2 yrows,
                                            const double2 *roots)
 {
-    int d, hf, j;
-    table_task<NW, TA>(twave * 64, d, hf, j);
-    j += lane;
     const int parts = d < 2 ? TableShape<NW, TA>::xy_parts : TableShape<NW, TA>::z_parts;
     const int n1 = parts == 1 ? nmax : nmax / 2;
     const int n_begin = hf == 0 ? 0 : n1 + 1, n_end = hf == 0 ? n1 : nmax;
@@ -273,6 +297,68 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int twave, int la
             cmul(pr, pi, cs, sn);
             store_z(n);
         }
+    }
+}
+
+// Z fragments of a 128-atom tile from one wave: lane l builds the neighbouring
+// atoms 2 l and 2 l + 1 (the same atom group, h and h + 1), powers n_begin ..
+// n_end of part hf (as in build_tile), the two atoms' recurrences interleaved,
+// and writes each part of a power of both atoms as one 4-byte entry (the
+// group's halves h, h + 1).  Atoms past the end (live false) get zero entries.
+template <int NW, int TA>
+__device__ __forceinline__ void build_z_pairs(const TileBufs &tb, int lane, int hf, const bool (&live)[2],
+                                              const float (&x)[2], const float (&w)[2][NW],
+                                              const double (&wsc)[NW], double inv_box, int nmax,
+                                              const double2 *roots)
+{
+    static_assert(TA == 128, "a wave of atom pairs covers a 128-atom tile");
+    const int n1 = nmax / 2;
+    const int n_begin = hf == 0 ? 0 : n1 + 1, n_end = hf == 0 ? n1 : nmax;
+    double cs[2], sn[2], pr[2], pi[2], wd[2][NW];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const double f = (double)x[e] * inv_box;
+        unit_phase(f, roots, cs[e], sn[e]);
+        pr[e] = live[e] ? 1.0 : 0.0;
+        pi[e] = 0.0;
+        if (hf != 0) {
+            unit_phase(f * n1, roots, pr[e], pi[e]); // e^{i n1 theta}; n1 f is exact to 1 ulp
+            pr[e] = live[e] ? pr[e] : 0.0;
+            pi[e] = live[e] ? pi[e] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < NW; ++s) wd[e][s] = NW == 1 ? 1.0 : (double)w[e][s] * wsc[s];
+    }
+    const int j = 2 * lane;
+    const int ks = j / kKStep, g = (j % kKStep) / kAtomsPerLane, h = j % kAtomsPerLane; // h even
+    // the lane's entry (halves h, h + 1) of column 0, part 0 of B tile 0
+    uint32_t *const lane_b =
+        reinterpret_cast<uint32_t *>(tb.bfr) + bfrag_index(ks, 0, g, 0) * (kAtomsPerLane / 2) + h / 2;
+    auto store_z = [&](int n) {
+#pragma unroll
+        for (int s = 0; s < NW; ++s) {
+            const float zr0 = (float)(pr[0] * wd[0][s]), zr1 = (float)(pr[1] * wd[1][s]);
+            const float zi0 = (float)(pi[0] * wd[0][s]), zi1 = (float)(pi[1] * wd[1][s]);
+            // hi of both atoms in one packed conversion, lo by one
+            // mixed-precision fma each (as for P in the contraction)
+            const uint32_t hr = pack_half2(zr0, zr1), hi = pack_half2(zi0, zi1);
+            uint32_t lr, li;
+            lo_half2(lr, hr, zr0, zr1);
+            lo_half2(li, hi, zi0, zi1);
+            // column s (nmax + 1) + n of the packed B tiles
+            const int gc = s * (nmax + 1) + n, bt = gc / kMfmaCols, c = gc % kMfmaCols;
+            uint32_t *const e = lane_b + (bt * Tile<TA>::bfrags + c) * (kAtomsPerLane / 2);
+            e[0] = hr;
+            e[kBPartStride * (kAtomsPerLane / 2)] = lr;
+            e[2 * kBPartStride * (kAtomsPerLane / 2)] = hi;
+            e[3 * kBPartStride * (kAtomsPerLane / 2)] = li;
+        }
+    };
+    if (n_begin == 0) store_z(0);
+    for (int n = n_begin > 0 ? n_begin : 1; n <= n_end; ++n) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) cmul(pr[e], pi[e], cs[e], sn[e]);
+        store_z(n);
     }
 }
 
@@ -389,34 +475,46 @@ template <int NW, int TA, int NB> __device__ __forceinline__ void rhok_mfma_body
         }
     }
 
-    // table task of this thread and its inputs, loaded one tile ahead of their
-    // use; the Z task also loads the weights.  Task wave t = wave holds tasks
-    // 64 t .. 64 t + 63 (taken as a wave-uniform value: the build's loops and
-    // branches then stay scalar; `wave` itself stays a vector value, which
-    // measured 6% faster in the contraction).
+    // table role of this wave and its inputs, loaded one tile ahead of their
+    // use; the Z tasks also load the weights.  The role is taken from a
+    // wave-uniform copy of the wave index (the build's loops and branches then
+    // stay scalar; `wave` itself stays a vector value, which measured 6%
+    // faster in the contraction).
     const int twave = __builtin_amdgcn_readfirstlane(wave);
-    const int task = twave * 64 + lane;
-    const bool builder = twave * 64 < TableShape<NW, TA>::tasks; // wave-uniform
-    int td, thf, tj;
-    table_task<NW, TA>(task, td, thf, tj);
-    (void)thf; // both Z parts load the same atom's inputs
+    const TableRole role = table_role<NW, TA>(twave);
+    const bool builder = role.builder; // wave-uniform
+    const int td = role.d;
     const bool weighted = NW > 1 && td == 2;
-    auto load_in = [&](int it, float &x, float (&w)[NW]) -> bool {
-        const int64_t at = a_begin + (int64_t)it * Tile<TA>::atoms + tj;
-        const bool live = builder && it < n_tiles && at < a_end;
-        x = live ? a.pos[(int64_t)td * a.n_atoms + at] : 0.f;
+    // the lane's atoms of the tile: one, or two neighbours (Z pairs)
+    auto atom_of = [&](int e) { return role.pairs ? role.j0 + 2 * lane + e : role.j0 + lane; };
+    auto load_in = [&](int it, float (&x)[2], float (&w)[2][NW], bool (&lv)[2]) {
 #pragma unroll
-        for (int s = 0; s < NW; ++s)
-            w[s] = live && weighted ? a.pos[(int64_t)(3 + s) * a.n_atoms + at] : 1.f;
-        return live;
+        for (int e = 0; e < 2; ++e) {
+            const int64_t at = a_begin + (int64_t)it * Tile<TA>::atoms + atom_of(e);
+            lv[e] = builder && (e == 0 || role.pairs) && it < n_tiles && at < a_end;
+            x[e] = lv[e] ? a.pos[(int64_t)td * a.n_atoms + at] : 0.f;
+#pragma unroll
+            for (int s = 0; s < NW; ++s)
+                w[e][s] = lv[e] && weighted ? a.pos[(int64_t)(3 + s) * a.n_atoms + at] : 1.f;
+        }
     };
-    float x_cur, x_next, w_cur[NW], w_next[NW];
-    const bool live_cur = load_in(0, x_cur, w_cur);
-    bool live_next = load_in(1, x_next, w_next);
-    __syncthreads(); // roots and zero columns
-    if (builder)
-        build_tile<NW, TA>(tile_bufs(0), twave, lane, live_cur, x_cur, w_cur, wsc, a.inv_box, nmax,
+    auto build = [&](const TileBufs &tb, const float (&x)[2], const float (&w)[2][NW],
+                     const bool (&lv)[2]) {
+        if constexpr (TableShape<NW, TA>::z_pairs) {
+            if (role.pairs) {
+                build_z_pairs<NW, TA>(tb, lane, role.hf, lv, x, w, wsc, a.inv_box, nmax, lds_roots);
+                return;
+            }
+        }
+        build_tile<NW, TA>(tb, role.d, role.hf, atom_of(0), lv[0], x[0], w[0], wsc, a.inv_box, nmax,
                            xrows, yrows, lds_roots);
+    };
+    float x_cur[2], x_next[2], w_cur[2][NW], w_next[2][NW];
+    bool live_cur[2], live_next[2];
+    load_in(0, x_cur, w_cur, live_cur);
+    load_in(1, x_next, w_next, live_next);
+    __syncthreads(); // roots and zero columns
+    if (builder) build(tile_bufs(0), x_cur, w_cur, live_cur);
     __syncthreads();
 
     for (int it = 0; it < n_tiles; ++it) {
@@ -428,14 +526,15 @@ template <int NW, int TA, int NB> __device__ __forceinline__ void rhok_mfma_body
         // a memory latency per tile (the loads are conditional, so a wait
         // for older ones waits for them too)
         const bool building = builder && it + 1 < n_tiles;
-        float x_after = 0.f, w_after[NW];
-        bool live_after = false;
+        float x_after[2] = {0.f, 0.f}, w_after[2][NW];
+        bool live_after[2] = {false, false};
 #pragma unroll
-        for (int s = 0; s < NW; ++s) w_after[s] = 1.f;
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int s = 0; s < NW; ++s) w_after[e][s] = 1.f;
         if (building) {
-            build_tile<NW, TA>(tile_bufs((it + 1) & 1), twave, lane, live_next, x_next, w_next,
-                               wsc, a.inv_box, nmax, xrows, yrows, lds_roots);
-            live_after = load_in(it + 2, x_after, w_after);
+            build(tile_bufs((it + 1) & 1), x_next, w_next, live_next);
+            load_in(it + 2, x_after, w_after, live_after);
         }
         if (active) {
             const float4 *xrow = reinterpret_cast<const float4 *>(cur.tabx + xoff);
@@ -518,10 +617,13 @@ template <int NW, int TA, int NB> __device__ __forceinline__ void rhok_mfma_body
             }
         }
         if (building) {
-            x_next = x_after;
 #pragma unroll
-            for (int s = 0; s < NW; ++s) w_next[s] = w_after[s];
-            live_next = live_after;
+            for (int e = 0; e < 2; ++e) {
+                x_next[e] = x_after[e];
+#pragma unroll
+                for (int s = 0; s < NW; ++s) w_next[e][s] = w_after[e][s];
+                live_next[e] = live_after[e];
+            }
         }
         __syncthreads(); // next buffer complete; this one free for the tile after
     }
