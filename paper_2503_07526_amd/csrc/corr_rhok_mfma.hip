@@ -896,17 +896,15 @@ __device__ __forceinline__ void rhok_couple_body(const RhokMfmaArgs &a)
 
     for (int it = 0; it < n_tiles; ++it) {
         const CpBufs cur = bufs(it & 1);
-        // tables of the next tile into the other buffer
-        if ((zb || xyb) && it + 1 < n_tiles) {
-            float in_after[2];
-            bool lv_after[2];
-            load_in(it + 2, in_after, lv_after);
+        // tables of the next tile into the other buffer; the inputs of the
+        // tile after that are loaded after the build and move up after this
+        // tile's contraction (as in the current kernel: no wave waits for them)
+        const bool building = (zb || xyb) && it + 1 < n_tiles;
+        float in_after[2] = {0.f, 0.f};
+        bool lv_after[2] = {false, false};
+        if (building) {
             build(bufs((it + 1) & 1), in_next, lv_next);
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                in_next[e] = in_after[e];
-                lv_next[e] = lv_after[e];
-            }
+            load_in(it + 2, in_after, lv_after);
         }
         if (act[0]) {
             const halfv_t *bl = cur.bfr + boff;
@@ -958,6 +956,13 @@ __device__ __forceinline__ void rhok_couple_body(const RhokMfmaArgs &a)
                         for (int v = 0; v < 4; ++v) acc[t][s][v] += (double)sum[t][s][v];
                         sum[t][s] = float4_t{0.f, 0.f, 0.f, 0.f};
                     }
+            }
+        }
+        if (building) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                in_next[e] = in_after[e];
+                lv_next[e] = lv_after[e];
             }
         }
         __syncthreads(); // next buffer complete; this one free for the tile after
