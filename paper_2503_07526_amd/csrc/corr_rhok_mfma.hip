@@ -259,10 +259,23 @@ __device__ __forceinline__ void build_tile(const TileBufs &tb, int d, int hf, in
         float2 *zero = (d == 0 ? tb.tabx : tb.taby) + j - lo * Tile<TA>::stride;
         if (hf == 0 && lo <= 0 && hi >= 0) zero[0] = make_float2((float)pr, 0.f);
         const int n_last = min(n_end, max(-lo, hi));
-        for (int n = n_begin > 0 ? n_begin : 1; n <= n_last; ++n) {
-            cmul(pr, pi, cs, sn);
-            if (n >= lo && n <= hi) zero[n * Tile<TA>::stride] = make_float2((float)pr, (float)pi);
-            if (-n >= lo && -n <= hi) zero[-n * Tile<TA>::stride] = make_float2((float)pr, -(float)pi);
+        auto put = [&](int n, double r, double i) {
+            if (n >= lo && n <= hi) zero[n * Tile<TA>::stride] = make_float2((float)r, (float)i);
+            if (-n >= lo && -n <= hi) zero[-n * Tile<TA>::stride] = make_float2((float)r, -(float)i);
+        };
+        // two interleaved recurrences, powers n and n + 1 each stepping by
+        // the squared base: half the dependent chain of a single recurrence
+        const int n0 = n_begin > 0 ? n_begin : 1;
+        double ar = pr, ai = pi, c2r = cs, c2i = sn;
+        cmul(ar, ai, cs, sn); // power n0
+        double br = ar, bi = ai;
+        cmul(br, bi, cs, sn);   // power n0 + 1
+        cmul(c2r, c2i, cs, sn); // the base squared
+        for (int n = n0; n <= n_last; n += 2) {
+            put(n, ar, ai);
+            if (n + 1 <= n_last) put(n + 1, br, bi);
+            cmul(ar, ai, c2r, c2i);
+            cmul(br, bi, c2r, c2i);
         }
     } else {
         const int ks = j / kKStep, g = (j % kKStep) / kAtomsPerLane, h = j % kAtomsPerLane;
