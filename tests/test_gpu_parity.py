@@ -1000,6 +1000,47 @@ def test_fold_threads_bitwise(corrmod):
     assert np.array_equal(out[64], out[128]) and np.array_equal(out[256], out[128])
 
 
+def test_chained_runs_of_any_length(corrmod):
+    """Captured corr_push_steps runs with the producers forked beside a
+    block-deferred group (the two streams joined every few pushes, each
+    ending its pushes with its own counter): runs of 1, 3, 4, 5, 8, 255 and 257
+    pushes, across the first fold blocks, give the state of single pushes bit
+    for bit, with a readout of every group after every run, and the oracle's
+    result at the end."""
+    lengths = [1, 3, 4, 5, 8, 255, 257]
+    S, nv, N, box = sum(lengths), 2048, 1500, 40.0
+    kv = synth.kvectors(40)
+    xv = ou_inputs(71, 1, nv, S, "f32")
+    xg = ou_inputs(71, 2, 9, S, "f64")
+    pos, _ = synth.PositionSpec(71, 3, N, box).series(0, S)
+    say(f"[chained runs] S={S} lengths={lengths}")
+    groups = [corrmod.GroupDesc(nv, 6, 16, 2, dtype="f32", accum="kahan"),
+              corrmod.GroupDesc(len(kv), 5, 16, 2, dtype="cf32", accum="kahan", source="rhok",
+                                kvec=kv, n_atoms=N, box=box),
+              corrmod.GroupDesc(9, 8, 16, 2, dtype="f64", accum="f64")]
+    dev = torch.device("cuda:0")
+    hs = [torch.from_numpy(a).to(dev) for a in (xv, pos, xg)]
+    tune = {"overlap_producers": 1}
+    with corrmod.Correlator(groups, tuning=tune) as a, \
+            corrmod.Correlator(groups, graph=True, tuning=tune) as b:
+        s0 = 0
+        for n in lengths:
+            for s in range(s0, s0 + n):
+                a.push([h[s] for h in hs])
+            b.push_steps([h[s0:s0 + n] for h in hs])
+            s0 += n
+            torch.cuda.synchronize()
+            assert a.n_pushes() == b.n_pushes() == s0
+            for g in range(3):
+                ra, rb = a.finalize(g, slice_=(0, 3)), b.finalize(g, slice_=(0, 3))
+                assert np.array_equal(ra["t"], rb["t"]) and np.array_equal(ra["count"], rb["count"])
+                assert np.array_equal(ra["c_per_channel"], rb["c_per_channel"]), (n, g)
+        gate(b.finalize(0, slice_=(0, 3)), oracle_run(xv, 6, 16, 2), TOL[("f32", "kahan")],
+             slice_=(0, 3), label="velocity")
+        gate(b.finalize(2, slice_=(0, 3)), oracle_run(xg, 8, 16, 2), TOL[("f64", "f64")],
+             slice_=(0, 3), label="global")
+
+
 def test_graph_replay_equals_single_pushes(corrmod):
     """Graph mode: corr_push_steps captures its pushes once and replays the
     graph for later calls with the same histories -- the same state bit for
