@@ -251,7 +251,9 @@ struct RhokMfmaArgs {
     int32_t out_double;      // 1: double2 output
     int32_t nk;              // k-vectors
     int32_t nw;              // weight sets: 1 = n(k), 3 = current components
-    int32_t pad_;
+    int32_t early_loads;     // n(k): 1 when forked beside the flush with a join on every
+                             // push (the table builders then load the next inputs
+                             // before their build), else 0 (after it)
     const double *basis;     // nw == 3: [nk][3][3] rows khat, e1, e2
     FoldStamps *stamps;      // timing: the push's producer stamps, else null
 };

@@ -806,6 +806,16 @@ __device__ __forceinline__ void cp_build_z(halfv_t *bfr, int lane, const bool (&
     }
 }
 
+//
+// EARLY: the table builders load the inputs of the tile after next before their
+// build and move them up right after it.  The builder waves then wait for those
+// loads once per tile (the loads are conditional, so the wait covers them), and
+// that wait leaves issue slots to a flush kernel running beside the producer:
+// with a fork and join on every push the batched step took 0.198-0.203 ms this
+// way against 0.211-0.218 with the loads after the build.  Alone, or with the
+// two streams joined every few pushes, loading after the build and moving the
+// inputs up after the contraction is faster (93.7 against 96.6 us alone).
+template <bool EARLY>
 __device__ __forceinline__ void rhok_couple_body(const RhokMfmaArgs &a)
 {
     constexpr int TA = 128;
@@ -910,14 +920,24 @@ __device__ __forceinline__ void rhok_couple_body(const RhokMfmaArgs &a)
     for (int it = 0; it < n_tiles; ++it) {
         const CpBufs cur = bufs(it & 1);
         // tables of the next tile into the other buffer; the inputs of the
-        // tile after that are loaded after the build and move up after this
-        // tile's contraction (as in the current kernel: no wave waits for them)
+        // tile after that are loaded before (EARLY) or after the build and
+        // move up right after the build (EARLY) or after this tile's
+        // contraction
         const bool building = (zb || xyb) && it + 1 < n_tiles;
         float in_after[2] = {0.f, 0.f};
         bool lv_after[2] = {false, false};
         if (building) {
+            if constexpr (EARLY) load_in(it + 2, in_after, lv_after);
             build(bufs((it + 1) & 1), in_next, lv_next);
-            load_in(it + 2, in_after, lv_after);
+            if constexpr (EARLY) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    in_next[e] = in_after[e];
+                    lv_next[e] = lv_after[e];
+                }
+            } else {
+                load_in(it + 2, in_after, lv_after);
+            }
         }
         if (act[0]) {
             const halfv_t *bl = cur.bfr + boff;
@@ -971,7 +991,7 @@ __device__ __forceinline__ void rhok_couple_body(const RhokMfmaArgs &a)
                     }
             }
         }
-        if (building) {
+        if (!EARLY && building) {
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 in_next[e] = in_after[e];
@@ -1010,10 +1030,11 @@ __device__ __forceinline__ void rhok_couple_body(const RhokMfmaArgs &a)
 // One weight set: at most 120 registers, so that a SIMD holding three of its
 // waves (360 registers) keeps room for a wave of a flush kernel that runs
 // beside it on another stream.
+template <bool EARLY>
 __global__ __launch_bounds__(kMfmaMaxWaves * 64) __attribute__((amdgpu_num_vgpr(60)))
 void rhok_couple_kernel(RhokMfmaArgs a)
 {
-    rhok_couple_body(a);
+    rhok_couple_body<EARLY>(a);
 }
 
 // One wave per k-vector: sum the partials of its slot over the atom blocks in
@@ -1125,9 +1146,14 @@ hipError_t rhok_mfma_prepare(int table_rows, int nw, int nmax)
     const size_t lds = rhok_mfma_lds_bytes(table_rows, nw, nmax);
     if (lds > kLdsBytes) return hipErrorInvalidValue;
     if (lds <= 64 * 1024) return hipSuccess;
-    const void *fn = nw == 1 ? reinterpret_cast<const void *>(&rhok_couple_kernel)
-                             : current_kernel(tile_atoms(table_rows, current_btiles(nmax)),
-                                              current_btiles(nmax));
+    if (nw == 1) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rhok_couple_kernel<false>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(&rhok_couple_kernel<true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    const void *fn = current_kernel(tile_atoms(table_rows, current_btiles(nmax)), current_btiles(nmax));
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -1146,8 +1172,12 @@ static hipError_t launch_couples(const RhokMfmaArgs &a, hipStream_t st)
     int cwaves = (per_chunk + kCpTilesPerWave - 1) / kCpTilesPerWave;
     if (cwaves < kCpMinCWaves) cwaves = kCpMinCWaves;
     const size_t lds = couple_lds_bytes(a.x_rows + a.y_rows);
-    hipLaunchKernelGGL(rhok_couple_kernel, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
-                       dim3((cwaves + 1) * 64), lds, st, a);
+    if (a.early_loads)
+        hipLaunchKernelGGL(rhok_couple_kernel<true>, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
+                           dim3((cwaves + 1) * 64), lds, st, a);
+    else
+        hipLaunchKernelGGL(rhok_couple_kernel<false>, dim3((unsigned)chunks, (unsigned)a.n_atom_blocks),
+                           dim3((cwaves + 1) * 64), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rhok_mfma_final_kernel<1>, dim3((unsigned)((a.nk + 3) / 4)), dim3(256), 0, st,

@@ -605,6 +605,7 @@ int issue_push(corr_ctx *c, const void *const *src, hipStream_t st, bool with_fl
             RhokMfmaArgs ma = g.margs;
             ma.pos = static_cast<const float *>(src[i]);
             ma.stamps = pst_stamps;
+            ma.early_loads = fork && !chained ? 1 : 0; // beside the flush, joined every push
             HIP_TRY(c, launch_rhok_mfma(ma, pst));
         } else {
             RhokArgs ra = g.rargs;
