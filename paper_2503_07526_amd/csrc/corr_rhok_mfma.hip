@@ -85,10 +85,10 @@ constexpr int kBKsStride = kBParts * kBPartStride + 4;       // halfv per K-step
 constexpr int kAccAtoms = 256;
 
 // The LDS tile of TA atoms: K-steps, table row stride (float2; TA + 2 shifts
-// consecutive rows by 4 banks) and B fragments per weight set.  128-atom tiles
+// consecutive rows by 4 banks) and B fragments per B tile.  128-atom tiles
 // meet half the block-wide barriers of 64-atom tiles (n(k) 130 -> 108 us,
 // currents 366 -> 333 us at 10^6 atoms).  One weight set always takes them;
-// three weight sets triple the B fragments and take them only when two
+// three weight sets need NB packed B tiles and take them only when two
 // buffers fit in the 160 KB of LDS (k-sets with few table rows), else 64.
 template <int TA> struct Tile {
     static constexpr int atoms = TA;
@@ -375,8 +375,9 @@ __device__ __forceinline__ void build_z_pairs(const TileBufs &tb, int lane, int 
     }
 }
 
-// Waves per block: one M tile per wave.  With three weight sets a wave holds
-// three times the accumulators, so blocks stay at two waves per SIMD.
+// Waves per block: one M tile per contraction wave.  With three weight sets a
+// wave holds the accumulators of NB B tiles (about 200 registers for two), so
+// blocks stay at two waves per SIMD.
 template <int NW> struct MfmaShape {
     static constexpr int max_waves = NW == 1 ? kMfmaMaxWaves : 8;
 };
