@@ -29,9 +29,15 @@
 // Threads: a wave holds 64 consecutive channels (one per lane) and a
 // sub-block of LB consecutive lags of lag block j (LB = 8, or 4 when the
 // grid would be small); the waves of a block (and blockIdx.y) cover the
-// sub-blocks.  Each lane keeps LB partial sums and a sliding window of
-// LB - 1 + U lagged values in registers: per U pushes it loads U new and U
-// lagged values (one step ahead of the products) and does U x LB products.
+// sub-blocks.  The block first copies the values its waves read into LDS,
+// once each: the kWindowT new values of the folded block and the
+// kWindowT + (lags of the block) - 1 lagged values, as rows of 64 channels
+// (the waves' lagged ranges overlap, and every wave reads the same new
+// values; read straight from the ring, each value was loaded about 18 times
+// per push for the 4-lag waves of a long window).  Each lane then keeps LB
+// partial sums and a sliding window of LB - 1 + U lagged values in registers:
+// per U pushes it reads U new and U lagged values from LDS and does U x LB
+// products.
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
@@ -150,8 +156,6 @@ __device__ __forceinline__ int wrap_slot(int64_t v, int p0)
     return (int)r;
 }
 
-__device__ __forceinline__ int next_slot(int s, int p0) { return s + 1 == p0 ? 0 : s + 1; }
-
 template <int K, int LB>
 __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int64_t *step, int lpb,
                                                           int subs_per_block)
@@ -161,20 +165,23 @@ __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int
     using PT = typename WK<K>::PT;
     constexpr int NP = WK<K>::NP;
     constexpr int U = kWinU;
+    constexpr int T = kWindowT;
+    extern __shared__ __align__(16) unsigned char win_lds[];
+    S *const rows = reinterpret_cast<S *>(win_lds); // [row][64 channels]
 
     // Push P = *step + 1 (its sample is already staged): lag block j folds
     // block q.
     const int64_t P = *step + 1;
-    const int j = (int)(P % kWindowT);
-    const int64_t q = P / kWindowT;
+    const int j = (int)(P % T);
+    const int64_t q = P / T;
     if (q < 1) return;
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
-    const int sub = (int)blockIdx.y * subs_per_block + wave;
+    const int nwaves = (int)(blockDim.x >> 6);
     const int lag_end = min((j + 1) * lpb, g.p);
-    const int L0 = j * lpb + sub * LB;
-    if (L0 >= lag_end) return; // whole wave
-    const int nl = min(LB, lag_end - L0);
+    const int Lb0 = j * lpb + (int)blockIdx.y * subs_per_block * LB; // the block's first lag
+    if (Lb0 >= lag_end) return; // whole block
+    const int L0 = Lb0 + wave * LB;
 
     const int64_t ch = (int64_t)blockIdx.x * 64 + lane;
     const int64_t tile = ch / g.tw;
@@ -184,45 +191,38 @@ __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int
     char *tb = g.state + tile * g.tile_bytes;
     const S *ring = reinterpret_cast<const S *>(tb) + tl;
 
-    // New values s0 .. s0 + kWindowT - 1; the window starts at value
-    // s0 - L0 - (LB - 1).
-    const int64_t s0 = (q - 1) * kWindowT + 1;
-    int sn = wrap_slot(s0, p0);
-    int so = wrap_slot(s0 - L0 - (LB - 1), p0);
+    // Rows 0 .. T-1: the new values s0 .. s0 + T - 1.  Rows T .. : the lagged
+    // values from v_lo = s0 - Lb0 - (span - 1) on, span = the block's lags
+    // (some past lag_end in the last block: read, never used).
+    const int64_t s0 = (q - 1) * T + 1;
+    const int span = nwaves * LB;
+    const int64_t v_lo = s0 - Lb0 - (span - 1);
+    const int n_rows = 2 * T + span - 1;
+    for (int r = wave; r < n_rows; r += nwaves) {
+        const int64_t v = r < T ? s0 + r : v_lo + (r - T);
+        rows[(size_t)r * 64 + lane] = ring[(size_t)wrap_slot(v, p0) * tw];
+    }
+    __syncthreads();
+    if (L0 >= lag_end) return; // this wave's lags are past the lag block
+    const int nl = min(LB, lag_end - L0);
+
+    // Lagged value s0 + i - L0 - l (push s0 + i, lag L0 + l) sits in row
+    // wb + i - l with wb = T + span - 1 - wave LB; the window W[LB - 1 + u]
+    // holds the value of row wb + i + u.
+    const int wb = T + span - 1 - wave * LB;
     S W[LB - 1 + U];
 #pragma unroll
-    for (int k = 0; k < LB - 1; ++k) {
-        W[k] = ring[(size_t)so * tw];
-        so = next_slot(so, p0);
-    }
+    for (int k = 0; k < LB - 1; ++k) W[k] = rows[(size_t)(wb - (LB - 1) + k) * 64 + lane];
     Part<PT> part[LB];
 #pragma unroll
     for (int l = 0; l < LB; ++l) part[l] = Part<PT>{PT(0), PT(0)};
-    // The loads of step i + U are issued before the products of step i.
-    S Nn[U], Wn[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        Nn[u] = ring[(size_t)sn * tw];
-        sn = next_slot(sn, p0);
-        Wn[u] = ring[(size_t)so * tw];
-        so = next_slot(so, p0);
-    }
 #pragma unroll 1
-    for (int i = 0; i < kWindowT; i += U) {
+    for (int i = 0; i < T; i += U) {
         S N[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            N[u] = Nn[u];
-            W[LB - 1 + u] = Wn[u];
-        }
-        if (i + U < kWindowT) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                Nn[u] = ring[(size_t)sn * tw];
-                sn = next_slot(sn, p0);
-                Wn[u] = ring[(size_t)so * tw];
-                so = next_slot(so, p0);
-            }
+            N[u] = rows[(size_t)(i + u) * 64 + lane];
+            W[LB - 1 + u] = rows[(size_t)(wb + i + u) * 64 + lane];
         }
         // push s = s0 + i + u, lag L0 + l: lagged value s - L0 - l = W[LB - 1 + u - l]
 #pragma unroll
@@ -258,12 +258,24 @@ struct WindowShape {
     unsigned grid_x, grid_y, block;
 };
 
+// LDS rows of one block: 2 kWindowT + (waves) LB - 1 rows of 64 samples, at
+// most kWinLdsBytes so that two blocks share a CU.
+constexpr size_t kWinLdsBytes = 80 * 1024;
+
+size_t window_lds_bytes(const GroupArgs &g, int lb, int subs_per_block)
+{
+    const size_t sb = g.kind == K_CF32_F64 || g.kind == K_CF32_KAHAN || g.kind == K_CF32_F32 ? 8 : 4;
+    return (size_t)(2 * kWindowT + subs_per_block * lb - 1) * 64 * sb;
+}
+
 WindowShape window_shape(const GroupArgs &g, int lb)
 {
     WindowShape w{};
     w.lpb = (g.p + kWindowT - 1) / kWindowT;
     const int n_sub = (w.lpb + lb - 1) / lb;
-    const int by = (n_sub + 7) / 8; // at most 8 waves per block
+    int cap = 8; // at most 8 waves per block, and the block's rows within kWinLdsBytes
+    while (cap > 1 && window_lds_bytes(g, lb, cap) > kWinLdsBytes) --cap;
+    const int by = (n_sub + cap - 1) / cap;
     w.subs_per_block = (n_sub + by - 1) / by;
     w.grid_x = (unsigned)(g.n_tiles * g.tw / 64);
     w.grid_y = (unsigned)by;
@@ -271,21 +283,39 @@ WindowShape window_shape(const GroupArgs &g, int lb)
     return w;
 }
 
+// The kernel of kind K with LB lags per wave, allowed kWinLdsBytes of LDS
+// (above the 64 KiB default; set once per kernel, no stream operation).
+template <int K, int LB> const void *window_kernel()
+{
+    const void *fn = reinterpret_cast<const void *>(&window_fold_kernel<K, LB>);
+    static const hipError_t set =
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWinLdsBytes);
+    return set == hipSuccess ? fn : nullptr;
+}
+
 template <int LB>
 hipError_t launch_fold_lb(const GroupArgs &g, const int64_t *step, hipStream_t st)
 {
     const WindowShape w = window_shape(g, LB);
     const dim3 grid(w.grid_x, w.grid_y), block(w.block);
+    const size_t lds = window_lds_bytes(g, LB, w.subs_per_block);
+    if (lds > kWinLdsBytes) return hipErrorInvalidValue;
+    const void *fn = nullptr;
     switch (g.kind) {
-    case K_F32_F64: hipLaunchKernelGGL((window_fold_kernel<K_F32_F64, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
-    case K_F32_KAHAN: hipLaunchKernelGGL((window_fold_kernel<K_F32_KAHAN, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
-    case K_F32_F32: hipLaunchKernelGGL((window_fold_kernel<K_F32_F32, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
-    case K_CF32_F64: hipLaunchKernelGGL((window_fold_kernel<K_CF32_F64, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
-    case K_CF32_KAHAN: hipLaunchKernelGGL((window_fold_kernel<K_CF32_KAHAN, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
-    case K_CF32_F32: hipLaunchKernelGGL((window_fold_kernel<K_CF32_F32, LB>), grid, block, 0, st, g, step, w.lpb, w.subs_per_block); break;
+    case K_F32_F64: fn = window_kernel<K_F32_F64, LB>(); break;
+    case K_F32_KAHAN: fn = window_kernel<K_F32_KAHAN, LB>(); break;
+    case K_F32_F32: fn = window_kernel<K_F32_F32, LB>(); break;
+    case K_CF32_F64: fn = window_kernel<K_CF32_F64, LB>(); break;
+    case K_CF32_KAHAN: fn = window_kernel<K_CF32_KAHAN, LB>(); break;
+    case K_CF32_F32: fn = window_kernel<K_CF32_F32, LB>(); break;
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    if (!fn) return hipErrorInvalidValue;
+    GroupArgs ga = g;
+    const int64_t *sp = step;
+    int lpb = w.lpb, spb = w.subs_per_block;
+    void *args[] = {&ga, &sp, &lpb, &spb};
+    return hipLaunchKernel(fn, grid, block, args, lds, st);
 }
 
 } // namespace
