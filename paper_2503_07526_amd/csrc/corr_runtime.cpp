@@ -486,7 +486,7 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
         int64_t tf = 0;
         for (int i = 0; i < a.n_groups; ++i) {
             if (is_window_deferred(a.g[i])) {
-                HIP_TRY(c, launch_push_group(a.g[i], base.step, cpt, lch, block, st));
+                // the fold kernel also stages the push's sample
                 HIP_TRY(c, launch_window_fold(a.g[i], base.step, st));
                 continue;
             }

@@ -5,7 +5,7 @@
 // accumulators on every push moves every accumulator row through HBM once per
 // push.  The sums are linear, so the products of kWindowT consecutive pushes
 // can be added in one pass: each push only stages its sample in a ring of
-// P0 = p + 2 kWindowT slots (the push kernels' staging branch), and the lag
+// P0 = p + 2 kWindowT slots (written by the fold kernel of the push), and the lag
 // range is cut into kWindowT lag blocks of lpb = ceil(p / kWindowT) lags.  At
 // push kWindowT q + j, lag block j folds block q (pushes kWindowT (q-1) + 1 ..
 // kWindowT q) of every channel: the kWindowT x lpb products x_s conj(x_{s-L})
@@ -14,7 +14,8 @@
 // accumulator rows), and each accumulator row is read and written once per
 // kWindowT pushes.
 //
-// Ring: value v (1-based) sits in slot (v - 1) mod P0.  When lag block j
+// Ring: value v (1-based) sits in slot (v - 1) mod P0; the fold kernel of
+// push v writes it there (no separate staging launch).  When lag block j
 // folds block q at push kWindowT q + j, the oldest value it reads is
 // kWindowT (q - 1) + 1 - (p - 1), and the slots still hold every value from
 // kWindowT q + j - P0 + 1 on, which is older for every j < kWindowT.  Values
@@ -169,27 +170,33 @@ __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int
     extern __shared__ __align__(16) unsigned char win_lds[];
     S *const rows = reinterpret_cast<S *>(win_lds); // [row][64 channels]
 
-    // Push P = *step + 1 (its sample is already staged): lag block j folds
-    // block q.
+    // Push P = *step + 1: its sample goes to ring slot (P - 1) mod p0 (the
+    // first wave of each channel group's y = 0 block writes it; the blocks of
+    // this launch that need value P read it from the input instead, and none
+    // reads that slot for an older value: the oldest value folded is newer
+    // than P - p0).  Then lag block j folds block q.
     const int64_t P = *step + 1;
-    const int j = (int)(P % T);
-    const int64_t q = P / T;
-    if (q < 1) return;
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
-    const int nwaves = (int)(blockDim.x >> 6);
-    const int lag_end = min((j + 1) * lpb, g.p);
-    const int Lb0 = j * lpb + (int)blockIdx.y * subs_per_block * LB; // the block's first lag
-    if (Lb0 >= lag_end) return; // whole block
-    const int L0 = Lb0 + wave * LB;
-
     const int64_t ch = (int64_t)blockIdx.x * 64 + lane;
     const int64_t tile = ch / g.tw;
     const int tl = (int)(ch - tile * g.tw);
     const int tw = g.tw;
     const int p0 = g.p0;
     char *tb = g.state + tile * g.tile_bytes;
-    const S *ring = reinterpret_cast<const S *>(tb) + tl;
+    S *const ring = reinterpret_cast<S *>(tb) + tl;
+    // channels past the end of the group (the padded tail) hold zeros
+    const S xP = ch < g.n_ch ? static_cast<const S *>(g.samples)[ch] : S{};
+    if (blockIdx.y == 0 && wave == 0) ring[(size_t)wrap_slot(P, p0) * tw] = xP;
+
+    const int j = (int)(P % T);
+    const int64_t q = P / T;
+    if (q < 1) return;
+    const int nwaves = (int)(blockDim.x >> 6);
+    const int lag_end = min((j + 1) * lpb, g.p);
+    const int Lb0 = j * lpb + (int)blockIdx.y * subs_per_block * LB; // the block's first lag
+    if (Lb0 >= lag_end) return; // whole block
+    const int L0 = Lb0 + wave * LB;
 
     // Rows 0 .. T-1: the new values s0 .. s0 + T - 1.  Rows T .. : the lagged
     // values from v_lo = s0 - Lb0 - (span - 1) on, span = the block's lags
@@ -200,7 +207,7 @@ __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int
     const int n_rows = 2 * T + span - 1;
     for (int r = wave; r < n_rows; r += nwaves) {
         const int64_t v = r < T ? s0 + r : v_lo + (r - T);
-        rows[(size_t)r * 64 + lane] = ring[(size_t)wrap_slot(v, p0) * tw];
+        rows[(size_t)r * 64 + lane] = v == P ? xP : ring[(size_t)wrap_slot(v, p0) * tw];
     }
     __syncthreads();
     if (L0 >= lag_end) return; // this wave's lags are past the lag block
