@@ -360,14 +360,15 @@ def staggered_flush_bytes(g, s, tw):
 
 def window_deferred(g, direct=False):
     """One-level groups of >= 512 points with single-precision samples: the
-    library stages each push and folds one of 64 lag blocks per push."""
+    library's fold kernel of each push writes the sample into the ring and folds
+    one of 64 lag blocks."""
     return (not direct and g["levels"] == 1 and g["points"] >= 512
             and g["dtype"] in ("f32", "cf32"))
 
 
 def window_push_cost(g):
     """Algorithmic bytes and flop of one push of a block-deferred window, per
-    group: staging reads the sample and writes its ring slot; the fold of lag
+    group: the sample is read and written to its ring slot; the fold of lag
     block j (lpb = p / 64 lags) reads the 64 new and 63 + lpb older ring values
     and reads+writes lpb accumulators, and does 64 x lpb products (complex: 4
     fma = 8 flop each; real: 2 flop)."""
@@ -843,7 +844,7 @@ def run(args):
         wf = sum(window_push_cost(g)[1] for g in wins)
         wms = (kern_ms - rk_ms) / kern_n
         out["window_update"] = {
-            "kernels": "staging + one lag-block fold per group and push",
+            "kernels": "one lag-block fold per group and push (which also stages the sample)",
             "ms_per_push": wms, "alg_bytes_per_push": wb, "alg_flop_per_push": wf,
             "GBs": wb / (wms * 1e-3) / 1e9, "hbm_frac": wb / (wms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "TFLOPs": wf / (wms * 1e-3) / 1e12,
