@@ -482,6 +482,36 @@ def test_producers_with_double_samples(corrmod, source, valu):
     assert e0 < 2e-6 and e1 < 2e-6
 
 
+@pytest.mark.parametrize("N", [1, 7, 130])
+@pytest.mark.parametrize("source,valu", [("rhok", False), ("rhok", True), ("currents", False)])
+def test_producers_with_few_atoms(corrmod, source, valu, N):
+    """Fewer atoms than one atom tile (1, 7) or one tile and a ragged rest
+    (130): a single atom block whose tiles are mostly past the last atom.  With
+    one atom |n(k)|^2 / N = 1 for every k (a closed form); otherwise C(0) of
+    one push against the oracle's direct double sums."""
+    box = 30.0
+    kv = np.concatenate([synth.kvectors(96), [[15, -15, 15], [0, 0, -7]]]).astype(np.int32)
+    say(f"[few atoms] {source} valu={valu} N={N} nk={len(kv)}")
+    x = _currents_inputs(41 + N, N, box, 1)
+    nch = len(kv) * (3 if source == "currents" else 1)
+    if source == "currents":
+        expect = np.abs(oracle.currents(x[0, :3], x[0, 3:], kv, box).reshape(-1)) ** 2 / N
+        inp = x
+    else:
+        expect = np.abs(oracle.rhok(x[0, :3], kv, box)) ** 2 / N
+        if N == 1:
+            assert np.max(np.abs(expect - 1.0)) < 1e-12
+        inp = np.ascontiguousarray(x[:, :3])
+    g = corrmod.GroupDesc(nch, 2, 4, 2, dtype="cf32", accum="f64", source=source, kvec=kv,
+                          n_atoms=N, box=box)
+    with corrmod.Correlator([g], rhok_valu=valu) as c:
+        _push_all(c, [inp])
+        got = c.finalize(0, slice_=(0, nch))["c_per_channel"][:, 0]
+    err = np.max(np.abs(got - expect)) / np.max(expect)
+    say(f"  C(0) error {err:.2e}")
+    assert err < 2e-6
+
+
 def test_currents_lag0_against_oracle(corrmod):
     """One push: C(0) of channel 3q+c = |J_c(k_q)|^2 / N with J from the
     oracle's direct double sums, for a k-set spanning |n| up to 15 and
