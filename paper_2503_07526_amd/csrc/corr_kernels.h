@@ -50,6 +50,11 @@ hipError_t launch_gather(const ReduceArgs &a, hipStream_t st);
 bool window_deferred_supported(int kind);
 int window_lags_per_block(int p);
 hipError_t launch_window_fold(const GroupArgs &g, const int64_t *step, hipStream_t st);
+// Two block-deferred windows of the same kind and length in one launch (the
+// second's blocks after the first's): a small window alone keeps few waves
+// per SIMD.
+bool window_folds_share_launch(const GroupArgs &a, const GroupArgs &b);
+hipError_t launch_window_fold2(const GroupArgs &a, const GroupArgs &b, const int64_t *step, hipStream_t st);
 
 } // namespace corr
 

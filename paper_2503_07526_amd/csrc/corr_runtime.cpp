@@ -484,12 +484,24 @@ int launch_set(corr_ctx *c, const PushArgs &base, const std::vector<int> &idx,
         PushArgs rest = a;
         int n = 0;
         int64_t tf = 0;
+        // block-deferred windows: the fold kernel also stages the push's
+        // sample; two windows of one kind and length share a launch (not in
+        // the per-group form)
+        int pending = -1;
         for (int i = 0; i < a.n_groups; ++i) {
-            if (is_window_deferred(a.g[i])) {
-                // the fold kernel also stages the push's sample
-                HIP_TRY(c, launch_window_fold(a.g[i], base.step, st));
+            if (!is_window_deferred(a.g[i])) continue;
+            if (pending >= 0 && !(c->flags & CORR_FLAG_PER_GROUP) &&
+                window_folds_share_launch(a.g[pending], a.g[i])) {
+                HIP_TRY(c, launch_window_fold2(a.g[pending], a.g[i], base.step, st));
+                pending = -1;
                 continue;
             }
+            if (pending >= 0) HIP_TRY(c, launch_window_fold(a.g[pending], base.step, st));
+            pending = i;
+        }
+        if (pending >= 0) HIP_TRY(c, launch_window_fold(a.g[pending], base.step, st));
+        for (int i = 0; i < a.n_groups; ++i) {
+            if (is_window_deferred(a.g[i])) continue;
             if (is_window(a.g[i])) {
                 HIP_TRY(c, launch_push_window(a.g[i], base.step, cpt, lch, block, kWindowLags, st));
                 continue;

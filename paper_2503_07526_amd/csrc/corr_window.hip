@@ -157,9 +157,11 @@ __device__ __forceinline__ int wrap_slot(int64_t v, int p0)
     return (int)r;
 }
 
+// Blocks x < x1 fold window g0, the others window g1 (two windows of one
+// kind and length share a launch; a single window passes itself twice).
 template <int K, int LB>
-__global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int64_t *step, int lpb,
-                                                          int subs_per_block)
+__global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g0, GroupArgs g1, int x1,
+                                                          const int64_t *step, int lpb, int subs_per_block)
 {
     using S = typename WK<K>::S;
     using A = typename WK<K>::A;
@@ -176,24 +178,30 @@ __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int
     // reads that slot for an older value: the oldest value folded is newer
     // than P - p0).  Then lag block j folds block q.
     const int64_t P = *step + 1;
+    const bool second = (int)blockIdx.x >= x1; // uniform over the block
+    const int tw = second ? g1.tw : g0.tw;
+    const int p0 = second ? g1.p0 : g0.p0;
+    const int np = second ? g1.p : g0.p;
+    const int64_t n_ch = second ? g1.n_ch : g0.n_ch;
+    const int64_t tile_bytes = second ? g1.tile_bytes : g0.tile_bytes;
+    char *const state = second ? g1.state : g0.state;
+    const S *const samples = static_cast<const S *>(second ? g1.samples : g0.samples);
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t ch = (int64_t)blockIdx.x * 64 + lane;
-    const int64_t tile = ch / g.tw;
-    const int tl = (int)(ch - tile * g.tw);
-    const int tw = g.tw;
-    const int p0 = g.p0;
-    char *tb = g.state + tile * g.tile_bytes;
+    const int64_t ch = (int64_t)((int)blockIdx.x - (second ? x1 : 0)) * 64 + lane;
+    const int64_t tile = ch / tw;
+    const int tl = (int)(ch - tile * tw);
+    char *tb = state + tile * tile_bytes;
     S *const ring = reinterpret_cast<S *>(tb) + tl;
     // channels past the end of the group (the padded tail) hold zeros
-    const S xP = ch < g.n_ch ? static_cast<const S *>(g.samples)[ch] : S{};
+    const S xP = ch < n_ch ? samples[ch] : S{};
     if (blockIdx.y == 0 && wave == 0) ring[(size_t)wrap_slot(P, p0) * tw] = xP;
 
     const int j = (int)(P % T);
     const int64_t q = P / T;
     if (q < 1) return;
     const int nwaves = (int)(blockDim.x >> 6);
-    const int lag_end = min((j + 1) * lpb, g.p);
+    const int lag_end = min((j + 1) * lpb, np);
     const int Lb0 = j * lpb + (int)blockIdx.y * subs_per_block * LB; // the block's first lag
     if (Lb0 >= lag_end) return; // whole block
     const int L0 = Lb0 + wave * LB;
@@ -241,7 +249,7 @@ __global__ __launch_bounds__(512) void window_fold_kernel(GroupArgs g, const int
     }
 
     A *hi = reinterpret_cast<A *>(tb + (int64_t)p0 * tw * (int64_t)sizeof(S)) + tl;
-    A *lo = hi + (size_t)g.p * tw;
+    A *lo = hi + (size_t)np * tw;
 #pragma unroll
     for (int l = 0; l < LB; ++l) {
         if (l < nl) {
@@ -300,15 +308,19 @@ template <int K, int LB> const void *window_kernel()
     return set == hipSuccess ? fn : nullptr;
 }
 
+// One launch of window g0 and, when g1 is given (same kind and length), of
+// window g1 in the blocks after g0's.
 template <int LB>
-hipError_t launch_fold_lb(const GroupArgs &g, const int64_t *step, hipStream_t st)
+hipError_t launch_fold_lb(const GroupArgs &g0, const GroupArgs *g1, const int64_t *step, hipStream_t st)
 {
-    const WindowShape w = window_shape(g, LB);
-    const dim3 grid(w.grid_x, w.grid_y), block(w.block);
-    const size_t lds = window_lds_bytes(g, LB, w.subs_per_block);
+    const WindowShape w = window_shape(g0, LB);
+    const unsigned x1 = w.grid_x;
+    const unsigned gx = x1 + (g1 ? window_shape(*g1, LB).grid_x : 0u);
+    const dim3 grid(gx, w.grid_y), block(w.block);
+    const size_t lds = window_lds_bytes(g0, LB, w.subs_per_block);
     if (lds > kWinLdsBytes) return hipErrorInvalidValue;
     const void *fn = nullptr;
-    switch (g.kind) {
+    switch (g0.kind) {
     case K_F32_F64: fn = window_kernel<K_F32_F64, LB>(); break;
     case K_F32_KAHAN: fn = window_kernel<K_F32_KAHAN, LB>(); break;
     case K_F32_F32: fn = window_kernel<K_F32_F32, LB>(); break;
@@ -318,11 +330,29 @@ hipError_t launch_fold_lb(const GroupArgs &g, const int64_t *step, hipStream_t s
     default: return hipErrorInvalidValue;
     }
     if (!fn) return hipErrorInvalidValue;
-    GroupArgs ga = g;
+    GroupArgs ga = g0, gb = g1 ? *g1 : g0;
+    int xs = (int)x1;
     const int64_t *sp = step;
     int lpb = w.lpb, spb = w.subs_per_block;
-    void *args[] = {&ga, &sp, &lpb, &spb};
+    void *args[] = {&ga, &gb, &xs, &sp, &lpb, &spb};
     return hipLaunchKernel(fn, grid, block, args, lds, st);
+}
+
+bool window_fold_valid(const GroupArgs &g)
+{
+    return g.levels == 1 && g.deferred && !g.pair && g.tw % 64 == 0 && g.p0 == g.p + 2 * kWindowT;
+}
+
+// Eight lags per wave reuse each loaded value more; four give twice the waves,
+// which wins while the grid holds fewer than four waves per SIMD (a few
+// thousand channels, the k-space groups of long windows).
+hipError_t launch_fold(const GroupArgs &g0, const GroupArgs *g1, const int64_t *step, hipStream_t st)
+{
+    const WindowShape w8 = window_shape(g0, 8);
+    const unsigned gx = w8.grid_x + (g1 ? window_shape(*g1, 8).grid_x : 0u);
+    const int64_t waves8 = (int64_t)gx * w8.grid_y * w8.subs_per_block;
+    if (waves8 < kWindowWideWaves) return launch_fold_lb<4>(g0, g1, step, st);
+    return launch_fold_lb<8>(g0, g1, step, st);
 }
 
 } // namespace
@@ -337,15 +367,22 @@ int window_lags_per_block(int p) { return (p + kWindowT - 1) / kWindowT; }
 
 hipError_t launch_window_fold(const GroupArgs &g, const int64_t *step, hipStream_t st)
 {
-    if (g.levels != 1 || !g.deferred || g.pair || g.tw % 64 != 0 || g.p0 != g.p + 2 * kWindowT)
+    if (!window_fold_valid(g)) return hipErrorInvalidValue;
+    return launch_fold(g, nullptr, step, st);
+}
+
+bool window_folds_share_launch(const GroupArgs &a, const GroupArgs &b)
+{
+    // the same kernel and block shape: kind (sample and accumulator types) and
+    // length (lags per lag block, LDS rows)
+    return a.kind == b.kind && a.p == b.p;
+}
+
+hipError_t launch_window_fold2(const GroupArgs &a, const GroupArgs &b, const int64_t *step, hipStream_t st)
+{
+    if (!window_fold_valid(a) || !window_fold_valid(b) || !window_folds_share_launch(a, b))
         return hipErrorInvalidValue;
-    // Eight lags per wave reuse each loaded value more; four give twice the
-    // waves, which wins while the grid holds fewer than four waves per SIMD
-    // (a few thousand channels, the k-space groups of long windows).
-    const WindowShape w8 = window_shape(g, 8);
-    const int64_t waves8 = (int64_t)w8.grid_x * w8.grid_y * w8.subs_per_block;
-    if (waves8 < kWindowWideWaves) return launch_fold_lb<4>(g, step, st);
-    return launch_fold_lb<8>(g, step, st);
+    return launch_fold(a, &b, step, st);
 }
 
 } // namespace corr
