@@ -38,7 +38,9 @@
 // per push for the 4-lag waves of a long window).  Each lane then keeps LB
 // partial sums and a sliding window of LB - 1 + U lagged values in registers:
 // per U pushes it reads U new and U lagged values from LDS and does U x LB
-// products.
+// products.  Two windows of one kind and length can share a launch, the
+// second's channel blocks after the first's (a few thousand channels alone
+// hold only about one wave per SIMD).
 #include <hip/hip_runtime.h>
 
 #include "corr_kernels.h"
