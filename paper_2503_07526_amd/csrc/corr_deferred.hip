@@ -689,6 +689,13 @@ hipError_t launch_deferred_t(const DeferredArgs &a, hipStream_t st)
 constexpr int kStageVec = 4;
 constexpr int kStageUnroll = 4;
 
+// The sample is read once and its ring row is read again only by the fold
+// of its subset, at least one push later (when a push's traffic has long
+// passed through the caches), so both streams are non-temporal: the staging
+// of 6e7 channels took about 9 us less per push (the large step 0.244
+// against 0.253 ms).
+typedef float stage_f4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void stage_kernel(GroupArgs g, const int64_t *step, int aligned)
 {
     const int64_t s = *step + 1;
@@ -706,7 +713,8 @@ __global__ __launch_bounds__(256) void stage_kernel(GroupArgs g, const int64_t *
             const int64_t c = v * kStageVec;
             if (v < nvec) {
                 if (aligned && c + kStageVec <= n) {
-                    x[u] = *reinterpret_cast<const float4 *>(src + c);
+                    const stage_f4 t = __builtin_nontemporal_load(reinterpret_cast<const stage_f4 *>(src + c));
+                    x[u] = make_float4(t[0], t[1], t[2], t[3]);
                 } else {
                     x[u].x = c + 0 < n ? src[c + 0] : 0.f;
                     x[u].y = c + 1 < n ? src[c + 1] : 0.f;
@@ -723,7 +731,8 @@ __global__ __launch_bounds__(256) void stage_kernel(GroupArgs g, const int64_t *
                 const int64_t tile = c / g.tw;
                 const int64_t lane = c - tile * g.tw;
                 float *ring = reinterpret_cast<float *>(g.state + tile * g.tile_bytes);
-                *reinterpret_cast<float4 *>(ring + (size_t)slot * g.tw + lane) = x[u];
+                __builtin_nontemporal_store(stage_f4{x[u].x, x[u].y, x[u].z, x[u].w},
+                                            reinterpret_cast<stage_f4 *>(ring + (size_t)slot * g.tw + lane));
             }
         }
     }
