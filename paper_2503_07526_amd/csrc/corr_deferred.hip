@@ -689,11 +689,11 @@ hipError_t launch_deferred_t(const DeferredArgs &a, hipStream_t st)
 constexpr int kStageVec = 4;
 constexpr int kStageUnroll = 4;
 
-// The sample is read once and its ring row is read again only by the fold
-// of its subset, at least one push later (when a push's traffic has long
-// passed through the caches), so both streams are non-temporal: the staging
-// of 6e7 channels took about 9 us less per push (the large step 0.244
-// against 0.253 ms).
+// The sample is read once, and its ring row is read again only by the fold
+// of its subset: in the same push for one subset in T, up to T pushes (and
+// hundreds of MB of traffic) later for the others.  So both streams are
+// non-temporal: the staging of 6e7 channels took about 9 us less per push
+// (the large step 0.244 against 0.253 ms).
 typedef float stage_f4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void stage_kernel(GroupArgs g, const int64_t *step, int aligned)
