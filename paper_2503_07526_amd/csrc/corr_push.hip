@@ -45,10 +45,12 @@ __device__ __forceinline__ void vstore(T *p, const T (&in)[N])
     *reinterpret_cast<V *>(p) = v;
 }
 
-// The same, non-temporal: for the accumulator rows, which a push reads and
-// writes once and no later push touches before the whole state has streamed
-// past the caches (the plain 3e6-channel push 267 against 294 us).  The ring
-// rows keep ordinary loads: each is read again by the next p - 1 pushes.
+// The same, non-temporal: for the accumulator rows of a group whose state is
+// larger than the last-level cache, which a push reads and writes once and no
+// later push touches before the whole state has streamed past the caches
+// (the plain 3e6-channel push 267 against 294 us: the ring, which the next
+// p - 1 pushes read again and which keeps ordinary loads, then stays cached).
+// A smaller group keeps its accumulators cached from push to push.
 template <typename T, int N>
 __device__ __forceinline__ void vload_nt(const T *p, T (&out)[N])
 {
@@ -67,6 +69,13 @@ __device__ __forceinline__ void vstore_nt(T *p, const T (&in)[N])
     __builtin_memcpy(&v, &in[0], sizeof(T) * N);
     __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
 }
+
+// A group whose state is above this size streams its accumulator rows (the
+// device's last-level cache holds 256 MB).  The choice is a template argument
+// of the kernel: a branch between the two forms of the same load lets the
+// compiler merge them and drop the non-temporal hint.
+constexpr int64_t kStreamAccBytes = (int64_t)256 << 20;
+static bool stream_acc(const GroupArgs &g) { return g.n_tiles * g.tile_bytes > kStreamAccBytes; }
 
 // ---------------------------------------------------------------- kinds
 template <int K> struct KT;
@@ -161,7 +170,7 @@ template <> struct Acc<K_CF64_F64> {
 // independent memory requests in flight.  Lag L reads ring slot
 // (slot - L) mod p of the lagged series; lag 0 takes the newest lagged value
 // y0 from registers (y0 = x for an autocorrelation).
-template <int K, int CPT, int NJ>
+template <int K, int CPT, int NJ, bool NTA>
 __device__ __forceinline__ void lag_chunk(const typename KT<K>::S (&x)[CPT],
                                           const typename KT<K>::S (&y0)[CPT],
                                           const typename KT<K>::S *ring, typename KT<K>::A *hi,
@@ -180,8 +189,13 @@ __device__ __forceinline__ void lag_chunk(const typename KT<K>::S (&x)[CPT],
         if (sl < 0) sl += p;
         vload<S, CPT>(ring + (size_t)sl * tw + lane_off, r[j]);
         const size_t ro = (size_t)(L0 + j - row_base) * tw + lane_off;
-        vload_nt<A, CPT>(hi + ro, h[j]);
-        if constexpr (NP == 2) vload_nt<A, CPT>(lo + ro, c[j]);
+        if constexpr (NTA) {
+            vload_nt<A, CPT>(hi + ro, h[j]);
+            if constexpr (NP == 2) vload_nt<A, CPT>(lo + ro, c[j]);
+        } else {
+            vload<A, CPT>(hi + ro, h[j]);
+            if constexpr (NP == 2) vload<A, CPT>(lo + ro, c[j]);
+        }
     }
     if (L0 == 0) {
 #pragma unroll
@@ -192,14 +206,19 @@ __device__ __forceinline__ void lag_chunk(const typename KT<K>::S (&x)[CPT],
 #pragma unroll
         for (int i = 0; i < CPT; ++i) Acc<K>::add(h[j][i], c[j][i], x[i], r[j][i]);
         const size_t ro = (size_t)(L0 + j - row_base) * tw + lane_off;
-        vstore_nt<A, CPT>(hi + ro, h[j]);
-        if constexpr (NP == 2) vstore_nt<A, CPT>(lo + ro, c[j]);
+        if constexpr (NTA) {
+            vstore_nt<A, CPT>(hi + ro, h[j]);
+            if constexpr (NP == 2) vstore_nt<A, CPT>(lo + ro, c[j]);
+        } else {
+            vstore<A, CPT>(hi + ro, h[j]);
+            if constexpr (NP == 2) vstore<A, CPT>(lo + ro, c[j]);
+        }
     }
 }
 
 // Lag loop of one level: lags [l_begin, l_end), accumulator row L - row_base.
 // Full chunks of LCH lags, then chunks of 4, then single lags.
-template <int K, int CPT, int LCH>
+template <int K, int CPT, int LCH, bool NTA>
 __device__ __forceinline__ void lag_loop(const typename KT<K>::S (&x)[CPT],
                                          const typename KT<K>::S (&y0)[CPT],
                                          const typename KT<K>::S *ring, typename KT<K>::A *hi,
@@ -209,15 +228,15 @@ __device__ __forceinline__ void lag_loop(const typename KT<K>::S (&x)[CPT],
     int L = l_begin;
 #pragma unroll 1
     for (; L + LCH <= l_end; L += LCH)
-        lag_chunk<K, CPT, LCH>(x, y0, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
+        lag_chunk<K, CPT, LCH, NTA>(x, y0, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
     if constexpr (LCH > 4) {
 #pragma unroll 1
         for (; L + 4 <= l_end; L += 4)
-            lag_chunk<K, CPT, 4>(x, y0, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
+            lag_chunk<K, CPT, 4, NTA>(x, y0, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
     }
 #pragma unroll 1
     for (; L < l_end; ++L)
-        lag_chunk<K, CPT, 1>(x, y0, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
+        lag_chunk<K, CPT, 1, NTA>(x, y0, ring, hi, lo, slot, p, L, row_base, tw, lane_off);
 }
 
 // One push of one tile of one group.  s = 1-based push index.  PAIR: the
@@ -226,7 +245,7 @@ __device__ __forceinline__ void lag_loop(const typename KT<K>::S (&x)[CPT],
 // level-0 lags this call adds; head: the call also writes the ring slots and
 // runs the cascade (one head call per tile and push; the level-0 lags of a
 // push never read the slot it writes, so the calls are independent).
-template <int K, int CPT, int LCH, bool PAIR = false>
+template <int K, int CPT, int LCH, bool PAIR = false, bool NTA = false>
 __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int64_t s,
                                           int lag_lo = 0, int lag_hi = 1 << 30, bool head = true)
 {
@@ -276,7 +295,7 @@ __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int6
         const int nlag = (int)(s < p ? s : p);
         const int l_end = lag_hi < nlag ? lag_hi : nlag;
         if (lag_lo < l_end)
-            lag_loop<K, CPT, LCH>(x, y, ring, hi, lo, slot, p, lag_lo, l_end, 0, tw, lane_off);
+            lag_loop<K, CPT, LCH, NTA>(x, y, ring, hi, lo, slot, p, lag_lo, l_end, 0, tw, lane_off);
     }
     if (!head) return;
 
@@ -339,7 +358,7 @@ __device__ __forceinline__ void push_tile(const GroupArgs &g, int64_t tile, int6
         vstore<S, CPT>(ring + (size_t)slot * tw + lane_off, v);
         if constexpr (PAIR) vstore<S, CPT>(ring + (size_t)(p + slot) * tw + lane_off, vx);
         const int nl = (int)(sk < p ? sk : p);
-        if (nl > lag0) lag_loop<K, CPT, LCH>(vx, v, ring, hi, lo, slot, p, lag0, nl, lag0, tw, lane_off);
+        if (nl > lag0) lag_loop<K, CPT, LCH, NTA>(vx, v, ring, hi, lo, slot, p, lag0, nl, lag0, tw, lane_off);
 #pragma unroll
         for (int i = 0; i < CPT; ++i) {
             vprev[i] = v[i];
@@ -395,12 +414,13 @@ __global__ __launch_bounds__(256) void push_batched_kernel(PushArgs a)
     }
 }
 
-// Plain form: one group per launch, one block per tile, kind fixed at compile time.
-template <int K, int CPT, int LCH, bool PAIR>
+// Plain form: one group per launch, one block per tile, kind fixed at compile
+// time (NTA: accumulator rows streamed, for groups larger than the cache).
+template <int K, int CPT, int LCH, bool PAIR, bool NTA>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void push_group_kernel(GroupArgs g, const int64_t *step)
 {
     const int64_t s = *step + 1;
-    push_tile<K, CPT, LCH, PAIR>(g, (int64_t)blockIdx.x, s);
+    push_tile<K, CPT, LCH, PAIR, NTA>(g, (int64_t)blockIdx.x, s);
 }
 
 // Group with few tiles: the level-0 lags of a push split over blockIdx.y
@@ -451,7 +471,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
     const int l_begin = (int)blockIdx.y * lags_per_block;
     const int l_end = l_begin + lags_per_block < nlag ? l_begin + lags_per_block : nlag;
     if (l_begin < l_end)
-        lag_loop<K, CPT, LCH>(x, y, ring, hi, lo, slot, p, l_begin, l_end, 0, tw, lane_off);
+        lag_loop<K, CPT, LCH, false>(x, y, ring, hi, lo, slot, p, l_begin, l_end, 0, tw, lane_off);
 }
 
 // Last kernel of a push S = *step + 1: tile group S mod T of every
@@ -536,42 +556,44 @@ hipError_t launch_push_batched(const PushArgs &a, int cpt, int lch, int grid, in
     return hipErrorInvalidValue;
 }
 
-template <int CPT, int LCH, bool PAIR>
+template <int CPT, int LCH, bool PAIR, bool NTA>
 static hipError_t launch_group_t(const GroupArgs &g, const int64_t *step, int block,
                                  hipStream_t st)
 {
     const dim3 grid((unsigned)g.n_tiles);
     switch (g.kind) {
-    case K_F32_F64: hipLaunchKernelGGL((push_group_kernel<K_F32_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
-    case K_F32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_F32_KAHAN, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
-    case K_F32_F32: hipLaunchKernelGGL((push_group_kernel<K_F32_F32, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
-    case K_F64_F64: hipLaunchKernelGGL((push_group_kernel<K_F64_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
-    case K_CF32_F64: hipLaunchKernelGGL((push_group_kernel<K_CF32_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
-    case K_CF32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_CF32_KAHAN, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
-    case K_CF32_F32: hipLaunchKernelGGL((push_group_kernel<K_CF32_F32, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
-    default: hipLaunchKernelGGL((push_group_kernel<K_CF64_F64, CPT, LCH, PAIR>), grid, dim3(block), 0, st, g, step); break;
+    case K_F32_F64: hipLaunchKernelGGL((push_group_kernel<K_F32_F64, CPT, LCH, PAIR, NTA>), grid, dim3(block), 0, st, g, step); break;
+    case K_F32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_F32_KAHAN, CPT, LCH, PAIR, NTA>), grid, dim3(block), 0, st, g, step); break;
+    case K_F32_F32: hipLaunchKernelGGL((push_group_kernel<K_F32_F32, CPT, LCH, PAIR, NTA>), grid, dim3(block), 0, st, g, step); break;
+    case K_F64_F64: hipLaunchKernelGGL((push_group_kernel<K_F64_F64, CPT, LCH, PAIR, NTA>), grid, dim3(block), 0, st, g, step); break;
+    case K_CF32_F64: hipLaunchKernelGGL((push_group_kernel<K_CF32_F64, CPT, LCH, PAIR, NTA>), grid, dim3(block), 0, st, g, step); break;
+    case K_CF32_KAHAN: hipLaunchKernelGGL((push_group_kernel<K_CF32_KAHAN, CPT, LCH, PAIR, NTA>), grid, dim3(block), 0, st, g, step); break;
+    case K_CF32_F32: hipLaunchKernelGGL((push_group_kernel<K_CF32_F32, CPT, LCH, PAIR, NTA>), grid, dim3(block), 0, st, g, step); break;
+    default: hipLaunchKernelGGL((push_group_kernel<K_CF64_F64, CPT, LCH, PAIR, NTA>), grid, dim3(block), 0, st, g, step); break;
     }
     return hipGetLastError();
 }
 
-template <bool PAIR>
+template <bool PAIR, bool NTA>
 static hipError_t launch_push_group_p(const GroupArgs &g, const int64_t *step, int cpt, int lch,
                                       int block, hipStream_t st)
 {
-    if (cpt == 1 && lch == 16) return launch_group_t<1, 16, PAIR>(g, step, block, st);
-    if (cpt == 1 && lch == 8) return launch_group_t<1, 8, PAIR>(g, step, block, st);
-    if (cpt == 2 && lch == 8) return launch_group_t<2, 8, PAIR>(g, step, block, st);
-    if (cpt == 2 && lch == 4) return launch_group_t<2, 4, PAIR>(g, step, block, st);
-    if (cpt == 4 && lch == 4) return launch_group_t<4, 4, PAIR>(g, step, block, st);
-    if (cpt == 4 && lch == 8) return launch_group_t<4, 8, PAIR>(g, step, block, st);
+    if (cpt == 1 && lch == 16) return launch_group_t<1, 16, PAIR, NTA>(g, step, block, st);
+    if (cpt == 1 && lch == 8) return launch_group_t<1, 8, PAIR, NTA>(g, step, block, st);
+    if (cpt == 2 && lch == 8) return launch_group_t<2, 8, PAIR, NTA>(g, step, block, st);
+    if (cpt == 2 && lch == 4) return launch_group_t<2, 4, PAIR, NTA>(g, step, block, st);
+    if (cpt == 4 && lch == 4) return launch_group_t<4, 4, PAIR, NTA>(g, step, block, st);
+    if (cpt == 4 && lch == 8) return launch_group_t<4, 8, PAIR, NTA>(g, step, block, st);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_push_group(const GroupArgs &g, const int64_t *step, int cpt, int lch, int block,
                              hipStream_t st)
 {
-    return g.pair ? launch_push_group_p<true>(g, step, cpt, lch, block, st)
-                  : launch_push_group_p<false>(g, step, cpt, lch, block, st);
+    // pair groups keep cached accumulators (one form each)
+    if (g.pair) return launch_push_group_p<true, false>(g, step, cpt, lch, block, st);
+    return stream_acc(g) ? launch_push_group_p<false, true>(g, step, cpt, lch, block, st)
+                         : launch_push_group_p<false, false>(g, step, cpt, lch, block, st);
 }
 
 template <int CPT, int LCH, bool PAIR>
