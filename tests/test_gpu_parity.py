@@ -721,6 +721,36 @@ def test_window_deferred_readouts(corrmod, dtype, accum):
         assert np.array_equal(a["c_per_channel"], r["c_per_channel"])
 
 
+def test_window_folds_sharing_launches(corrmod):
+    """Four block-deferred windows in one context: two of one kind and
+    length (their folds share a launch, the second's channel blocks after the
+    first's), one of another length and one of another kind (launched alone).
+    The shared launches give the same state bit for bit as one launch per
+    window (the per-group form), and every window matches the oracle."""
+    S = 700
+    specs = [(300, 512, "f32", "kahan"), (700, 512, "f32", "kahan"), (200, 576, "f32", "kahan"),
+             (100, 512, "cf32", "kahan")]
+    say(f"[windows sharing launches] {[sp[:2] for sp in specs]}")
+    xs = [ou_inputs(47, 20 + i, n, S, dt, tau=50.0, tau_hi=None) for i, (n, p, dt, acc) in enumerate(specs)]
+    groups = [corrmod.GroupDesc(n, 1, p, 2, dtype=dt, accum=acc) for (n, p, dt, acc) in specs]
+    dev = torch.device("cuda:0")
+    out = {}
+    for per_group in (False, True):
+        with corrmod.Correlator(groups, per_group=per_group) as c:
+            _push_all(c, xs)
+            out[per_group] = [c.finalize(i, slice_=(0, sp[0])) for i, sp in enumerate(specs)]
+    for i in range(len(specs)):
+        assert np.array_equal(out[True][i]["c_per_channel"], out[False][i]["c_per_channel"]), i
+        assert np.array_equal(out[True][i]["c"], out[False][i]["c"]), i
+    for i, (n, p, dt, acc) in enumerate(specs):
+        cplx = np.iscomplexobj(xs[i])
+        o = oracle.OracleCorrelator(n, 1, p, 2, complex_=cplx)
+        for s in range(S):
+            o.push(xs[i][s].astype(np.complex128 if cplx else np.float64))
+        res = dict(out[False][i], c_per_channel=out[False][i]["c_per_channel"][n - 3:n])
+        gate(res, o, TOL[(dt, acc)], slice_=(n - 3, n), label=f"window {i}")
+
+
 @pytest.mark.parametrize("dtype", ["f32", "cf32"])
 def test_window_deferred_equals_direct(corrmod, dtype):
     """The block-deferred window regroups the sums of the per-step window
